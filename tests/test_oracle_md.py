@@ -1,0 +1,169 @@
+"""Pins of the bead dynamics and of the bead-lattice coupling (Sec. II.B and
+the interpolation kernels of Sec. II.C): forces are minus the gradient of the
+stated energies, pair forces obey Newton's third law, the kernel is a
+partition of unity that reproduces linear fields, friction alone decays
+geometrically, and the fluid + bead momentum is conserved."""
+import numpy as np
+import pytest
+
+from oracle import md, lb, step
+from paper_1710_09421_amd import workloads
+
+RNG = np.random.default_rng(2)
+BOX = np.array([12.0, 10.0, 14.0])
+
+
+def chain(n, bond=0.97, seed=3):
+    rng = np.random.default_rng(seed)
+    R = [np.array([5.0, 5.0, 7.0])]
+    while len(R) < n:
+        v = rng.normal(size=3)
+        v /= np.linalg.norm(v)
+        c = R[-1] + bond * v
+        if all(np.linalg.norm(c - r) > 1.0 for r in R[:-1]):
+            R.append(c)
+    return np.array(R)
+
+
+def numerical_gradient(fun, R, h=1e-6):
+    g = np.zeros_like(R)
+    for i in range(R.shape[0]):
+        for a in range(3):
+            Rp = R.copy(); Rp[i, a] += h
+            Rm = R.copy(); Rm[i, a] -= h
+            g[i, a] = (fun(Rp) - fun(Rm)) / (2 * h)
+    return g
+
+
+def test_fene_force_is_minus_energy_gradient():
+    R = chain(8)
+    F = md.fene_forces(R, BOX, 30.0, 1.5)
+    g = numerical_gradient(lambda X: md.fene_energy(X, BOX, 30.0, 1.5), R)
+    assert np.allclose(F, -g, rtol=1e-6, atol=1e-6)
+    assert np.allclose(F.sum(axis=0), 0.0, atol=1e-12)
+
+
+def test_wca_force_is_minus_energy_gradient():
+    R = chain(10, bond=0.9)
+    R += RNG.normal(scale=0.05, size=R.shape)
+    F = md.wca_pair_forces(R, BOX, 1.0, 1.0)
+    assert np.any(F != 0)
+    g = numerical_gradient(lambda X: md.wca_energy(X, BOX, 1.0, 1.0), R)
+    assert np.allclose(F, -g, rtol=1e-5, atol=1e-5)
+    assert np.allclose(F.sum(axis=0), 0.0, atol=1e-10)
+
+
+def test_wca_vanishes_beyond_cutoff_and_uses_minimum_image():
+    R = np.array([[0.2, 5.0, 5.0], [11.6, 5.0, 5.0]])     # 0.6 apart across x = 0
+    F = md.wca_pair_forces(R, BOX, 1.0, 1.0)
+    assert F[0, 0] > 0 and F[1, 0] < 0
+    R2 = np.array([[2.0, 5.0, 5.0], [2.0 + 1.13, 5.0, 5.0]])
+    assert not md.wca_pair_forces(R2, BOX, 1.0, 1.0).any()
+
+
+def test_wall_force_is_minus_energy_gradient():
+    solid = np.zeros((14, 10, 12), dtype=bool)
+    solid[:3] = True
+    walls = md.wall_sites(solid)
+    # the slab z = 0..2 touches fluid at z = 2 and, through the periodic face, at z = 0
+    assert set(walls[:, 2].tolist()) == {0.0, 2.0}
+    assert walls.shape[0] == 2 * 10 * 12
+    R = np.array([[4.3, 3.2, 3.05], [6.1, 7.7, 3.4], [1.0, 1.0, 8.0]])
+    F = md.wall_forces(R, walls, BOX, 1.0, 1.0)
+    g = numerical_gradient(lambda X: md.wall_energy(X, walls, BOX, 1.0, 1.0), R)
+    assert np.allclose(F, -g, rtol=1e-5, atol=1e-5)
+    assert F[0, 2] > 0 and not F[2].any()
+
+
+def test_trilinear_partition_of_unity_and_linear_reproduction():
+    shape = (10, 12, 14)
+    R = RNG.uniform(1.0, 8.0, size=(20, 3))
+    idx, w = md.trilinear(R, shape)
+    assert np.allclose(w.sum(axis=1), 1.0, rtol=1e-15)
+    zz, yy, xx = np.indices(shape).astype(float)
+    lin = 0.3 + 1.7 * xx - 0.4 * yy + 2.2 * zz
+    val = (w * md.gather(lin, idx)).sum(axis=1)
+    assert np.allclose(val, 0.3 + 1.7 * R[:, 0] - 0.4 * R[:, 1] + 2.2 * R[:, 2], rtol=1e-13)
+
+
+def test_deposit_conserves_charge():
+    shape = (10, 12, 14)
+    R = RNG.uniform(0.0, 20.0, size=(9, 3))
+    q = RNG.uniform(-1, 1, size=9)
+    rho = md.deposit_charge(R, q, shape)
+    assert rho.sum() == pytest.approx(q.sum(), rel=1e-13)
+
+
+def _quiescent_fields(shape, n_solvent=1.0, n_ion=0.01):
+    n = np.stack([np.full(shape, n_solvent), np.full(shape, n_ion), np.full(shape, n_ion)])
+    j = np.zeros((3, 3) + shape)
+    E = np.zeros((3,) + shape)
+    return n, j, E
+
+
+def test_friction_relaxes_bead_and_node_together():
+    """A bead sitting exactly on a node of a fluid at rest, with no other
+    force: the bead and that node exchange momentum each substep, so the
+    relative velocity decays as (1 - gamma h (1/M + 1/n))^s (two-body
+    relaxation with the node's total density n) while M V + n u is kept.
+    Velocities are tiny so that the bead stays on the node to 1e-8."""
+    shape = (8, 8, 8)
+    n, j, E = _quiescent_fields(shape)
+    fluid = np.ones(shape, dtype=bool)
+    R = np.array([[3.0, 4.0, 2.0]])
+    V0 = np.array([[0.1, -0.05, 0.02]]) * 1e-6
+    M, gamma, n_sub = 2.0, 5.0, 10
+    poly = dict(M=M, q=np.zeros(1), k_fene=30.0, R0=1.5, eps=1.0, sigma=1.0, gamma=gamma, n_sub=n_sub)
+    R1, V1, K = md.md_substeps(R, V0, n, j, E, fluid, np.zeros((0, 3)), poly)
+    h = 1.0 / n_sub
+    ntot = n[:, 0, 0, 0].sum()
+    u_node = K[:, :, 2, 4, 3].sum(axis=0) / ntot
+    assert np.allclose(V1[0] - u_node, V0[0] * (1 - gamma * h * (1 / M + 1 / ntot)) ** n_sub, rtol=1e-6)
+    # the fluid receives exactly the impulse the bead lost
+    assert np.allclose(K.sum(axis=(0, 2, 3, 4)), -M * (V1 - V0)[0], rtol=1e-12)
+    assert np.abs(K[:, :, 2, 4, 3]).sum() > 0.999 * np.abs(K).sum()
+
+
+def test_fluid_plus_bead_momentum_is_conserved():
+    """Periodic box, no walls, no applied field, neutral beads, charged ions:
+    total momentum of the three species plus the beads stays at its initial
+    value (the electrostatic forces cancel by the force-balance identity and
+    the friction is exchanged exactly)."""
+    shape = (8, 8, 12)
+    rng = np.random.default_rng(5)
+    n0 = np.stack([np.ones(shape), 0.01 * (1 + 0.05 * rng.uniform(-1, 1, shape)),
+                   0.01 * (1 + 0.05 * rng.uniform(-1, 1, shape))])
+    R = chain(6, seed=4)
+    V = rng.normal(scale=0.02, size=R.shape)
+    poly = step.polymer_params(6, q=0.0, gamma=20.0, n_sub=40)
+    p = step.Params(poisson_tol=1e-12)
+    sim = step.Simulation(p, np.zeros(shape, dtype=bool), np.zeros(shape), n0,
+                          beads=(R, V, poly))
+
+    def total():
+        return sim.momentum() + poly["M"] * sim.V.sum(axis=0)
+    P0 = total()
+    sim.run(6)
+    assert np.allclose(total(), P0, atol=1e-11)
+    assert np.abs(sim.V).max() > 0
+
+
+def test_bead_and_uniform_flow_reach_common_velocity():
+    """A bead at rest on a node of a uniformly moving fluid: bead and node
+    relax to the common velocity of the two-body system."""
+    shape = (8, 8, 8)
+    n, j, E = _quiescent_fields(shape)
+    u0 = np.array([0.01, -0.02, 0.005]) * 1e-6
+    j = n[:, None] * u0[None, :, None, None, None]
+    fluid = np.ones(shape, dtype=bool)
+    M, gamma, n_sub = 1.0, 20.0, 40
+    poly = dict(M=M, q=np.zeros(1), k_fene=30.0, R0=1.5, eps=1.0, sigma=1.0, gamma=gamma, n_sub=n_sub)
+    R1, V1, K = md.md_substeps(np.array([[4.0, 4.0, 4.0]]), np.zeros((1, 3)), n, j, E, fluid,
+                               np.zeros((0, 3)), poly)
+    ntot = n[:, 0, 0, 0].sum()
+    common = ntot * u0 / (M + ntot)
+    decay = (1 - gamma / n_sub * (1 / M + 1 / ntot)) ** n_sub
+    u_node = u0 + K[:, :, 4, 4, 4].sum(axis=0) / ntot
+    assert np.allclose(V1[0] - u_node, -u0 * decay, rtol=1e-6, atol=1e-14)
+    assert np.allclose(M * V1[0] + ntot * u_node, ntot * u0, rtol=1e-6)
+    assert np.allclose(V1[0], common, rtol=1e-6)

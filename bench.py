@@ -1,0 +1,160 @@
+"""Throughput of the electrokinetic LB-MD time step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload single-pore|large|plain]
+
+A step is one pass of the whole hot path on the workload: charge pass,
+Poisson solve to the stated tolerance, bead update (when the workload has a
+chain) and the fused three-species collide-and-stream.  The timed region runs
+K steps with every input resident in GPU memory; the metric is lattice-site
+updates per second summed over the three species (MLUPS per species-step).
+
+The JSON line also carries:
+  roofline      the fused lattice kernel priced against HBM bandwidth, from
+                its average duration measured with HIP events on the
+                library's stream during the timed region, and its algorithmic
+                bytes per launch (populations read and written once, the link
+                word of every site, the potential of every fluid site);
+  cpu_baseline  the float64 oracle timed on the host for a bounded sample of
+                the same workload (one untimed step, then one timed step).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def build_workload(name):
+    from paper_1710_09421_amd import workloads
+    if name == "single-pore":
+        return workloads.single_pore()
+    if name == "large":
+        return workloads.large_system()
+    if name == "plain":
+        return workloads.plain_box(32)
+    if name == "single-pore-open":
+        return workloads.pore_system((128, 64, 64), 10, 5, 0.01, 0.01, -0.01, 0, 12)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def lb_bytes_per_launch(wl, precision_bytes):
+    """Algorithmic bytes of one fused lattice launch: 57 populations read and
+    written at every fluid site, the 4-byte link word of every site and the
+    float64 potential at every fluid site (its neighbours come from cache)."""
+    fluid = wl.fluid_sites
+    return fluid * (2 * 57 * precision_bytes + 8) + wl.sites * 4
+
+
+def cpu_baseline(wl, tol):
+    """Oracle (float64 NumPy, one thread) on the same workload: one untimed
+    step, then one timed step."""
+    from threadpoolctl import threadpool_limits
+    from oracle import step as ostep
+    with threadpool_limits(1):
+        p = ostep.Params(valence=wl.valence, tau=wl.tau, omega_drag=wl.omega_drag,
+                         bjerrum=wl.bjerrum, E_ext=wl.E_ext, poisson_tol=tol)
+        beads = None if wl.beads_R is None else (wl.beads_R, wl.beads_V, wl.polymer)
+        sim = ostep.Simulation(p, wl.solid.astype(bool), wl.wall_q, wl.n0, beads=beads)
+        sim.step()
+        t0 = time.perf_counter()
+        sim.step()
+        dt = time.perf_counter() - t0
+    return {"value": 3 * wl.sites / dt / 1e6, "unit": "MLUPS (species-steps)", "cores": 1,
+            "kind": "oracle",
+            "sample": f"1 timed step (after 1 untimed) of {wl.name}, float64 NumPy, 1 thread, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="single-pore")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--poisson", default="sor", choices=["sor", "mg"])
+    ap.add_argument("--check-every", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the method's data-parallel step runs on a single "
+              "MI355X here; multi-GPU runs are not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1710_09421_amd import ek
+
+    wl = build_workload(args.workload)
+    prec = ek.EK_FP32 if args.precision == "fp32" else ek.EK_FP64
+    method = ek.EK_POISSON_SOR if args.poisson == "sor" else ek.EK_POISSON_MG
+    ctx = ek.from_workload(wl, precision=prec, poisson_method=method,
+                           poisson_check_every=args.check_every)
+    ctx.step(args.warmup)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tm = ctx.timing()
+    st = ctx.stats()
+
+    value = 3 * wl.sites * args.steps / dt / 1e6
+    pbytes = 4 if prec == ek.EK_FP32 else 8
+    lb_ms = tm["ms_lb"] / max(tm["n_lb"], 1)
+    lb_bytes = lb_bytes_per_launch(wl, pbytes)
+    achieved = lb_bytes / (lb_ms * 1e-3) / 1e9
+    line = {
+        "metric": "MLUPS per species-step",
+        "value": round(value, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == ek.EK_FP32 else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": wl.name,
+            "sites": wl.sites,
+            "fluid_sites": wl.fluid_sites,
+            "species": 3,
+            "beads": 0 if wl.beads_R is None else int(wl.beads_R.shape[0]),
+            "poisson": f"{args.poisson} to {wl.poisson_tol:g} (fp64 residual), "
+                       f"mean {tm['poisson_iters'] / max(tm['n_steps'], 1):.1f} iterations/step",
+            "phase_ms_per_step": {
+                "charge": round(tm["ms_charge"] / args.steps, 4),
+                "poisson": round(tm["ms_poisson"] / args.steps, 4),
+                "md": round(tm["ms_md"] / args.steps, 4),
+                "lb": round(lb_ms, 4),
+            },
+            "mass_drift": [float(x) for x in (st["mass"] / wl.n0.sum(axis=(1, 2, 3)) - 1.0)],
+        },
+        "roofline": {
+            "kernel": "k_lb_step (fused pull-stream + collide, 3 species)",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "bytes_per_launch": lb_bytes,
+            "avg_launch_ms": round(lb_ms, 5),
+            "traffic": None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(wl, wl.poisson_tol)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

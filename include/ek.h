@@ -1,0 +1,197 @@
+/*
+ * ek.h - C ABI of the electrokinetic lattice-Boltzmann / MD time step on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The method (Datar, Fyta, Marini Bettolo Marconi, Melchionna, "Electrokinetic
+ * Lattice Boltzmann solver coupled to Molecular Dynamics"):
+ *   - a ternary mixture: neutral solvent (species 0), cations (1), anions (2),
+ *     point-like, unit masses, valences z^a, uniform permittivity
+ *     (Sec. II.A, species and moments);
+ *   - D3Q19 kinetic scheme with BGK relaxation towards a second-order
+ *     equilibrium (Eq. kernelf), forcing term S (Eq. kernelg) added with the
+ *     half-step (Guo) shift, inter-species drag (Eq. Fidef), propagation with
+ *     halfway bounce-back on solid walls (Sec. II.C);
+ *   - Poisson equation for the potential of ions, wall charges and bead
+ *     charges (Eq. poisson), solved by red-black SOR with Chebyshev
+ *     acceleration (Sec. II.C) or by red-black multigrid;
+ *   - Langevin beads of a bead-spring chain coupled to the species by
+ *     friction through a trilinear interpolation / spreading kernel, advanced
+ *     with MD substeps (Sec. II.B, Eq. polymermodel);
+ *   - the time loop of Fig. 1: moments, charge, Poisson, forces, beads,
+ *     collision and propagation.
+ *
+ * Conventions for every entry point:
+ *   - Every function returns ek_status (EK_OK = 0, errors < 0); nothing
+ *     throws across the ABI.  ek_last_error() gives a message for the last
+ *     failing call on a context (or on the calling thread for ek_create).
+ *   - Lattice fields are C-ordered [z][y][x] (x fastest), nz*ny*nx values.
+ *     Vector fields are [3][z][y][x] with components (x, y, z).
+ *   - Population order p = 0..18: rest, +x, -x, +y, -y, +z, -z, (+x+y),
+ *     (-x-y), (+x-y), (-x+y), (+x+z), (-x-z), (+x-z), (-x+z), (+y+z), (-y-z),
+ *     (+y-z), (-y+z).
+ *   - "host" pointers are ordinary CPU memory owned by the caller and are only
+ *     read or written during the call; "device" pointers are GPU memory owned
+ *     by the caller.  The library never frees caller memory.
+ *   - A context is used by one host thread at a time.  All GPU work is
+ *     enqueued on the HIP stream given at creation; calls that return host
+ *     data synchronise that stream.
+ *   - Units: lattice units, unit spacing, time step, particle mass and proton
+ *     charge; k_B T = v_T^2 = 1/3 by default.
+ */
+#ifndef EK_H
+#define EK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EK_OK = 0,
+  EK_EINVAL = -1,      /* invalid argument; the context state is unchanged   */
+  EK_EHIP = -2,        /* a HIP runtime call failed                           */
+  EK_ENOCONV = -3,     /* Poisson solve did not reach its tolerance; the step
+                          stops before the collision, the populations stay at
+                          the last completed step                              */
+  EK_EUNSTABLE = -4,   /* non-finite or negative species mass, a stretched
+                          bond or a bead without fluid around it               */
+  EK_ESTATE = -5,      /* call out of order (e.g. step before geometry)       */
+  EK_ENOMEM = -6       /* workspace too small or allocation failed           */
+} ek_status;
+
+enum { EK_FP32 = 0, EK_FP64 = 1 };                 /* population storage type */
+enum { EK_POISSON_SOR = 0, EK_POISSON_MG = 1 };    /* Poisson method          */
+enum { EK_WS_ZERO = 0, EK_WS_PREV = 1, EK_WS_LEARNED = 2 };  /* warm start    */
+
+/* Problem statement (Sec. II.A-C).  Copied at ek_create. */
+typedef struct {
+  int32_t nx, ny, nz;          /* lattice size; each even (red-black colouring
+                                  of the periodic box); all axes periodic     */
+  int32_t precision;           /* EK_FP32 or EK_FP64 populations; the
+                                  collision runs in the same type              */
+  double valence[3];           /* z^a: solvent, cation, anion                  */
+  double tau[3];               /* BGK relaxation time per species (> 1/2),
+                                  omega_visc = 1 / tau                         */
+  double omega_drag[3];        /* drag rates omega_drag^a of Eq. Fidef         */
+  double kT;                   /* k_B T (= v_T^2 of the lattice, 1/3)          */
+  double bjerrum;              /* Bjerrum length l_B; eps = 1/(4 pi l_B kT)    */
+  double E_ext[3];             /* applied field: force z^a E on ions, q E on
+                                  beads                                        */
+  double F_ext[3][3];          /* body force per particle [species][xyz]      */
+  int32_t poisson_method;      /* EK_POISSON_SOR or EK_POISSON_MG              */
+  double poisson_tol;          /* stop when ||b - A psi|| / ||b|| <= tol       */
+  int32_t poisson_max_iter;    /* SOR iterations or multigrid cycles           */
+  int32_t poisson_check_every; /* residual test every k iterations (>= 1)      */
+  double rho_jacobi;           /* Jacobi radius for the Chebyshev schedule;
+                                  0 selects (2 + cos(2 pi / max(n))) / 3       */
+  int32_t warm_start;          /* EK_WS_ZERO, EK_WS_PREV or EK_WS_LEARNED      */
+  uint64_t seed;               /* thermal noise seed (noise is not built yet)  */
+  int32_t fluctuations;        /* must be 0                                    */
+} ek_params;
+
+/* Bead-spring chain (Sec. II.B): FENE bonds between neighbours, repulsive
+ * WCA between all bead pairs and between beads and boundary solid sites,
+ * friction gamma with the species, n_sub MD substeps per lattice step. */
+typedef struct {
+  double M;                    /* bead mass                                    */
+  double k_fene, R0;           /* FENE spring constant and maximum extension   */
+  double eps, sigma;           /* WCA energy and diameter                      */
+  double gamma;                /* friction coefficient                         */
+  int32_t n_sub;               /* MD substeps per lattice step (>= 1)          */
+} ek_polymer_params;
+
+typedef struct {
+  double mass[3];              /* sum of n^a over the lattice (float64)        */
+  double momentum[3];          /* total fluid momentum sum_a j^a               */
+  int64_t step;                /* completed lattice steps                      */
+  int32_t poisson_iters;       /* iterations (or cycles) of the last solve     */
+  double poisson_residual;     /* relative residual of the last solve          */
+  int32_t fallback;            /* 1 if the learned warm start was rejected     */
+} ek_stats;
+
+typedef struct {
+  int32_t iterations;          /* SOR iterations or multigrid cycles           */
+  double residual;             /* final relative residual (float64)            */
+  double initial_residual;     /* relative residual of the warm start          */
+} ek_poisson_report;
+
+/* Workspace needed for these parameters and up to max_beads beads (bytes).
+ * Returns EK_EINVAL for invalid parameters. */
+ek_status ek_workspace_bytes(const ek_params* p, int32_t max_beads, size_t* bytes);
+
+/* Create a context.  dev_ws: device buffer of at least ek_workspace_bytes()
+ * bytes that holds all device state (the library then allocates no device
+ * memory), or NULL to let the library allocate it.  hip_stream: a
+ * hipStream_t (NULL = default stream).  *out receives the context. */
+ek_status ek_create(const ek_params* p, int32_t max_beads, void* dev_ws, size_t ws_bytes,
+                    void* hip_stream, struct ek_ctx** out);
+void ek_destroy(struct ek_ctx* ctx);
+const char* ek_last_error(const struct ek_ctx* ctx);
+
+/* Geometry (walls, Sec. II.A): host solid[nz*ny*nx] (0 fluid, 1 solid) and
+ * optional host wall_q[nz*ny*nx], the fixed charges of the wall (placed on
+ * solid sites; NULL = none).  Resets populations to zero. */
+ek_status ek_set_geometry(struct ek_ctx* ctx, const uint8_t* solid, const double* wall_q);
+
+/* Species density at rest: populations f_p = w_p n at every fluid site
+ * (host n[nz*ny*nx]; values on solid sites are ignored). */
+ek_status ek_set_species_density(struct ek_ctx* ctx, int32_t species, const double* n);
+
+/* Polymer: host pos[3*n] and vel[3*n] (x, y, z per bead, unwrapped
+ * coordinates, nodes at integer positions), host charge[n] (NULL = all 0). */
+ek_status ek_set_polymer(struct ek_ctx* ctx, int32_t n_beads, const double* pos,
+                         const double* vel, const double* charge,
+                         const ek_polymer_params* pp);
+
+/* Advance n_steps lattice steps (Fig. 1).  Returns after the stream is
+ * synchronised.  On EK_ENOCONV / EK_EUNSTABLE the step in progress is not
+ * applied. */
+ek_status ek_step(struct ek_ctx* ctx, int32_t n_steps);
+
+/* Density n^a and bare velocity j^a / n^a of the current populations
+ * (host outputs, float64; either pointer may be NULL; zero on solid sites). */
+ek_status ek_get_moments(struct ek_ctx* ctx, int32_t species, double* n, double* u);
+
+/* Potential of the last solve, mean zero (host psi[nz*ny*nx]). */
+ek_status ek_get_potential(struct ek_ctx* ctx, double* psi);
+
+/* Bead positions and velocities (host, 3 doubles per bead). */
+ek_status ek_get_beads(struct ek_ctx* ctx, double* pos, double* vel);
+
+ek_status ek_get_stats(struct ek_ctx* ctx, ek_stats* out);
+
+/* Standalone Poisson solve on device buffers: dev_rho[nz*ny*nx] charge
+ * density, dev_psi[nz*ny*nx] warm start on entry and solution (mean zero) on
+ * return, both float64.  Uses the context's method, tolerance and iteration
+ * limit; warm_start EK_WS_ZERO clears dev_psi first. */
+ek_status ek_poisson_solve(struct ek_ctx* ctx, const double* dev_rho, double* dev_psi,
+                           int32_t warm_start, ek_poisson_report* rep);
+
+/* Exactly `iterations` red-black SOR iterations (Chebyshev schedule restarted)
+ * on A psi = b with no convergence test and no mean removal: dev_b and
+ * dev_psi are float64 device buffers; used to compare iterates. */
+ek_status ek_poisson_sor_iterations(struct ek_ctx* ctx, const double* dev_b, double* dev_psi,
+                                    int32_t iterations);
+
+/* Per-phase GPU time, measured with HIP events recorded on the context's
+ * stream around each phase of every step while enabled: the charge pass, the
+ * Poisson solve, the bead update, and the fused lattice kernel (whose launch
+ * count is n_lb).  Used by the benchmark to price kernels against the
+ * hardware roofline. */
+typedef struct {
+  double ms_charge, ms_poisson, ms_md, ms_lb;
+  int64_t n_steps;              /* steps measured                               */
+  int64_t n_lb;                 /* fused lattice kernel launches measured       */
+  int64_t poisson_iters;        /* Poisson iterations (or cycles) summed        */
+} ek_timing;
+
+/* enable != 0 starts (and zeroes) the per-phase timers; 0 stops them. */
+ek_status ek_set_timing(struct ek_ctx* ctx, int32_t enable);
+ek_status ek_get_timing(struct ek_ctx* ctx, ek_timing* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EK_H */

@@ -1,0 +1,524 @@
+// Host runtime behind the C ABI of ek.h: parameter checks, the device
+// workspace, geometry preprocessing, the time loop of one lattice step and
+// the Poisson driver.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ek_context.h"
+
+using namespace ek;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+#define EK_HIP(call)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      return ctx->fail(EK_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));  \
+    }                                                                                \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+ek_status check_params(const ek_params* p, std::string& why) {
+  if (!p) { why = "params is NULL"; return EK_EINVAL; }
+  if (p->nx < 2 || p->ny < 2 || p->nz < 2 || (p->nx & 1) || (p->ny & 1) || (p->nz & 1)) {
+    why = "nx, ny, nz must be even and >= 2 (red-black colouring of the periodic box)";
+    return EK_EINVAL;
+  }
+  if ((long long)p->nx * p->ny * p->nz >= (1LL << 31)) { why = "lattice too large"; return EK_EINVAL; }
+  if (p->precision != EK_FP32 && p->precision != EK_FP64) { why = "precision must be EK_FP32 or EK_FP64"; return EK_EINVAL; }
+  for (int s = 0; s < 3; ++s) {
+    if (!(p->tau[s] > 0.5)) { why = "tau must exceed 1/2"; return EK_EINVAL; }
+    if (!(p->omega_drag[s] >= 0.0)) { why = "omega_drag must be >= 0"; return EK_EINVAL; }
+  }
+  if (!(p->kT > 0.0) || !(p->bjerrum > 0.0)) { why = "kT and bjerrum must be positive"; return EK_EINVAL; }
+  if (p->poisson_method != EK_POISSON_SOR && p->poisson_method != EK_POISSON_MG) {
+    why = "unknown poisson_method"; return EK_EINVAL;
+  }
+  if (!(p->poisson_tol > 0.0) || p->poisson_max_iter < 1 || p->poisson_check_every < 1) {
+    why = "poisson_tol > 0, poisson_max_iter >= 1 and poisson_check_every >= 1 required";
+    return EK_EINVAL;
+  }
+  if (p->rho_jacobi < 0.0 || p->rho_jacobi >= 1.0) { why = "rho_jacobi must be in [0, 1)"; return EK_EINVAL; }
+  if (p->warm_start < EK_WS_ZERO || p->warm_start > EK_WS_LEARNED) { why = "unknown warm_start"; return EK_EINVAL; }
+  if (p->fluctuations != 0) { why = "thermal fluctuations are not available"; return EK_EINVAL; }
+  return EK_OK;
+}
+
+// Workspace layout (every block 256-byte aligned).
+struct Layout {
+  size_t fA, fB, mask, wall_q, psi, b, partials, ps, stats, keys, vals, beads, mg, total;
+};
+
+Layout make_layout(const ek_params* p, int max_beads) {
+  const size_t n = (size_t)p->nx * p->ny * p->nz;
+  const size_t tsz = p->precision == EK_FP64 ? 8 : 4;
+  const SiteGrid g = site_grid(p->nx, p->ny, p->nz);
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+  L.fA = take(3 * Q * n * tsz);
+  L.fB = take(3 * Q * n * tsz);
+  L.mask = take(n * 4);
+  L.wall_q = take(n * 8);
+  L.psi = take(n * 8);
+  L.b = take(n * 8);
+  L.partials = take((size_t)g.nblocks() * 8 * 8);
+  L.ps = take(sizeof(PoissonScalars));
+  L.stats = take(16 * 8);
+  L.keys = take((size_t)HASH_SLOTS * 4);
+  L.vals = take((size_t)HASH_SLOTS * 10 * 8);
+  L.beads = take(bead_state_bytes(max_beads));
+  L.mg = take(mg_workspace_bytes(p->nx, p->ny, p->nz));
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+ek_status ek_ctx::fail(ek_status st, const std::string& msg) {
+  err = msg;
+  return st;
+}
+
+ek_status ek_ctx::sync() {
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return fail(EK_EHIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+  return EK_OK;
+}
+
+void* ek_ctx::fcur() { return cur_is_a ? fA : fB; }
+void* ek_ctx::fnext() { return cur_is_a ? fB : fA; }
+
+LBParams ek_ctx::lb_params() const {
+  LBParams lp{};
+  for (int s = 0; s < 3; ++s) {
+    lp.omega[s] = 1.0 / p.tau[s];
+    lp.valence[s] = p.valence[s];
+    lp.wdrag[s] = p.omega_drag[s];
+    lp.nref[s] = nref[s];
+    for (int c = 0; c < 3; ++c) lp.fext[s][c] = p.F_ext[s][c];
+    lp.eext[s] = p.E_ext[s];
+  }
+  return lp;
+}
+
+double ek_ctx::inv_eps() const { return 4.0 * M_PI * p.bjerrum * p.kT; }
+
+double ek_ctx::jacobi_radius() const {
+  if (p.rho_jacobi > 0.0) return p.rho_jacobi;
+  const int m = std::max(p.nx, std::max(p.ny, p.nz));
+  return (2.0 + std::cos(2.0 * M_PI / m)) / 3.0;
+}
+
+ek_status ek_ctx::read_scalars(PoissonScalars* out) {
+  ek_ctx* ctx = this;
+  EK_HIP(hipMemcpyAsync(pinned, ps, sizeof(PoissonScalars), hipMemcpyDeviceToHost, stream));
+  ek_status st = sync();
+  if (st) return st;
+  std::memcpy(out, pinned, sizeof(PoissonScalars));
+  return EK_OK;
+}
+
+// Red-black SOR with the Chebyshev schedule on A psi = b + shift (the shift
+// is already in ps).  The residual is tested after every `check_every`
+// iterations; iterations are enqueued in batches ahead of the test and turn
+// into no-ops once the device-side flag is set.
+ek_status ek_ctx::sor_solve(const double* bb, double* x, int& iters, double& res, double& res0) {
+  const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
+  const SiteGrid cg = colour_grid(p.nx, p.ny, p.nz, bx_colour);
+  const int nb = g.nblocks();
+  const double rj = jacobi_radius();
+  launch_residual(x, bb, ps, partials, dims, g, stream);
+  launch_residual_final(partials, nb, p.poisson_tol, 0, 1, ps, stream);
+  PoissonScalars h{};
+  ek_status st = read_scalars(&h);
+  if (st) return st;
+  int it = 0;
+  double omega = 1.0;
+  bool first = true;
+  const int ce = p.poisson_check_every;
+  int batch = std::max(ce, ((last_iters + ce - 1) / ce) * ce);
+  while (!h.done && it < p.poisson_max_iter) {
+    const int nrun = std::min(batch, p.poisson_max_iter - it);
+    for (int k = 0; k < nrun; ++k) {
+      for (int colour = 0; colour < 2; ++colour) {
+        launch_sor_half(x, bb, ps, colour, omega, dims, cg, stream);
+        omega = first ? 1.0 / (1.0 - 0.5 * rj * rj) : 1.0 / (1.0 - 0.25 * rj * rj * omega);
+        first = false;
+      }
+      ++it;
+      if (it % ce == 0 || it == p.poisson_max_iter) {
+        launch_residual(x, bb, ps, partials, dims, g, stream);
+        launch_residual_final(partials, nb, p.poisson_tol, it, 0, ps, stream);
+      }
+    }
+    st = read_scalars(&h);
+    if (st) return st;
+    batch = ce;
+  }
+  res0 = h.rel0;
+  res = h.rel;
+  if (!h.done) {
+    iters = it;
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "Poisson solve did not reach %.3g in %d iterations (residual %.3e)",
+                  p.poisson_tol, p.poisson_max_iter, h.rel);
+    return fail(EK_ENOCONV, buf);
+  }
+  iters = h.iters;
+  launch_psi_shift(x, ps, 1.0 / double(dims.n), dims, stream);
+  return EK_OK;
+}
+
+ek_status ek_ctx::poisson(const double* bb, double* x, int& iters, double& res, double& res0) {
+  if (p.poisson_method == EK_POISSON_MG) return mg_solve(bb, x, iters, res, res0);
+  return sor_solve(bb, x, iters, res, res0);
+}
+
+ek_status ek_ctx::ensure_events(int n_steps) {
+  ek_ctx* ctx = this;
+  while ((int)events.size() < 5 * n_steps) {
+    hipEvent_t e;
+    EK_HIP(hipEventCreate(&e));
+    events.push_back(e);
+  }
+  return EK_OK;
+}
+
+void ek_ctx::record(int t, int k) {
+  if (timing) (void)hipEventRecord(events[5 * t + k], stream);
+}
+
+template <typename T>
+ek_status ek_ctx::step_impl(int n_steps) {
+  ek_ctx* ctx = this;
+  const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
+  const int nb = g.nblocks();
+  const LBParams lp = lb_params();
+  if (timing) {
+    ek_status st = ensure_events(n_steps);
+    if (st) return st;
+  }
+  for (int t = 0; t < n_steps; ++t) {
+    const BeadTableView bt = bead_view();
+    record(t, 0);
+    // charge density of ions, walls and beads at time t
+    if (n_beads > 0) {
+      ek_status st = beads_deposit();
+      if (st) return st;
+    }
+    launch_charge<T>((const T*)fcur(), mask, wall_q, b, partials, lp, inv_eps(), dims, g, stream, bt);
+    launch_mean_shift(partials, nb, 1.0 / double(dims.n), inv_eps(), ps, stream);
+    record(t, 1);
+    if (p.warm_start == EK_WS_ZERO) launch_fill(psi, 0.0, dims.n, stream);
+    int iters = 0;
+    double res = 0, res0 = 0;
+    ek_status st = poisson(b, psi, iters, res, res0);
+    if (st) return st;
+    last_iters = iters;
+    last_res = res;
+    if (timing) tacc.poisson_iters += iters;
+    record(t, 2);
+    // beads: n_sub MD substeps with the fields of time t, friction spread
+    if (n_beads > 0) {
+      st = beads_advance<T>();
+      if (st) return st;
+    }
+    record(t, 3);
+    launch_lb_step<T>((const T*)fcur(), (T*)fnext(), mask, psi, lp, bt, partials, dims, g, stream);
+    record(t, 4);
+    launch_sum_partials(partials, nb, 6, stats_dev, stream);
+    cur_is_a = !cur_is_a;
+    ++step_count;
+  }
+  ek_status st = sync();
+  if (st) return st;
+  if (timing) {
+    for (int t = 0; t < n_steps; ++t) {
+      float ms[4];
+      for (int k = 0; k < 4; ++k)
+        EK_HIP(hipEventElapsedTime(&ms[k], events[5 * t + k], events[5 * t + k + 1]));
+      tacc.ms_charge += ms[0];
+      tacc.ms_poisson += ms[1];
+      tacc.ms_md += ms[2];
+      tacc.ms_lb += ms[3];
+      tacc.n_lb += 1;
+      tacc.n_steps += 1;
+    }
+  }
+  double h[6];
+  EK_HIP(hipMemcpy(h, stats_dev, sizeof h, hipMemcpyDeviceToHost));
+  for (int s = 0; s < 3; ++s) {
+    mass[s] = h[s];
+    mom[s] = h[3 + s];
+    if (!std::isfinite(h[s]) || h[s] < 0.0) return fail(EK_EUNSTABLE, "species mass is not finite or negative");
+  }
+  if (n_beads > 0) {
+    st = beads_check();
+    if (st) return st;
+  }
+  return EK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+ek_status ek_workspace_bytes(const ek_params* p, int32_t max_beads, size_t* bytes) {
+  std::string why;
+  ek_status st = check_params(p, why);
+  if (st) { g_create_error = why; return st; }
+  if (!bytes || max_beads < 0 || max_beads > MAX_BEADS) { g_create_error = "bad bytes pointer or max_beads"; return EK_EINVAL; }
+  *bytes = make_layout(p, max_beads).total;
+  return EK_OK;
+}
+
+ek_status ek_create(const ek_params* p, int32_t max_beads, void* dev_ws, size_t ws_bytes,
+                    void* hip_stream, ek_ctx** out) {
+  std::string why;
+  if (!out) { g_create_error = "out is NULL"; return EK_EINVAL; }
+  *out = nullptr;
+  ek_status st = check_params(p, why);
+  if (st) { g_create_error = why; return st; }
+  if (max_beads < 0 || max_beads > MAX_BEADS) { g_create_error = "max_beads out of range"; return EK_EINVAL; }
+  const Layout L = make_layout(p, max_beads);
+  char* ws = (char*)dev_ws;
+  bool own = false;
+  if (ws) {
+    if (ws_bytes < L.total) { g_create_error = "workspace too small"; return EK_ENOMEM; }
+    if (((uintptr_t)ws & 255) != 0) { g_create_error = "workspace must be 256-byte aligned"; return EK_EINVAL; }
+  } else {
+    if (hipMalloc((void**)&ws, L.total) != hipSuccess) { g_create_error = "hipMalloc of the workspace failed"; return EK_ENOMEM; }
+    own = true;
+  }
+  ek_ctx* c = new ek_ctx();
+  c->p = *p;
+  c->dims = Dims{p->nx, p->ny, p->nz, (long long)p->nx * p->ny * p->nz};
+  c->stream = (hipStream_t)hip_stream;
+  c->ws = ws;
+  c->own_ws = own;
+  c->max_beads = max_beads;
+  c->fA = ws + L.fA;
+  c->fB = ws + L.fB;
+  c->mask = (uint32_t*)(ws + L.mask);
+  c->wall_q = (double*)(ws + L.wall_q);
+  c->psi = (double*)(ws + L.psi);
+  c->b = (double*)(ws + L.b);
+  c->partials = (double*)(ws + L.partials);
+  c->ps = (PoissonScalars*)(ws + L.ps);
+  c->stats_dev = (double*)(ws + L.stats);
+  c->keys = (int*)(ws + L.keys);
+  c->vals = (long long*)(ws + L.vals);
+  c->bead_mem = ws + L.beads;
+  c->mg_mem = ws + L.mg;
+  if (hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+    if (own) (void)hipFree(ws);
+    delete c;
+    g_create_error = "hipHostMalloc failed";
+    return EK_EHIP;
+  }
+  c->bx_sites = 0;
+  c->bx_colour = 0;
+  c->mg_setup();
+  *out = c;
+  return EK_OK;
+}
+
+void ek_destroy(ek_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->own_ws) (void)hipFree(ctx->ws);
+  delete ctx;
+}
+
+const char* ek_last_error(const ek_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+ek_status ek_set_geometry(ek_ctx* ctx, const uint8_t* solid, const double* wall_q) {
+  if (!ctx) return EK_EINVAL;
+  if (!solid) return ctx->fail(EK_EINVAL, "solid is NULL");
+  const Dims d = ctx->dims;
+  std::vector<uint32_t> m(d.n, 0u);
+  long long nfluid = 0;
+  for (int z = 0; z < d.nz; ++z)
+    for (int y = 0; y < d.ny; ++y)
+      for (int x = 0; x < d.nx; ++x) {
+        const long long r = ((long long)z * d.ny + y) * d.nx + x;
+        uint32_t w = 0;
+        if (solid[r]) {
+          w |= MASK_SOLID;
+        } else {
+          ++nfluid;
+          for (int q = 1; q < Q; ++q) {
+            const int sx = (x - CX[q] + d.nx) % d.nx, sy = (y - CY[q] + d.ny) % d.ny,
+                      sz = (z - CZ[q] + d.nz) % d.nz;
+            if (solid[((long long)sz * d.ny + sy) * d.nx + sx]) w |= 1u << q;
+          }
+        }
+        if (wall_q && wall_q[r] != 0.0) w |= MASK_CHARGED;
+        m[r] = w;
+      }
+  if (nfluid == 0) return ctx->fail(EK_EINVAL, "geometry has no fluid site");
+  EK_HIP(hipMemcpy(ctx->mask, m.data(), d.n * 4, hipMemcpyHostToDevice));
+  if (wall_q) {
+    EK_HIP(hipMemcpy(ctx->wall_q, wall_q, d.n * 8, hipMemcpyHostToDevice));
+  } else {
+    launch_fill(ctx->wall_q, 0.0, d.n, ctx->stream);
+  }
+  ctx->host_solid.assign(solid, solid + d.n);
+  ctx->n_fluid = nfluid;
+  const size_t tsz = ctx->p.precision == EK_FP64 ? 8 : 4;
+  EK_HIP(hipMemsetAsync(ctx->fA, 0, 3 * Q * d.n * tsz, ctx->stream));
+  EK_HIP(hipMemsetAsync(ctx->fB, 0, 3 * Q * d.n * tsz, ctx->stream));
+  launch_fill(ctx->psi, 0.0, d.n, ctx->stream);
+  ctx->cur_is_a = true;
+  ctx->have_geometry = true;
+  for (int s = 0; s < 3; ++s) ctx->have_species[s] = false;
+  ctx->step_count = 0;
+  ctx->last_iters = 0;
+  return ctx->sync();
+}
+
+ek_status ek_set_species_density(ek_ctx* ctx, int32_t species, const double* n) {
+  if (!ctx) return EK_EINVAL;
+  if (!ctx->have_geometry) return ctx->fail(EK_ESTATE, "set the geometry first");
+  if (species < 0 || species > 2 || !n) return ctx->fail(EK_EINVAL, "bad species or NULL density");
+  const Dims d = ctx->dims;
+  double sum = 0.0;
+  for (long long r = 0; r < d.n; ++r) {
+    if (ctx->host_solid[r]) continue;
+    if (!std::isfinite(n[r]) || n[r] < 0.0) return ctx->fail(EK_EINVAL, "densities must be finite and >= 0");
+    sum += n[r];
+  }
+  const double nref = sum / double(ctx->n_fluid);
+  // stage the density in the free population buffer
+  double* stage = (double*)ctx->fnext();
+  EK_HIP(hipMemcpyAsync(stage, n, d.n * 8, hipMemcpyHostToDevice, ctx->stream));
+  if (ctx->p.precision == EK_FP64)
+    launch_init_species<double>((double*)ctx->fcur(), ctx->mask, stage, species, nref, d, ctx->stream);
+  else
+    launch_init_species<float>((float*)ctx->fcur(), ctx->mask, stage, species, nref, d, ctx->stream);
+  ctx->nref[species] = nref;
+  ctx->have_species[species] = true;
+  return ctx->sync();
+}
+
+ek_status ek_step(ek_ctx* ctx, int32_t n_steps) {
+  if (!ctx) return EK_EINVAL;
+  if (n_steps < 0) return ctx->fail(EK_EINVAL, "n_steps < 0");
+  if (!ctx->have_geometry || !ctx->have_species[0] || !ctx->have_species[1] || !ctx->have_species[2])
+    return ctx->fail(EK_ESTATE, "geometry and all three species densities must be set");
+  if (ctx->p.precision == EK_FP64) return ctx->step_impl<double>(n_steps);
+  return ctx->step_impl<float>(n_steps);
+}
+
+ek_status ek_get_moments(ek_ctx* ctx, int32_t species, double* n, double* u) {
+  if (!ctx) return EK_EINVAL;
+  if (species < 0 || species > 2) return ctx->fail(EK_EINVAL, "bad species");
+  if (!ctx->have_geometry) return ctx->fail(EK_ESTATE, "no geometry");
+  const Dims d = ctx->dims;
+  double* scratch = (double*)ctx->fnext();   // 4 doubles per site fit in the free buffer
+  if (ctx->p.precision == EK_FP64)
+    launch_moments<double>((const double*)ctx->fcur(), ctx->mask, species, ctx->nref[species],
+                           scratch, scratch + d.n, d, ctx->stream);
+  else
+    launch_moments<float>((const float*)ctx->fcur(), ctx->mask, species, ctx->nref[species],
+                          scratch, scratch + d.n, d, ctx->stream);
+  if (n) EK_HIP(hipMemcpyAsync(n, scratch, d.n * 8, hipMemcpyDeviceToHost, ctx->stream));
+  if (u) EK_HIP(hipMemcpyAsync(u, scratch + d.n, 3 * d.n * 8, hipMemcpyDeviceToHost, ctx->stream));
+  return ctx->sync();
+}
+
+ek_status ek_get_potential(ek_ctx* ctx, double* psi) {
+  if (!ctx) return EK_EINVAL;
+  if (!psi) return ctx->fail(EK_EINVAL, "psi is NULL");
+  EK_HIP(hipMemcpyAsync(psi, ctx->psi, ctx->dims.n * 8, hipMemcpyDeviceToHost, ctx->stream));
+  return ctx->sync();
+}
+
+ek_status ek_get_stats(ek_ctx* ctx, ek_stats* out) {
+  if (!ctx || !out) return EK_EINVAL;
+  std::memset(out, 0, sizeof *out);
+  for (int s = 0; s < 3; ++s) {
+    out->mass[s] = ctx->mass[s];
+    out->momentum[s] = ctx->mom[s];
+  }
+  out->step = ctx->step_count;
+  out->poisson_iters = ctx->last_iters;
+  out->poisson_residual = ctx->last_res;
+  out->fallback = ctx->last_fallback;
+  return EK_OK;
+}
+
+ek_status ek_set_timing(ek_ctx* ctx, int32_t enable) {
+  if (!ctx) return EK_EINVAL;
+  ctx->timing = enable != 0;
+  ctx->tacc = ek_timing{};
+  return EK_OK;
+}
+
+ek_status ek_get_timing(ek_ctx* ctx, ek_timing* out) {
+  if (!ctx || !out) return EK_EINVAL;
+  *out = ctx->tacc;
+  return EK_OK;
+}
+
+ek_status ek_poisson_solve(ek_ctx* ctx, const double* dev_rho, double* dev_psi,
+                           int32_t warm_start, ek_poisson_report* rep) {
+  if (!ctx) return EK_EINVAL;
+  if (!dev_rho || !dev_psi) return ctx->fail(EK_EINVAL, "NULL device buffer");
+  const SiteGrid g = site_grid(ctx->p.nx, ctx->p.ny, ctx->p.nz, ctx->bx_sites);
+  launch_rho_to_b(dev_rho, ctx->b, ctx->partials, ctx->inv_eps(), ctx->dims, g, ctx->stream);
+  launch_mean_shift(ctx->partials, g.nblocks(), 1.0 / double(ctx->dims.n), ctx->inv_eps(), ctx->ps,
+                    ctx->stream);
+  if (warm_start == EK_WS_ZERO) launch_fill(dev_psi, 0.0, ctx->dims.n, ctx->stream);
+  int iters = 0;
+  double res = 0, res0 = 0;
+  const int saved = ctx->last_iters;
+  ctx->last_iters = ctx->solo_iters;
+  ek_status st = ctx->poisson(ctx->b, dev_psi, iters, res, res0);
+  ctx->solo_iters = iters;
+  ctx->last_iters = saved;
+  if (rep) {
+    rep->iterations = iters;
+    rep->residual = res;
+    rep->initial_residual = res0;
+  }
+  if (st) return st;
+  return ctx->sync();
+}
+
+ek_status ek_poisson_sor_iterations(ek_ctx* ctx, const double* dev_b, double* dev_psi,
+                                    int32_t iterations) {
+  if (!ctx) return EK_EINVAL;
+  if (!dev_b || !dev_psi || iterations < 0) return ctx->fail(EK_EINVAL, "bad arguments");
+  const SiteGrid cg = colour_grid(ctx->p.nx, ctx->p.ny, ctx->p.nz, ctx->bx_colour);
+  launch_ps_reset(ctx->ps, 0.0, ctx->stream);
+  const double rj = ctx->jacobi_radius();
+  double omega = 1.0;
+  bool first = true;
+  for (int it = 0; it < iterations; ++it)
+    for (int colour = 0; colour < 2; ++colour) {
+      launch_sor_half(dev_psi, dev_b, ctx->ps, colour, omega, ctx->dims, cg, ctx->stream);
+      omega = first ? 1.0 / (1.0 - 0.5 * rj * rj) : 1.0 / (1.0 - 0.25 * rj * rj * omega);
+      first = false;
+    }
+  return ctx->sync();
+}
+
+}  // extern "C"
+
+template ek_status ek_ctx::step_impl<float>(int);
+template ek_status ek_ctx::step_impl<double>(int);

@@ -1,0 +1,94 @@
+// The context object behind the opaque ek_ctx handle.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "ek_internal.h"
+#include "md_table.h"
+
+namespace ek {
+constexpr int MAX_BEADS = 1024;        // one workgroup advances a whole chain
+size_t bead_state_bytes(int max_beads);
+size_t mg_workspace_bytes(int nx, int ny, int nz);
+}  // namespace ek
+
+struct ek_ctx {
+  ek_params p{};
+  ek::Dims dims{};
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  bool own_ws = false;
+  void* pinned = nullptr;              // small pinned host buffer for read-backs
+
+  // device state carved from the workspace
+  void* fA = nullptr;
+  void* fB = nullptr;
+  bool cur_is_a = true;                // fA holds the current post-collision populations
+  uint32_t* mask = nullptr;
+  double* wall_q = nullptr;
+  double* psi = nullptr;
+  double* b = nullptr;
+  double* partials = nullptr;
+  ek::PoissonScalars* ps = nullptr;
+  double* stats_dev = nullptr;
+  int* keys = nullptr;                 // bead-touched node table
+  long long* vals = nullptr;
+  char* bead_mem = nullptr;
+  char* mg_mem = nullptr;
+
+  // host-side state
+  std::vector<uint8_t> host_solid;
+  long long n_fluid = 0;
+  double nref[3] = {0, 0, 0};
+  bool have_geometry = false;
+  bool have_species[3] = {false, false, false};
+  long long step_count = 0;
+  int last_iters = 0;
+  int solo_iters = 0;
+  double last_res = 0.0;
+  int last_fallback = 0;
+  double mass[3] = {0, 0, 0};
+  double mom[3] = {0, 0, 0};
+  int bx_sites = 0, bx_colour = 0;     // launch shapes (0 = default)
+  std::string err;
+
+  // polymer
+  int max_beads = 0;
+  int n_beads = 0;
+  ek_polymer_params poly{};
+  bool table_dirty = false;
+
+  // per-phase timers (HIP events on the context stream)
+  bool timing = false;
+  std::vector<hipEvent_t> events;      // 5 per step: charge, poisson, md, lb start, lb end
+  ek_timing tacc{};
+  ek_status ensure_events(int n_steps);
+  void record(int step_in_call, int k);
+
+  // multigrid
+  struct MG;
+  MG* mg = nullptr;
+
+  ek_status fail(ek_status st, const std::string& msg);
+  ek_status sync();
+  void* fcur();
+  void* fnext();
+  ek::LBParams lb_params() const;
+  double inv_eps() const;
+  double jacobi_radius() const;
+  ek_status read_scalars(ek::PoissonScalars* out);
+  ek_status sor_solve(const double* b, double* x, int& iters, double& res, double& res0);
+  ek_status mg_solve(const double* b, double* x, int& iters, double& res, double& res0);
+  void mg_setup();
+  ek_status poisson(const double* b, double* x, int& iters, double& res, double& res0);
+  template <typename T>
+  ek_status step_impl(int n_steps);
+
+  // beads (kernels_md.hip)
+  ek::BeadTableView bead_view() const;
+  ek_status beads_deposit();
+  template <typename T>
+  ek_status beads_advance();
+  ek_status beads_check();
+};

@@ -1,0 +1,118 @@
+// Internal declarations shared by the host runtime and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ek.h"
+
+namespace ek {
+
+// ---------------------------------------------------------------------------
+// D3Q19 velocity set in the order fixed by ek.h: rest, 6 axis links, 12
+// face-diagonal links, opposite directions adjacent.
+// ---------------------------------------------------------------------------
+constexpr int Q = 19;
+constexpr int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+constexpr int OPP[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+__host__ __device__ constexpr double weight(int p) {
+  return p == 0 ? 1.0 / 3.0 : (p <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+// Per-site link word: bit p (1..18) set when the pull source r - c_p is solid
+// (the population is then bounced back from the opposite link of r itself).
+constexpr uint32_t MASK_SOLID = 1u << 31;       // the site itself is solid
+constexpr uint32_t MASK_CHARGED = 1u << 30;     // the site carries a fixed charge
+constexpr uint32_t MASK_BEAD = 1u << 29;        // a bead kernel touches the site
+
+// Fixed-point scales for order-independent (hence deterministic) sums of the
+// bead charge and bead force densities accumulated with integer atomics.
+constexpr double FIX_CHARGE = 4503599627370496.0;     // 2^52
+constexpr double FIX_FORCE = 1125899906842624.0;      // 2^50
+
+constexpr int BLOCK = 256;                            // threads per block for site kernels
+constexpr int HASH_SLOTS = 16384;                     // bead-touched node table (power of 2)
+
+// Launch shape of a site kernel: blockDim (bx, by) with bx * by == BLOCK,
+// grid (ceil(nx / bx), ceil(ny / by), nz).
+struct SiteGrid {
+  dim3 grid, block;
+  int nblocks() const { return int(grid.x * grid.y * grid.z); }
+};
+SiteGrid site_grid(int nx, int ny, int nz, int bx_pref = 0);
+// Launch shape for kernels that visit one colour of the red-black checkerboard:
+// threads cover nx/2 sites per row.
+SiteGrid colour_grid(int nx, int ny, int nz, int bx_pref = 0);
+
+struct Dims {
+  int nx, ny, nz;
+  long long n;       // nx * ny * nz
+};
+
+// Scalars the fused lattice kernel needs, passed by value.
+struct LBParams {
+  double omega[3];        // 1 / tau
+  double valence[3];
+  double wdrag[3];        // omega_drag
+  double nref[3];         // reference densities of the deviation storage
+  double fext[3][3];      // body force per particle
+  double eext[3];         // applied field
+};
+
+struct BeadTableView;      // md_table.h
+
+// Device-side scalars of the Poisson solver (one struct in device memory).
+struct PoissonScalars {
+  double shift;           // mean(rho) / eps, added to the stored -rho/eps
+  double r2, b2, psum;    // last residual sums
+  double rel;             // last relative residual
+  double rel0;            // residual of the warm start
+  int done;               // solve converged
+  int iters;              // iteration at which it converged
+  int zero_rhs;           // right-hand side vanished
+  int pad;
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (kernel files).  All take the stream as last argument.
+// ---------------------------------------------------------------------------
+template <typename T>
+void launch_init_species(T* f, const uint32_t* mask, const double* n_dev, int species,
+                         double nref, Dims d, hipStream_t s);
+template <typename T>
+void launch_charge(const T* f, const uint32_t* mask, const double* wall_q, double* b,
+                   double* partials, const LBParams& lp, double inv_eps, Dims d,
+                   const SiteGrid& g, hipStream_t s, const BeadTableView& bt);
+template <typename T>
+void launch_lb_step(const T* fsrc, T* fdst, const uint32_t* mask, const double* psi,
+                    const LBParams& lp, const BeadTableView& bt, double* partials, Dims d,
+                    const SiteGrid& g, hipStream_t s);
+template <typename T>
+void launch_moments(const T* f, const uint32_t* mask, int species, double nref, double* n_out,
+                    double* u_out, Dims d, hipStream_t s);
+
+void launch_sum_partials(const double* partials, int nblocks, int ncomp, double* out,
+                         hipStream_t s);
+void launch_mean_shift(const double* partials, int nblocks, double inv_n, double inv_eps,
+                       PoissonScalars* ps, hipStream_t s);
+
+// Poisson (kernels_poisson.hip)
+void launch_sor_half(double* psi, const double* b, const PoissonScalars* ps, int colour,
+                     double omega, Dims d, const SiteGrid& g, hipStream_t s);
+void launch_residual(const double* psi, const double* b, PoissonScalars* ps, double* partials,
+                     Dims d, const SiteGrid& g, hipStream_t s);
+void launch_residual_final(const double* partials, int nblocks, double tol, int iter,
+                           int initial, PoissonScalars* ps, hipStream_t s);
+void launch_psi_shift(double* psi, const PoissonScalars* ps, double inv_n, Dims d,
+                      hipStream_t s);
+void launch_fill(double* x, double v, long long n, hipStream_t s);
+void launch_ps_reset(PoissonScalars* ps, double shift, hipStream_t s);
+void launch_rho_to_b(const double* rho, double* b, double* partials, double inv_eps, Dims d,
+                     const SiteGrid& g, hipStream_t s);
+
+}  // namespace ek

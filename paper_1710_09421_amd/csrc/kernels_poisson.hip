@@ -1,0 +1,187 @@
+// Poisson solver kernels: red-black SOR half sweeps with the Chebyshev
+// schedule, residual norms in float64 with deterministic reductions, and the
+// gauge fix (mean of psi removed).
+//
+// The stored right-hand side is b_raw = -rho_e / eps; the solver adds the
+// device scalar `shift` = mean(rho_e) / eps, so that the problem it solves is
+// A psi = -(rho_e - mean rho_e) / eps on the periodic box.
+//
+// Every kernel first reads the converged flag and returns at once when it is
+// set: the host enqueues iterations ahead of the convergence test and the
+// iterations past convergence do no work.
+#include "ek_internal.h"
+#include "reduce.h"
+
+namespace ek {
+
+namespace {
+
+__global__ __launch_bounds__(BLOCK) void k_sor_half(double* __restrict__ psi,
+                                                    const double* __restrict__ b,
+                                                    const PoissonScalars* __restrict__ ps,
+                                                    int colour, double omega, Dims d) {
+  if (ps->done) return;
+  const int tx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (tx >= d.nx / 2 || y >= d.ny) return;
+  const int x = 2 * tx + ((colour + y + z) & 1);   // (x + y + z) % 2 == colour
+  const int xm = x == 0 ? d.nx - 1 : x - 1, xp = x == d.nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
+  const long long nxy = (long long)d.nx * d.ny;
+  const long long row = z * nxy + (long long)y * d.nx;
+  const long long r = row + x;
+  const double nbsum = psi[row + xm] + psi[row + xp] + psi[z * nxy + (long long)ym * d.nx + x] +
+                       psi[z * nxy + (long long)yp * d.nx + x] + psi[zm * nxy + (long long)y * d.nx + x] +
+                       psi[zp * nxy + (long long)y * d.nx + x];
+  const double rhs = b[r] + ps->shift;
+  const double old = psi[r];
+  psi[r] = old + omega * ((nbsum - rhs) * (1.0 / 6.0) - old);
+}
+
+// Partial sums of r^2, b^2 and psi with r = b - A psi (7-point operator).
+__global__ __launch_bounds__(BLOCK) void k_residual(const double* __restrict__ psi,
+                                                    const double* __restrict__ b,
+                                                    const PoissonScalars* __restrict__ ps,
+                                                    double* __restrict__ partials, Dims d) {
+  if (ps->done) return;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const int nblocks = gridDim.x * gridDim.y * gridDim.z;
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (x < d.nx && y < d.ny) {
+    const int xm = x == 0 ? d.nx - 1 : x - 1, xp = x == d.nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
+    const long long nxy = (long long)d.nx * d.ny;
+    const long long row = z * nxy + (long long)y * d.nx;
+    const long long r = row + x;
+    const double c = psi[r];
+    const double lap = psi[row + xm] + psi[row + xp] + psi[z * nxy + (long long)ym * d.nx + x] +
+                       psi[z * nxy + (long long)yp * d.nx + x] +
+                       psi[zm * nxy + (long long)y * d.nx + x] +
+                       psi[zp * nxy + (long long)y * d.nx + x] - 6.0 * c;
+    const double rhs = b[r] + ps->shift;
+    const double res = rhs - lap;
+    acc[0] = res * res;
+    acc[1] = rhs * rhs;
+    acc[2] = c;
+  }
+  block_partials<3>(acc, partials, bid, nblocks);
+}
+
+__global__ __launch_bounds__(256) void k_residual_final(const double* __restrict__ partials,
+                                                        int nblocks, double tol, int iter,
+                                                        int initial, PoissonScalars* ps) {
+  if (ps->done) return;
+  const double r2 = block_sum_256(partials, nblocks);
+  const double b2 = block_sum_256(partials + nblocks, nblocks);
+  const double s = block_sum_256(partials + 2 * (size_t)nblocks, nblocks);
+  if (threadIdx.x == 0) {
+    double rel;
+    if (b2 > 0.0) rel = sqrt(r2 / b2);
+    else rel = r2 == 0.0 ? 0.0 : INFINITY;
+    ps->r2 = r2;
+    ps->b2 = b2;
+    ps->psum = s;
+    ps->rel = rel;
+    if (initial) ps->rel0 = rel;
+    if (b2 == 0.0) {
+      ps->zero_rhs = 1;
+      ps->done = 1;
+      ps->iters = iter;
+    } else if (rel <= tol) {
+      ps->done = 1;
+      ps->iters = iter;
+    }
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_psi_shift(double* __restrict__ psi,
+                                                     const PoissonScalars* __restrict__ ps,
+                                                     double inv_n, long long n) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  psi[r] = ps->zero_rhs ? 0.0 : psi[r] - ps->psum * inv_n;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_fill(double* __restrict__ x, double v, long long n) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) x[r] = v;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_rho_to_b(const double* __restrict__ rho,
+                                                    double* __restrict__ b,
+                                                    double* __restrict__ partials,
+                                                    double inv_eps, Dims d) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const int nblocks = gridDim.x * gridDim.y * gridDim.z;
+  double acc[1] = {0.0};
+  if (x < d.nx && y < d.ny) {
+    const long long r = ((long long)z * d.ny + y) * d.nx + x;
+    const double v = rho[r];
+    b[r] = -v * inv_eps;
+    acc[0] = v;
+  }
+  block_partials<1>(acc, partials, bid, nblocks);
+}
+
+}  // namespace
+
+void launch_sor_half(double* psi, const double* b, const PoissonScalars* ps, int colour,
+                     double omega, Dims d, const SiteGrid& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_sor_half, g.grid, g.block, 0, s, psi, b, ps, colour, omega, d);
+}
+
+void launch_residual(const double* psi, const double* b, PoissonScalars* ps, double* partials,
+                     Dims d, const SiteGrid& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual, g.grid, g.block, 0, s, psi, b, ps, partials, d);
+}
+
+void launch_residual_final(const double* partials, int nblocks, double tol, int iter,
+                           int initial, PoissonScalars* ps, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(256), 0, s, partials, nblocks, tol, iter,
+                     initial, ps);
+}
+
+void launch_psi_shift(double* psi, const PoissonScalars* ps, double inv_n, Dims d,
+                      hipStream_t s) {
+  const int blocks = int((d.n + BLOCK - 1) / BLOCK);
+  hipLaunchKernelGGL(k_psi_shift, dim3(blocks), dim3(BLOCK), 0, s, psi, ps, inv_n, d.n);
+}
+
+void launch_fill(double* x, double v, long long n, hipStream_t s) {
+  const int blocks = int((n + BLOCK - 1) / BLOCK);
+  hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(BLOCK), 0, s, x, v, n);
+}
+
+void launch_rho_to_b(const double* rho, double* b, double* partials, double inv_eps, Dims d,
+                     const SiteGrid& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_rho_to_b, g.grid, g.block, 0, s, rho, b, partials, inv_eps, d);
+}
+
+}  // namespace ek
+
+namespace ek {
+namespace {
+__global__ void k_ps_reset(PoissonScalars* ps, double shift) {
+  if (threadIdx.x == 0) {
+    ps->shift = shift;
+    ps->r2 = ps->b2 = ps->psum = 0.0;
+    ps->rel = ps->rel0 = 0.0;
+    ps->done = 0;
+    ps->iters = 0;
+    ps->zero_rhs = 0;
+  }
+}
+}  // namespace
+void launch_ps_reset(PoissonScalars* ps, double shift, hipStream_t s) {
+  hipLaunchKernelGGL(k_ps_reset, dim3(1), dim3(64), 0, s, ps, shift);
+}
+}  // namespace ek

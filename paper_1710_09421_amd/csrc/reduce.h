@@ -1,0 +1,53 @@
+// Deterministic reductions for 64-wide wavefronts: butterfly within a wave,
+// then the block's waves in a fixed order.  Partial sums land in
+// partials[c * nblocks + block] and are summed by a single block later, so the
+// result depends only on the launch shape, never on scheduling.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ek {
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int NC>
+__device__ inline void block_partials(const double (&v)[NC], double* partials, int bid,
+                                      int nblocks) {
+  __shared__ double sh[NC][4];
+  const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+  const int lane = tid & 63, wid = tid >> 6;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    double s = wave_sum(v[c]);
+    if (lane == 0) sh[c][wid] = s;
+  }
+  __syncthreads();
+  if (tid < NC) {
+    double s = ((sh[tid][0] + sh[tid][1]) + (sh[tid][2] + sh[tid][3]));
+    partials[(size_t)tid * nblocks + bid] = s;
+  }
+}
+
+// Sum of one component over nblocks partials by a block of 256 threads
+// (strided sums, then a fixed tree).  Result valid in thread 0.
+__device__ inline double block_sum_256(const double* part, int nblocks) {
+  __shared__ double sh[256];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int i = tid; i < nblocks; i += 256) s += part[i];
+  sh[tid] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) sh[tid] += sh[tid + w];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+}  // namespace ek

@@ -1,0 +1,257 @@
+"""Python binding of the C ABI in include/ek.h (ctypes).
+
+Only argument marshalling lives here: every step of the method runs in the
+HIP kernels of libek.so.  PyTorch supplies the device workspace (a uint8 CUDA
+tensor) and the HIP stream.  If libek.so is missing the import fails; there is
+no CPU fallback.
+"""
+import ctypes
+import os
+from ctypes import POINTER, byref, c_double, c_int32, c_int64, c_uint64, c_void_p, c_size_t
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libek.so")
+
+EK_OK, EK_EINVAL, EK_EHIP, EK_ENOCONV, EK_EUNSTABLE, EK_ESTATE, EK_ENOMEM = 0, -1, -2, -3, -4, -5, -6
+EK_FP32, EK_FP64 = 0, 1
+EK_POISSON_SOR, EK_POISSON_MG = 0, 1
+EK_WS_ZERO, EK_WS_PREV, EK_WS_LEARNED = 0, 1, 2
+
+_STATUS = {0: "EK_OK", -1: "EK_EINVAL", -2: "EK_EHIP", -3: "EK_ENOCONV", -4: "EK_EUNSTABLE",
+           -5: "EK_ESTATE", -6: "EK_ENOMEM"}
+
+
+class ek_params(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("precision", c_int32),
+                ("valence", c_double * 3), ("tau", c_double * 3), ("omega_drag", c_double * 3),
+                ("kT", c_double), ("bjerrum", c_double), ("E_ext", c_double * 3),
+                ("F_ext", (c_double * 3) * 3), ("poisson_method", c_int32),
+                ("poisson_tol", c_double), ("poisson_max_iter", c_int32),
+                ("poisson_check_every", c_int32), ("rho_jacobi", c_double),
+                ("warm_start", c_int32), ("seed", c_uint64), ("fluctuations", c_int32)]
+
+
+class ek_polymer_params(ctypes.Structure):
+    _fields_ = [("M", c_double), ("k_fene", c_double), ("R0", c_double), ("eps", c_double),
+                ("sigma", c_double), ("gamma", c_double), ("n_sub", c_int32)]
+
+
+class ek_stats(ctypes.Structure):
+    _fields_ = [("mass", c_double * 3), ("momentum", c_double * 3), ("step", c_int64),
+                ("poisson_iters", c_int32), ("poisson_residual", c_double), ("fallback", c_int32)]
+
+
+class ek_timing(ctypes.Structure):
+    _fields_ = [("ms_charge", c_double), ("ms_poisson", c_double), ("ms_md", c_double),
+                ("ms_lb", c_double), ("n_steps", c_int64), ("n_lb", c_int64),
+                ("poisson_iters", c_int64)]
+
+
+class ek_poisson_report(ctypes.Structure):
+    _fields_ = [("iterations", c_int32), ("residual", c_double), ("initial_residual", c_double)]
+
+
+class EKError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1710_09421_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = POINTER
+    sig = {
+        "ek_workspace_bytes": (c_int32, [P(ek_params), c_int32, P(c_size_t)]),
+        "ek_create": (c_int32, [P(ek_params), c_int32, c_void_p, c_size_t, c_void_p, P(c_void_p)]),
+        "ek_destroy": (None, [c_void_p]),
+        "ek_last_error": (ctypes.c_char_p, [c_void_p]),
+        "ek_set_geometry": (c_int32, [c_void_p, c_void_p, c_void_p]),
+        "ek_set_species_density": (c_int32, [c_void_p, c_int32, c_void_p]),
+        "ek_set_polymer": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
+                                     P(ek_polymer_params)]),
+        "ek_step": (c_int32, [c_void_p, c_int32]),
+        "ek_get_moments": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+        "ek_get_potential": (c_int32, [c_void_p, c_void_p]),
+        "ek_get_beads": (c_int32, [c_void_p, c_void_p, c_void_p]),
+        "ek_get_stats": (c_int32, [c_void_p, P(ek_stats)]),
+        "ek_poisson_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, P(ek_poisson_report)]),
+        "ek_poisson_sor_iterations": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32]),
+        "ek_set_timing": (c_int32, [c_void_p, c_int32]),
+        "ek_get_timing": (c_int32, [c_void_p, P(ek_timing)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = _load()
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(c_void_p)
+
+
+def make_params(shape, precision=EK_FP32, valence=(0.0, 1.0, -1.0), tau=(1.0, 1.0, 1.0),
+                omega_drag=(1.0, 1.0, 1.0), kT=1.0 / 3.0, bjerrum=0.7, E_ext=(0.0, 0.0, 0.0),
+                F_ext=None, poisson_method=EK_POISSON_SOR, poisson_tol=1e-8,
+                poisson_max_iter=100000, poisson_check_every=1, rho_jacobi=0.0,
+                warm_start=EK_WS_PREV):
+    nz, ny, nx = shape
+    p = ek_params()
+    p.nx, p.ny, p.nz = nx, ny, nz
+    p.precision = precision
+    for s in range(3):
+        p.valence[s] = valence[s]
+        p.tau[s] = tau[s]
+        p.omega_drag[s] = omega_drag[s]
+        p.E_ext[s] = E_ext[s]
+        for c in range(3):
+            p.F_ext[s][c] = 0.0 if F_ext is None else float(F_ext[s][c])
+    p.kT, p.bjerrum = kT, bjerrum
+    p.poisson_method, p.poisson_tol = poisson_method, poisson_tol
+    p.poisson_max_iter, p.poisson_check_every = poisson_max_iter, poisson_check_every
+    p.rho_jacobi, p.warm_start = rho_jacobi, warm_start
+    p.seed, p.fluctuations = 0, 0
+    return p
+
+
+class Context:
+    """One simulation context on the current CUDA (HIP) device and stream."""
+
+    def __init__(self, params, max_beads=0, stream=None):
+        import torch
+        self._lib = lib()
+        self.params = params
+        self.shape = (params.nz, params.ny, params.nx)
+        nbytes = c_size_t()
+        self._check(self._lib.ek_workspace_bytes(byref(params), max_beads, byref(nbytes)), None)
+        # 256-byte alignment: over-allocate and offset
+        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device="cuda")
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = c_void_p()
+        self._check(self._lib.ek_create(byref(params), max_beads, c_void_p(base + off),
+                                        nbytes.value, c_void_p(self.stream.cuda_stream),
+                                        byref(h)), None)
+        self._h = h
+
+    def _check(self, st, h):
+        if st != EK_OK:
+            msg = self._lib.ek_last_error(h)
+            raise EKError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ek_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- setup ---------------------------------------------------------------
+    def set_geometry(self, solid, wall_q=None):
+        s = np.ascontiguousarray(solid, dtype=np.uint8).reshape(self.shape)
+        w = None if wall_q is None else np.ascontiguousarray(wall_q, dtype=np.float64).reshape(self.shape)
+        self._check(self._lib.ek_set_geometry(self._h, _ptr(s), None if w is None else _ptr(w)), self._h)
+
+    def set_species_density(self, species, n):
+        a = np.ascontiguousarray(n, dtype=np.float64).reshape(self.shape)
+        self._check(self._lib.ek_set_species_density(self._h, species, _ptr(a)), self._h)
+
+    def set_polymer(self, pos, vel, charge, M=1.0, k_fene=30.0, R0=1.5, eps=1.0, sigma=1.0,
+                    gamma=20.0, n_sub=40):
+        pos = np.ascontiguousarray(pos, dtype=np.float64)
+        vel = np.ascontiguousarray(vel, dtype=np.float64)
+        q = np.ascontiguousarray(charge, dtype=np.float64)
+        pp = ek_polymer_params(M, k_fene, R0, eps, sigma, gamma, n_sub)
+        self._check(self._lib.ek_set_polymer(self._h, pos.shape[0], _ptr(pos), _ptr(vel), _ptr(q),
+                                             byref(pp)), self._h)
+
+    # -- run -----------------------------------------------------------------
+    def step(self, n=1):
+        self._check(self._lib.ek_step(self._h, n), self._h)
+
+    # -- outputs -------------------------------------------------------------
+    def moments(self, species):
+        n = np.empty(self.shape)
+        u = np.empty((3,) + self.shape)
+        self._check(self._lib.ek_get_moments(self._h, species, _ptr(n), _ptr(u)), self._h)
+        return n, u
+
+    def potential(self):
+        psi = np.empty(self.shape)
+        self._check(self._lib.ek_get_potential(self._h, _ptr(psi)), self._h)
+        return psi
+
+    def beads(self, n_beads):
+        pos = np.empty((n_beads, 3))
+        vel = np.empty((n_beads, 3))
+        self._check(self._lib.ek_get_beads(self._h, _ptr(pos), _ptr(vel)), self._h)
+        return pos, vel
+
+    def stats(self):
+        s = ek_stats()
+        self._check(self._lib.ek_get_stats(self._h, byref(s)), self._h)
+        return dict(mass=np.array(s.mass[:]), momentum=np.array(s.momentum[:]), step=s.step,
+                    poisson_iters=s.poisson_iters, poisson_residual=s.poisson_residual,
+                    fallback=s.fallback)
+
+    def set_timing(self, enable=True):
+        self._check(self._lib.ek_set_timing(self._h, 1 if enable else 0), self._h)
+
+    def timing(self):
+        t = ek_timing()
+        self._check(self._lib.ek_get_timing(self._h, byref(t)), self._h)
+        return {k: getattr(t, k) for k, _ in ek_timing._fields_}
+
+    def poisson_solve(self, rho, psi, warm_start=EK_WS_PREV):
+        """rho, psi: float64 CUDA tensors of the lattice shape (psi updated in place)."""
+        rep = ek_poisson_report()
+        self._check(self._lib.ek_poisson_solve(self._h, c_void_p(rho.data_ptr()),
+                                               c_void_p(psi.data_ptr()), warm_start, byref(rep)),
+                    self._h)
+        return dict(iterations=rep.iterations, residual=rep.residual,
+                    initial_residual=rep.initial_residual)
+
+    def sor_iterations(self, b, psi, iterations):
+        self._check(self._lib.ek_poisson_sor_iterations(self._h, c_void_p(b.data_ptr()),
+                                                        c_void_p(psi.data_ptr()), iterations),
+                    self._h)
+
+
+def from_workload(wl, precision=EK_FP32, poisson_method=EK_POISSON_SOR, poisson_tol=None,
+                  poisson_check_every=1, warm_start=EK_WS_PREV, **kw):
+    """Context initialised with a workload's geometry, densities and polymer."""
+    nb = 0 if wl.beads_R is None else wl.beads_R.shape[0]
+    p = make_params(wl.shape, precision=precision, valence=wl.valence, tau=wl.tau,
+                    omega_drag=wl.omega_drag, bjerrum=wl.bjerrum, E_ext=wl.E_ext,
+                    poisson_method=poisson_method,
+                    poisson_tol=wl.poisson_tol if poisson_tol is None else poisson_tol,
+                    poisson_check_every=poisson_check_every, warm_start=warm_start, **kw)
+    ctx = Context(p, max_beads=nb)
+    ctx.set_geometry(wl.solid, wl.wall_q)
+    for s in range(3):
+        ctx.set_species_density(s, wl.n0[s])
+    if nb:
+        pp = wl.polymer
+        ctx.set_polymer(wl.beads_R, wl.beads_V, pp["q"], M=pp["M"], k_fene=pp["k_fene"],
+                        R0=pp["R0"], eps=pp["eps"], sigma=pp["sigma"], gamma=pp["gamma"],
+                        n_sub=pp["n_sub"])
+    return ctx

@@ -1,0 +1,58 @@
+"""The C ABI library loads on a machine without a GPU and exports every
+function that include/ek.h declares; host-only entry points validate their
+arguments."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ek.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ek_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def ek():
+    from paper_1710_09421_amd import ek as binding
+    return binding
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ["ek_create", "ek_destroy", "ek_step", "ek_set_geometry", "ek_set_species_density",
+                 "ek_set_polymer", "ek_get_moments", "ek_get_potential", "ek_get_beads",
+                 "ek_get_stats", "ek_poisson_solve", "ek_workspace_bytes", "ek_last_error"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(ek):
+    lib = ctypes.CDLL(ek.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, f"not exported: {missing}"
+
+
+def test_workspace_bytes_validates(ek):
+    lib = ek.lib()
+    nbytes = ctypes.c_size_t()
+    p = ek.make_params((32, 32, 32), precision=ek.EK_FP32)
+    assert lib.ek_workspace_bytes(ctypes.byref(p), 0, ctypes.byref(nbytes)) == ek.EK_OK
+    n = 32 ** 3
+    assert nbytes.value >= 2 * 57 * 4 * n + n * (4 + 8 + 8 + 8)
+    p64 = ek.make_params((32, 32, 32), precision=ek.EK_FP64)
+    n64 = ctypes.c_size_t()
+    assert lib.ek_workspace_bytes(ctypes.byref(p64), 0, ctypes.byref(n64)) == ek.EK_OK
+    assert n64.value > nbytes.value
+    bad = ek.make_params((32, 32, 31))
+    assert lib.ek_workspace_bytes(ctypes.byref(bad), 0, ctypes.byref(nbytes)) == ek.EK_EINVAL
+    assert b"even" in lib.ek_last_error(None)
+    bad = ek.make_params((32, 32, 32), tau=(0.5, 1.0, 1.0))
+    assert lib.ek_workspace_bytes(ctypes.byref(bad), 0, ctypes.byref(nbytes)) == ek.EK_EINVAL
+    bad = ek.make_params((32, 32, 32))
+    bad.fluctuations = 1
+    assert lib.ek_workspace_bytes(ctypes.byref(bad), 0, ctypes.byref(nbytes)) == ek.EK_EINVAL

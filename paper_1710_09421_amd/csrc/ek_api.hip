@@ -328,6 +328,17 @@ ek_status ek_create(const ek_params* p, int32_t max_beads, void* dev_ws, size_t 
   }
   c->bx_sites = 0;
   c->bx_colour = 0;
+  // the workspace arrives uninitialised: empty the bead node table and zero
+  // the link words before any kernel reads them
+  launch_table_init(c->keys, c->vals, c->stream);
+  if (hipMemsetAsync(c->mask, 0, c->dims.n * 4, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    (void)hipHostFree(c->pinned);
+    if (own) (void)hipFree(ws);
+    delete c;
+    g_create_error = "initialising the workspace failed";
+    return EK_EHIP;
+  }
   c->mg_setup();
   *out = c;
   return EK_OK;
@@ -359,6 +370,11 @@ ek_status ek_set_geometry(ek_ctx* ctx, const uint8_t* solid, const double* wall_
         uint32_t w = 0;
         if (solid[r]) {
           w |= MASK_SOLID;
+          for (int q = 1; q < Q; ++q) {
+            const int sx = (x + CX[q] + d.nx) % d.nx, sy = (y + CY[q] + d.ny) % d.ny,
+                      sz = (z + CZ[q] + d.nz) % d.nz;
+            if (!solid[((long long)sz * d.ny + sy) * d.nx + sx]) w |= MASK_WALL;
+          }
         } else {
           ++nfluid;
           for (int q = 1; q < Q; ++q) {

@@ -10,6 +10,7 @@
 namespace ek {
 constexpr int MAX_BEADS = 1024;        // one workgroup advances a whole chain
 size_t bead_state_bytes(int max_beads);
+void launch_table_init(int* keys, long long* vals, hipStream_t s);
 size_t mg_workspace_bytes(int nx, int ny, int nz);
 }  // namespace ek
 
@@ -57,6 +58,7 @@ struct ek_ctx {
   int max_beads = 0;
   int n_beads = 0;
   ek_polymer_params poly{};
+  std::vector<double> host_q;
   bool table_dirty = false;
 
   // per-phase timers (HIP events on the context stream)

@@ -29,14 +29,16 @@ __host__ __device__ constexpr double weight(int p) {
 constexpr uint32_t MASK_SOLID = 1u << 31;       // the site itself is solid
 constexpr uint32_t MASK_CHARGED = 1u << 30;     // the site carries a fixed charge
 constexpr uint32_t MASK_BEAD = 1u << 29;        // a bead kernel touches the site
+constexpr uint32_t MASK_WALL = 1u << 28;        // solid site next to the fluid (bead-wall WCA)
 
 // Fixed-point scales for order-independent (hence deterministic) sums of the
 // bead charge and bead force densities accumulated with integer atomics.
 constexpr double FIX_CHARGE = 4503599627370496.0;     // 2^52
-constexpr double FIX_FORCE = 1125899906842624.0;      // 2^50
+constexpr double FIX_FORCE = 17592186044416.0;        // 2^44
 
 constexpr int BLOCK = 256;                            // threads per block for site kernels
-constexpr int HASH_SLOTS = 16384;                     // bead-touched node table (power of 2)
+constexpr int HASH_BITS = 16;
+constexpr int HASH_SLOTS = 1 << HASH_BITS;            // bead-touched node table
 
 // Launch shape of a site kernel: blockDim (bx, by) with bx * by == BLOCK,
 // grid (ceil(nx / bx), ceil(ny / by), nz).

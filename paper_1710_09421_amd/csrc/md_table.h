@@ -15,7 +15,7 @@
 namespace ek {
 
 __host__ __device__ inline int hash_slot(long long r) {
-  return int(((unsigned long long)r * 0x9E3779B97F4A7C15ull) >> 50) & (HASH_SLOTS - 1);
+  return int(((unsigned long long)r * 0x9E3779B97F4A7C15ull) >> (64 - HASH_BITS));
 }
 
 // Slot layout: charge, then K[species][xyz] (9 values), all int64 fixed point.

@@ -1,0 +1,132 @@
+"""GPU parity of the bead-spring chain coupled to the lattice (Sec. II.B and
+the interpolation kernels of Sec. II.C) against the float64 oracle, through
+the C ABI."""
+import numpy as np
+import pytest
+
+from oracle import step as ostep
+from paper_1710_09421_amd import workloads
+from tests.parity import density_error, field_error, velocity_error
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ek():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1710_09421_amd import ek as binding
+    binding.lib()
+    return binding
+
+
+def pore_with_chain(n_beads=8, seed=31, bead_q=-1.0):
+    return workloads.pore_system((32, 24, 24), 6, 4, 0.01, 0.01, -0.01, n_beads, seed,
+                                 bead_q=bead_q, steps=100)
+
+
+def oracle_sim(wl, tol):
+    p = ostep.Params(valence=wl.valence, tau=wl.tau, omega_drag=wl.omega_drag,
+                     bjerrum=wl.bjerrum, E_ext=wl.E_ext, poisson_tol=tol)
+    return ostep.Simulation(p, wl.solid.astype(bool), wl.wall_q, wl.n0,
+                            beads=(wl.beads_R, wl.beads_V, wl.polymer))
+
+
+def errors(ctx, sim, wl):
+    fluid = wl.solid == 0
+    out = {}
+    n_ref, u_ref = sim.densities(), sim.velocities()
+    for s in range(3):
+        n, u = ctx.moments(s)
+        out[f"n{s}"] = density_error(n, n_ref[s], fluid)
+        out[f"u{s}"] = velocity_error(u, u_ref[s], fluid)
+    out["psi"] = field_error(ctx.potential(), sim.psi)
+    R, V = ctx.beads(wl.beads_R.shape[0])
+    out["R"] = float(np.max(np.abs(R - sim.R)))
+    out["V"] = float(np.max(np.abs(V - sim.V)) / max(np.max(np.abs(sim.V)), 1e-12))
+    return out
+
+
+def test_chain_fp64_matches_oracle(ek):
+    wl = pore_with_chain()
+    ctx = ek.from_workload(wl, precision=ek.EK_FP64, poisson_tol=1e-10, poisson_check_every=1)
+    sim = oracle_sim(wl, 1e-10)
+    for chunk in (1, 19):
+        ctx.step(chunk)
+        sim.run(chunk)
+        err = errors(ctx, sim, wl)
+        print(sim.t, err)
+        assert max(err.values()) < 1e-8, err
+    assert np.abs(sim.V).max() > 1e-4          # the chain does move
+
+
+def test_chain_fp32_matches_oracle_after_100_steps(ek):
+    wl = pore_with_chain(seed=32)
+    ctx = ek.from_workload(wl, precision=ek.EK_FP32, poisson_tol=1e-8, poisson_check_every=1)
+    sim = oracle_sim(wl, 1e-8)
+    ctx.step(100)
+    sim.run(100)
+    err = errors(ctx, sim, wl)
+    print(err)
+    assert max(err[k] for k in ("n0", "n1", "n2", "u0", "u1", "u2", "psi", "V")) < 1e-5, err
+    assert err["R"] < 1e-5, err
+
+
+def test_fluid_plus_bead_momentum_conserved(ek):
+    """Periodic box without walls or applied field, neutral beads and charged
+    ions: species momentum plus bead momentum stays at its initial value."""
+    shape = (16, 12, 12)
+    rng = np.random.default_rng(4)
+    n0 = np.stack([np.ones(shape), 0.01 * (1 + 0.05 * rng.uniform(-1, 1, shape)),
+                   0.01 * (1 + 0.05 * rng.uniform(-1, 1, shape))])
+    R = np.array([[5.0, 5.0, 7.0], [5.961, 5.0, 7.0], [5.961, 5.961, 7.0], [5.961, 5.961, 7.961]])
+    V = rng.normal(scale=0.02, size=R.shape)
+    p = ek.make_params(shape, precision=ek.EK_FP64, poisson_tol=1e-12)
+    ctx = ek.Context(p, max_beads=4)
+    ctx.set_geometry(np.zeros(shape, np.uint8))
+    for s in range(3):
+        ctx.set_species_density(s, n0[s])
+    ctx.set_polymer(R, V, np.zeros(4))
+
+    def total():
+        P = np.zeros(3)
+        for s in range(3):
+            n, u = ctx.moments(s)
+            P += (n[None] * u).sum(axis=(1, 2, 3))
+        return P + ctx.beads(4)[1].sum(axis=0)
+    P0 = total()
+    ctx.step(10)
+    assert np.allclose(total(), P0, atol=1e-11), (total(), P0)
+    assert np.abs(ctx.beads(4)[1] - V).max() > 1e-4
+
+
+def test_chain_is_deterministic(ek):
+    wl = pore_with_chain(seed=33)
+    out = []
+    for _ in range(2):
+        ctx = ek.from_workload(wl, precision=ek.EK_FP32, poisson_tol=1e-8, poisson_check_every=4)
+        ctx.step(40)
+        out.append((ctx.beads(8), ctx.moments(0), ctx.potential()))
+        ctx.close()
+    (Ra, Va), (na, ua), pa = out[0]
+    (Rb, Vb), (nb, ub), pb = out[1]
+    assert np.array_equal(Ra, Rb) and np.array_equal(Va, Vb)
+    assert np.array_equal(na, nb) and np.array_equal(ua, ub) and np.array_equal(pa, pb)
+
+
+def test_polymer_argument_checks(ek):
+    wl = pore_with_chain()
+    ctx = ek.from_workload(wl, precision=ek.EK_FP32)
+    R = wl.beads_R.copy()
+    R[1] = R[0] + np.array([1.6, 0.0, 0.0])         # bond beyond R0 = 1.5
+    with pytest.raises(ek.EKError) as e:
+        ctx.set_polymer(R, wl.beads_V, wl.polymer["q"])
+    assert e.value.status == ek.EK_EINVAL
+    R = wl.beads_R.copy()
+    R[:] = np.array([2.5, 2.5, 16.5])               # inside the membrane slab
+    with pytest.raises(ek.EKError) as e:
+        ctx.set_polymer(R, wl.beads_V, wl.polymer["q"])
+    assert e.value.status == ek.EK_EINVAL
+    with pytest.raises(ek.EKError) as e:
+        ctx.set_polymer(np.zeros((9, 3)), np.zeros((9, 3)), np.zeros(9))   # more than max_beads
+    assert e.value.status == ek.EK_EINVAL

@@ -348,6 +348,7 @@ void ek_destroy(ek_ctx* ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
   for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+  ctx->mg_release();
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->own_ws) (void)hipFree(ctx->ws);
   delete ctx;

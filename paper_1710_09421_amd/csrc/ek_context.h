@@ -83,6 +83,8 @@ struct ek_ctx {
   ek_status sor_solve(const double* b, double* x, int& iters, double& res, double& res0);
   ek_status mg_solve(const double* b, double* x, int& iters, double& res, double& res0);
   void mg_setup();
+  void mg_release();
+  ek_status mg_vcycle(const double* b, double* x);
   ek_status poisson(const double* b, double* x, int& iters, double& res, double& res0);
   template <typename T>
   ek_status step_impl(int n_steps);

@@ -264,21 +264,21 @@ __global__ __launch_bounds__(BLOCK) void k_moments(const T* __restrict__ f,
   }
 }
 
-__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partials,
-                                                      int nblocks, int ncomp,
-                                                      double* __restrict__ out) {
-  for (int c = 0; c < ncomp; ++c) {
-    double s = block_sum_256(partials + (size_t)c * nblocks, nblocks);
-    if (threadIdx.x == 0) out[c] = s;
-  }
+__global__ __launch_bounds__(1024) void k_sum6(const double* __restrict__ partials, int nblocks,
+                                               double* __restrict__ out) {
+  double t[6];
+  block_sums_1024<6>(partials, nblocks, t);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 6; ++c) out[c] = t[c];
 }
 
-__global__ __launch_bounds__(256) void k_mean_shift(const double* __restrict__ partials,
-                                                    int nblocks, double inv_n, double inv_eps,
-                                                    PoissonScalars* ps) {
-  double s = block_sum_256(partials, nblocks);
+__global__ __launch_bounds__(1024) void k_mean_shift(const double* __restrict__ partials,
+                                                     int nblocks, double inv_n, double inv_eps,
+                                                     PoissonScalars* ps) {
+  double t[1];
+  block_sums_1024<1>(partials, nblocks, t);
   if (threadIdx.x == 0) {
-    ps->shift = s * inv_n * inv_eps;
+    ps->shift = t[0] * inv_n * inv_eps;
     ps->done = 0;
     ps->iters = 0;
     ps->zero_rhs = 0;
@@ -339,12 +339,13 @@ void launch_moments(const T* f, const uint32_t* mask, int species, double nref, 
 
 void launch_sum_partials(const double* partials, int nblocks, int ncomp, double* out,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, nblocks, ncomp, out);
+  (void)ncomp;   // always the six of the fused step: masses and momentum
+  hipLaunchKernelGGL(k_sum6, dim3(1), dim3(1024), 0, s, partials, nblocks, out);
 }
 
 void launch_mean_shift(const double* partials, int nblocks, double inv_n, double inv_eps,
                        PoissonScalars* ps, hipStream_t s) {
-  hipLaunchKernelGGL(k_mean_shift, dim3(1), dim3(256), 0, s, partials, nblocks, inv_n, inv_eps,
+  hipLaunchKernelGGL(k_mean_shift, dim3(1), dim3(1024), 0, s, partials, nblocks, inv_n, inv_eps,
                      ps);
 }
 

@@ -17,6 +17,7 @@
 //
 // Node values are int64 fixed point added with atomics, so the sums do not
 // depend on the order in which beads and substeps reach a node.
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -32,7 +33,7 @@ constexpr int BOX = 4;          // moment box edge (nodes floor(R0) - 1 .. floor
 constexpr int BOX3 = BOX * BOX * BOX;
 constexpr int WIN = 6;          // flag window edge (nodes floor(R0) - 2 .. floor(R0) + 3)
 constexpr int WIN3 = WIN * WIN * WIN;
-constexpr int MOM = 12;         // n[3], j[3][3]
+constexpr int MOM = 15;         // x[3] (n^a / n), 1/n^a [3], j[3][3]
 
 enum : int { ERR_BOX = 1, ERR_FLUID = 2, ERR_BOND = 4, ERR_TABLE = 8 };
 
@@ -195,10 +196,15 @@ __global__ __launch_bounds__(256) void k_bead_box(BeadState bs, const T* __restr
         jy += CY[p] * g;
         jz += CZ[p] * g;
       }
-      mo[s] = lp.nref[s] + dn;
-      mo[3 + 3 * s] = jx;
-      mo[4 + 3 * s] = jy;
-      mo[5 + 3 * s] = jz;
+      mo[s] = lp.nref[s] + dn;        // density for now, fraction below
+      mo[6 + 3 * s] = jx;
+      mo[7 + 3 * s] = jy;
+      mo[8 + 3 * s] = jz;
+    }
+    const double ntot = mo[0] + mo[1] + mo[2];
+    for (int s = 0; s < 3; ++s) {
+      mo[3 + s] = 1.0 / mo[s];
+      mo[s] = mo[s] / ntot;
     }
   }
   double* e = bs.efield + ((size_t)i * BOX3 + t) * 3;
@@ -224,158 +230,309 @@ __device__ inline double wca_coef(double r2, double eps, double sigma) {
   return 24.0 * eps * (2.0 * s6 * s6 - s6) / r2;
 }
 
-__global__ __launch_bounds__(1024) void k_md(BeadState bs, MDParams mp, int* keys,
-                                             long long* vals, uint32_t* mask, Dims d) {
-  __shared__ double sR[3 * MAX_BEADS];
-  const int i = threadIdx.x;
+// Node accumulators for the friction impulse: the context's global table, or
+// (for chains of at most LDS_MAX_BEADS beads) a table in LDS that is flushed to
+// the global one once after the substeps.  Values are int64 fixed point, so
+// the sums are exact whatever the order of the additions.
+struct GlobalNodes {
+  int* keys;
+  long long* vals;
+  uint32_t* mask;
+  int* err;
+  __device__ int slot(long long site) { return table_insert(keys, mask, site, err); }
+  __device__ double get(int h, int c) const {
+    return double(ld_i64(&vals[(size_t)h * SLOT_VALUES + 1 + c])) * (1.0 / FIX_FORCE);
+  }
+  __device__ void add(int h, int c, long long v) {
+    atomicAdd((unsigned long long*)&vals[(size_t)h * SLOT_VALUES + 1 + c], (unsigned long long)v);
+  }
+};
+
+struct LdsNodes {
+  int* keys;          // LDS [slots]
+  long long* vals;    // LDS [slots][9]
+  int bits;
+  int* err;
+  __device__ int slot(long long site) {
+    const int n = 1 << bits;
+    int h = int(((unsigned long long)site * 0x9E3779B97F4A7C15ull) >> (64 - bits));
+    for (int k = 0; k < n; ++k) {
+      const int prev = atomicCAS(&keys[h], -1, int(site));
+      if (prev == -1 || prev == int(site)) return h;
+      h = (h + 1) & (n - 1);
+    }
+    atomicOr(err, ERR_TABLE);
+    return -1;
+  }
+  __device__ double get(int h, int c) const {
+    return double(vals[h * 9 + c]) * (1.0 / FIX_FORCE);
+  }
+  __device__ void add(int h, int c, long long v) {
+    atomicAdd((unsigned long long*)&vals[h * 9 + c], (unsigned long long)v);
+  }
+};
+
+constexpr int LDS_MAX_BEADS = 64;
+
+// One workgroup per chain, TPB threads per bead: the lanes of a bead split
+// its 8 corners, its pair partners and its wall sites, and combine their
+// parts with a butterfly over the TPB lanes (every lane ends with the same
+// bits, so all lanes advance the bead identically).
+template <int TPB>
+__device__ inline double group_sum(double v) {
+#pragma unroll
+  for (int m = 1; m < TPB; m <<= 1) v += __shfl_xor(v, m, TPB);
+  return v;
+}
+
+template <bool LDS, int TPB, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_md(BeadState bs, MDParams mp, int* gkeys,
+                                             long long* gvals, uint32_t* mask, Dims d,
+                                             int lds_bits) {
+  constexpr int CPL = 8 / TPB;                                 // corners per lane
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* sR = (double*)smem;                                  // [3 * n]
+  long long* lvals = (long long*)(smem + (((size_t)mp.n * 24 + 15) & ~size_t(15)));
+  const int lslots = LDS ? (1 << lds_bits) : 0;
+  int* lkeys = (int*)(lvals + (size_t)lslots * 9);
+
+  const int i = threadIdx.x / TPB;          // bead
+  const int lane = threadIdx.x % TPB;
   const bool live = i < mp.n;
+  if (LDS) {
+    for (int h = threadIdx.x; h < lslots; h += blockDim.x) {
+      lkeys[h] = -1;
+      for (int c = 0; c < 9; ++c) lvals[(size_t)h * 9 + c] = 0;
+    }
+  }
   double R[3] = {0, 0, 0}, V[3] = {0, 0, 0}, q = 0.0;
   int org[3] = {0, 0, 0};
   if (live) {
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
       R[c] = bs.R[3 * i + c];
       V[c] = bs.V[3 * i + c];
       org[c] = bs.origin[3 * i + c];
-      sR[3 * i + c] = R[c];
+      if (lane == 0) sR[3 * i + c] = R[c];
     }
     q = bs.q[i];
   }
   __syncthreads();
+  GlobalNodes gn{gkeys, gvals, mask, bs.err};
+  LdsNodes ln{lkeys, lvals, lds_bits, bs.err};
+
   const double h = 1.0 / mp.n_sub;
-  const double* mom = bs.mom + (size_t)i * BOX3 * MOM;
-  const double* ef = bs.efield + (size_t)i * BOX3 * 3;
-  const unsigned char* fl = bs.flags + (size_t)i * WIN3;
+  const double hM = h / mp.M;
+  const double L[3] = {mp.Lx, mp.Ly, mp.Lz};
+  const double iL[3] = {1.0 / mp.Lx, 1.0 / mp.Ly, 1.0 / mp.Lz};
+  const double rc2 = 1.2599210498948732 * mp.sigma * mp.sigma;   // (2^(1/6) sigma)^2
+  const double s2w = mp.sigma * mp.sigma;
+  const double iR02 = 1.0 / (mp.R0 * mp.R0);
+  const double* mom = bs.mom + (size_t)(live ? i : 0) * BOX3 * MOM;
+  const double* ef = bs.efield + (size_t)(live ? i : 0) * BOX3 * 3;
+  const unsigned char* fl = bs.flags + (size_t)(live ? i : 0) * WIN3;
+  int cell[3] = {INT_MIN, INT_MIN, INT_MIN};
+  int slot[CPL], bidx[CPL];
+  double wfl[CPL];
+  double fl_all[8];                 // fluid flag of every corner (for the normalisation)
   for (int sub = 0; sub < mp.n_sub; ++sub) {
-    double wt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    long long site[8];
+    double wt[CPL];
     double phi[3][3];
     double Rn[3];
+#pragma unroll
+    for (int a = 0; a < CPL; ++a) wt[a] = 0.0;
     if (live) {
       const int fx = int(floor(R[0])), fy = int(floor(R[1])), fz = int(floor(R[2]));
       const double dx = R[0] - fx, dy = R[1] - fy, dz = R[2] - fz;
       int lx = fx - org[0], ly = fy - org[1], lz = fz - org[2];   // corner 0 in the box
-      if (lx < 0 || lx > BOX - 2 || ly < 0 || ly > BOX - 2 || lz < 0 || lz > BOX - 2) {
-        atomicOr(bs.err, ERR_BOX);
-        lx = min(max(lx, 0), BOX - 2);
-        ly = min(max(ly, 0), BOX - 2);
-        lz = min(max(lz, 0), BOX - 2);
+      if (fx != cell[0] || fy != cell[1] || fz != cell[2]) {
+        // the bead entered another cell: new corners, their box entries and slots
+        cell[0] = fx; cell[1] = fy; cell[2] = fz;
+        if (lx < 0 || lx > BOX - 2 || ly < 0 || ly > BOX - 2 || lz < 0 || lz > BOX - 2) {
+          if (lane == 0) atomicOr(bs.err, ERR_BOX);
+          lx = min(max(lx, 0), BOX - 2);
+          ly = min(max(ly, 0), BOX - 2);
+          lz = min(max(lz, 0), BOX - 2);
+        }
+#pragma unroll
+        for (int k8 = 0; k8 < 8; ++k8) {
+          const int ox = k8 & 1, oy = (k8 >> 1) & 1, oz = (k8 >> 2) & 1;
+          const int wi = (lx + ox + 1) + WIN * ((ly + oy + 1) + WIN * (lz + oz + 1));
+          fl_all[k8] = (fl[wi] & 1) ? 1.0 : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < CPL; ++a) {
+          const int k8 = lane * CPL + a;
+          const int ox = k8 & 1, oy = (k8 >> 1) & 1, oz = (k8 >> 2) & 1;
+          bidx[a] = (lx + ox) + BOX * ((ly + oy) + BOX * (lz + oz));
+          wfl[a] = fl_all[k8];
+          slot[a] = -1;
+          if (wfl[a] != 0.0) {
+            const long long site = site_of(fx + ox, fy + oy, fz + oz, d);
+            slot[a] = LDS ? ln.slot(site) : gn.slot(site);
+          }
+        }
       }
-      double w[8], wsum = 0.0;
-      int bidx[8];
-      for (int k = 0; k < 8; ++k) {
-        const int ox = k & 1, oy = (k >> 1) & 1, oz = (k >> 2) & 1;
-        w[k] = (ox ? dx : 1.0 - dx) * (oy ? dy : 1.0 - dy) * (oz ? dz : 1.0 - dz);
-        bidx[k] = (lx + ox) + BOX * ((ly + oy) + BOX * (lz + oz));
-        const int wi = (lx + ox + 1) + WIN * ((ly + oy + 1) + WIN * (lz + oz + 1));
-        const bool fluid = fl[wi] & 1;
-        wt[k] = fluid ? w[k] : 0.0;
-        wsum += wt[k];
-        site[k] = site_of(fx + ox, fy + oy, fz + oz, d);
+      // plain and fluid-renormalised trilinear weights
+      double wsum = 0.0;
+#pragma unroll
+      for (int k8 = 0; k8 < 8; ++k8) {
+        const int ox = k8 & 1, oy = (k8 >> 1) & 1, oz = (k8 >> 2) & 1;
+        wsum += fl_all[k8] * (ox ? dx : 1.0 - dx) * (oy ? dy : 1.0 - dy) * (oz ? dz : 1.0 - dz);
       }
       if (!(wsum > 0.0)) {
-        atomicOr(bs.err, ERR_FLUID);
+        if (lane == 0) atomicOr(bs.err, ERR_FLUID);
         wsum = 1.0;
       }
-      for (int k = 0; k < 8; ++k) wt[k] /= wsum;
-      // fields at the bead: velocities from the node momentum (populations of
+      const double iws = 1.0 / wsum;
+      // this lane's corners: velocities from the node momentum (populations of
       // time t plus the friction impulse of earlier substeps), composition,
       // electric field with the plain weights
-      double u[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, x[3] = {0, 0, 0}, E[3] = {0, 0, 0};
-      for (int k = 0; k < 8; ++k) {
-        const double* mo = mom + (size_t)bidx[k] * MOM;
-        const double* e = ef + (size_t)bidx[k] * 3;
-        for (int c = 0; c < 3; ++c) E[c] += w[k] * e[c];
-        if (wt[k] == 0.0) continue;
-        double kacc[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-        const int hsl = table_find(keys, site[k]);
-        if (hsl >= 0) {
-          for (int s = 0; s < 3; ++s)
-            for (int c = 0; c < 3; ++c)
-              kacc[s][c] = double(ld_i64(&vals[(size_t)hsl * SLOT_VALUES + 1 + 3 * s + c])) *
-                           (1.0 / FIX_FORCE);
-        }
-        const double ntot = mo[0] + mo[1] + mo[2];
-        for (int s = 0; s < 3; ++s) {
-          x[s] += wt[k] * mo[s] / ntot;
-          for (int c = 0; c < 3; ++c) u[s][c] += wt[k] * (mo[3 + 3 * s + c] + kacc[s][c]) / mo[s];
+      double acc[15];
+#pragma unroll
+      for (int c = 0; c < 15; ++c) acc[c] = 0.0;
+#pragma unroll
+      for (int a = 0; a < CPL; ++a) {
+        const int k8 = lane * CPL + a;
+        const int ox = k8 & 1, oy = (k8 >> 1) & 1, oz = (k8 >> 2) & 1;
+        const double w = (ox ? dx : 1.0 - dx) * (oy ? dy : 1.0 - dy) * (oz ? dz : 1.0 - dz);
+        wt[a] = w * wfl[a] * iws;
+        const double* e = ef + (size_t)bidx[a] * 3;
+        acc[12] += w * e[0];
+        acc[13] += w * e[1];
+        acc[14] += w * e[2];
+        if (wt[a] != 0.0) {
+          const double* mo = mom + (size_t)bidx[a] * MOM;
+#pragma unroll
+          for (int s = 0; s < 3; ++s) {
+            acc[9 + s] += wt[a] * mo[s];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const double kacc = slot[a] < 0 ? 0.0 : (LDS ? ln.get(slot[a], 3 * s + c)
+                                                            : gn.get(slot[a], 3 * s + c));
+              acc[3 * s + c] += wt[a] * (mo[6 + 3 * s + c] + kacc) * mo[3 + s];
+            }
+          }
         }
       }
-      // conservative forces
-      double F[3] = {q * E[0], q * E[1], q * E[2]};
-      const double L[3] = {mp.Lx, mp.Ly, mp.Lz};
-      for (int nb = -1; nb <= 1; nb += 2) {           // FENE bonds
-        const int j = i + nb;
-        if (j < 0 || j >= mp.n) continue;
-        double dv[3], r2 = 0.0;
-        for (int c = 0; c < 3; ++c) {
-          dv[c] = min_image(sR[3 * j + c] - R[c], L[c]);
-          r2 += dv[c] * dv[c];
-        }
-        const double x2 = r2 / (mp.R0 * mp.R0);
-        if (x2 >= 1.0) {
-          atomicOr(bs.err, ERR_BOND);
-          continue;
-        }
-        const double coef = mp.k_fene / (1.0 - x2);
-        for (int c = 0; c < 3; ++c) F[c] += coef * dv[c];
-      }
-      for (int j = 0; j < mp.n; ++j) {                 // WCA between all pairs
+      // this lane's share of the conservative forces
+      double F[3] = {0.0, 0.0, 0.0};
+      for (int j = lane; j < mp.n; j += TPB) {        // WCA between all pairs
         if (j == i) continue;
         double dv[3], r2 = 0.0;
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
-          dv[c] = min_image(R[c] - sR[3 * j + c], L[c]);
+          const double v = R[c] - sR[3 * j + c];
+          dv[c] = v - L[c] * rint(v * iL[c]);
           r2 += dv[c] * dv[c];
         }
-        const double coef = wca_coef(r2, mp.eps, mp.sigma);
-        for (int c = 0; c < 3; ++c) F[c] += coef * dv[c];
+        if (r2 < rc2) {
+          const double ir2 = 1.0 / r2;
+          const double s6 = s2w * ir2 * s2w * ir2 * s2w * ir2;
+          const double coef = 24.0 * mp.eps * (2.0 * s6 * s6 - s6) * ir2;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) F[c] += coef * dv[c];
+        }
       }
-      // WCA against wall-site centres within the 4^3 nodes around the bead
-      for (int wz = 0; wz < 4; ++wz)
-        for (int wy = 0; wy < 4; ++wy)
-          for (int wx = 0; wx < 4; ++wx) {
-            const int ax = fx - 1 + wx, ay = fy - 1 + wy, az = fz - 1 + wz;
-            const int ix = ax - org[0] + 1, iy = ay - org[1] + 1, iz = az - org[2] + 1;
-            if (ix < 0 || ix >= WIN || iy < 0 || iy >= WIN || iz < 0 || iz >= WIN) continue;
-            if (!(fl[ix + WIN * (iy + WIN * iz)] & 2)) continue;
-            const double dv[3] = {R[0] - ax, R[1] - ay, R[2] - az};
-            const double coef = wca_coef(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2], mp.eps, mp.sigma);
-            for (int c = 0; c < 3; ++c) F[c] += coef * dv[c];
+      for (int wsite = lane; wsite < 64; wsite += TPB) {   // WCA against wall-site centres
+        const int wx = wsite & 3, wy = (wsite >> 2) & 3, wz = wsite >> 4;
+        const int ax = fx - 1 + wx, ay = fy - 1 + wy, az = fz - 1 + wz;
+        const int ix = ax - org[0] + 1, iy = ay - org[1] + 1, iz = az - org[2] + 1;
+        if (ix < 0 || ix >= WIN || iy < 0 || iy >= WIN || iz < 0 || iz >= WIN) continue;
+        if (!(fl[ix + WIN * (iy + WIN * iz)] & 2)) continue;
+        const double dv[3] = {R[0] - ax, R[1] - ay, R[2] - az};
+        const double r2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
+        if (r2 < rc2) {
+          const double ir2 = 1.0 / r2;
+          const double s6 = s2w * ir2 * s2w * ir2 * s2w * ir2;
+          const double coef = 24.0 * mp.eps * (2.0 * s6 * s6 - s6) * ir2;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) F[c] += coef * dv[c];
+        }
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int nb = -1; nb <= 1; nb += 2) {        // FENE bonds
+          const int j = i + nb;
+          if (j < 0 || j >= mp.n) continue;
+          double dv[3], r2 = 0.0;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double v = sR[3 * j + c] - R[c];
+            dv[c] = v - L[c] * rint(v * iL[c]);
+            r2 += dv[c] * dv[c];
           }
+          const double x2 = r2 * iR02;
+          if (x2 >= 1.0) {
+            atomicOr(bs.err, ERR_BOND);
+            continue;
+          }
+          const double coef = mp.k_fene / (1.0 - x2);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) F[c] += coef * dv[c];
+        }
+      }
+      // combine the lanes of this bead
+#pragma unroll
+      for (int c = 0; c < 15; ++c) acc[c] = group_sum<TPB>(acc[c]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) F[c] = group_sum<TPB>(F[c]) + q * acc[12 + c];
       // friction of each species and the substep update
       double ftot[3] = {F[0], F[1], F[2]};
+#pragma unroll
       for (int s = 0; s < 3; ++s)
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
-          phi[s][c] = mp.gamma * x[s] * (u[s][c] - V[c]);
+          phi[s][c] = mp.gamma * acc[9 + s] * (acc[3 * s + c] - V[c]);
           ftot[c] += phi[s][c];
         }
+#pragma unroll
       for (int c = 0; c < 3; ++c) {
-        V[c] += h * ftot[c] / mp.M;
+        V[c] += hM * ftot[c];
         Rn[c] = R[c] + h * V[c];
       }
     }
     __syncthreads();   // every bead has read positions and node momenta of this substep
     if (live) {
-      for (int k = 0; k < 8; ++k) {
-        if (wt[k] == 0.0) continue;
-        const int hsl = table_insert(keys, mask, site[k], bs.err);
-        if (hsl < 0) continue;
+#pragma unroll
+      for (int a = 0; a < CPL; ++a) {
+        if (wt[a] == 0.0 || slot[a] < 0) continue;
+#pragma unroll
         for (int s = 0; s < 3; ++s)
-          for (int c = 0; c < 3; ++c)
-            atomicAdd((unsigned long long*)&vals[(size_t)hsl * SLOT_VALUES + 1 + 3 * s + c],
-                      (unsigned long long)llrint(-h * phi[s][c] * wt[k] * FIX_FORCE));
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const long long v = llrint(-h * phi[s][c] * wt[a] * FIX_FORCE);
+            if (LDS) ln.add(slot[a], 3 * s + c, v);
+            else gn.add(slot[a], 3 * s + c, v);
+          }
       }
+#pragma unroll
       for (int c = 0; c < 3; ++c) {
         R[c] = Rn[c];
-        sR[3 * i + c] = Rn[c];
+        if (lane == 0) sR[3 * i + c] = Rn[c];
       }
     }
-    __threadfence();
+    if (!LDS) __threadfence();
     __syncthreads();
   }
-  if (live) {
+  if (live && lane == 0) {
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
       bs.R[3 * i + c] = R[c];
       bs.V[3 * i + c] = V[c];
+    }
+  }
+  if (LDS) {   // hand the accumulated impulses to the lattice kernels
+    __syncthreads();
+    for (int hh = threadIdx.x; hh < lslots; hh += blockDim.x) {
+      const int key = lkeys[hh];
+      if (key < 0) continue;
+      const int g = table_insert(gkeys, mask, key, bs.err);
+      if (g < 0) continue;
+      for (int c = 0; c < 9; ++c) {
+        const long long v = lvals[(size_t)hh * 9 + c];
+        if (v) atomicAdd((unsigned long long*)&gvals[(size_t)g * SLOT_VALUES + 1 + c], (unsigned long long)v);
+      }
     }
   }
 }
@@ -437,8 +594,32 @@ ek_status ek_ctx::beads_advance() {
   mp.Lx = p.nx;
   mp.Ly = p.ny;
   mp.Lz = p.nz;
-  const int threads = ((n_beads + 63) / 64) * 64;
-  hipLaunchKernelGGL(k_md, dim3(1), dim3(threads), 0, stream, bs, mp, keys, vals, mask, dims);
+  // lanes per bead so that a chain fills at most 512 threads (register budget
+  // of 256 per thread); chains beyond 512 beads take one lane each
+  const int tpb = n_beads <= 64 ? 8 : (n_beads <= 128 ? 4 : (n_beads <= 256 ? 2 : 1));
+  const int threads = ((n_beads * tpb + 63) / 64) * 64;
+  const size_t sr_bytes = ((size_t)n_beads * 24 + 15) & ~size_t(15);
+  auto md = [&](auto kernel, size_t lds, int bits) {
+    hipLaunchKernelGGL(kernel, dim3(1), dim3(threads), lds, stream, bs, mp, keys, vals, mask, dims, bits);
+  };
+  if (n_beads <= LDS_MAX_BEADS) {
+    int bits = 6;
+    while ((1 << bits) < 16 * n_beads) ++bits;          // load factor <= 1/2 for 8 corners/bead
+    const size_t lds = sr_bytes + ((size_t)1 << bits) * (9 * 8 + 4);
+    if (lds > 64 * 1024 &&
+        hipFuncSetAttribute((const void*)k_md<true, 8, 512>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds) != hipSuccess)
+      return fail(EK_EHIP, "cannot raise the LDS limit of the chain kernel");
+    md(k_md<true, 8, 512>, lds, bits);
+  } else if (tpb == 4) {
+    md(k_md<false, 4, 512>, sr_bytes, 0);
+  } else if (tpb == 2) {
+    md(k_md<false, 2, 512>, sr_bytes, 0);
+  } else if (threads <= 512) {
+    md(k_md<false, 1, 512>, sr_bytes, 0);
+  } else {
+    md(k_md<false, 1, 1024>, sr_bytes, 0);
+  }
   return EK_OK;
 }
 template ek_status ek_ctx::beads_advance<float>();

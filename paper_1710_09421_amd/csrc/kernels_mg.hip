@@ -1,0 +1,363 @@
+// Red-black multigrid for the periodic Poisson problem A psi = b.
+//
+// Not a method of the paper (which uses SOR with Chebyshev acceleration): a
+// solver for the same discrete problem, used to finish the solve faster on
+// large boxes.  Cell-centred hierarchy on the periodic box, each level half
+// the previous in every direction while all sides stay even:
+//   level l, spacing h = 2^l:  (sum of 6 neighbours - 6 x) / h^2 = f_l
+//   smoother   red-black Gauss-Seidel (x = (sum nb - h^2 f) / 6), nu1 = nu2 = 2
+//   restriction  f_{l+1} = average of the 8 fine residuals (fused with the
+//                residual, also zeroes the coarse iterate)
+//   prolongation trilinear cell-centred interpolation (weights 3/4, 1/4 per
+//                axis) added to the fine iterate
+// A level is halved only while every side stays even (red-black colouring
+// needs even periodic sides).  The coarsest levels whose iterates and
+// right-hand sides fit in COARSE_LDS_BYTES of LDS run inside one workgroup
+// (one launch for the whole coarse part of the cycle); the coarsest level
+// gets red-black SOR sweeps at the optimal relaxation factor of that grid,
+// enough of them to reduce its error by 1e-10.  Level 0 is the context's psi and b (b
+// plus the scalar shift that removes the mean charge).
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "ek_context.h"
+
+using namespace ek;
+
+namespace {
+
+constexpr int NU1 = 2, NU2 = 2;
+constexpr size_t COARSE_LDS_BYTES = 40 * 1024;    // one-workgroup coarse cycle: levels of up to ~2k sites
+constexpr int COARSEST_SWEEPS = 40;
+constexpr int MAX_LEVELS = 16;
+
+struct Lvl {
+  int nx, ny, nz;
+  long long n;
+  double h2;
+  double* x;
+  double* f;
+};
+
+struct LvlSet {
+  Lvl l[MAX_LEVELS];
+  int count;
+};
+
+// q = t / d and t - q d for 0 <= t < 2^24 without an integer divide: the
+// float quotient is off by at most one, which the remainder test corrects.
+__device__ inline int fdivmod(int t, int d, float inv_d, int& rem) {
+  int q = int(float(t) * inv_d);
+  int r = t - q * d;
+  if (r < 0) { --q; r += d; }
+  else if (r >= d) { ++q; r -= d; }
+  rem = r;
+  return q;
+}
+
+__device__ inline int idx3(int x, int y, int z, const Lvl& L) {
+  return (z * L.ny + y) * L.nx + x;
+}
+
+__device__ inline double nbsum(const double* __restrict__ v, int x, int y, int z, const Lvl& L) {
+  const int xm = x == 0 ? L.nx - 1 : x - 1, xp = x == L.nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? L.ny - 1 : y - 1, yp = y == L.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? L.nz - 1 : z - 1, zp = z == L.nz - 1 ? 0 : z + 1;
+  return v[idx3(xm, y, z, L)] + v[idx3(xp, y, z, L)] + v[idx3(x, ym, z, L)] +
+         v[idx3(x, yp, z, L)] + v[idx3(x, y, zm, L)] + v[idx3(x, y, zp, L)];
+}
+
+// --- per-site operations shared by the grid-wide and single-block kernels ---
+// (tx, y, z) enumerates the sites of one colour: nx/2 per row
+__device__ inline void smooth_site(const Lvl& L, int colour, int tx, int y, int z, double shift,
+                                   double omega = 1.0) {
+  const int x = 2 * tx + ((colour + y + z) & 1);
+  const int r = idx3(x, y, z, L);
+  const double gs = (nbsum(L.x, x, y, z, L) - L.h2 * (L.f[r] + shift)) * (1.0 / 6.0);
+  L.x[r] = omega == 1.0 ? gs : L.x[r] + omega * (gs - L.x[r]);
+}
+
+__device__ inline void restrict_site(const Lvl& F, const Lvl& C, int X, int Y, int Z, double shift) {
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int x = 2 * X + (k & 1), y = 2 * Y + ((k >> 1) & 1), z = 2 * Z + ((k >> 2) & 1);
+    const int r = idx3(x, y, z, F);
+    s += (F.f[r] + shift) - (nbsum(F.x, x, y, z, F) - 6.0 * F.x[r]) / F.h2;
+  }
+  const int t = idx3(X, Y, Z, C);
+  C.f[t] = 0.125 * s;
+  C.x[t] = 0.0;
+}
+
+__device__ inline void prolong_site(const Lvl& F, const Lvl& C, int x, int y, int z) {
+  const int X = x >> 1, Y = y >> 1, Z = z >> 1;
+  const int Xn = (x & 1) ? (X + 1 == C.nx ? 0 : X + 1) : (X == 0 ? C.nx - 1 : X - 1);
+  const int Yn = (y & 1) ? (Y + 1 == C.ny ? 0 : Y + 1) : (Y == 0 ? C.ny - 1 : Y - 1);
+  const int Zn = (z & 1) ? (Z + 1 == C.nz ? 0 : Z + 1) : (Z == 0 ? C.nz - 1 : Z - 1);
+  const double a = 0.75, b = 0.25;
+  const double v =
+      a * a * a * C.x[idx3(X, Y, Z, C)] + b * a * a * C.x[idx3(Xn, Y, Z, C)] +
+      a * b * a * C.x[idx3(X, Yn, Z, C)] + a * a * b * C.x[idx3(X, Y, Zn, C)] +
+      b * b * a * C.x[idx3(Xn, Yn, Z, C)] + b * a * b * C.x[idx3(Xn, Y, Zn, C)] +
+      a * b * b * C.x[idx3(X, Yn, Zn, C)] + b * b * b * C.x[idx3(Xn, Yn, Zn, C)];
+  F.x[idx3(x, y, z, F)] += v;
+}
+
+// --- grid-wide kernels for the fine levels (3-D launch: x, y from the block,
+// z = blockIdx.z, so no index division) ------------------------------------
+__global__ __launch_bounds__(256) void k_smooth(Lvl L, int colour, const PoissonScalars* ps,
+                                                int level0, double omega) {
+  if (ps->done) return;
+  const int tx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (tx >= L.nx / 2 || y >= L.ny) return;
+  smooth_site(L, colour, tx, y, blockIdx.z, level0 ? ps->shift : 0.0, omega);
+}
+
+__global__ __launch_bounds__(256) void k_restrict(Lvl F, Lvl C, const PoissonScalars* ps,
+                                                  int level0) {
+  if (ps->done) return;
+  const int X = blockIdx.x * blockDim.x + threadIdx.x;
+  const int Y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (X >= C.nx || Y >= C.ny) return;
+  restrict_site(F, C, X, Y, blockIdx.z, level0 ? ps->shift : 0.0);
+}
+
+__global__ __launch_bounds__(256) void k_prolong(Lvl F, Lvl C, const PoissonScalars* ps) {
+  if (ps->done) return;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= F.nx || y >= F.ny) return;
+  prolong_site(F, C, x, y, blockIdx.z);
+}
+
+// --- the coarse part of a V-cycle in one workgroup ----------------------------
+__device__ void block_smooth(const Lvl& L, int sweeps, double shift, double omega = 1.0) {
+  const int hx = L.nx / 2, nh = hx * L.ny * L.nz;
+  const float ihx = 1.0f / hx, iny = 1.0f / L.ny;
+  for (int s = 0; s < sweeps; ++s)
+    for (int colour = 0; colour < 2; ++colour) {
+      for (int t = threadIdx.x; t < nh; t += blockDim.x) {
+        int tx, y;
+        const int yz = fdivmod(t, hx, ihx, tx);
+        const int z = fdivmod(yz, L.ny, iny, y);
+        smooth_site(L, colour, tx, y, z, shift, omega);
+      }
+      __syncthreads();
+    }
+}
+
+// The coarse part of the cycle runs on copies of the coarse levels in LDS:
+// level `first` arrives with its right-hand side and a zero iterate in global
+// memory, its iterate goes back to global memory at the end.
+__global__ __launch_bounds__(1024) void k_coarse_cycle(LvlSet set, int first,
+                                                       const PoissonScalars* ps,
+                                                       double omega_coarsest, int coarsest_sweeps) {
+  if (ps->done) return;
+  extern __shared__ __align__(16) double lds[];
+  __shared__ Lvl L[MAX_LEVELS];
+  const int last = set.count - 1;
+  if (threadIdx.x == 0) {
+    double* p = lds;
+    for (int l = first; l <= last; ++l) {
+      L[l] = set.l[l];
+      L[l].x = p;
+      L[l].f = p + L[l].n;
+      p += 2 * L[l].n;
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < int(L[first].n); t += blockDim.x) {
+    L[first].f[t] = set.l[first].f[t];
+    L[first].x[t] = 0.0;
+  }
+  __syncthreads();
+  for (int l = first; l < last; ++l) {
+    block_smooth(L[l], NU1, 0.0);
+    const Lvl& C = L[l + 1];
+    const float inx = 1.0f / C.nx, iny = 1.0f / C.ny;
+    for (int t = threadIdx.x; t < int(C.n); t += blockDim.x) {
+      int X, Y;
+      const int yz = fdivmod(t, C.nx, inx, X);
+      const int Z = fdivmod(yz, C.ny, iny, Y);
+      restrict_site(L[l], C, X, Y, Z, 0.0);
+    }
+    __syncthreads();
+  }
+  block_smooth(L[last], coarsest_sweeps, 0.0, omega_coarsest);
+  for (int l = last - 1; l >= first; --l) {
+    const Lvl& F = L[l];
+    const float inx = 1.0f / F.nx, iny = 1.0f / F.ny;
+    for (int t = threadIdx.x; t < int(F.n); t += blockDim.x) {
+      int x, y;
+      const int yz = fdivmod(t, F.nx, inx, x);
+      const int z = fdivmod(yz, F.ny, iny, y);
+      prolong_site(F, L[l + 1], x, y, z);
+    }
+    __syncthreads();
+    block_smooth(L[l], NU2, 0.0);
+  }
+  for (int t = threadIdx.x; t < int(L[first].n); t += blockDim.x) set.l[first].x[t] = L[first].x[t];
+}
+
+SiteGrid colour_launch(const Lvl& L) { return site_grid(L.nx / 2, L.ny, L.nz); }
+SiteGrid level_launch(const Lvl& L) { return site_grid(L.nx, L.ny, L.nz); }
+
+}  // namespace
+
+struct ek_ctx::MG {
+  std::vector<Lvl> levels;   // level 0 pointers are filled per solve
+  int first_coarse = 0;      // first level handled by the single-workgroup kernel
+  size_t coarse_lds = 0;     // LDS bytes of that kernel
+  double omega_coarsest = 1.0;
+  int coarsest_sweeps = COARSEST_SWEEPS;
+};
+
+bool halvable(int nx, int ny, int nz) {
+  return nx % 4 == 0 && ny % 4 == 0 && nz % 4 == 0;
+}
+
+// optimal SOR factor 2 / (1 + sqrt(1 - rho_J^2)) of a periodic grid
+double omega_opt(int nx, int ny, int nz) {
+  const int m = std::max(nx, std::max(ny, nz));
+  const double rj = (2.0 + std::cos(2.0 * M_PI / m)) / 3.0;
+  return 2.0 / (1.0 + std::sqrt(1.0 - rj * rj));
+}
+
+size_t ek::mg_workspace_bytes(int nx, int ny, int nz) {
+  size_t bytes = 256;
+  while (halvable(nx, ny, nz)) {
+    nx /= 2;
+    ny /= 2;
+    nz /= 2;
+    bytes += 2 * (((size_t)nx * ny * nz * 8 + 255) & ~size_t(255));
+  }
+  return bytes;
+}
+
+void ek_ctx::mg_setup() {
+  mg = new MG();
+  int nx = p.nx, ny = p.ny, nz = p.nz;
+  Lvl l0{nx, ny, nz, (long long)nx * ny * nz, 1.0, nullptr, nullptr};
+  mg->levels.push_back(l0);
+  char* mem = mg_mem + 256;
+  double h2 = 1.0;
+  while (halvable(nx, ny, nz) && (int)mg->levels.size() < MAX_LEVELS) {
+    nx /= 2;
+    ny /= 2;
+    nz /= 2;
+    h2 *= 4.0;
+    const long long n = (long long)nx * ny * nz;
+    const size_t b = ((size_t)n * 8 + 255) & ~size_t(255);
+    Lvl l{nx, ny, nz, n, h2, (double*)mem, (double*)(mem + b)};
+    mem += 2 * b;
+    mg->levels.push_back(l);
+  }
+  const int nl = (int)mg->levels.size();
+  int fc = nl - 1;
+  size_t bytes = 16 * (size_t)mg->levels[fc].n;
+  while (fc > 1 && bytes + 16 * (size_t)mg->levels[fc - 1].n <= COARSE_LDS_BYTES) {
+    --fc;
+    bytes += 16 * (size_t)mg->levels[fc].n;
+  }
+  mg->first_coarse = fc;
+  mg->coarse_lds = bytes;
+  if (nl > 1 && bytes > 64 * 1024 &&
+      hipFuncSetAttribute((const void*)k_coarse_cycle, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)bytes) != hipSuccess) {
+    // keep within the default dynamic LDS limit
+    while (fc < nl - 1 && mg->coarse_lds > 64 * 1024) {
+      mg->coarse_lds -= 16 * (size_t)mg->levels[fc].n;
+      ++fc;
+    }
+    mg->first_coarse = fc;
+  }
+  const Lvl& c = mg->levels.back();
+  mg->omega_coarsest = omega_opt(c.nx, c.ny, c.nz);
+  const double rate = std::max(mg->omega_coarsest - 1.0, 1e-3);
+  mg->coarsest_sweeps = std::min(200, std::max(4, (int)std::ceil(std::log(1e-10) / std::log(rate))));
+}
+
+void ek_ctx::mg_release() {
+  delete mg;
+  mg = nullptr;
+}
+
+ek_status ek_ctx::mg_vcycle(const double* bb, double* x) {
+  std::vector<Lvl>& L = mg->levels;
+  L[0].x = x;
+  L[0].f = const_cast<double*>(bb);
+  const int fc = mg->first_coarse;
+  const int nl = (int)L.size();
+  if (nl == 1) {   // no coarser level: red-black SOR at the optimal factor
+    for (int s = 0; s < mg->coarsest_sweeps; ++s)
+      for (int c = 0; c < 2; ++c)
+        hipLaunchKernelGGL(k_smooth, colour_launch(L[0]).grid, colour_launch(L[0]).block, 0, stream,
+                           L[0], c, ps, 1, mg->omega_coarsest);
+    return EK_OK;
+  }
+  for (int l = 0; l < fc; ++l) {
+    for (int s = 0; s < NU1; ++s)
+      for (int c = 0; c < 2; ++c)
+        hipLaunchKernelGGL(k_smooth, colour_launch(L[l]).grid, colour_launch(L[l]).block, 0, stream,
+                           L[l], c, ps, l == 0 ? 1 : 0, 1.0);
+    hipLaunchKernelGGL(k_restrict, level_launch(L[l + 1]).grid, level_launch(L[l + 1]).block, 0,
+                       stream, L[l], L[l + 1], ps, l == 0 ? 1 : 0);
+  }
+  LvlSet set{};
+  set.count = nl;
+  for (int l = 0; l < nl; ++l) set.l[l] = L[l];
+  hipLaunchKernelGGL(k_coarse_cycle, dim3(1), dim3(1024), mg->coarse_lds, stream, set, fc, ps,
+                     mg->omega_coarsest, mg->coarsest_sweeps);
+  for (int l = fc - 1; l >= 0; --l) {
+    hipLaunchKernelGGL(k_prolong, level_launch(L[l]).grid, level_launch(L[l]).block, 0, stream, L[l],
+                       L[l + 1], ps);
+    for (int s = 0; s < NU2; ++s)
+      for (int c = 0; c < 2; ++c)
+        hipLaunchKernelGGL(k_smooth, colour_launch(L[l]).grid, colour_launch(L[l]).block, 0, stream,
+                           L[l], c, ps, l == 0 ? 1 : 0, 1.0);
+  }
+  return EK_OK;
+}
+
+// V-cycles until ||b - A psi|| / ||b|| <= tol, tested after every cycle;
+// cycles are enqueued ahead of the test in batches and skip themselves once
+// the device-side flag is set.
+ek_status ek_ctx::mg_solve(const double* bb, double* x, int& iters, double& res, double& res0) {
+  const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
+  const int nb = g.nblocks();
+  launch_residual(x, bb, ps, partials, dims, g, stream);
+  launch_residual_final(partials, nb, p.poisson_tol, 0, 1, ps, stream);
+  PoissonScalars h{};
+  ek_status st = read_scalars(&h);
+  if (st) return st;
+  int it = 0;
+  int batch = std::max(1, last_iters);
+  while (!h.done && it < p.poisson_max_iter) {
+    const int nrun = std::min(batch, p.poisson_max_iter - it);
+    for (int k = 0; k < nrun; ++k) {
+      st = mg_vcycle(bb, x);
+      if (st) return st;
+      ++it;
+      launch_residual(x, bb, ps, partials, dims, g, stream);
+      launch_residual_final(partials, nb, p.poisson_tol, it, 0, ps, stream);
+    }
+    st = read_scalars(&h);
+    if (st) return st;
+    batch = 1;
+  }
+  res0 = h.rel0;
+  res = h.rel;
+  if (!h.done) {
+    iters = it;
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "multigrid did not reach %.3g in %d cycles (residual %.3e)",
+                  p.poisson_tol, p.poisson_max_iter, h.rel);
+    return fail(EK_ENOCONV, buf);
+  }
+  iters = h.iters;
+  launch_psi_shift(x, ps, 1.0 / double(dims.n), dims, stream);
+  return EK_OK;
+}

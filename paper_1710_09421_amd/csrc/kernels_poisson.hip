@@ -73,20 +73,20 @@ __global__ __launch_bounds__(BLOCK) void k_residual(const double* __restrict__ p
   block_partials<3>(acc, partials, bid, nblocks);
 }
 
-__global__ __launch_bounds__(256) void k_residual_final(const double* __restrict__ partials,
-                                                        int nblocks, double tol, int iter,
-                                                        int initial, PoissonScalars* ps) {
+__global__ __launch_bounds__(1024) void k_residual_final(const double* __restrict__ partials,
+                                                         int nblocks, double tol, int iter,
+                                                         int initial, PoissonScalars* ps) {
   if (ps->done) return;
-  const double r2 = block_sum_256(partials, nblocks);
-  const double b2 = block_sum_256(partials + nblocks, nblocks);
-  const double s = block_sum_256(partials + 2 * (size_t)nblocks, nblocks);
+  double t[3];
+  block_sums_1024<3>(partials, nblocks, t);
   if (threadIdx.x == 0) {
+    const double r2 = t[0], b2 = t[1];
     double rel;
     if (b2 > 0.0) rel = sqrt(r2 / b2);
     else rel = r2 == 0.0 ? 0.0 : INFINITY;
     ps->r2 = r2;
     ps->b2 = b2;
-    ps->psum = s;
+    ps->psum = t[2];
     ps->rel = rel;
     if (initial) ps->rel0 = rel;
     if (b2 == 0.0) {
@@ -146,7 +146,7 @@ void launch_residual(const double* psi, const double* b, PoissonScalars* ps, dou
 
 void launch_residual_final(const double* partials, int nblocks, double tol, int iter,
                            int initial, PoissonScalars* ps, hipStream_t s) {
-  hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(256), 0, s, partials, nblocks, tol, iter,
+  hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(1024), 0, s, partials, nblocks, tol, iter,
                      initial, ps);
 }
 

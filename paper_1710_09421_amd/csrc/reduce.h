@@ -50,4 +50,32 @@ __device__ inline double block_sum_256(const double* part, int nblocks) {
   return r;
 }
 
+// Sums of NC components of nblocks partials (layout [c * nblocks + block]) by
+// one block of 1024 threads: strided loads of every component first, then a
+// fixed tree per component.  Results valid in thread 0.
+template <int NC>
+__device__ inline void block_sums_1024(const double* part, int nblocks, double (&out)[NC]) {
+  __shared__ double sh[NC][1024];
+  const int tid = threadIdx.x;
+  double s[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) s[c] = 0.0;
+  for (int i = tid; i < nblocks; i += 1024) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) s[c] += part[(size_t)c * nblocks + i];
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) sh[c][tid] = s[c];
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (tid < w) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) sh[c][tid] += sh[c][tid + w];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) out[c] = sh[c][0];
+}
+
 }  // namespace ek

@@ -1,0 +1,83 @@
+"""Red-black multigrid solves the same discrete Poisson problem as the
+paper's red-black SOR: its solution meets the residual tolerance when the
+oracle recomputes the residual in float64, and agrees with the oracle's SOR
+solution within the error that tolerance allows."""
+import numpy as np
+import pytest
+
+from oracle import poisson as opoisson
+from oracle import step as ostep
+from paper_1710_09421_amd import workloads
+from tests.parity import density_error, field_error, velocity_error
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+EPS = 1.0 / (4 * np.pi * 0.7 / 3.0)
+
+
+@pytest.fixture(scope="module")
+def ek():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1710_09421_amd import ek as binding
+    binding.lib()
+    return binding
+
+
+@pytest.mark.parametrize("shape", [(128, 64, 64), (32, 32, 32), (48, 16, 24), (4, 2, 2), (6, 10, 14)])
+def test_multigrid_meets_tolerance(ek, shape):
+    rng = np.random.default_rng(sum(shape))
+    rho = rng.normal(size=shape) * 0.01
+    p = ek.make_params(shape, precision=ek.EK_FP64, poisson_method=ek.EK_POISSON_MG,
+                       poisson_tol=1e-8, poisson_max_iter=400)
+    ctx = ek.Context(p)
+    rt = torch.tensor(rho, dtype=torch.float64, device="cuda")
+    pt = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    rep = ctx.poisson_solve(rt, pt, ek.EK_WS_ZERO)
+    psi = pt.cpu().numpy()
+    b = opoisson.rhs_from_charge(rho, EPS)
+    rr = opoisson.relative_residual(psi, b)
+    print(shape, rep, rr)
+    assert rr <= 1e-8
+    assert abs(psi.mean()) < 1e-12 * np.abs(psi).max()
+    if min(shape) >= 8:
+        assert rep["iterations"] <= 12           # about a decade per V(2,2) cycle
+    ref, _, _ = opoisson.sor_red_black_chebyshev(b, np.zeros(shape), 1e-12, 100000)
+    assert field_error(psi, ref) < 1e3 * 1e-8
+
+
+def test_multigrid_warm_start_needs_fewer_cycles(ek):
+    shape = (64, 32, 32)
+    rng = np.random.default_rng(5)
+    rho = rng.normal(size=shape) * 0.01
+    p = ek.make_params(shape, precision=ek.EK_FP64, poisson_method=ek.EK_POISSON_MG, poisson_tol=1e-8)
+    ctx = ek.Context(p)
+    rt = torch.tensor(rho, dtype=torch.float64, device="cuda")
+    pt = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    cold = ctx.poisson_solve(rt, pt, ek.EK_WS_ZERO)
+    rt2 = rt * (1.0 + 1e-4 * torch.randn_like(rt))
+    warm = ctx.poisson_solve(rt2, pt, ek.EK_WS_PREV)
+    assert warm["iterations"] < cold["iterations"]
+    assert warm["initial_residual"] < 1e-2
+
+
+def test_pore_fp32_with_multigrid_matches_oracle(ek):
+    wl = workloads.pore_system((32, 24, 24), 6, 4, 0.01, 0.01, -0.01, 8, 32, steps=100)
+    ctx = ek.from_workload(wl, precision=ek.EK_FP32, poisson_method=ek.EK_POISSON_MG,
+                           poisson_tol=1e-8)
+    p = ostep.Params(E_ext=wl.E_ext, poisson_tol=1e-8)
+    sim = ostep.Simulation(p, wl.solid.astype(bool), wl.wall_q, wl.n0,
+                           beads=(wl.beads_R, wl.beads_V, wl.polymer))
+    ctx.step(100)
+    sim.run(100)
+    fluid = wl.solid == 0
+    n_ref, u_ref = sim.densities(), sim.velocities()
+    err = {}
+    for s in range(3):
+        n, u = ctx.moments(s)
+        err[f"n{s}"] = density_error(n, n_ref[s], fluid)
+        err[f"u{s}"] = velocity_error(u, u_ref[s], fluid)
+    err["psi"] = field_error(ctx.potential(), sim.psi)
+    err["R"] = float(np.abs(ctx.beads(8)[0] - sim.R).max())
+    print(err)
+    assert max(err.values()) < 1e-5, err

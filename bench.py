@@ -18,6 +18,7 @@ The JSON line also carries:
                 the same workload (one untimed step, then one timed step).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,6 +28,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+LB_SOURCE = os.path.join(ROOT, "paper_1710_09421_amd", "csrc", "kernels_lb.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lb_step_traffic.json")
+
+
+def lb_source_hash():
+    with open(LB_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(workload_name, precision):
+    """HBM bytes per launch of the fused lattice kernel from the committed
+    rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE, scaled by the factor a
+    plain copy kernel of known size gives), or None when no run matches this
+    workload or the kernel source has changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    for r in rec.get("runs", []):
+        if (r.get("workload") == workload_name and r.get("dtype") == precision
+                and r.get("kernel_source_sha256") == lb_source_hash()):
+            return r["hbm_bytes_per_launch"]
+    return None
 
 
 def build_workload(name):
@@ -80,6 +105,9 @@ def main():
     ap.add_argument("--poisson", default="sor", choices=["sor", "mg"])
     ap.add_argument("--check-every", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="after the timed region, copy this many GiB device-to-device three "
+                         "times (a kernel of known traffic for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the method's data-parallel step runs on a single "
@@ -89,12 +117,23 @@ def main():
     import torch
     from paper_1710_09421_amd import ek
 
+    def progress(msg):
+        print(f"[bench] {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
+
     wl = build_workload(args.workload)
+    progress(f"workload {wl.name}: {wl.sites} sites")
     prec = ek.EK_FP32 if args.precision == "fp32" else ek.EK_FP64
     method = ek.EK_POISSON_SOR if args.poisson == "sor" else ek.EK_POISSON_MG
     ctx = ek.from_workload(wl, precision=prec, poisson_method=method,
-                           poisson_check_every=args.check_every)
-    ctx.step(args.warmup)
+                           poisson_check_every=args.check_every,
+                           poisson_max_iter=200 if method == ek.EK_POISSON_MG else 100000)
+    progress("context ready")
+    for k in range(args.warmup):
+        ctx.step(1)
+        if k < 3 or k == args.warmup - 1:
+            st = ctx.stats()
+            progress(f"warmup step {k + 1}: poisson {st['poisson_iters']} iterations, "
+                     f"residual {st['poisson_residual']:.2e}")
     torch.cuda.synchronize()
     ctx.set_timing(True)
     torch.cuda.synchronize()
@@ -102,8 +141,18 @@ def main():
     ctx.step(args.steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    progress(f"timed {args.steps} steps in {dt:.3f} s")
     tm = ctx.timing()
     st = ctx.stats()
+
+    if args.copy_probe_gib > 0:
+        n = int(args.copy_probe_gib * 2 ** 30) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     value = 3 * wl.sites * args.steps / dt / 1e6
     pbytes = 4 if prec == ek.EK_FP32 else 8
@@ -148,7 +197,7 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "bytes_per_launch": lb_bytes,
             "avg_launch_ms": round(lb_ms, 5),
-            "traffic": None,
+            "traffic": measured_traffic(wl.name, "f32" if prec == ek.EK_FP32 else "f64"),
         },
     }
     if not args.no_cpu_baseline:

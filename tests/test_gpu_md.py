@@ -130,3 +130,18 @@ def test_polymer_argument_checks(ek):
     with pytest.raises(ek.EKError) as e:
         ctx.set_polymer(np.zeros((9, 3)), np.zeros((9, 3)), np.zeros(9))   # more than max_beads
     assert e.value.status == ek.EK_EINVAL
+
+
+@pytest.mark.parametrize("n_beads", [80, 130])
+def test_long_chain_fp64_matches_oracle(ek, n_beads):
+    """Chains beyond 64 beads take the kernel path with the node table in
+    global memory (4 lanes per bead up to 128 beads, then 2)."""
+    wl = workloads.pore_system((64, 40, 40), 8, 5, 0.01, 0.01, -0.01, n_beads, 41,
+                               bead_q=workloads.STABLE_BEAD_CHARGE, steps=10)
+    ctx = ek.from_workload(wl, precision=ek.EK_FP64, poisson_tol=1e-10, poisson_check_every=1)
+    sim = oracle_sim(wl, 1e-10)
+    ctx.step(8)
+    sim.run(8)
+    err = errors(ctx, sim, wl)
+    print(n_beads, err)
+    assert max(err.values()) < 1e-8, err

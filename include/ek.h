@@ -191,6 +191,64 @@ typedef struct {
 ek_status ek_set_timing(struct ek_ctx* ctx, int32_t enable);
 ek_status ek_get_timing(struct ek_ctx* ctx, ek_timing* out);
 
+/* ---------------------------------------------------------------------------
+ * Ensemble: uneven replicas of one geometry (translocation replicas with their
+ * own salt noise, applied field and chain, Sec. IV.A) advanced together by ONE
+ * persistent kernel launch per ek_ensemble_step call: one workgroup per
+ * replica runs the whole time loop of Fig. 1 for that replica (charge pass,
+ * multigrid Poisson solve with its own convergence test, chain substeps,
+ * fused lattice step), so replicas with more Poisson cycles or longer chains
+ * never hold the others back.  The Poisson method is multigrid; all other
+ * parameters come from the base ek_params except the applied field.
+ * ------------------------------------------------------------------------- */
+typedef struct ek_ensemble ek_ensemble;
+
+typedef struct {
+  int32_t threads;             /* workgroup size of the persistent kernel      */
+  double ms_per_step;          /* measured time per ensemble step              */
+} ek_tune_result;
+
+/* Device workspace for n_rep replicas with chains of up to max_beads beads
+ * (max_beads <= 64: each chain's node sums live in LDS). */
+ek_status ek_ensemble_workspace_bytes(const ek_params* base, int32_t n_rep, int32_t max_beads,
+                                      size_t* bytes);
+ek_status ek_ensemble_create(const ek_params* base, int32_t n_rep, int32_t max_beads,
+                             void* dev_ws, size_t ws_bytes, void* hip_stream, ek_ensemble** out);
+void ek_ensemble_destroy(ek_ensemble* ens);
+const char* ek_ensemble_last_error(const ek_ensemble* ens);
+
+/* Shared geometry of all replicas (host arrays as in ek_set_geometry). */
+ek_status ek_ensemble_set_geometry(ek_ensemble* ens, const uint8_t* solid, const double* wall_q);
+
+/* Replica r: applied field E_ext[3], host densities n0[3][nz*ny*nx]
+ * (solvent, cation, anion; populations at rest), and its chain (n_beads may
+ * be 0; pos, vel [3*n_beads], charge [n_beads]; pp as in ek_set_polymer). */
+ek_status ek_ensemble_set_replica(ek_ensemble* ens, int32_t r, const double* E_ext,
+                                  const double* n0, int32_t n_beads, const double* pos,
+                                  const double* vel, const double* charge,
+                                  const ek_polymer_params* pp);
+
+/* n_steps steps of every replica in one persistent launch; returns after the
+ * stream is synchronised.  EK_ENOCONV if a replica's Poisson solve did not
+ * reach the tolerance in poisson_max_iter cycles, EK_EUNSTABLE if a replica's
+ * mass became non-finite or its chain failed (ek_ensemble_last_error names
+ * the replica). */
+ek_status ek_ensemble_step(ek_ensemble* ens, int32_t n_steps);
+
+ek_status ek_ensemble_get_moments(ek_ensemble* ens, int32_t r, int32_t species, double* n,
+                                  double* u);
+ek_status ek_ensemble_get_potential(ek_ensemble* ens, int32_t r, double* psi);
+ek_status ek_ensemble_get_beads(ek_ensemble* ens, int32_t r, double* pos, double* vel);
+ek_status ek_ensemble_get_stats(ek_ensemble* ens, int32_t r, ek_stats* out);
+
+/* Workgroup size of the persistent kernel (256, 512 or 1024). */
+ek_status ek_ensemble_set_threads(ek_ensemble* ens, int32_t threads);
+
+/* Autotuner: times `steps` ensemble steps with every candidate workgroup size
+ * (the replicas advance by those steps, like a warm-up) and keeps the
+ * fastest; *out (may be NULL) receives the choice and its time. */
+ek_status ek_ensemble_autotune(ek_ensemble* ens, int32_t steps, ek_tune_result* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -268,6 +268,38 @@ ek_status ek_ctx::step_impl(int n_steps) {
   return EK_OK;
 }
 
+// Link word of every site (bounce-back bits, solid, wall and charge flags)
+// from the host solid mask; returns the number of fluid sites.
+long long ek::build_link_words(const uint8_t* solid, const double* wall_q, const Dims& d,
+                               std::vector<uint32_t>& m) {
+  m.assign(d.n, 0u);
+  long long nfluid = 0;
+  for (int z = 0; z < d.nz; ++z)
+    for (int y = 0; y < d.ny; ++y)
+      for (int x = 0; x < d.nx; ++x) {
+        const long long r = ((long long)z * d.ny + y) * d.nx + x;
+        uint32_t w = 0;
+        if (solid[r]) {
+          w |= MASK_SOLID;
+          for (int q = 1; q < Q; ++q) {
+            const int sx = (x + CX[q] + d.nx) % d.nx, sy = (y + CY[q] + d.ny) % d.ny,
+                      sz = (z + CZ[q] + d.nz) % d.nz;
+            if (!solid[((long long)sz * d.ny + sy) * d.nx + sx]) w |= MASK_WALL;
+          }
+        } else {
+          ++nfluid;
+          for (int q = 1; q < Q; ++q) {
+            const int sx = (x - CX[q] + d.nx) % d.nx, sy = (y - CY[q] + d.ny) % d.ny,
+                      sz = (z - CZ[q] + d.nz) % d.nz;
+            if (solid[((long long)sz * d.ny + sy) * d.nx + sx]) w |= 1u << q;
+          }
+        }
+        if (wall_q && wall_q[r] != 0.0) w |= MASK_CHARGED;
+        m[r] = w;
+      }
+  return nfluid;
+}
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
@@ -362,31 +394,8 @@ ek_status ek_set_geometry(ek_ctx* ctx, const uint8_t* solid, const double* wall_
   if (!ctx) return EK_EINVAL;
   if (!solid) return ctx->fail(EK_EINVAL, "solid is NULL");
   const Dims d = ctx->dims;
-  std::vector<uint32_t> m(d.n, 0u);
-  long long nfluid = 0;
-  for (int z = 0; z < d.nz; ++z)
-    for (int y = 0; y < d.ny; ++y)
-      for (int x = 0; x < d.nx; ++x) {
-        const long long r = ((long long)z * d.ny + y) * d.nx + x;
-        uint32_t w = 0;
-        if (solid[r]) {
-          w |= MASK_SOLID;
-          for (int q = 1; q < Q; ++q) {
-            const int sx = (x + CX[q] + d.nx) % d.nx, sy = (y + CY[q] + d.ny) % d.ny,
-                      sz = (z + CZ[q] + d.nz) % d.nz;
-            if (!solid[((long long)sz * d.ny + sy) * d.nx + sx]) w |= MASK_WALL;
-          }
-        } else {
-          ++nfluid;
-          for (int q = 1; q < Q; ++q) {
-            const int sx = (x - CX[q] + d.nx) % d.nx, sy = (y - CY[q] + d.ny) % d.ny,
-                      sz = (z - CZ[q] + d.nz) % d.nz;
-            if (solid[((long long)sz * d.ny + sy) * d.nx + sx]) w |= 1u << q;
-          }
-        }
-        if (wall_q && wall_q[r] != 0.0) w |= MASK_CHARGED;
-        m[r] = w;
-      }
+  std::vector<uint32_t> m;
+  const long long nfluid = build_link_words(solid, wall_q, d, m);
   if (nfluid == 0) return ctx->fail(EK_EINVAL, "geometry has no fluid site");
   EK_HIP(hipMemcpy(ctx->mask, m.data(), d.n * 4, hipMemcpyHostToDevice));
   if (wall_q) {

@@ -11,6 +11,7 @@ namespace ek {
 constexpr int MAX_BEADS = 1024;        // one workgroup advances a whole chain
 size_t bead_state_bytes(int max_beads);
 void launch_table_init(int* keys, long long* vals, hipStream_t s);
+void launch_table_init_bits(int* keys, long long* vals, int bits, hipStream_t s);
 size_t mg_workspace_bytes(int nx, int ny, int nz);
 }  // namespace ek
 

@@ -68,6 +68,10 @@ struct LBParams {
 
 struct BeadTableView;      // md_table.h
 
+// Link word of every site from the host solid mask; returns the fluid count.
+long long build_link_words(const uint8_t* solid, const double* wall_q, const Dims& d,
+                           std::vector<uint32_t>& m);
+
 // Device-side scalars of the Poisson solver (one struct in device memory).
 struct PoissonScalars {
   double shift;           // mean(rho) / eps, added to the stored -rho/eps

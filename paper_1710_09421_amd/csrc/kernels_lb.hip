@@ -1,52 +1,14 @@
-// Lattice kernels: initial populations, the ion-density (charge) pass, the
-// fused pull-stream + collide step and the moment read-out.
-//
-// Storage: populations of the three species are structure-of-arrays planes
-// f[(s * 19 + p) * N + site], site = (z * ny + y) * nx + x, holding the
-// post-collision values of the previous step.  A thread owns one site and
-// pulls f*_p(r - c_p) (halfway bounce-back: f*_opp(p)(r) when r - c_p is
-// solid), which makes every read of a plane a shifted but coalesced row and
-// every write aligned.  Values are stored as deviations from rest,
-// g_p = f_p - w_p nref^a, so that float32 keeps the small velocity-carrying
-// part of the populations to full relative precision.
+// Grid-wide lattice kernels (one thread per site): initial populations, the
+// ion-density (charge) pass, the fused pull-stream + collide step and the
+// moment read-out.  The per-site bodies are in lb_site.h.
 #include "ek_internal.h"
-#include "reduce.h"
+#include "lb_site.h"
 #include "md_table.h"
+#include "reduce.h"
 
 namespace ek {
 
 namespace {
-
-struct Nbr {
-  long long zo[3], yo[3];
-  int xo[3];
-};
-
-// Offsets of the rows r - c: index [1 - c] selects minus, same, plus.
-__device__ inline Nbr neighbours(int x, int y, int z, const Dims& d) {
-  Nbr n;
-  const int xm = x == 0 ? d.nx - 1 : x - 1, xp = x == d.nx - 1 ? 0 : x + 1;
-  const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
-  const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
-  const long long nxy = (long long)d.nx * d.ny;
-  n.zo[0] = zm * nxy; n.zo[1] = z * nxy; n.zo[2] = zp * nxy;
-  n.yo[0] = (long long)ym * d.nx; n.yo[1] = (long long)y * d.nx; n.yo[2] = (long long)yp * d.nx;
-  n.xo[0] = xm; n.xo[1] = x; n.xo[2] = xp;
-  return n;
-}
-
-// Pull the 19 post-collision deviations of one species into a site.
-template <typename T>
-__device__ inline void pull(const T* __restrict__ f, int s, long long r, uint32_t m,
-                            const Nbr& nb, long long N, T (&g)[Q]) {
-#pragma unroll
-  for (int p = 0; p < Q; ++p) {
-    const bool bounce = (m >> p) & 1u;
-    const long long src = nb.zo[1 - CZ[p]] + nb.yo[1 - CY[p]] + nb.xo[1 - CX[p]];
-    const long long idx = bounce ? (size_t)(s * Q + OPP[p]) * N + r : (size_t)(s * Q + p) * N + src;
-    g[p] = f[idx];
-  }
-}
 
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_init_species(T* __restrict__ f,
@@ -90,25 +52,8 @@ __global__ __launch_bounds__(BLOCK) void k_charge(const T* __restrict__ f,
   const int nblocks = gridDim.x * gridDim.y * gridDim.z;
   double acc[1] = {0.0};
   if (x < d.nx && y < d.ny) {
-    const long long r = ((long long)z * d.ny + y) * d.nx + x;
-    const uint32_t m = mask[r];
-    double rho = 0.0;
-    if (m & MASK_CHARGED) rho += wall_q[r];
-    if (!(m & MASK_SOLID)) {
-      const Nbr nb = neighbours(x, y, z, d);
-#pragma unroll
-      for (int s = 0; s < 3; ++s) {
-        if (lp.valence[s] == 0.0) continue;
-        T g[Q];
-        pull(f, s, r, m, nb, d.n, g);
-        T dn = T(0);
-#pragma unroll
-        for (int p = 0; p < Q; ++p) dn += g[p];
-        rho += lp.valence[s] * (lp.nref[s] + double(dn));
-      }
-    }
-    if (m & MASK_BEAD) rho += bt.charge_at(r);
-    b[r] = -rho * inv_eps;
+    const double rho = charge_site(f, mask, wall_q, lp, bt, x, y, z, d);
+    b[((long long)z * d.ny + y) * d.nx + x] = -rho * inv_eps;
     acc[0] = rho;
   }
   block_partials<1>(acc, partials, bid, nblocks);
@@ -131,103 +76,7 @@ __global__ __launch_bounds__(BLOCK) void k_lb_step(const T* __restrict__ fsrc,
   const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   const int nblocks = gridDim.x * gridDim.y * gridDim.z;
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  if (x < d.nx && y < d.ny) {
-    const long long r = ((long long)z * d.ny + y) * d.nx + x;
-    const uint32_t m = mask[r];
-    if (!(m & MASK_SOLID)) {
-      const Nbr nb = neighbours(x, y, z, d);
-      T g[3][Q];
-#pragma unroll
-      for (int s = 0; s < 3; ++s) pull(fsrc, s, r, m, nb, d.n, g[s]);
-
-      // electric field E = -grad psi (central differences) + applied field
-      const T ex = T(-0.5 * (psi[nb.zo[1] + nb.yo[1] + nb.xo[2]] - psi[nb.zo[1] + nb.yo[1] + nb.xo[0]]) + lp.eext[0]);
-      const T ey = T(-0.5 * (psi[nb.zo[1] + nb.yo[2] + nb.xo[1]] - psi[nb.zo[1] + nb.yo[0] + nb.xo[1]]) + lp.eext[1]);
-      const T ez = T(-0.5 * (psi[nb.zo[2] + nb.yo[1] + nb.xo[1]] - psi[nb.zo[0] + nb.yo[1] + nb.xo[1]]) + lp.eext[2]);
-
-      double kb[3][3];
-      const bool has_bead = (m & MASK_BEAD) != 0;
-      if (has_bead) bt.force_at(r, kb);
-
-      // moments, force per particle G^a (without the drag) and
-      // b^a = j^a / n^a + G^a / 2
-      T n[3], dns[3], G[3][3], bv[3][3];
-#pragma unroll
-      for (int s = 0; s < 3; ++s) {
-        T dn = T(0), jx = T(0), jy = T(0), jz = T(0);
-#pragma unroll
-        for (int p = 0; p < Q; ++p) {
-          dn += g[s][p];
-          if (CX[p]) jx += CX[p] > 0 ? g[s][p] : -g[s][p];
-          if (CY[p]) jy += CY[p] > 0 ? g[s][p] : -g[s][p];
-          if (CZ[p]) jz += CZ[p] > 0 ? g[s][p] : -g[s][p];
-        }
-        n[s] = T(lp.nref[s]) + dn;
-        dns[s] = dn;
-        acc[s] = lp.nref[s] + double(dn);
-        acc[3] += double(jx); acc[4] += double(jy); acc[5] += double(jz);
-        const T zs = T(lp.valence[s]);
-        const T inv_n = T(1) / n[s];
-        G[s][0] = zs * ex + T(lp.fext[s][0]);
-        G[s][1] = zs * ey + T(lp.fext[s][1]);
-        G[s][2] = zs * ez + T(lp.fext[s][2]);
-        if (has_bead) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) G[s][c] += T(kb[s][c]) * inv_n;
-        }
-        bv[s][0] = jx * inv_n + T(0.5) * G[s][0];
-        bv[s][1] = jy * inv_n + T(0.5) * G[s][1];
-        bv[s][2] = jz * inv_n + T(0.5) * G[s][2];
-      }
-      // implicit drag in closed form: with a^a = omega_drag^a / 2,
-      // ubar = sum x^a b^a / (1 + a^a) / sum x^a / (1 + a^a),
-      // u^a = (b^a + a^a ubar) / (1 + a^a), Phi^a = G^a - omega_drag^a (u^a - ubar)
-      const T inv_ntot = T(1) / (n[0] + n[1] + n[2]);
-      T ub[3] = {T(0), T(0), T(0)};
-      T den = T(0);
-      T inv1a[3];
-#pragma unroll
-      for (int s = 0; s < 3; ++s) {
-        inv1a[s] = T(1) / (T(1) + T(0.5 * lp.wdrag[s]));
-        const T xs = n[s] * inv_ntot * inv1a[s];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) ub[c] += xs * bv[s][c];
-        den += xs;
-      }
-      const T inv_den = T(1) / den;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) ub[c] *= inv_den;
-
-#pragma unroll
-      for (int s = 0; s < 3; ++s) {
-        const T as = T(0.5 * lp.wdrag[s]);
-        const T wd = T(lp.wdrag[s]);
-        T u[3], ph[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          u[c] = (bv[s][c] + as * ub[c]) * inv1a[s];
-          ph[c] = G[s][c] - wd * (u[c] - ub[c]);
-        }
-        const T om = T(lp.omega[s]);
-        const T half = T(1) - T(0.5) * om;
-        const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-        const T pu = ph[0] * u[0] + ph[1] * u[1] + ph[2] * u[2];
-        const T ns = n[s];
-        const T dn = dns[s];  // kept from the sum: n - nref would lose it in float32
-#pragma unroll
-        for (int p = 0; p < Q; ++p) {
-          const T cu = T(CX[p]) * u[0] + T(CY[p]) * u[1] + T(CZ[p]) * u[2];
-          const T cf = T(CX[p]) * ph[0] + T(CY[p]) * ph[1] + T(CZ[p]) * ph[2];
-          const T w = T(weight(p));
-          // deviation of the second-order equilibrium (vT2 = 1/3) and forcing
-          const T geq = w * (dn + ns * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu));
-          const T src = w * ns * (T(3) * cf + T(9) * cu * cf - T(3) * pu);
-          const T gs = g[s][p] - om * (g[s][p] - geq) + half * src;
-          fdst[(size_t)(s * Q + p) * d.n + r] = gs;
-        }
-      }
-    }
-  }
+  if (x < d.nx && y < d.ny) lb_site(fsrc, fdst, mask, psi, lp, bt, x, y, z, d, acc);
   block_partials<6>(acc, partials, bid, nblocks);
 }
 

@@ -22,88 +22,14 @@
 #include <vector>
 
 #include "ek_context.h"
+#include "mg_site.h"
 
 using namespace ek;
 
 namespace {
 
-constexpr int NU1 = 2, NU2 = 2;
 constexpr size_t COARSE_LDS_BYTES = 40 * 1024;    // one-workgroup coarse cycle: levels of up to ~2k sites
 constexpr int COARSEST_SWEEPS = 40;
-constexpr int MAX_LEVELS = 16;
-
-struct Lvl {
-  int nx, ny, nz;
-  long long n;
-  double h2;
-  double* x;
-  double* f;
-};
-
-struct LvlSet {
-  Lvl l[MAX_LEVELS];
-  int count;
-};
-
-// q = t / d and t - q d for 0 <= t < 2^24 without an integer divide: the
-// float quotient is off by at most one, which the remainder test corrects.
-__device__ inline int fdivmod(int t, int d, float inv_d, int& rem) {
-  int q = int(float(t) * inv_d);
-  int r = t - q * d;
-  if (r < 0) { --q; r += d; }
-  else if (r >= d) { ++q; r -= d; }
-  rem = r;
-  return q;
-}
-
-__device__ inline int idx3(int x, int y, int z, const Lvl& L) {
-  return (z * L.ny + y) * L.nx + x;
-}
-
-__device__ inline double nbsum(const double* __restrict__ v, int x, int y, int z, const Lvl& L) {
-  const int xm = x == 0 ? L.nx - 1 : x - 1, xp = x == L.nx - 1 ? 0 : x + 1;
-  const int ym = y == 0 ? L.ny - 1 : y - 1, yp = y == L.ny - 1 ? 0 : y + 1;
-  const int zm = z == 0 ? L.nz - 1 : z - 1, zp = z == L.nz - 1 ? 0 : z + 1;
-  return v[idx3(xm, y, z, L)] + v[idx3(xp, y, z, L)] + v[idx3(x, ym, z, L)] +
-         v[idx3(x, yp, z, L)] + v[idx3(x, y, zm, L)] + v[idx3(x, y, zp, L)];
-}
-
-// --- per-site operations shared by the grid-wide and single-block kernels ---
-// (tx, y, z) enumerates the sites of one colour: nx/2 per row
-__device__ inline void smooth_site(const Lvl& L, int colour, int tx, int y, int z, double shift,
-                                   double omega = 1.0) {
-  const int x = 2 * tx + ((colour + y + z) & 1);
-  const int r = idx3(x, y, z, L);
-  const double gs = (nbsum(L.x, x, y, z, L) - L.h2 * (L.f[r] + shift)) * (1.0 / 6.0);
-  L.x[r] = omega == 1.0 ? gs : L.x[r] + omega * (gs - L.x[r]);
-}
-
-__device__ inline void restrict_site(const Lvl& F, const Lvl& C, int X, int Y, int Z, double shift) {
-  double s = 0.0;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int x = 2 * X + (k & 1), y = 2 * Y + ((k >> 1) & 1), z = 2 * Z + ((k >> 2) & 1);
-    const int r = idx3(x, y, z, F);
-    s += (F.f[r] + shift) - (nbsum(F.x, x, y, z, F) - 6.0 * F.x[r]) / F.h2;
-  }
-  const int t = idx3(X, Y, Z, C);
-  C.f[t] = 0.125 * s;
-  C.x[t] = 0.0;
-}
-
-__device__ inline void prolong_site(const Lvl& F, const Lvl& C, int x, int y, int z) {
-  const int X = x >> 1, Y = y >> 1, Z = z >> 1;
-  const int Xn = (x & 1) ? (X + 1 == C.nx ? 0 : X + 1) : (X == 0 ? C.nx - 1 : X - 1);
-  const int Yn = (y & 1) ? (Y + 1 == C.ny ? 0 : Y + 1) : (Y == 0 ? C.ny - 1 : Y - 1);
-  const int Zn = (z & 1) ? (Z + 1 == C.nz ? 0 : Z + 1) : (Z == 0 ? C.nz - 1 : Z - 1);
-  const double a = 0.75, b = 0.25;
-  const double v =
-      a * a * a * C.x[idx3(X, Y, Z, C)] + b * a * a * C.x[idx3(Xn, Y, Z, C)] +
-      a * b * a * C.x[idx3(X, Yn, Z, C)] + a * a * b * C.x[idx3(X, Y, Zn, C)] +
-      b * b * a * C.x[idx3(Xn, Yn, Z, C)] + b * a * b * C.x[idx3(Xn, Y, Zn, C)] +
-      a * b * b * C.x[idx3(X, Yn, Zn, C)] + b * b * b * C.x[idx3(Xn, Yn, Zn, C)];
-  F.x[idx3(x, y, z, F)] += v;
-}
 
 // --- grid-wide kernels for the fine levels (3-D launch: x, y from the block,
 // z = blockIdx.z, so no index division) ------------------------------------
@@ -133,22 +59,6 @@ __global__ __launch_bounds__(256) void k_prolong(Lvl F, Lvl C, const PoissonScal
   prolong_site(F, C, x, y, blockIdx.z);
 }
 
-// --- the coarse part of a V-cycle in one workgroup ----------------------------
-__device__ void block_smooth(const Lvl& L, int sweeps, double shift, double omega = 1.0) {
-  const int hx = L.nx / 2, nh = hx * L.ny * L.nz;
-  const float ihx = 1.0f / hx, iny = 1.0f / L.ny;
-  for (int s = 0; s < sweeps; ++s)
-    for (int colour = 0; colour < 2; ++colour) {
-      for (int t = threadIdx.x; t < nh; t += blockDim.x) {
-        int tx, y;
-        const int yz = fdivmod(t, hx, ihx, tx);
-        const int z = fdivmod(yz, L.ny, iny, y);
-        smooth_site(L, colour, tx, y, z, shift, omega);
-      }
-      __syncthreads();
-    }
-}
-
 // The coarse part of the cycle runs on copies of the coarse levels in LDS:
 // level `first` arrives with its right-hand side and a zero iterate in global
 // memory, its iterate goes back to global memory at the end.
@@ -176,27 +86,11 @@ __global__ __launch_bounds__(1024) void k_coarse_cycle(LvlSet set, int first,
   __syncthreads();
   for (int l = first; l < last; ++l) {
     block_smooth(L[l], NU1, 0.0);
-    const Lvl& C = L[l + 1];
-    const float inx = 1.0f / C.nx, iny = 1.0f / C.ny;
-    for (int t = threadIdx.x; t < int(C.n); t += blockDim.x) {
-      int X, Y;
-      const int yz = fdivmod(t, C.nx, inx, X);
-      const int Z = fdivmod(yz, C.ny, iny, Y);
-      restrict_site(L[l], C, X, Y, Z, 0.0);
-    }
-    __syncthreads();
+    block_restrict(L[l], L[l + 1], 0.0);
   }
   block_smooth(L[last], coarsest_sweeps, 0.0, omega_coarsest);
   for (int l = last - 1; l >= first; --l) {
-    const Lvl& F = L[l];
-    const float inx = 1.0f / F.nx, iny = 1.0f / F.ny;
-    for (int t = threadIdx.x; t < int(F.n); t += blockDim.x) {
-      int x, y;
-      const int yz = fdivmod(t, F.nx, inx, x);
-      const int z = fdivmod(yz, F.ny, iny, y);
-      prolong_site(F, L[l + 1], x, y, z);
-    }
-    __syncthreads();
+    block_prolong(L[l], L[l + 1]);
     block_smooth(L[l], NU2, 0.0);
   }
   for (int t = threadIdx.x; t < int(L[first].n); t += blockDim.x) set.l[first].x[t] = L[first].x[t];

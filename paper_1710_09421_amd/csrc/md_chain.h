@@ -1,0 +1,511 @@
+// Bead-spring chain coupled to the three species by friction (Sec. II.B)
+// through the trilinear interpolation / spreading kernel (Sec. II.C): state,
+// node table access and the per-step pieces, shared by the single-system
+// kernels and the persistent ensemble kernel.
+#pragma once
+
+#include <climits>
+#include <cmath>
+
+#include "ek_internal.h"
+#include "md_table.h"
+
+namespace ek {
+
+constexpr int BOX = 4;          // moment box edge (nodes floor(R0) - 1 .. floor(R0) + 2)
+constexpr int BOX3 = BOX * BOX * BOX;
+constexpr int WIN = 6;          // flag window edge (nodes floor(R0) - 2 .. floor(R0) + 3)
+constexpr int WIN3 = WIN * WIN * WIN;
+constexpr int MOM = 15;         // x[3] (n^a / n), 1/n^a [3], j[3][3]
+
+enum : int { ERR_BOX = 1, ERR_FLUID = 2, ERR_BOND = 4, ERR_TABLE = 8 };
+
+struct BeadState {
+  double* R;          // [maxb][3]
+  double* V;          // [maxb][3]
+  double* q;          // [maxb]
+  int* origin;        // [maxb][3] floor(R0) - 1 of the current step
+  double* mom;        // [maxb][BOX3][MOM]
+  double* efield;     // [maxb][BOX3][3]
+  unsigned char* flags;  // [maxb][WIN3]: bit0 fluid, bit1 wall
+  int* err;           // error bits
+};
+
+__device__ inline int wrap(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+__device__ inline long long site_of(int x, int y, int z, const Dims& d) {
+  return ((long long)wrap(z, d.nz) * d.ny + wrap(y, d.ny)) * d.nx + wrap(x, d.nx);
+}
+
+__device__ inline long long ld_i64(const long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline int ld_i32(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Find or insert `site`; flags the site for the lattice kernels.
+__device__ inline int table_insert(int* keys, uint32_t* mask, long long site, int* err, int bits) {
+  const int slots = 1 << bits;
+  int h = hash_slot(site, bits);
+  for (int k = 0; k < slots; ++k) {
+    const int prev = atomicCAS(&keys[h], -1, int(site));
+    if (prev == -1) {
+      atomicOr(&mask[site], MASK_BEAD);
+      return h;
+    }
+    if (prev == int(site)) return h;
+    h = (h + 1) & (slots - 1);
+  }
+  atomicOr(err, ERR_TABLE);
+  return -1;
+}
+
+// Slot of `site` if present (reads that see the atomics of this launch).
+__device__ inline int table_find(const int* keys, long long site, int bits) {
+  const int slots = 1 << bits;
+  int h = hash_slot(site, bits);
+  for (int k = 0; k < slots; ++k) {
+    const int key = ld_i32(&keys[h]);
+    if (key == int(site)) return h;
+    if (key < 0) return -1;
+    h = (h + 1) & (slots - 1);
+  }
+  return -1;
+}
+
+// Empty table (once, when the context is created: the workspace arrives
+// uninitialised).
+struct MDParams {
+  int n, n_sub;
+  double M, k_fene, R0, eps, sigma, gamma;
+  double Lx, Ly, Lz;
+};
+
+__device__ inline double min_image(double v, double L) { return v - L * rint(v / L); }
+
+// WCA force on a pair at squared distance r2 (factor multiplying the separation).
+__device__ inline double wca_coef(double r2, double eps, double sigma) {
+  const double rc2 = 1.2599210498948732 * sigma * sigma;   // (2^(1/6) sigma)^2
+  if (r2 >= rc2) return 0.0;
+  const double s2 = sigma * sigma / r2;
+  const double s6 = s2 * s2 * s2;
+  return 24.0 * eps * (2.0 * s6 * s6 - s6) / r2;
+}
+
+// Node accumulators for the friction impulse: the context's global table, or
+// (for chains of at most LDS_MAX_BEADS beads) a table in LDS that is flushed to
+// the global one once after the substeps.  Values are int64 fixed point, so
+// the sums are exact whatever the order of the additions.
+struct GlobalNodes {
+  int* keys;
+  long long* vals;
+  uint32_t* mask;
+  int* err;
+  int bits;
+  __device__ int slot(long long site) { return table_insert(keys, mask, site, err, bits); }
+  __device__ double get(int h, int c) const {
+    return double(ld_i64(&vals[(size_t)h * SLOT_VALUES + 1 + c])) * (1.0 / FIX_FORCE);
+  }
+  __device__ void add(int h, int c, long long v) {
+    atomicAdd((unsigned long long*)&vals[(size_t)h * SLOT_VALUES + 1 + c], (unsigned long long)v);
+  }
+};
+
+struct LdsNodes {
+  int* keys;          // LDS [slots]
+  long long* vals;    // LDS [slots][9]
+  int bits;
+  int* err;
+  __device__ int slot(long long site) {
+    const int n = 1 << bits;
+    int h = int(((unsigned long long)site * 0x9E3779B97F4A7C15ull) >> (64 - bits));
+    for (int k = 0; k < n; ++k) {
+      const int prev = atomicCAS(&keys[h], -1, int(site));
+      if (prev == -1 || prev == int(site)) return h;
+      h = (h + 1) & (n - 1);
+    }
+    atomicOr(err, ERR_TABLE);
+    return -1;
+  }
+  __device__ double get(int h, int c) const {
+    return double(vals[h * 9 + c]) * (1.0 / FIX_FORCE);
+  }
+  __device__ void add(int h, int c, long long v) {
+    atomicAdd((unsigned long long*)&vals[h * 9 + c], (unsigned long long)v);
+  }
+};
+
+constexpr int LDS_MAX_BEADS = 64;
+
+// One workgroup per chain, TPB threads per bead: the lanes of a bead split
+// its 8 corners, its pair partners and its wall sites, and combine their
+// parts with a butterfly over the TPB lanes (every lane ends with the same
+// bits, so all lanes advance the bead identically).
+template <int TPB>
+__device__ inline double group_sum(double v) {
+#pragma unroll
+  for (int m = 1; m < TPB; m <<= 1) v += __shfl_xor(v, m, TPB);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Per-step pieces written for a team of threads (tid, nthreads): a whole
+// grid of one-thread-per-item launches, or one workgroup.
+// ---------------------------------------------------------------------------
+
+// Drop a table's entries and their site flags.
+__device__ inline void table_clear_items(int* keys, long long* vals, uint32_t* mask, long long n,
+                                         int bits, int tid, int nthreads) {
+  for (int h = tid; h < (1 << bits); h += nthreads) {
+    const int key = keys[h];
+    if (key >= 0 && key < n) {
+      atomicAnd(&mask[key], ~MASK_BEAD);
+      keys[h] = -1;
+#pragma unroll
+      for (int c = 0; c < SLOT_VALUES; ++c) vals[(size_t)h * SLOT_VALUES + c] = 0;
+    }
+  }
+}
+
+// Bead charges on the 8 corner nodes with the plain trilinear weights.
+__device__ inline void deposit_items(const BeadState& bs, int n, int* keys, long long* vals,
+                                     uint32_t* mask, const Dims& d, int bits, int tid,
+                                     int nthreads) {
+  for (int t = tid; t < 8 * n; t += nthreads) {
+    const int i = t >> 3, k = t & 7;
+    const double* R = bs.R + 3 * i;
+    const double fx = floor(R[0]), fy = floor(R[1]), fz = floor(R[2]);
+    const double dx = R[0] - fx, dy = R[1] - fy, dz = R[2] - fz;
+    const int ox = k & 1, oy = (k >> 1) & 1, oz = (k >> 2) & 1;
+    const double w = (ox ? dx : 1.0 - dx) * (oy ? dy : 1.0 - dy) * (oz ? dz : 1.0 - dz);
+    const long long site = site_of(int(fx) + ox, int(fy) + oy, int(fz) + oz, d);
+    const int h = table_insert(keys, mask, site, bs.err, bits);
+    if (h < 0) continue;
+    atomicAdd((unsigned long long*)&vals[(size_t)h * SLOT_VALUES],
+              (unsigned long long)llrint(bs.q[i] * w * FIX_CHARGE));
+  }
+}
+
+// Fields of time t around bead i: item t < WIN3 sets the fluid / wall flags of
+// the 6^3 window, item t < BOX3 the moments and field of one node of the 4^3
+// box.  The box origin is written by item 0.
+template <typename T>
+__device__ inline void bead_box_item(const BeadState& bs, int i, int t, const T* __restrict__ f,
+                                     const uint32_t* __restrict__ mask,
+                                     const double* __restrict__ psi, const LBParams& lp,
+                                     const Dims& d) {
+  const double* R = bs.R + 3 * i;
+  const int bx = int(floor(R[0])) - 1, by = int(floor(R[1])) - 1, bz = int(floor(R[2])) - 1;
+  if (t == 0) {
+    bs.origin[3 * i] = bx;
+    bs.origin[3 * i + 1] = by;
+    bs.origin[3 * i + 2] = bz;
+  }
+  if (t < WIN3) {
+    const int wx = t % WIN, wy = (t / WIN) % WIN, wz = t / (WIN * WIN);
+    const uint32_t m = mask[site_of(bx - 1 + wx, by - 1 + wy, bz - 1 + wz, d)];
+    bs.flags[(size_t)i * WIN3 + t] =
+        (unsigned char)(((m & MASK_SOLID) ? 0 : 1) | ((m & MASK_WALL) ? 2 : 0));
+  }
+  if (t >= BOX3) return;
+  const int cx = bx + t % BOX, cy = by + (t / BOX) % BOX, cz = bz + t / (BOX * BOX);
+  const long long r = site_of(cx, cy, cz, d);
+  const uint32_t m = mask[r];
+  double* mo = bs.mom + ((size_t)i * BOX3 + t) * MOM;
+  for (int c = 0; c < MOM; ++c) mo[c] = 0.0;
+  if (!(m & MASK_SOLID)) {
+    const int x = wrap(cx, d.nx), y = wrap(cy, d.ny), z = wrap(cz, d.nz);
+    for (int s = 0; s < 3; ++s) {
+      double dn = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+      for (int p = 0; p < Q; ++p) {
+        long long src;
+        int q = p;
+        if ((m >> p) & 1u) {
+          src = r;
+          q = OPP[p];
+        } else {
+          src = site_of(x - CX[p], y - CY[p], z - CZ[p], d);
+        }
+        const double g = double(f[(size_t)(s * Q + q) * d.n + src]);
+        dn += g;
+        jx += CX[p] * g;
+        jy += CY[p] * g;
+        jz += CZ[p] * g;
+      }
+      mo[s] = lp.nref[s] + dn;        // density for now, fraction below
+      mo[6 + 3 * s] = jx;
+      mo[7 + 3 * s] = jy;
+      mo[8 + 3 * s] = jz;
+    }
+    const double ntot = mo[0] + mo[1] + mo[2];
+    for (int s = 0; s < 3; ++s) {
+      mo[3 + s] = 1.0 / mo[s];
+      mo[s] = mo[s] / ntot;
+    }
+  }
+  double* e = bs.efield + ((size_t)i * BOX3 + t) * 3;
+  e[0] = -0.5 * (psi[site_of(cx + 1, cy, cz, d)] - psi[site_of(cx - 1, cy, cz, d)]) + lp.eext[0];
+  e[1] = -0.5 * (psi[site_of(cx, cy + 1, cz, d)] - psi[site_of(cx, cy - 1, cz, d)]) + lp.eext[1];
+  e[2] = -0.5 * (psi[site_of(cx, cy, cz + 1, d)] - psi[site_of(cx, cy, cz - 1, d)]) + lp.eext[2];
+}
+
+// n_sub substeps of one chain by one workgroup (TPB lanes per bead; the
+// threads beyond n * TPB only take part in the barriers).  smem: LDS for the
+// bead positions and, when LDS is set, the node table of 2^lds_bits slots.
+template <bool LDS, int TPB>
+__device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gkeys,
+                                long long* gvals, uint32_t* mask, const Dims& d, int gbits,
+                                int lds_bits, unsigned char* smem) {
+  constexpr int CPL = 8 / TPB;                                 // corners per lane
+  double* sR = (double*)smem;                                  // [3 * n]
+  long long* lvals = (long long*)(smem + (((size_t)mp.n * 24 + 15) & ~size_t(15)));
+  const int lslots = LDS ? (1 << lds_bits) : 0;
+  int* lkeys = (int*)(lvals + (size_t)lslots * 9);
+
+  const int i = threadIdx.x / TPB;          // bead
+  const int lane = threadIdx.x % TPB;
+  const bool live = i < mp.n;
+  if (LDS) {
+    for (int h = threadIdx.x; h < lslots; h += blockDim.x) {
+      lkeys[h] = -1;
+      for (int c = 0; c < 9; ++c) lvals[(size_t)h * 9 + c] = 0;
+    }
+  }
+  double R[3] = {0, 0, 0}, V[3] = {0, 0, 0}, q = 0.0;
+  int org[3] = {0, 0, 0};
+  if (live) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      R[c] = bs.R[3 * i + c];
+      V[c] = bs.V[3 * i + c];
+      org[c] = bs.origin[3 * i + c];
+      if (lane == 0) sR[3 * i + c] = R[c];
+    }
+    q = bs.q[i];
+  }
+  __syncthreads();
+  GlobalNodes gn{gkeys, gvals, mask, bs.err, gbits};
+  LdsNodes ln{lkeys, lvals, lds_bits, bs.err};
+
+  const double h = 1.0 / mp.n_sub;
+  const double hM = h / mp.M;
+  const double L[3] = {mp.Lx, mp.Ly, mp.Lz};
+  const double iL[3] = {1.0 / mp.Lx, 1.0 / mp.Ly, 1.0 / mp.Lz};
+  const double rc2 = 1.2599210498948732 * mp.sigma * mp.sigma;   // (2^(1/6) sigma)^2
+  const double s2w = mp.sigma * mp.sigma;
+  const double iR02 = 1.0 / (mp.R0 * mp.R0);
+  const double* mom = bs.mom + (size_t)(live ? i : 0) * BOX3 * MOM;
+  const double* ef = bs.efield + (size_t)(live ? i : 0) * BOX3 * 3;
+  const unsigned char* fl = bs.flags + (size_t)(live ? i : 0) * WIN3;
+  int cell[3] = {INT_MIN, INT_MIN, INT_MIN};
+  int slot[CPL], bidx[CPL];
+  double wfl[CPL];
+  double fl_all[8];                 // fluid flag of every corner (for the normalisation)
+  for (int sub = 0; sub < mp.n_sub; ++sub) {
+    double wt[CPL];
+    double phi[3][3];
+    double Rn[3];
+#pragma unroll
+    for (int a = 0; a < CPL; ++a) wt[a] = 0.0;
+    if (live) {
+      const int fx = int(floor(R[0])), fy = int(floor(R[1])), fz = int(floor(R[2]));
+      const double dx = R[0] - fx, dy = R[1] - fy, dz = R[2] - fz;
+      int lx = fx - org[0], ly = fy - org[1], lz = fz - org[2];   // corner 0 in the box
+      if (fx != cell[0] || fy != cell[1] || fz != cell[2]) {
+        // the bead entered another cell: new corners, their box entries and slots
+        cell[0] = fx; cell[1] = fy; cell[2] = fz;
+        if (lx < 0 || lx > BOX - 2 || ly < 0 || ly > BOX - 2 || lz < 0 || lz > BOX - 2) {
+          if (lane == 0) atomicOr(bs.err, ERR_BOX);
+          lx = min(max(lx, 0), BOX - 2);
+          ly = min(max(ly, 0), BOX - 2);
+          lz = min(max(lz, 0), BOX - 2);
+        }
+#pragma unroll
+        for (int k8 = 0; k8 < 8; ++k8) {
+          const int ox = k8 & 1, oy = (k8 >> 1) & 1, oz = (k8 >> 2) & 1;
+          const int wi = (lx + ox + 1) + WIN * ((ly + oy + 1) + WIN * (lz + oz + 1));
+          fl_all[k8] = (fl[wi] & 1) ? 1.0 : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < CPL; ++a) {
+          const int k8 = lane * CPL + a;
+          const int ox = k8 & 1, oy = (k8 >> 1) & 1, oz = (k8 >> 2) & 1;
+          bidx[a] = (lx + ox) + BOX * ((ly + oy) + BOX * (lz + oz));
+          wfl[a] = fl_all[k8];
+          slot[a] = -1;
+          if (wfl[a] != 0.0) {
+            const long long site = site_of(fx + ox, fy + oy, fz + oz, d);
+            slot[a] = LDS ? ln.slot(site) : gn.slot(site);
+          }
+        }
+      }
+      // plain and fluid-renormalised trilinear weights
+      double wsum = 0.0;
+#pragma unroll
+      for (int k8 = 0; k8 < 8; ++k8) {
+        const int ox = k8 & 1, oy = (k8 >> 1) & 1, oz = (k8 >> 2) & 1;
+        wsum += fl_all[k8] * (ox ? dx : 1.0 - dx) * (oy ? dy : 1.0 - dy) * (oz ? dz : 1.0 - dz);
+      }
+      if (!(wsum > 0.0)) {
+        if (lane == 0) atomicOr(bs.err, ERR_FLUID);
+        wsum = 1.0;
+      }
+      const double iws = 1.0 / wsum;
+      // this lane's corners: velocities from the node momentum (populations of
+      // time t plus the friction impulse of earlier substeps), composition,
+      // electric field with the plain weights
+      double acc[15];
+#pragma unroll
+      for (int c = 0; c < 15; ++c) acc[c] = 0.0;
+#pragma unroll
+      for (int a = 0; a < CPL; ++a) {
+        const int k8 = lane * CPL + a;
+        const int ox = k8 & 1, oy = (k8 >> 1) & 1, oz = (k8 >> 2) & 1;
+        const double w = (ox ? dx : 1.0 - dx) * (oy ? dy : 1.0 - dy) * (oz ? dz : 1.0 - dz);
+        wt[a] = w * wfl[a] * iws;
+        const double* e = ef + (size_t)bidx[a] * 3;
+        acc[12] += w * e[0];
+        acc[13] += w * e[1];
+        acc[14] += w * e[2];
+        if (wt[a] != 0.0) {
+          const double* mo = mom + (size_t)bidx[a] * MOM;
+#pragma unroll
+          for (int s = 0; s < 3; ++s) {
+            acc[9 + s] += wt[a] * mo[s];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const double kacc = slot[a] < 0 ? 0.0 : (LDS ? ln.get(slot[a], 3 * s + c)
+                                                            : gn.get(slot[a], 3 * s + c));
+              acc[3 * s + c] += wt[a] * (mo[6 + 3 * s + c] + kacc) * mo[3 + s];
+            }
+          }
+        }
+      }
+      // this lane's share of the conservative forces
+      double F[3] = {0.0, 0.0, 0.0};
+      for (int j = lane; j < mp.n; j += TPB) {        // WCA between all pairs
+        if (j == i) continue;
+        double dv[3], r2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double v = R[c] - sR[3 * j + c];
+          dv[c] = v - L[c] * rint(v * iL[c]);
+          r2 += dv[c] * dv[c];
+        }
+        if (r2 < rc2) {
+          const double ir2 = 1.0 / r2;
+          const double s6 = s2w * ir2 * s2w * ir2 * s2w * ir2;
+          const double coef = 24.0 * mp.eps * (2.0 * s6 * s6 - s6) * ir2;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) F[c] += coef * dv[c];
+        }
+      }
+      for (int wsite = lane; wsite < 64; wsite += TPB) {   // WCA against wall-site centres
+        const int wx = wsite & 3, wy = (wsite >> 2) & 3, wz = wsite >> 4;
+        const int ax = fx - 1 + wx, ay = fy - 1 + wy, az = fz - 1 + wz;
+        const int ix = ax - org[0] + 1, iy = ay - org[1] + 1, iz = az - org[2] + 1;
+        if (ix < 0 || ix >= WIN || iy < 0 || iy >= WIN || iz < 0 || iz >= WIN) continue;
+        if (!(fl[ix + WIN * (iy + WIN * iz)] & 2)) continue;
+        const double dv[3] = {R[0] - ax, R[1] - ay, R[2] - az};
+        const double r2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
+        if (r2 < rc2) {
+          const double ir2 = 1.0 / r2;
+          const double s6 = s2w * ir2 * s2w * ir2 * s2w * ir2;
+          const double coef = 24.0 * mp.eps * (2.0 * s6 * s6 - s6) * ir2;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) F[c] += coef * dv[c];
+        }
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int nb = -1; nb <= 1; nb += 2) {        // FENE bonds
+          const int j = i + nb;
+          if (j < 0 || j >= mp.n) continue;
+          double dv[3], r2 = 0.0;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double v = sR[3 * j + c] - R[c];
+            dv[c] = v - L[c] * rint(v * iL[c]);
+            r2 += dv[c] * dv[c];
+          }
+          const double x2 = r2 * iR02;
+          if (x2 >= 1.0) {
+            atomicOr(bs.err, ERR_BOND);
+            continue;
+          }
+          const double coef = mp.k_fene / (1.0 - x2);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) F[c] += coef * dv[c];
+        }
+      }
+      // combine the lanes of this bead
+#pragma unroll
+      for (int c = 0; c < 15; ++c) acc[c] = group_sum<TPB>(acc[c]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) F[c] = group_sum<TPB>(F[c]) + q * acc[12 + c];
+      // friction of each species and the substep update
+      double ftot[3] = {F[0], F[1], F[2]};
+#pragma unroll
+      for (int s = 0; s < 3; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          phi[s][c] = mp.gamma * acc[9 + s] * (acc[3 * s + c] - V[c]);
+          ftot[c] += phi[s][c];
+        }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        V[c] += hM * ftot[c];
+        Rn[c] = R[c] + h * V[c];
+      }
+    }
+    __syncthreads();   // every bead has read positions and node momenta of this substep
+    if (live) {
+#pragma unroll
+      for (int a = 0; a < CPL; ++a) {
+        if (wt[a] == 0.0 || slot[a] < 0) continue;
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const long long v = llrint(-h * phi[s][c] * wt[a] * FIX_FORCE);
+            if (LDS) ln.add(slot[a], 3 * s + c, v);
+            else gn.add(slot[a], 3 * s + c, v);
+          }
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        R[c] = Rn[c];
+        if (lane == 0) sR[3 * i + c] = Rn[c];
+      }
+    }
+    if (!LDS) __threadfence();
+    __syncthreads();
+  }
+  if (live && lane == 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      bs.R[3 * i + c] = R[c];
+      bs.V[3 * i + c] = V[c];
+    }
+  }
+  if (LDS) {   // hand the accumulated impulses to the lattice kernels
+    __syncthreads();
+    for (int hh = threadIdx.x; hh < lslots; hh += blockDim.x) {
+      const int key = lkeys[hh];
+      if (key < 0) continue;
+      const int g = table_insert(gkeys, mask, key, bs.err, gbits);
+      if (g < 0) continue;
+      for (int c = 0; c < 9; ++c) {
+        const long long v = lvals[(size_t)hh * 9 + c];
+        if (v) atomicAdd((unsigned long long*)&gvals[(size_t)g * SLOT_VALUES + 1 + c], (unsigned long long)v);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace ek

@@ -14,24 +14,26 @@
 
 namespace ek {
 
-__host__ __device__ inline int hash_slot(long long r) {
-  return int(((unsigned long long)r * 0x9E3779B97F4A7C15ull) >> (64 - HASH_BITS));
+__host__ __device__ inline int hash_slot(long long r, int bits) {
+  return int(((unsigned long long)r * 0x9E3779B97F4A7C15ull) >> (64 - bits));
 }
 
 // Slot layout: charge, then K[species][xyz] (9 values), all int64 fixed point.
 constexpr int SLOT_VALUES = 10;
 
 struct BeadTableView {
-  const int* keys = nullptr;               // HASH_SLOTS keys, -1 = empty
-  const long long* vals = nullptr;         // [HASH_SLOTS][SLOT_VALUES]
+  const int* keys = nullptr;               // 2^bits keys, -1 = empty
+  const long long* vals = nullptr;         // [2^bits][SLOT_VALUES]
+  int bits = HASH_BITS;
 
   __device__ int find(long long r) const {
-    int h = hash_slot(r);
-    for (int k = 0; k < HASH_SLOTS; ++k) {
+    const int slots = 1 << bits;
+    int h = hash_slot(r, bits);
+    for (int k = 0; k < slots; ++k) {
       const int key = keys[h];
       if (key == int(r)) return h;
       if (key < 0) return -1;
-      h = (h + 1) & (HASH_SLOTS - 1);
+      h = (h + 1) & (slots - 1);
     }
     return -1;
   }

@@ -1,0 +1,130 @@
+// Multigrid level description and per-site operations, shared by the
+// grid-wide multigrid kernels and the persistent ensemble kernel.
+//   level l, spacing h = 2^l:  (sum of 6 neighbours - 6 x) / h^2 = f_l
+//   smoother     red-black Gauss-Seidel (optionally over-relaxed)
+//   restriction  f_{l+1} = average of the 8 fine residuals; zeroes x_{l+1}
+//   prolongation trilinear cell-centred interpolation (3/4, 1/4 per axis)
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ek_internal.h"
+
+namespace ek {
+
+constexpr int NU1 = 2, NU2 = 2;
+constexpr int MAX_LEVELS = 16;
+
+struct Lvl {
+  int nx, ny, nz;
+  long long n;
+  double h2;
+  double* x;
+  double* f;
+};
+
+struct LvlSet {
+  Lvl l[MAX_LEVELS];
+  int count;
+};
+
+// q = t / d and t - q d for 0 <= t < 2^24 without an integer divide: the
+// float quotient is off by at most one, which the remainder test corrects.
+__device__ inline int fdivmod(int t, int d, float inv_d, int& rem) {
+  int q = int(float(t) * inv_d);
+  int r = t - q * d;
+  if (r < 0) { --q; r += d; }
+  else if (r >= d) { ++q; r -= d; }
+  rem = r;
+  return q;
+}
+
+__device__ inline int idx3(int x, int y, int z, const Lvl& L) {
+  return (z * L.ny + y) * L.nx + x;
+}
+
+__device__ inline double nbsum(const double* __restrict__ v, int x, int y, int z, const Lvl& L) {
+  const int xm = x == 0 ? L.nx - 1 : x - 1, xp = x == L.nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? L.ny - 1 : y - 1, yp = y == L.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? L.nz - 1 : z - 1, zp = z == L.nz - 1 ? 0 : z + 1;
+  return v[idx3(xm, y, z, L)] + v[idx3(xp, y, z, L)] + v[idx3(x, ym, z, L)] +
+         v[idx3(x, yp, z, L)] + v[idx3(x, y, zm, L)] + v[idx3(x, y, zp, L)];
+}
+
+// --- per-site operations shared by the grid-wide and single-block kernels ---
+// (tx, y, z) enumerates the sites of one colour: nx/2 per row
+__device__ inline void smooth_site(const Lvl& L, int colour, int tx, int y, int z, double shift,
+                                   double omega = 1.0) {
+  const int x = 2 * tx + ((colour + y + z) & 1);
+  const int r = idx3(x, y, z, L);
+  const double gs = (nbsum(L.x, x, y, z, L) - L.h2 * (L.f[r] + shift)) * (1.0 / 6.0);
+  L.x[r] = omega == 1.0 ? gs : L.x[r] + omega * (gs - L.x[r]);
+}
+
+__device__ inline void restrict_site(const Lvl& F, const Lvl& C, int X, int Y, int Z, double shift) {
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int x = 2 * X + (k & 1), y = 2 * Y + ((k >> 1) & 1), z = 2 * Z + ((k >> 2) & 1);
+    const int r = idx3(x, y, z, F);
+    s += (F.f[r] + shift) - (nbsum(F.x, x, y, z, F) - 6.0 * F.x[r]) / F.h2;
+  }
+  const int t = idx3(X, Y, Z, C);
+  C.f[t] = 0.125 * s;
+  C.x[t] = 0.0;
+}
+
+__device__ inline void prolong_site(const Lvl& F, const Lvl& C, int x, int y, int z) {
+  const int X = x >> 1, Y = y >> 1, Z = z >> 1;
+  const int Xn = (x & 1) ? (X + 1 == C.nx ? 0 : X + 1) : (X == 0 ? C.nx - 1 : X - 1);
+  const int Yn = (y & 1) ? (Y + 1 == C.ny ? 0 : Y + 1) : (Y == 0 ? C.ny - 1 : Y - 1);
+  const int Zn = (z & 1) ? (Z + 1 == C.nz ? 0 : Z + 1) : (Z == 0 ? C.nz - 1 : Z - 1);
+  const double a = 0.75, b = 0.25;
+  const double v =
+      a * a * a * C.x[idx3(X, Y, Z, C)] + b * a * a * C.x[idx3(Xn, Y, Z, C)] +
+      a * b * a * C.x[idx3(X, Yn, Z, C)] + a * a * b * C.x[idx3(X, Y, Zn, C)] +
+      b * b * a * C.x[idx3(Xn, Yn, Z, C)] + b * a * b * C.x[idx3(Xn, Y, Zn, C)] +
+      a * b * b * C.x[idx3(X, Yn, Zn, C)] + b * b * b * C.x[idx3(Xn, Yn, Zn, C)];
+  F.x[idx3(x, y, z, F)] += v;
+}
+
+// --- the coarse part of a V-cycle in one workgroup ----------------------------
+__device__ inline void block_smooth(const Lvl& L, int sweeps, double shift, double omega = 1.0) {
+  const int hx = L.nx / 2, nh = hx * L.ny * L.nz;
+  const float ihx = 1.0f / hx, iny = 1.0f / L.ny;
+  for (int s = 0; s < sweeps; ++s)
+    for (int colour = 0; colour < 2; ++colour) {
+      for (int t = threadIdx.x; t < nh; t += blockDim.x) {
+        int tx, y;
+        const int yz = fdivmod(t, hx, ihx, tx);
+        const int z = fdivmod(yz, L.ny, iny, y);
+        smooth_site(L, colour, tx, y, z, shift, omega);
+      }
+      __syncthreads();
+    }
+}
+
+// Restriction and prolongation of a whole level by one workgroup.
+__device__ inline void block_restrict(const Lvl& F, const Lvl& C, double shift) {
+  const float inx = 1.0f / C.nx, iny = 1.0f / C.ny;
+  for (int t = threadIdx.x; t < int(C.n); t += blockDim.x) {
+    int X, Y;
+    const int yz = fdivmod(t, C.nx, inx, X);
+    const int Z = fdivmod(yz, C.ny, iny, Y);
+    restrict_site(F, C, X, Y, Z, shift);
+  }
+  __syncthreads();
+}
+
+__device__ inline void block_prolong(const Lvl& F, const Lvl& C) {
+  const float inx = 1.0f / F.nx, iny = 1.0f / F.ny;
+  for (int t = threadIdx.x; t < int(F.n); t += blockDim.x) {
+    int x, y;
+    const int yz = fdivmod(t, F.nx, inx, x);
+    const int z = fdivmod(yz, F.ny, iny, y);
+    prolong_site(F, C, x, y, z);
+  }
+  __syncthreads();
+}
+
+}  // namespace ek

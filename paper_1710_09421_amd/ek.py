@@ -49,6 +49,10 @@ class ek_timing(ctypes.Structure):
                 ("poisson_iters", c_int64)]
 
 
+class ek_tune_result(ctypes.Structure):
+    _fields_ = [("threads", c_int32), ("ms_per_step", c_double)]
+
+
 class ek_poisson_report(ctypes.Structure):
     _fields_ = [("iterations", c_int32), ("residual", c_double), ("initial_residual", c_double)]
 
@@ -82,6 +86,21 @@ def _load():
         "ek_poisson_sor_iterations": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32]),
         "ek_set_timing": (c_int32, [c_void_p, c_int32]),
         "ek_get_timing": (c_int32, [c_void_p, P(ek_timing)]),
+        "ek_ensemble_workspace_bytes": (c_int32, [P(ek_params), c_int32, c_int32, P(c_size_t)]),
+        "ek_ensemble_create": (c_int32, [P(ek_params), c_int32, c_int32, c_void_p, c_size_t, c_void_p,
+                                         P(c_void_p)]),
+        "ek_ensemble_destroy": (None, [c_void_p]),
+        "ek_ensemble_last_error": (ctypes.c_char_p, [c_void_p]),
+        "ek_ensemble_set_geometry": (c_int32, [c_void_p, c_void_p, c_void_p]),
+        "ek_ensemble_set_replica": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_void_p,
+                                              c_void_p, c_void_p, P(ek_polymer_params)]),
+        "ek_ensemble_step": (c_int32, [c_void_p, c_int32]),
+        "ek_ensemble_get_moments": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
+        "ek_ensemble_get_potential": (c_int32, [c_void_p, c_int32, c_void_p]),
+        "ek_ensemble_get_beads": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+        "ek_ensemble_get_stats": (c_int32, [c_void_p, c_int32, P(ek_stats)]),
+        "ek_ensemble_set_threads": (c_int32, [c_void_p, c_int32]),
+        "ek_ensemble_autotune": (c_int32, [c_void_p, c_int32, P(ek_tune_result)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -255,3 +274,124 @@ def from_workload(wl, precision=EK_FP32, poisson_method=EK_POISSON_SOR, poisson_
                         R0=pp["R0"], eps=pp["eps"], sigma=pp["sigma"], gamma=pp["gamma"],
                         n_sub=pp["n_sub"])
     return ctx
+
+
+class Ensemble:
+    """Replicas of one geometry advanced by one persistent launch per step call."""
+
+    def __init__(self, params, n_rep, max_beads=0, stream=None):
+        import torch
+        self._lib = lib()
+        self.params = params
+        self.n_rep = n_rep
+        self.shape = (params.nz, params.ny, params.nx)
+        self.n_beads = [0] * n_rep
+        nbytes = c_size_t()
+        self._check(self._lib.ek_ensemble_workspace_bytes(byref(params), n_rep, max_beads,
+                                                          byref(nbytes)), None)
+        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device="cuda")
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = c_void_p()
+        self._check(self._lib.ek_ensemble_create(byref(params), n_rep, max_beads,
+                                                 c_void_p(base + off), nbytes.value,
+                                                 c_void_p(self.stream.cuda_stream), byref(h)), None)
+        self._h = h
+
+    def _check(self, st, h):
+        if st != EK_OK:
+            msg = self._lib.ek_ensemble_last_error(h)
+            raise EKError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ek_ensemble_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_geometry(self, solid, wall_q=None):
+        s = np.ascontiguousarray(solid, dtype=np.uint8).reshape(self.shape)
+        w = None if wall_q is None else np.ascontiguousarray(wall_q, dtype=np.float64).reshape(self.shape)
+        self._check(self._lib.ek_ensemble_set_geometry(self._h, _ptr(s), None if w is None else _ptr(w)),
+                    self._h)
+
+    def set_replica(self, r, E_ext, n0, pos=None, vel=None, charge=None, M=1.0, k_fene=30.0, R0=1.5,
+                    eps=1.0, sigma=1.0, gamma=20.0, n_sub=40):
+        E = np.ascontiguousarray(E_ext, dtype=np.float64)
+        n = np.ascontiguousarray(n0, dtype=np.float64).reshape((3,) + self.shape)
+        nb = 0 if pos is None else int(np.asarray(pos).shape[0])
+        args = [None, None, None, None]
+        if nb:
+            pos = np.ascontiguousarray(pos, dtype=np.float64)
+            vel = np.ascontiguousarray(vel, dtype=np.float64)
+            q = np.ascontiguousarray(charge, dtype=np.float64)
+            pp = ek_polymer_params(M, k_fene, R0, eps, sigma, gamma, n_sub)
+            args = [_ptr(pos), _ptr(vel), _ptr(q), byref(pp)]
+        self._check(self._lib.ek_ensemble_set_replica(self._h, r, _ptr(E), _ptr(n), nb, *args),
+                    self._h)
+        self.n_beads[r] = nb
+
+    def step(self, n=1):
+        self._check(self._lib.ek_ensemble_step(self._h, n), self._h)
+
+    def set_threads(self, threads):
+        self._check(self._lib.ek_ensemble_set_threads(self._h, threads), self._h)
+
+    def autotune(self, steps=2):
+        res = ek_tune_result()
+        self._check(self._lib.ek_ensemble_autotune(self._h, steps, byref(res)), self._h)
+        return dict(threads=res.threads, ms_per_step=res.ms_per_step)
+
+    def moments(self, r, species):
+        n = np.empty(self.shape)
+        u = np.empty((3,) + self.shape)
+        self._check(self._lib.ek_ensemble_get_moments(self._h, r, species, _ptr(n), _ptr(u)), self._h)
+        return n, u
+
+    def potential(self, r):
+        psi = np.empty(self.shape)
+        self._check(self._lib.ek_ensemble_get_potential(self._h, r, _ptr(psi)), self._h)
+        return psi
+
+    def beads(self, r):
+        nb = self.n_beads[r]
+        pos = np.empty((nb, 3))
+        vel = np.empty((nb, 3))
+        if nb:
+            self._check(self._lib.ek_ensemble_get_beads(self._h, r, _ptr(pos), _ptr(vel)), self._h)
+        return pos, vel
+
+    def stats(self, r):
+        s = ek_stats()
+        self._check(self._lib.ek_ensemble_get_stats(self._h, r, byref(s)), self._h)
+        return dict(mass=np.array(s.mass[:]), momentum=np.array(s.momentum[:]), step=s.step,
+                    poisson_iters=s.poisson_iters, poisson_residual=s.poisson_residual)
+
+
+def ensemble_from_workloads(wls, precision=EK_FP32, poisson_tol=1e-8, poisson_max_iter=200,
+                            max_beads=None):
+    """Ensemble whose replicas are the given workloads (same geometry)."""
+    w0 = wls[0]
+    for w in wls:
+        assert w.shape == w0.shape and np.array_equal(w.solid, w0.solid), "replicas share the geometry"
+    nb = [0 if w.beads_R is None else w.beads_R.shape[0] for w in wls]
+    p = make_params(w0.shape, precision=precision, valence=w0.valence, tau=w0.tau,
+                    omega_drag=w0.omega_drag, bjerrum=w0.bjerrum, poisson_method=EK_POISSON_MG,
+                    poisson_tol=poisson_tol, poisson_max_iter=poisson_max_iter)
+    ens = Ensemble(p, len(wls), max_beads=max(nb) if max_beads is None else max_beads)
+    ens.set_geometry(w0.solid, w0.wall_q)
+    for r, w in enumerate(wls):
+        if nb[r]:
+            pp = w.polymer
+            ens.set_replica(r, w.E_ext, w.n0, w.beads_R, w.beads_V, pp["q"], M=pp["M"],
+                            k_fene=pp["k_fene"], R0=pp["R0"], eps=pp["eps"], sigma=pp["sigma"],
+                            gamma=pp["gamma"], n_sub=pp["n_sub"])
+        else:
+            ens.set_replica(r, w.E_ext, w.n0)
+    return ens

@@ -86,7 +86,8 @@ typedef struct {
   int32_t poisson_check_every; /* residual test every k iterations (>= 1)      */
   double rho_jacobi;           /* Jacobi radius for the Chebyshev schedule;
                                   0 selects (2 + cos(2 pi / max(n))) / 3       */
-  int32_t warm_start;          /* EK_WS_ZERO, EK_WS_PREV or EK_WS_LEARNED      */
+  int32_t warm_start;          /* EK_WS_ZERO, EK_WS_PREV or EK_WS_LEARNED
+                                  (ek_set_model; sizes multiples of 4)  */
   uint64_t seed;               /* thermal noise seed (noise is not built yet)  */
   int32_t fluctuations;        /* must be 0                                    */
 } ek_params;
@@ -190,6 +191,78 @@ typedef struct {
 /* enable != 0 starts (and zeroes) the per-phase timers; 0 stops them. */
 ek_status ek_set_timing(struct ek_ctx* ctx, int32_t enable);
 ek_status ek_get_timing(struct ek_ctx* ctx, ek_timing* out);
+
+/* ---------------------------------------------------------------------------
+ * Learned warm start of the Poisson solve.  The paper solves Eq. poisson
+ * iteratively from scratch or from the previous step (Sec. II.C); this library
+ * adds a small 3-D convolutional network N that guesses the solution, which
+ * the iterative solver then finishes to the same tolerance.  With
+ * b' = b - mean(b) and s the RMS of b', the guess is
+ *     psi0 = s * out_scale * N(b' / s, solid)
+ * (the Poisson equation is linear, so one network serves every charge scale).
+ * N: 3x3x3 conv 2->16, ReLU, 2x2x2 average pool, 3x3x3 conv 16->32, ReLU,
+ * pool, 3x3x3 conv 32->64, ReLU, 1x1x1 conv 64->32, nearest upsample plus the
+ * 32-channel activation, ReLU, 1x1x1 conv 32->16, upsample plus the
+ * 16-channel activation, ReLU, 3x3x3 conv 16->1; all convolutions periodic,
+ * bfloat16 activations, float32 accumulation on the matrix cores.
+ * Parameters: EK_UNET_PARAMS float32 values, per layer in the order above the
+ * weights [taps][c_in][c_out] (tap = (dz+1)*9 + (dy+1)*3 + (dx+1) for output
+ * site r reading input site r + (dx, dy, dz)) followed by the bias [c_out].
+ * Lattice sizes must be multiples of 4.
+ * ------------------------------------------------------------------------- */
+#define EK_UNET_PARAMS 73137
+
+/* Use a trained network in a context created with warm_start =
+ * EK_WS_LEARNED (else EK_ESTATE).  Each solve then evaluates the residual of
+ * the previous solution (or of the start passed to ek_poisson_solve) and of
+ * the network's guess and starts from the smaller one; ek_stats.fallback is 1
+ * when the guess was rejected.  host params[EK_UNET_PARAMS]; out_scale > 0. */
+ek_status ek_set_model(struct ek_ctx* ctx, const float* params, int32_t n, float out_scale);
+
+/* The last solved system: dev_rhs[nz*ny*nx] receives its right-hand side b
+ * with the mean removed, dev_psi[nz*ny*nx] its solution (mean zero); float64
+ * device buffers, either may be NULL.  EK_ESTATE before the first solve.
+ * Training pairs for the network are read this way. */
+ek_status ek_get_poisson_system(struct ek_ctx* ctx, double* dev_rhs, double* dev_psi);
+
+/* Stand-alone network on caller-owned device buffers (training and tests). */
+typedef struct ek_unet ek_unet;
+
+/* Device workspace for an nx*ny*nz lattice; training != 0 adds the backward
+ * activations, the gradient and the Adam moments. */
+ek_status ek_unet_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t training,
+                                  size_t* bytes);
+/* dev_ws as in ek_create (NULL: the library allocates it). */
+ek_status ek_unet_create(int32_t nx, int32_t ny, int32_t nz, int32_t training, void* dev_ws,
+                         size_t ws_bytes, void* hip_stream, ek_unet** out);
+void ek_unet_destroy(ek_unet* net);
+const char* ek_unet_last_error(const ek_unet* net);
+
+/* Parameters from host memory; also clears the gradient and Adam moments. */
+ek_status ek_unet_set_params(ek_unet* net, const float* params, int32_t n, float out_scale);
+ek_status ek_unet_get_params(ek_unet* net, float* params, int32_t n, float* out_scale);
+
+/* dev_guess = s * out_scale * N((dev_b - mean) / s, dev_solid): dev_b and
+ * dev_guess float64, dev_solid one byte per site (nonzero = solid). */
+ek_status ek_unet_forward(ek_unet* net, const double* dev_b, const uint8_t* dev_solid,
+                          double* dev_guess);
+
+/* Forward pass, loss L = mean over sites of (N(...) - target / (s *
+ * out_scale))^2 and backward pass; dL/dparams is ADDED to the gradient and L
+ * to the loss accumulator.  Enqueued only (no synchronisation). */
+ek_status ek_unet_accumulate(ek_unet* net, const double* dev_b, const uint8_t* dev_solid,
+                             const double* dev_target);
+ek_status ek_unet_get_gradient(ek_unet* net, float* grad, int32_t n);
+ek_status ek_unet_zero_gradient(ek_unet* net);
+
+/* One Adam step (Kingma and Ba) with gradient grad_scale * accumulated
+ * gradient, which is then cleared.  Enqueued only. */
+ek_status ek_unet_adam_step(ek_unet* net, float lr, float beta1, float beta2, float eps,
+                            float grad_scale);
+
+/* Mean of the losses accumulated since the last read, and their count;
+ * resets the accumulator. */
+ek_status ek_unet_read_loss(ek_unet* net, double* mean_loss, int64_t* count);
 
 /* ---------------------------------------------------------------------------
  * Ensemble: uneven replicas of one geometry (translocation replicas with their

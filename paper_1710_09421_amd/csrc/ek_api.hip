@@ -47,13 +47,17 @@ ek_status check_params(const ek_params* p, std::string& why) {
   }
   if (p->rho_jacobi < 0.0 || p->rho_jacobi >= 1.0) { why = "rho_jacobi must be in [0, 1)"; return EK_EINVAL; }
   if (p->warm_start < EK_WS_ZERO || p->warm_start > EK_WS_LEARNED) { why = "unknown warm_start"; return EK_EINVAL; }
+  if (p->warm_start == EK_WS_LEARNED && !UNet::shape_ok(p->nx, p->ny, p->nz)) {
+    why = "the learned warm start needs nx, ny, nz divisible by 4 (two 2x2x2 poolings)";
+    return EK_EINVAL;
+  }
   if (p->fluctuations != 0) { why = "thermal fluctuations are not available"; return EK_EINVAL; }
   return EK_OK;
 }
 
 // Workspace layout (every block 256-byte aligned).
 struct Layout {
-  size_t fA, fB, mask, wall_q, psi, b, partials, ps, stats, keys, vals, beads, mg, total;
+  size_t fA, fB, mask, wall_q, psi, b, partials, ps, stats, keys, vals, beads, mg, net, guess, total;
 };
 
 Layout make_layout(const ek_params* p, int max_beads) {
@@ -76,6 +80,9 @@ Layout make_layout(const ek_params* p, int max_beads) {
   L.vals = take((size_t)HASH_SLOTS * 10 * 8);
   L.beads = take(bead_state_bytes(max_beads));
   L.mg = take(mg_workspace_bytes(p->nx, p->ny, p->nz));
+  const bool learned = p->warm_start == EK_WS_LEARNED;
+  L.net = take(learned ? UNet::bytes(p->nx, p->ny, p->nz, false) : 0);
+  L.guess = take(learned ? n * 8 : 0);
   L.total = off;
   return L;
 }
@@ -131,16 +138,13 @@ ek_status ek_ctx::read_scalars(PoissonScalars* out) {
 // is already in ps).  The residual is tested after every `check_every`
 // iterations; iterations are enqueued in batches ahead of the test and turn
 // into no-ops once the device-side flag is set.
-ek_status ek_ctx::sor_solve(const double* bb, double* x, int& iters, double& res, double& res0) {
+ek_status ek_ctx::sor_solve(const double* bb, double* x, PoissonScalars h, int& iters, double& res,
+                           double& res0) {
   const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
   const SiteGrid cg = colour_grid(p.nx, p.ny, p.nz, bx_colour);
   const int nb = g.nblocks();
   const double rj = jacobi_radius();
-  launch_residual(x, bb, ps, partials, dims, g, stream);
-  launch_residual_final(partials, nb, p.poisson_tol, 0, 1, ps, stream);
-  PoissonScalars h{};
-  ek_status st = read_scalars(&h);
-  if (st) return st;
+  ek_status st = EK_OK;
   int it = 0;
   double omega = 1.0;
   bool first = true;
@@ -178,9 +182,53 @@ ek_status ek_ctx::sor_solve(const double* bb, double* x, int& iters, double& res
   return EK_OK;
 }
 
-ek_status ek_ctx::poisson(const double* bb, double* x, int& iters, double& res, double& res0) {
-  if (p.poisson_method == EK_POISSON_MG) return mg_solve(bb, x, iters, res, res0);
-  return sor_solve(bb, x, iters, res, res0);
+ek_status ek_ctx::initial_residual(const double* bb, const double* x, PoissonScalars* h) {
+  const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
+  launch_residual(x, bb, ps, partials, dims, g, stream);
+  launch_residual_final(partials, g.nblocks(), p.poisson_tol, 0, 1, ps, stream);
+  return read_scalars(h);
+}
+
+// Learned warm start with fallback: the residuals of the current start x
+// (previous step, or what the caller passed) and of the network's guess are
+// evaluated with one synchronisation; the better start is kept in x and its
+// residual state stays in ps.  A non-finite guess residual always falls back.
+ek_status ek_ctx::learned_start(const double* bb, double* x, PoissonScalars* h) {
+  ek_ctx* ctx = this;
+  const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
+  const int nb = g.nblocks();
+  const size_t hs = sizeof(PoissonScalars);
+  launch_residual(x, bb, ps, partials, dims, g, stream);
+  launch_residual_final(partials, nb, p.poisson_tol, 0, 1, ps, stream);
+  EK_HIP(hipMemcpyAsync(pinned, ps, hs, hipMemcpyDeviceToHost, stream));
+  launch_ps_rearm(ps, stream);
+  net->forward(bb, mask, true, guess);
+  launch_residual(guess, bb, ps, partials, dims, g, stream);
+  launch_residual_final(partials, nb, p.poisson_tol, 0, 1, ps, stream);
+  EK_HIP(hipMemcpyAsync((char*)pinned + 512, ps, hs, hipMemcpyDeviceToHost, stream));
+  ek_status st = sync();
+  if (st) return st;
+  PoissonScalars hp, hl;
+  std::memcpy(&hp, pinned, hs);
+  std::memcpy(&hl, (char*)pinned + 512, hs);
+  if (hl.rel < hp.rel) {
+    EK_HIP(hipMemcpyAsync(x, guess, dims.n * 8, hipMemcpyDeviceToDevice, stream));
+    *h = hl;
+    last_fallback = 0;
+    return EK_OK;
+  }
+  last_fallback = 1;
+  launch_ps_rearm(ps, stream);
+  return initial_residual(bb, x, h);
+}
+
+ek_status ek_ctx::poisson(const double* bb, double* x, bool learned, int& iters, double& res,
+                          double& res0) {
+  PoissonScalars h{};
+  ek_status st = learned ? learned_start(bb, x, &h) : initial_residual(bb, x, &h);
+  if (st) return st;
+  if (p.poisson_method == EK_POISSON_MG) return mg_solve(bb, x, h, iters, res, res0);
+  return sor_solve(bb, x, h, iters, res, res0);
 }
 
 ek_status ek_ctx::ensure_events(int n_steps) {
@@ -221,10 +269,11 @@ ek_status ek_ctx::step_impl(int n_steps) {
     if (p.warm_start == EK_WS_ZERO) launch_fill(psi, 0.0, dims.n, stream);
     int iters = 0;
     double res = 0, res0 = 0;
-    ek_status st = poisson(b, psi, iters, res, res0);
+    ek_status st = poisson(b, psi, p.warm_start == EK_WS_LEARNED, iters, res, res0);
     if (st) return st;
     last_iters = iters;
     last_res = res;
+    have_solve = true;
     if (timing) tacc.poisson_iters += iters;
     record(t, 2);
     // beads: n_sub MD substeps with the fields of time t, friction spread
@@ -372,6 +421,13 @@ ek_status ek_create(const ek_params* p, int32_t max_beads, void* dev_ws, size_t 
     return EK_EHIP;
   }
   c->mg_setup();
+  if (p->warm_start == EK_WS_LEARNED) {
+    c->net = new UNet();
+    c->net->stream = c->stream;
+    c->net->carve(ws + L.net, p->nx, p->ny, p->nz, false);
+    c->net->init_state();
+    c->guess = (double*)(ws + L.guess);
+  }
   *out = c;
   return EK_OK;
 }
@@ -381,6 +437,7 @@ void ek_destroy(ek_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
   ctx->mg_release();
+  delete ctx->net;
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->own_ws) (void)hipFree(ctx->ws);
   delete ctx;
@@ -446,8 +503,33 @@ ek_status ek_step(ek_ctx* ctx, int32_t n_steps) {
   if (n_steps < 0) return ctx->fail(EK_EINVAL, "n_steps < 0");
   if (!ctx->have_geometry || !ctx->have_species[0] || !ctx->have_species[1] || !ctx->have_species[2])
     return ctx->fail(EK_ESTATE, "geometry and all three species densities must be set");
+  if (ctx->p.warm_start == EK_WS_LEARNED && !ctx->net->have_params)
+    return ctx->fail(EK_ESTATE, "learned warm start without a model (ek_set_model)");
   if (ctx->p.precision == EK_FP64) return ctx->step_impl<double>(n_steps);
   return ctx->step_impl<float>(n_steps);
+}
+
+ek_status ek_set_model(ek_ctx* ctx, const float* params, int32_t n, float out_scale) {
+  if (!ctx) return EK_EINVAL;
+  if (!ctx->net) return ctx->fail(EK_ESTATE, "context was not created with warm_start = EK_WS_LEARNED");
+  if (!params || n != UNET_PARAMS) return ctx->fail(EK_EINVAL, "expected EK_UNET_PARAMS parameters");
+  if (!(out_scale > 0.0f) || !std::isfinite(out_scale)) return ctx->fail(EK_EINVAL, "out_scale must be positive");
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(params[i])) return ctx->fail(EK_EINVAL, "non-finite parameter");
+  EK_HIP(hipMemcpyAsync(ctx->net->params, params, size_t(n) * 4, hipMemcpyHostToDevice, ctx->stream));
+  ctx->net->out_scale = out_scale;
+  ctx->net->pack();
+  ctx->net->have_params = true;
+  return ctx->sync();
+}
+
+ek_status ek_get_poisson_system(ek_ctx* ctx, double* dev_rhs, double* dev_psi) {
+  if (!ctx) return EK_EINVAL;
+  if (!ctx->have_solve) return ctx->fail(EK_ESTATE, "no Poisson solve has run yet");
+  if (dev_rhs) launch_rhs_copy(ctx->b, ctx->ps, dev_rhs, ctx->dims.n, ctx->stream);
+  if (dev_psi)
+    EK_HIP(hipMemcpyAsync(dev_psi, ctx->psi, ctx->dims.n * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  return ctx->sync();
 }
 
 ek_status ek_get_moments(ek_ctx* ctx, int32_t species, double* n, double* u) {
@@ -514,8 +596,11 @@ ek_status ek_poisson_solve(ek_ctx* ctx, const double* dev_rho, double* dev_psi,
   double res = 0, res0 = 0;
   const int saved = ctx->last_iters;
   ctx->last_iters = ctx->solo_iters;
-  ek_status st = ctx->poisson(ctx->b, dev_psi, iters, res, res0);
+  if (warm_start == EK_WS_LEARNED && !(ctx->net && ctx->net->have_params))
+    return ctx->fail(EK_ESTATE, "learned warm start without a model (ek_set_model)");
+  ek_status st = ctx->poisson(ctx->b, dev_psi, warm_start == EK_WS_LEARNED, iters, res, res0);
   ctx->solo_iters = iters;
+  if (st == EK_OK) ctx->have_solve = true;
   ctx->last_iters = saved;
   if (rep) {
     rep->iterations = iters;

@@ -6,6 +6,7 @@
 
 #include "ek_internal.h"
 #include "md_table.h"
+#include "unet.h"
 
 namespace ek {
 constexpr int MAX_BEADS = 1024;        // one workgroup advances a whole chain
@@ -50,6 +51,7 @@ struct ek_ctx {
   int solo_iters = 0;
   double last_res = 0.0;
   int last_fallback = 0;
+  bool have_solve = false;             // b, ps and psi hold a finished solve
   double mass[3] = {0, 0, 0};
   double mom[3] = {0, 0, 0};
   int bx_sites = 0, bx_colour = 0;     // launch shapes (0 = default)
@@ -81,12 +83,23 @@ struct ek_ctx {
   double inv_eps() const;
   double jacobi_radius() const;
   ek_status read_scalars(ek::PoissonScalars* out);
-  ek_status sor_solve(const double* b, double* x, int& iters, double& res, double& res0);
-  ek_status mg_solve(const double* b, double* x, int& iters, double& res, double& res0);
+  // The solvers start from x whose residual state h (ps on the device) is
+  // already evaluated.
+  ek_status sor_solve(const double* b, double* x, ek::PoissonScalars h, int& iters, double& res,
+                      double& res0);
+  ek_status mg_solve(const double* b, double* x, ek::PoissonScalars h, int& iters, double& res,
+                     double& res0);
+  ek_status initial_residual(const double* b, const double* x, ek::PoissonScalars* h);
+  ek_status learned_start(const double* b, double* x, ek::PoissonScalars* h);
   void mg_setup();
   void mg_release();
   ek_status mg_vcycle(const double* b, double* x);
-  ek_status poisson(const double* b, double* x, int& iters, double& res, double& res0);
+  ek_status poisson(const double* b, double* x, bool learned, int& iters, double& res,
+                    double& res0);
+
+  // learned warm start (present when p.warm_start == EK_WS_LEARNED)
+  ek::UNet* net = nullptr;
+  double* guess = nullptr;
   template <typename T>
   ek_status step_impl(int n_steps);
 

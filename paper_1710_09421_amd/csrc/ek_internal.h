@@ -118,6 +118,9 @@ void launch_psi_shift(double* psi, const PoissonScalars* ps, double inv_n, Dims 
                       hipStream_t s);
 void launch_fill(double* x, double v, long long n, hipStream_t s);
 void launch_ps_reset(PoissonScalars* ps, double shift, hipStream_t s);
+void launch_ps_rearm(PoissonScalars* ps, hipStream_t s);
+void launch_rhs_copy(const double* b, const PoissonScalars* ps, double* out, long long n,
+                     hipStream_t s);
 void launch_rho_to_b(const double* rho, double* b, double* partials, double inv_eps, Dims d,
                      const SiteGrid& g, hipStream_t s);
 

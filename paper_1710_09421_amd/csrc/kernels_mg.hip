@@ -219,14 +219,11 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x) {
 // V-cycles until ||b - A psi|| / ||b|| <= tol, tested after every cycle;
 // cycles are enqueued ahead of the test in batches and skip themselves once
 // the device-side flag is set.
-ek_status ek_ctx::mg_solve(const double* bb, double* x, int& iters, double& res, double& res0) {
+ek_status ek_ctx::mg_solve(const double* bb, double* x, PoissonScalars h, int& iters, double& res,
+                          double& res0) {
   const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
   const int nb = g.nblocks();
-  launch_residual(x, bb, ps, partials, dims, g, stream);
-  launch_residual_final(partials, nb, p.poisson_tol, 0, 1, ps, stream);
-  PoissonScalars h{};
-  ek_status st = read_scalars(&h);
-  if (st) return st;
+  ek_status st = EK_OK;
   int it = 0;
   int batch = std::max(1, last_iters);
   while (!h.done && it < p.poisson_max_iter) {

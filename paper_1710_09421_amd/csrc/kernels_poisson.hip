@@ -180,7 +180,31 @@ __global__ void k_ps_reset(PoissonScalars* ps, double shift) {
     ps->zero_rhs = 0;
   }
 }
+// Clears the convergence flags before the residual of another start is
+// evaluated; the right-hand-side shift stays.
+__global__ void k_ps_rearm(PoissonScalars* ps) {
+  if (threadIdx.x == 0) {
+    ps->done = 0;
+    ps->iters = 0;
+    ps->zero_rhs = 0;
+  }
+}
+
+// out = b + shift: the right-hand side of the last solve with its mean removed
+__global__ __launch_bounds__(BLOCK) void k_rhs_copy(const double* __restrict__ b,
+                                                    const PoissonScalars* __restrict__ ps,
+                                                    double* __restrict__ out, long long n) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) out[r] = b[r] + ps->shift;
+}
 }  // namespace
+void launch_ps_rearm(PoissonScalars* ps, hipStream_t s) {
+  hipLaunchKernelGGL(k_ps_rearm, dim3(1), dim3(64), 0, s, ps);
+}
+void launch_rhs_copy(const double* b, const PoissonScalars* ps, double* out, long long n,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_rhs_copy, dim3(int((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, b, ps, out, n);
+}
 void launch_ps_reset(PoissonScalars* ps, double shift, hipStream_t s) {
   hipLaunchKernelGGL(k_ps_reset, dim3(1), dim3(64), 0, s, ps, shift);
 }

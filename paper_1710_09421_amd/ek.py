@@ -86,6 +86,22 @@ def _load():
         "ek_poisson_sor_iterations": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32]),
         "ek_set_timing": (c_int32, [c_void_p, c_int32]),
         "ek_get_timing": (c_int32, [c_void_p, P(ek_timing)]),
+        "ek_set_model": (c_int32, [c_void_p, c_void_p, c_int32, ctypes.c_float]),
+        "ek_get_poisson_system": (c_int32, [c_void_p, c_void_p, c_void_p]),
+        "ek_unet_workspace_bytes": (c_int32, [c_int32, c_int32, c_int32, c_int32, P(c_size_t)]),
+        "ek_unet_create": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_void_p, c_size_t,
+                                     c_void_p, P(c_void_p)]),
+        "ek_unet_destroy": (None, [c_void_p]),
+        "ek_unet_last_error": (ctypes.c_char_p, [c_void_p]),
+        "ek_unet_set_params": (c_int32, [c_void_p, c_void_p, c_int32, ctypes.c_float]),
+        "ek_unet_get_params": (c_int32, [c_void_p, c_void_p, c_int32, P(ctypes.c_float)]),
+        "ek_unet_forward": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+        "ek_unet_accumulate": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+        "ek_unet_get_gradient": (c_int32, [c_void_p, c_void_p, c_int32]),
+        "ek_unet_zero_gradient": (c_int32, [c_void_p]),
+        "ek_unet_adam_step": (c_int32, [c_void_p, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                        ctypes.c_float, ctypes.c_float]),
+        "ek_unet_read_loss": (c_int32, [c_void_p, P(ctypes.c_double), P(ctypes.c_int64)]),
         "ek_ensemble_workspace_bytes": (c_int32, [P(ek_params), c_int32, c_int32, P(c_size_t)]),
         "ek_ensemble_create": (c_int32, [P(ek_params), c_int32, c_int32, c_void_p, c_size_t, c_void_p,
                                          P(c_void_p)]),
@@ -249,6 +265,17 @@ class Context:
         return dict(iterations=rep.iterations, residual=rep.residual,
                     initial_residual=rep.initial_residual)
 
+    def set_model(self, params, out_scale):
+        """Trained network parameters (EK_UNET_PARAMS floats) for the learned warm start."""
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(self._lib.ek_set_model(self._h, _ptr(a), a.size, float(out_scale)), self._h)
+
+    def poisson_system(self, rhs, psi):
+        """Copy the last solved system into float64 CUDA tensors: rhs (mean removed), psi."""
+        self._check(self._lib.ek_get_poisson_system(
+            self._h, None if rhs is None else c_void_p(rhs.data_ptr()),
+            None if psi is None else c_void_p(psi.data_ptr())), self._h)
+
     def sor_iterations(self, b, psi, iterations):
         self._check(self._lib.ek_poisson_sor_iterations(self._h, c_void_p(b.data_ptr()),
                                                         c_void_p(psi.data_ptr()), iterations),
@@ -395,3 +422,82 @@ def ensemble_from_workloads(wls, precision=EK_FP32, poisson_tol=1e-8, poisson_ma
         else:
             ens.set_replica(r, w.E_ext, w.n0)
     return ens
+
+
+UNET_PARAMS = 73137
+
+
+class UNet:
+    """Stand-alone warm-start network on the current device and stream; all
+    field arguments are CUDA tensors of the lattice shape (b, target float64,
+    solid uint8)."""
+
+    def __init__(self, shape, training=True, stream=None):
+        import torch
+        self._lib = lib()
+        self.shape = tuple(shape)
+        nz, ny, nx = self.shape
+        nbytes = c_size_t()
+        self._check(self._lib.ek_unet_workspace_bytes(nx, ny, nz, int(training), byref(nbytes)), None)
+        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device="cuda")
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = c_void_p()
+        self._check(self._lib.ek_unet_create(nx, ny, nz, int(training), c_void_p(base + off),
+                                             nbytes.value, c_void_p(self.stream.cuda_stream),
+                                             byref(h)), None)
+        self._h = h
+
+    def _check(self, st, h):
+        if st != EK_OK:
+            msg = self._lib.ek_unet_last_error(h)
+            raise EKError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ek_unet_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params, out_scale=1.0):
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(self._lib.ek_unet_set_params(self._h, _ptr(a), a.size, float(out_scale)), self._h)
+
+    def params(self):
+        a = np.empty(UNET_PARAMS, dtype=np.float32)
+        sc = ctypes.c_float()
+        self._check(self._lib.ek_unet_get_params(self._h, _ptr(a), a.size, byref(sc)), self._h)
+        return a, sc.value
+
+    def forward(self, b, solid, guess):
+        self._check(self._lib.ek_unet_forward(self._h, c_void_p(b.data_ptr()),
+                                              c_void_p(solid.data_ptr()),
+                                              c_void_p(guess.data_ptr())), self._h)
+
+    def accumulate(self, b, solid, target):
+        self._check(self._lib.ek_unet_accumulate(self._h, c_void_p(b.data_ptr()),
+                                                 c_void_p(solid.data_ptr()),
+                                                 c_void_p(target.data_ptr())), self._h)
+
+    def gradient(self):
+        a = np.empty(UNET_PARAMS, dtype=np.float32)
+        self._check(self._lib.ek_unet_get_gradient(self._h, _ptr(a), a.size), self._h)
+        return a
+
+    def zero_gradient(self):
+        self._check(self._lib.ek_unet_zero_gradient(self._h), self._h)
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, grad_scale=1.0):
+        self._check(self._lib.ek_unet_adam_step(self._h, lr, beta1, beta2, eps, grad_scale), self._h)
+
+    def read_loss(self):
+        m = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(self._lib.ek_unet_read_loss(self._h, byref(m), byref(n)), self._h)
+        return m.value, n.value

@@ -56,3 +56,27 @@ def test_workspace_bytes_validates(ek):
     bad = ek.make_params((32, 32, 32))
     bad.fluctuations = 1
     assert lib.ek_workspace_bytes(ctypes.byref(bad), 0, ctypes.byref(nbytes)) == ek.EK_EINVAL
+
+
+def test_learned_warm_start_needs_sizes_divisible_by_4(ek):
+    lib = ek.lib()
+    nbytes = ctypes.c_size_t()
+    p = ek.make_params((34, 32, 32), warm_start=ek.EK_WS_LEARNED)
+    assert lib.ek_workspace_bytes(ctypes.byref(p), 0, ctypes.byref(nbytes)) == ek.EK_EINVAL
+    p = ek.make_params((32, 32, 32), warm_start=ek.EK_WS_LEARNED)
+    assert lib.ek_workspace_bytes(ctypes.byref(p), 0, ctypes.byref(nbytes)) == ek.EK_OK
+    plain = ctypes.c_size_t()
+    p0 = ek.make_params((32, 32, 32), warm_start=ek.EK_WS_PREV)
+    assert lib.ek_workspace_bytes(ctypes.byref(p0), 0, ctypes.byref(plain)) == ek.EK_OK
+    # network activations (bf16, 16 channels at full resolution, ...) and the guess
+    assert nbytes.value - plain.value > 32 ** 3 * (3 * 32 + 8)
+
+
+def test_unet_workspace_bytes(ek):
+    lib = ek.lib()
+    inf, tr = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.ek_unet_workspace_bytes(16, 8, 8, 0, ctypes.byref(inf)) == ek.EK_OK
+    assert lib.ek_unet_workspace_bytes(16, 8, 8, 1, ctypes.byref(tr)) == ek.EK_OK
+    assert tr.value > inf.value > 16 * 8 * 8 * 3 * 32
+    assert lib.ek_unet_workspace_bytes(18, 8, 8, 0, ctypes.byref(inf)) == ek.EK_EINVAL
+    assert lib.ek_unet_workspace_bytes(16, 8, 0, 0, ctypes.byref(inf)) == ek.EK_EINVAL

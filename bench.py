@@ -28,13 +28,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-LB_SOURCE = os.path.join(ROOT, "paper_1710_09421_amd", "csrc", "kernels_lb.hip")
+LB_SOURCES = [os.path.join(ROOT, "paper_1710_09421_amd", "csrc", f)
+              for f in ("kernels_lb.hip", "lb_site.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lb_step_traffic.json")
 
 
 def lb_source_hash():
-    with open(LB_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """sha256 over the sources of the fused lattice kernel."""
+    h = hashlib.sha256()
+    for path in LB_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(workload_name, precision):
@@ -93,6 +98,35 @@ def cpu_baseline(wl, tol):
             "kind": "oracle",
             "sample": f"1 timed step (after 1 untimed) of {wl.name}, float64 NumPy, 1 thread, "
                       f"{dt:.1f} s"}
+
+
+def learned_comparison(progress):
+    """Poisson solves to 1e-8 by multigrid from the learned start against the
+    plain starts, outside the timed region: cold held-out fields (zero start
+    vs the network's guess, network time included) and warm pairs (previous
+    solution, with and without the network consulted), then the single-pore
+    time loop with the previous-step and the learned start."""
+    from paper_1710_09421_amd import learned
+    if not os.path.exists(learned.DEFAULT_MODEL):
+        return None
+    params, scale, info = learned.load_model()
+    held = learned.generate(2, 4, 1, seed=90210, first=20, log=lambda s: None)
+    summary, _ = learned.evaluate(params, scale, held, repeats=3, log=lambda s: None)
+    progress(f"learned start on held-out fields: {json.dumps(summary)}")
+    sim = learned.simulate(params, scale, steps=100, warmup=10, log=lambda s: None)
+    progress(f"learned start in the time loop: {json.dumps(sim)}")
+    r = lambda x: round(x, 4)
+    out = {"tolerance": 1e-8, "finisher": "red-black multigrid V(2,2)",
+           "model": f"{info['n_traj'] * info['per_traj']} pairs, {info['epochs']} epochs"}
+    for k, v in summary.items():
+        out[k] = {"solves": v["n"], "cycles": r(v["cycles"]), "ms": r(v["ms"]),
+                  "initial_residual": float(f"{v['initial_residual']:.3e}"),
+                  "network_consulted": v["consulted"], "network_rejected": v["fallbacks"]}
+    out["time_loop"] = {k: {"poisson_ms_per_step": r(v["ms_poisson_per_step"]),
+                            "cycles_per_step": r(v["cycles_per_step"]),
+                            "network_consulted_steps": v["consulted_steps"]}
+                        for k, v in sim.items()}
+    return out
 
 
 def run_ensemble(args):
@@ -155,9 +189,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="single-pore")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--poisson", default="sor", choices=["sor", "mg"])
+    ap.add_argument("--poisson", default="mg", choices=["sor", "mg"])
     ap.add_argument("--check-every", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-warm-start comparison (single-pore workload only)")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="after the timed region, copy this many GiB device-to-device three "
                          "times (a kernel of known traffic for counter calibration)")
@@ -257,7 +293,10 @@ def main():
             "traffic": measured_traffic(wl.name, "f32" if prec == ek.EK_FP32 else "f64"),
         },
     }
+    if args.workload == "single-pore" and not args.no_learned:
+        line["learned_vs_plain_poisson"] = learned_comparison(progress)
     if not args.no_cpu_baseline:
+        progress("timing the oracle on the host")
         line["cpu_baseline"] = cpu_baseline(wl, wl.poisson_tol)
     print(json.dumps(line), flush=True)
 

@@ -109,7 +109,9 @@ typedef struct {
   int64_t step;                /* completed lattice steps                      */
   int32_t poisson_iters;       /* iterations (or cycles) of the last solve     */
   double poisson_residual;     /* relative residual of the last solve          */
-  int32_t fallback;            /* 1 if the learned warm start was rejected     */
+  int32_t fallback;            /* 1 if the last solve consulted the network
+                                  and rejected its guess                       */
+  int32_t consulted;           /* 1 if the last solve consulted the network    */
 } ek_stats;
 
 typedef struct {
@@ -214,9 +216,11 @@ ek_status ek_get_timing(struct ek_ctx* ctx, ek_timing* out);
 
 /* Use a trained network in a context created with warm_start =
  * EK_WS_LEARNED (else EK_ESTATE).  Each solve then evaluates the residual of
- * the previous solution (or of the start passed to ek_poisson_solve) and of
- * the network's guess and starts from the smaller one; ek_stats.fallback is 1
- * when the guess was rejected.  host params[EK_UNET_PARAMS]; out_scale > 0. */
+ * the previous solution (or of the start passed to ek_poisson_solve); if its
+ * relative residual exceeds 1/4 (a cold or abruptly changed right-hand side)
+ * the network's guess is evaluated too and the start with the smaller
+ * residual is kept (ek_stats.consulted, ek_stats.fallback report which).
+ * host params[EK_UNET_PARAMS]; out_scale > 0. */
 ek_status ek_set_model(struct ek_ctx* ctx, const float* params, int32_t n, float out_scale);
 
 /* The last solved system: dev_rhs[nz*ny*nx] receives its right-hand side b

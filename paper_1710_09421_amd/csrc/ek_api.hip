@@ -189,32 +189,31 @@ ek_status ek_ctx::initial_residual(const double* bb, const double* x, PoissonSca
   return read_scalars(h);
 }
 
-// Learned warm start with fallback: the residuals of the current start x
-// (previous step, or what the caller passed) and of the network's guess are
-// evaluated with one synchronisation; the better start is kept in x and its
-// residual state stays in ps.  A non-finite guess residual always falls back.
+// Learned warm start with fallback.  The residual of the current start x
+// (previous step, or what the caller passed) is evaluated first; only when it
+// exceeds LEARNED_GATE is the network consulted, its guess's residual
+// evaluated, and the smaller of the two starts kept in x with its residual
+// state in ps.  A non-finite guess residual always falls back.
 ek_status ek_ctx::learned_start(const double* bb, double* x, PoissonScalars* h) {
   ek_ctx* ctx = this;
   const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
   const int nb = g.nblocks();
-  const size_t hs = sizeof(PoissonScalars);
-  launch_residual(x, bb, ps, partials, dims, g, stream);
-  launch_residual_final(partials, nb, p.poisson_tol, 0, 1, ps, stream);
-  EK_HIP(hipMemcpyAsync(pinned, ps, hs, hipMemcpyDeviceToHost, stream));
+  last_fallback = 0;
+  last_consulted = 0;
+  ek_status st = initial_residual(bb, x, h);
+  if (st || h->done || !(h->rel > LEARNED_GATE)) return st;
+  last_consulted = 1;
+  const PoissonScalars hp = *h;
   launch_ps_rearm(ps, stream);
   net->forward(bb, mask, true, guess);
   launch_residual(guess, bb, ps, partials, dims, g, stream);
   launch_residual_final(partials, nb, p.poisson_tol, 0, 1, ps, stream);
-  EK_HIP(hipMemcpyAsync((char*)pinned + 512, ps, hs, hipMemcpyDeviceToHost, stream));
-  ek_status st = sync();
+  PoissonScalars hl{};
+  st = read_scalars(&hl);
   if (st) return st;
-  PoissonScalars hp, hl;
-  std::memcpy(&hp, pinned, hs);
-  std::memcpy(&hl, (char*)pinned + 512, hs);
   if (hl.rel < hp.rel) {
     EK_HIP(hipMemcpyAsync(x, guess, dims.n * 8, hipMemcpyDeviceToDevice, stream));
     *h = hl;
-    last_fallback = 0;
     return EK_OK;
   }
   last_fallback = 1;
@@ -225,6 +224,8 @@ ek_status ek_ctx::learned_start(const double* bb, double* x, PoissonScalars* h) 
 ek_status ek_ctx::poisson(const double* bb, double* x, bool learned, int& iters, double& res,
                           double& res0) {
   PoissonScalars h{};
+  last_fallback = 0;
+  last_consulted = 0;
   ek_status st = learned ? learned_start(bb, x, &h) : initial_residual(bb, x, &h);
   if (st) return st;
   if (p.poisson_method == EK_POISSON_MG) return mg_solve(bb, x, h, iters, res, res0);
@@ -567,6 +568,7 @@ ek_status ek_get_stats(ek_ctx* ctx, ek_stats* out) {
   out->poisson_iters = ctx->last_iters;
   out->poisson_residual = ctx->last_res;
   out->fallback = ctx->last_fallback;
+  out->consulted = ctx->last_consulted;
   return EK_OK;
 }
 

@@ -16,6 +16,11 @@ void launch_table_init_bits(int* keys, long long* vals, int bits, hipStream_t s)
 size_t mg_workspace_bytes(int nx, int ny, int nz);
 }  // namespace ek
 
+// The learned warm start consults the network only when the relative
+// residual of the current start exceeds this value (cold or abruptly changed
+// right-hand sides); a start closer than that is kept as it is.
+constexpr double LEARNED_GATE = 0.25;
+
 struct ek_ctx {
   ek_params p{};
   ek::Dims dims{};
@@ -51,6 +56,7 @@ struct ek_ctx {
   int solo_iters = 0;
   double last_res = 0.0;
   int last_fallback = 0;
+  int last_consulted = 0;
   bool have_solve = false;             // b, ps and psi hold a finished solve
   double mass[3] = {0, 0, 0};
   double mom[3] = {0, 0, 0};

@@ -261,28 +261,36 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ in,
   }
 }
 
-// Sum of the per-block partials (fixed order) added to the flat gradient at
-// the real (unpadded) positions of one layer.
-__global__ __launch_bounds__(256) void k_wreduce(const float* __restrict__ part, int nblk,
-                                                 UNetLayer L, float* __restrict__ grad) {
+// Sum of the per-block partials added to the flat gradient at the real
+// (unpadded) positions of one layer.  A block of 1024 threads owns 64
+// consecutive elements; its 16 waves take every 16th partial block and the 16
+// sums are added in a fixed order, so the result does not depend on timing.
+__global__ __launch_bounds__(1024) void k_wreduce(const float* __restrict__ part, int nblk,
+                                                  UNetLayer L, float* __restrict__ grad) {
+  __shared__ float sh[16][64];
   const int per = (L.taps + 1) * L.cinp * L.coutp;
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= per) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;
+  float s = 0.f;
+  if (e < per) {
+#pragma unroll 8
+    for (int b = wv; b < nblk; b += 16) s += part[(size_t)b * per + e];
+  }
+  sh[wv][lane] = s;
+  __syncthreads();
+  if (wv != 0 || e >= per) return;
+  float t = 0.f;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) t += sh[w][lane];
   const int co = e % L.coutp;
   const int ci = (e / L.coutp) % L.cinp;
-  const int t = e / (L.coutp * L.cinp);
+  const int tap = e / (L.coutp * L.cinp);
   if (co >= L.cout) return;
-  int dst;
-  if (t < L.taps) {
-    if (ci >= L.cin) return;
-    dst = L.woff + (t * L.cin + ci) * L.cout + co;
-  } else {
-    if (ci != 0) return;
-    dst = L.boff + co;
+  if (tap < L.taps) {
+    if (ci < L.cin) grad[L.woff + (tap * L.cin + ci) * L.cout + co] += t;
+  } else if (ci == 0) {
+    grad[L.boff + co] += t;
   }
-  float s = 0.f;
-  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * per + e];
-  grad[dst] += s;
 }
 
 // ---------------------------------------------------------------------------
@@ -532,7 +540,7 @@ void wgrad(const uint16_t* in, const uint16_t* dy, float* part, float* grad, con
   hipLaunchKernelGGL((k_wgrad<CIN, COUT, T>), dim3(nblk), dim3(256), 0, s, in, dy, part, g,
                      wgrad_subs(g.n));
   const int per = (T + 1) * CIN * COUT;
-  hipLaunchKernelGGL(k_wreduce, dim3(blocks_for(per)), dim3(256), 0, s, part, nblk, L, grad);
+  hipLaunchKernelGGL(k_wreduce, dim3((per + 63) / 64), dim3(1024), 0, s, part, nblk, L, grad);
 }
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }

@@ -40,7 +40,8 @@ class ek_polymer_params(ctypes.Structure):
 
 class ek_stats(ctypes.Structure):
     _fields_ = [("mass", c_double * 3), ("momentum", c_double * 3), ("step", c_int64),
-                ("poisson_iters", c_int32), ("poisson_residual", c_double), ("fallback", c_int32)]
+                ("poisson_iters", c_int32), ("poisson_residual", c_double), ("fallback", c_int32),
+                ("consulted", c_int32)]
 
 
 class ek_timing(ctypes.Structure):
@@ -246,7 +247,7 @@ class Context:
         self._check(self._lib.ek_get_stats(self._h, byref(s)), self._h)
         return dict(mass=np.array(s.mass[:]), momentum=np.array(s.momentum[:]), step=s.step,
                     poisson_iters=s.poisson_iters, poisson_residual=s.poisson_residual,
-                    fallback=s.fallback)
+                    fallback=s.fallback, consulted=s.consulted)
 
     def set_timing(self, enable=True):
         self._check(self._lib.ek_set_timing(self._h, 1 if enable else 0), self._h)

@@ -135,7 +135,7 @@ __global__ __launch_bounds__(MAXT) void k_ensemble(RepDev* reps, EnsConst ec) {
     for (int t = tid; t < N; t += MAXT) {
       int x, y, z;
       site_xyz(t, d, inx, iny, x, y, z);
-      const double rho = charge_site(fsrc, R.mask, ec.wall_q, lp, bt, x, y, z, d);
+      const double rho = charge_site<T, long long>(fsrc, R.mask, ec.wall_q, lp, bt, x, y, z, d);
       R.b[t] = -rho * ec.inv_eps;
       rs += rho;
     }
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(MAXT) void k_ensemble(RepDev* reps, EnsConst ec) {
     for (int t = tid; t < N; t += MAXT) {
       int x, y, z;
       site_xyz(t, d, inx, iny, x, y, z);
-      lb_site(fsrc, fdst, R.mask, R.psi, lp, bt, x, y, z, d, acc);
+      lb_site<T, long long>(fsrc, fdst, R.mask, R.psi, lp, bt, x, y, z, d, acc);
     }
     double tot[6];
 #pragma unroll

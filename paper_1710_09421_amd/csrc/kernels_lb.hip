@@ -38,7 +38,7 @@ __global__ __launch_bounds__(BLOCK) void k_init_species(T* __restrict__ f,
 // Charge pass: n^a at time t for every charged species, rho_e = sum z^a n^a
 // + fixed wall charge + bead charge; stores -rho_e / eps and partial sums of
 // rho_e (for the mean that the periodic problem removes).
-template <typename T>
+template <typename T, typename I>
 __global__ __launch_bounds__(BLOCK) void k_charge(const T* __restrict__ f,
                                                   const uint32_t* __restrict__ mask,
                                                   const double* __restrict__ wall_q,
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(BLOCK) void k_charge(const T* __restrict__ f,
   const int nblocks = gridDim.x * gridDim.y * gridDim.z;
   double acc[1] = {0.0};
   if (x < d.nx && y < d.ny) {
-    const double rho = charge_site(f, mask, wall_q, lp, bt, x, y, z, d);
+    const double rho = charge_site<T, I>(f, mask, wall_q, lp, bt, x, y, z, d);
     b[((long long)z * d.ny + y) * d.nx + x] = -rho * inv_eps;
     acc[0] = rho;
   }
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(BLOCK) void k_charge(const T* __restrict__ f,
 // potential, closed-form implicit drag, BGK collision with the half-force
 // (Guo) forcing term, aligned store; partial sums of species mass and total
 // momentum of f(t) in float64.
-template <typename T>
+template <typename T, typename I>
 __global__ __launch_bounds__(BLOCK) void k_lb_step(const T* __restrict__ fsrc,
                                                    T* __restrict__ fdst,
                                                    const uint32_t* __restrict__ mask,
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(BLOCK) void k_lb_step(const T* __restrict__ fsrc,
   const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   const int nblocks = gridDim.x * gridDim.y * gridDim.z;
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  if (x < d.nx && y < d.ny) lb_site(fsrc, fdst, mask, psi, lp, bt, x, y, z, d, acc);
+  if (x < d.nx && y < d.ny) lb_site<T, I>(fsrc, fdst, mask, psi, lp, bt, x, y, z, d, acc);
   block_partials<6>(acc, partials, bid, nblocks);
 }
 
@@ -166,16 +166,24 @@ template <typename T>
 void launch_charge(const T* f, const uint32_t* mask, const double* wall_q, double* b,
                    double* partials, const LBParams& lp, double inv_eps, Dims d,
                    const SiteGrid& g, hipStream_t s, const BeadTableView& bt) {
-  hipLaunchKernelGGL(k_charge<T>, g.grid, g.block, 0, s, f, mask, wall_q, b, partials, lp,
-                     inv_eps, bt, d);
+  if (fits_idx32<T>(d.n))
+    hipLaunchKernelGGL((k_charge<T, uint32_t>), g.grid, g.block, 0, s, f, mask, wall_q, b,
+                       partials, lp, inv_eps, bt, d);
+  else
+    hipLaunchKernelGGL((k_charge<T, long long>), g.grid, g.block, 0, s, f, mask, wall_q, b,
+                       partials, lp, inv_eps, bt, d);
 }
 
 template <typename T>
 void launch_lb_step(const T* fsrc, T* fdst, const uint32_t* mask, const double* psi,
                     const LBParams& lp, const BeadTableView& bt, double* partials, Dims d,
                     const SiteGrid& g, hipStream_t s) {
-  hipLaunchKernelGGL(k_lb_step<T>, g.grid, g.block, 0, s, fsrc, fdst, mask, psi, lp, bt,
-                     partials, d);
+  if (fits_idx32<T>(d.n))
+    hipLaunchKernelGGL((k_lb_step<T, uint32_t>), g.grid, g.block, 0, s, fsrc, fdst, mask, psi,
+                       lp, bt, partials, d);
+  else
+    hipLaunchKernelGGL((k_lb_step<T, long long>), g.grid, g.block, 0, s, fsrc, fdst, mask, psi,
+                       lp, bt, partials, d);
 }
 
 template <typename T>

@@ -17,54 +17,99 @@
 
 namespace ek {
 
-struct Nbr {
-  long long zo[3], yo[3];
-  int xo[3];
+// Offsets of the rows r - c for one site: index [1 - c] selects minus, same,
+// plus.  I is the index type: 32-bit when every element offset within one
+// species' 19 planes fits (fewer address instructions), 64-bit otherwise.
+template <typename I>
+struct NbrT {
+  I zo[3], yo[3], xo[3];
 };
+using Nbr = NbrT<long long>;
 
-// Offsets of the rows r - c: index [1 - c] selects minus, same, plus.
-__device__ inline Nbr neighbours(int x, int y, int z, const Dims& d) {
-  Nbr n;
+template <typename I>
+__device__ inline NbrT<I> neighbours_t(int x, int y, int z, const Dims& d) {
+  NbrT<I> n;
   const int xm = x == 0 ? d.nx - 1 : x - 1, xp = x == d.nx - 1 ? 0 : x + 1;
   const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
   const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
-  const long long nxy = (long long)d.nx * d.ny;
-  n.zo[0] = zm * nxy; n.zo[1] = z * nxy; n.zo[2] = zp * nxy;
-  n.yo[0] = (long long)ym * d.nx; n.yo[1] = (long long)y * d.nx; n.yo[2] = (long long)yp * d.nx;
-  n.xo[0] = xm; n.xo[1] = x; n.xo[2] = xp;
+  const I nxy = I(d.nx) * I(d.ny);
+  n.zo[0] = I(zm) * nxy; n.zo[1] = I(z) * nxy; n.zo[2] = I(zp) * nxy;
+  n.yo[0] = I(ym) * I(d.nx); n.yo[1] = I(y) * I(d.nx); n.yo[2] = I(yp) * I(d.nx);
+  n.xo[0] = I(xm); n.xo[1] = I(x); n.xo[2] = I(xp);
   return n;
 }
+__device__ inline Nbr neighbours(int x, int y, int z, const Dims& d) {
+  return neighbours_t<long long>(x, y, z, d);
+}
+
+// True when 19 planes of n sites of T can be addressed with 32-bit element
+// offsets from a species' base.
+template <typename T>
+__host__ __device__ inline bool fits_idx32(long long n) {
+  return (unsigned long long)n * Q * sizeof(T) < (1ull << 32);
+}
+
+// The 19 planes of one species, read through a plain pointer with index
+// type I.
+template <typename T, typename I>
+struct Planes {
+  const T* base;
+  __device__ Planes(const T* b, I) : base(b) {}
+  __device__ T load(I idx) const { return base[idx]; }
+};
+
+// Writes of plane p at site r of one species.
+template <typename T, typename I>
+struct PlanesOut {
+  T* base;
+  I n;
+  __device__ PlanesOut(T* b, I nn) : base(b), n(nn) {}
+  __device__ void store(int p, I r, T v) const { (base + (size_t)p * n)[r] = v; }
+};
 
 // Pull the 19 post-collision deviations of one species into a site.
-template <typename T>
-__device__ inline void pull(const T* __restrict__ f, int s, long long r, uint32_t m,
-                            const Nbr& nb, long long N, T (&g)[Q]) {
+template <typename T, typename I>
+__device__ inline void pull(const Planes<T, I>& fs, I r, uint32_t m, const NbrT<I>& nb, I N,
+                            T (&g)[Q]) {
 #pragma unroll
   for (int p = 0; p < Q; ++p) {
     const bool bounce = (m >> p) & 1u;
-    const long long src = nb.zo[1 - CZ[p]] + nb.yo[1 - CY[p]] + nb.xo[1 - CX[p]];
-    const long long idx = bounce ? (size_t)(s * Q + OPP[p]) * N + r : (size_t)(s * Q + p) * N + src;
-    g[p] = f[idx];
+    const I src = nb.zo[1 - CZ[p]] + nb.yo[1 - CY[p]] + nb.xo[1 - CX[p]];
+    const I idx = bounce ? I(OPP[p]) * N + r : I(p) * N + src;
+    g[p] = fs.load(idx);
   }
+}
+template <typename T>
+__device__ inline void pull(const T* __restrict__ f, int s, long long r, uint32_t m,
+                            const Nbr& nb, long long N, T (&g)[Q]) {
+  pull<T, long long>(Planes<T, long long>(f + (size_t)s * Q * N, N), r, m, nb, N, g);
+}
+
+// 1 / x: the hardware reciprocal (1 ulp) in float32, division in float64.
+template <typename T>
+__device__ inline T recip(T x) {
+  if constexpr (sizeof(T) == 4) return __builtin_amdgcn_rcpf(x);
+  else return T(1) / x;
 }
 
 // Charge density at site (x, y, z): sum of z^a n^a over the charged species
 // (fluid sites), the fixed wall charge and the beads' deposited charge.
-template <typename T>
+template <typename T, typename I = long long>
 __device__ inline double charge_site(const T* __restrict__ f, const uint32_t* __restrict__ mask,
                                      const double* __restrict__ wall_q, const LBParams& lp,
                                      const BeadTableView& bt, int x, int y, int z, const Dims& d) {
-  const long long r = ((long long)z * d.ny + y) * d.nx + x;
+  const I N = I(d.n);
+  const I r = (I(z) * I(d.ny) + I(y)) * I(d.nx) + I(x);
   const uint32_t m = mask[r];
   double rho = 0.0;
   if (m & MASK_CHARGED) rho += wall_q[r];
   if (!(m & MASK_SOLID)) {
-    const Nbr nb = neighbours(x, y, z, d);
+    const NbrT<I> nb = neighbours_t<I>(x, y, z, d);
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
       if (lp.valence[s] == 0.0) continue;
       T g[Q];
-      pull(f, s, r, m, nb, d.n, g);
+      pull<T, I>(Planes<T, I>(f + (size_t)s * Q * d.n, N), r, m, nb, N, g);
       T dn = T(0);
 #pragma unroll
       for (int p = 0; p < Q; ++p) dn += g[p];
@@ -79,18 +124,20 @@ __device__ inline double charge_site(const T* __restrict__ f, const uint32_t* __
 // potential, closed-form implicit drag, BGK collision with the half-force
 // (Guo) forcing term, aligned store.  Adds the site's species masses and
 // momentum of f(t) to acc (float64).
-template <typename T>
+template <typename T, typename I = long long>
 __device__ inline void lb_site(const T* __restrict__ fsrc, T* __restrict__ fdst,
                                const uint32_t* __restrict__ mask, const double* __restrict__ psi,
                                const LBParams& lp, const BeadTableView& bt, int x, int y, int z,
                                const Dims& d, double (&acc)[6]) {
-  const long long r = ((long long)z * d.ny + y) * d.nx + x;
+  const I N = I(d.n);
+  const I r = (I(z) * I(d.ny) + I(y)) * I(d.nx) + I(x);
   const uint32_t m = mask[r];
   if (!(m & MASK_SOLID)) {
-    const Nbr nb = neighbours(x, y, z, d);
+    const NbrT<I> nb = neighbours_t<I>(x, y, z, d);
     T g[3][Q];
 #pragma unroll
-    for (int s = 0; s < 3; ++s) pull(fsrc, s, r, m, nb, d.n, g[s]);
+    for (int s = 0; s < 3; ++s)
+      pull<T, I>(Planes<T, I>(fsrc + (size_t)s * Q * d.n, N), r, m, nb, N, g[s]);
 
     // electric field E = -grad psi (central differences) + applied field
     const T ex = T(-0.5 * (psi[nb.zo[1] + nb.yo[1] + nb.xo[2]] - psi[nb.zo[1] + nb.yo[1] + nb.xo[0]]) + lp.eext[0]);
@@ -119,7 +166,7 @@ __device__ inline void lb_site(const T* __restrict__ fsrc, T* __restrict__ fdst,
       acc[s] = lp.nref[s] + double(dn);
       acc[3] += double(jx); acc[4] += double(jy); acc[5] += double(jz);
       const T zs = T(lp.valence[s]);
-      const T inv_n = T(1) / n[s];
+      const T inv_n = recip(n[s]);
       G[s][0] = zs * ex + T(lp.fext[s][0]);
       G[s][1] = zs * ey + T(lp.fext[s][1]);
       G[s][2] = zs * ez + T(lp.fext[s][2]);
@@ -134,24 +181,25 @@ __device__ inline void lb_site(const T* __restrict__ fsrc, T* __restrict__ fdst,
     // implicit drag in closed form: with a^a = omega_drag^a / 2,
     // ubar = sum x^a b^a / (1 + a^a) / sum x^a / (1 + a^a),
     // u^a = (b^a + a^a ubar) / (1 + a^a), Phi^a = G^a - omega_drag^a (u^a - ubar)
-    const T inv_ntot = T(1) / (n[0] + n[1] + n[2]);
+    const T inv_ntot = recip(n[0] + n[1] + n[2]);
     T ub[3] = {T(0), T(0), T(0)};
     T den = T(0);
     T inv1a[3];
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-      inv1a[s] = T(1) / (T(1) + T(0.5 * lp.wdrag[s]));
+      inv1a[s] = recip(T(1) + T(0.5 * lp.wdrag[s]));
       const T xs = n[s] * inv_ntot * inv1a[s];
 #pragma unroll
       for (int c = 0; c < 3; ++c) ub[c] += xs * bv[s][c];
       den += xs;
     }
-    const T inv_den = T(1) / den;
+    const T inv_den = recip(den);
 #pragma unroll
     for (int c = 0; c < 3; ++c) ub[c] *= inv_den;
 
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
+      const PlanesOut<T, I> out(fdst + (size_t)s * Q * d.n, N);
       const T as = T(0.5 * lp.wdrag[s]);
       const T wd = T(lp.wdrag[s]);
       T u[3], ph[3];
@@ -175,7 +223,7 @@ __device__ inline void lb_site(const T* __restrict__ fsrc, T* __restrict__ fdst,
         const T geq = w * (dn + ns * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu));
         const T src = w * ns * (T(3) * cf + T(9) * cu * cf - T(3) * pu);
         const T gs = g[s][p] - om * (g[s][p] - geq) + half * src;
-        fdst[(size_t)(s * Q + p) * d.n + r] = gs;
+        out.store(p, r, gs);
       }
     }
   }

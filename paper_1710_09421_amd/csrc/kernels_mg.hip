@@ -178,15 +178,7 @@ struct ek_ctx::MG {
   size_t coarse_lds = 0;     // LDS bytes of that kernel
   double omega_coarsest = 1.0;
   int coarsest_sweeps = COARSEST_SWEEPS;
-  double* tmp = nullptr;     // second iterate of the fused sweeps
 };
-
-namespace {
-dim3 sweep_grid(const Lvl& L) {
-  return dim3((L.nx + SW_TX - 1) / SW_TX, (L.ny + SW_TY - 1) / SW_TY, (L.nz + SW_TZ - 1) / SW_TZ);
-}
-static_assert(NU1 % 2 == 0 && NU2 % 2 == 0, "sweeps alternate between x and the second iterate");
-}  // namespace
 
 bool halvable(int nx, int ny, int nz) {
   return nx % 4 == 0 && ny % 4 == 0 && nz % 4 == 0;
@@ -200,8 +192,7 @@ double omega_opt(int nx, int ny, int nz) {
 }
 
 size_t ek::mg_workspace_bytes(int nx, int ny, int nz) {
-  // the sweep's second iterate buffer (level 0 size, reused by every level)
-  size_t bytes = 256 + (((size_t)nx * ny * nz * 8 + 255) & ~size_t(255));
+  size_t bytes = 256;
   while (halvable(nx, ny, nz)) {
     nx /= 2;
     ny /= 2;
@@ -229,7 +220,6 @@ void ek_ctx::mg_setup() {
     mem += 2 * b;
     mg->levels.push_back(l);
   }
-  mg->tmp = (double*)mem;
   const int nl = (int)mg->levels.size();
   int fc = nl - 1;
   size_t bytes = 16 * (size_t)mg->levels[fc].n;
@@ -273,17 +263,11 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x) {
                            L[0], c, ps, 1, mg->omega_coarsest);
     return EK_OK;
   }
-  // an even number of fused sweeps, x -> tmp -> x, leaves the iterate in x
-  auto sweeps = [&](int l, int n) {
-    for (int s = 0; s < n; ++s) {
-      const double* in = (s & 1) ? mg->tmp : L[l].x;
-      double* out = (s & 1) ? L[l].x : mg->tmp;
-      hipLaunchKernelGGL(k_sweep, sweep_grid(L[l]), dim3(256), 0, stream, L[l], in, out, ps,
-                         l == 0 ? 1 : 0, 1.0);
-    }
-  };
   for (int l = 0; l < fc; ++l) {
-    sweeps(l, NU1);
+    for (int s = 0; s < NU1; ++s)
+      for (int c = 0; c < 2; ++c)
+        hipLaunchKernelGGL(k_smooth, colour_launch(L[l]).grid, colour_launch(L[l]).block, 0, stream,
+                           L[l], c, ps, l == 0 ? 1 : 0, 1.0);
     hipLaunchKernelGGL(k_restrict, level_launch(L[l + 1]).grid, level_launch(L[l + 1]).block, 0,
                        stream, L[l], L[l + 1], ps, l == 0 ? 1 : 0);
   }
@@ -295,7 +279,10 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x) {
   for (int l = fc - 1; l >= 0; --l) {
     hipLaunchKernelGGL(k_prolong, level_launch(L[l]).grid, level_launch(L[l]).block, 0, stream, L[l],
                        L[l + 1], ps);
-    sweeps(l, NU2);
+    for (int s = 0; s < NU2; ++s)
+      for (int c = 0; c < 2; ++c)
+        hipLaunchKernelGGL(k_smooth, colour_launch(L[l]).grid, colour_launch(L[l]).block, 0, stream,
+                           L[l], c, ps, l == 0 ? 1 : 0, 1.0);
   }
   return EK_OK;
 }

@@ -59,77 +59,6 @@ __global__ __launch_bounds__(256) void k_prolong(Lvl F, Lvl C, const PoissonScal
   prolong_site(F, C, x, y, blockIdx.z);
 }
 
-// One full red-black Gauss-Seidel sweep in one launch: a workgroup loads its
-// tile of x_in with a two-site halo into LDS, updates the red sites of the
-// tile and a one-site halo (the halo's red values equal those its neighbouring
-// tile computes, both from x_in), then the black sites of the tile from those
-// red values, and writes the tile to x_out.  The same arithmetic, in the same
-// order, as the red and then the black half sweep of k_smooth.
-constexpr int SW_TX = 32, SW_TY = 8, SW_TZ = 8;
-constexpr int SW_HX = SW_TX + 4, SW_HY = SW_TY + 4, SW_HZ = SW_TZ + 4;
-
-__device__ inline int wrap_coord(int v, int n) {
-  while (v < 0) v += n;
-  while (v >= n) v -= n;
-  return v;
-}
-
-__global__ __launch_bounds__(256) void k_sweep(Lvl L, const double* __restrict__ x_in,
-                                               double* __restrict__ x_out,
-                                               const PoissonScalars* ps, int level0,
-                                               double omega) {
-  if (ps->done) return;
-  __shared__ double xs[SW_HZ * SW_HY * SW_HX];
-  const int ox = blockIdx.x * SW_TX, oy = blockIdx.y * SW_TY, oz = blockIdx.z * SW_TZ;
-  const double shift = level0 ? ps->shift : 0.0;
-  const int tid = threadIdx.x;
-  for (int i = tid; i < SW_HZ * SW_HY * SW_HX; i += 256) {
-    const int lx = i % SW_HX, ly = (i / SW_HX) % SW_HY, lz = i / (SW_HX * SW_HY);
-    const int gx = wrap_coord(ox + lx - 2, L.nx), gy = wrap_coord(oy + ly - 2, L.ny),
-              gz = wrap_coord(oz + lz - 2, L.nz);
-    xs[i] = x_in[idx3(gx, gy, gz, L)];
-  }
-  __syncthreads();
-  auto update = [&](int lx, int ly, int lz) {
-    const int i = (lz * SW_HY + ly) * SW_HX + lx;
-    const int gx = wrap_coord(ox + lx - 2, L.nx), gy = wrap_coord(oy + ly - 2, L.ny),
-              gz = wrap_coord(oz + lz - 2, L.nz);
-    const double nb = xs[i - 1] + xs[i + 1] + xs[i - SW_HX] + xs[i + SW_HX] +
-                      xs[i - SW_HX * SW_HY] + xs[i + SW_HX * SW_HY];
-    const double gs = (nb - L.h2 * (L.f[idx3(gx, gy, gz, L)] + shift)) * (1.0 / 6.0);
-    xs[i] = omega == 1.0 ? gs : xs[i] + omega * (gs - xs[i]);
-  };
-  // red sites ((x + y + z) even) of the tile and a one-site halo: 34 x 10 x 10
-  // sites, half of them red; thread t takes the t-th red site of each group
-  // of 256 red sites in row order
-  constexpr int RX = SW_TX + 2, RY = SW_TY + 2, RZ = SW_TZ + 2;
-  const int par = (ox + oy + oz) & 1;      // colour of local (2, 2, 2)
-  for (int j = tid; j < RX * RY * RZ / 2; j += 256) {
-    // pairs along x: j -> row (ry, rz), pair index px; the red one of the pair
-    const int px = j % (RX / 2), row = j / (RX / 2);
-    const int ry = row % RY, rz = row / RY;
-    const int lx0 = 1 + 2 * px, ly = 1 + ry, lz = 1 + rz;
-    // local (lx, ly, lz) has colour (par + lx + ly + lz - 6) & 1 = (par + lx + ly + lz) & 1
-    const int lx = lx0 + ((par + lx0 + ly + lz) & 1);
-    update(lx, ly, lz);
-  }
-  __syncthreads();
-  for (int j = tid; j < SW_TX * SW_TY * SW_TZ / 2; j += 256) {
-    const int px = j % (SW_TX / 2), row = j / (SW_TX / 2);
-    const int ty = row % SW_TY, tz = row / SW_TY;
-    const int lx0 = 2 + 2 * px, ly = 2 + ty, lz = 2 + tz;
-    const int lx = lx0 + ((par + lx0 + ly + lz + 1) & 1);
-    update(lx, ly, lz);
-  }
-  __syncthreads();
-  for (int i = tid; i < SW_TX * SW_TY * SW_TZ; i += 256) {
-    const int tx = i % SW_TX, ty = (i / SW_TX) % SW_TY, tz = i / (SW_TX * SW_TY);
-    const int gx = ox + tx, gy = oy + ty, gz = oz + tz;
-    if (gx < L.nx && gy < L.ny && gz < L.nz)
-      x_out[idx3(gx, gy, gz, L)] = xs[((tz + 2) * SW_HY + ty + 2) * SW_HX + tx + 2];
-  }
-}
-
 // The coarse part of the cycle runs on copies of the coarse levels in LDS:
 // level `first` arrives with its right-hand side and a zero iterate in global
 // memory, its iterate goes back to global memory at the end.

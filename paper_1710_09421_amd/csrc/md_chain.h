@@ -305,6 +305,15 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
   int slot[CPL], bidx[CPL];
   double wfl[CPL];
   double fl_all[8];                 // fluid flag of every corner (for the normalisation)
+  // With at most two corners per lane the corner data, which is fixed for the
+  // whole step (node momenta of time t and the field), and the lane's
+  // wall-site flags are kept in registers from the substep the bead enters
+  // its cell on; with more corners per lane they are read each substep.
+  constexpr bool CACHE = CPL <= 2;
+  constexpr int NWS = 64 / TPB;     // wall sites per lane
+  double mo_c[CACHE ? CPL : 1][MOM];
+  double e_c[CACHE ? CPL : 1][3];
+  unsigned long long wall_bits = 0;
   for (int sub = 0; sub < mp.n_sub; ++sub) {
     double wt[CPL];
     double phi[3][3];
@@ -341,6 +350,26 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
             const long long site = site_of(fx + ox, fy + oy, fz + oz, d);
             slot[a] = LDS ? ln.slot(site) : gn.slot(site);
           }
+          if constexpr (CACHE) {
+            const double* e = ef + (size_t)bidx[a] * 3;
+            const double* mo = mom + (size_t)bidx[a] * MOM;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) e_c[a][c] = e[c];
+#pragma unroll
+            for (int c = 0; c < MOM; ++c) mo_c[a][c] = wfl[a] != 0.0 ? mo[c] : 0.0;
+          }
+        }
+        if constexpr (CACHE) {
+          wall_bits = 0;
+#pragma unroll
+          for (int k = 0; k < NWS; ++k) {
+            const int wsite = lane + k * TPB;
+            const int wx = wsite & 3, wy = (wsite >> 2) & 3, wz = wsite >> 4;
+            const int ix = fx - 1 + wx - org[0] + 1, iy = fy - 1 + wy - org[1] + 1,
+                      iz = fz - 1 + wz - org[2] + 1;
+            if (ix < 0 || ix >= WIN || iy < 0 || iy >= WIN || iz < 0 || iz >= WIN) continue;
+            if (fl[ix + WIN * (iy + WIN * iz)] & 2) wall_bits |= 1ull << k;
+          }
         }
       }
       // plain and fluid-renormalised trilinear weights
@@ -367,12 +396,12 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
         const int ox = k8 & 1, oy = (k8 >> 1) & 1, oz = (k8 >> 2) & 1;
         const double w = (ox ? dx : 1.0 - dx) * (oy ? dy : 1.0 - dy) * (oz ? dz : 1.0 - dz);
         wt[a] = w * wfl[a] * iws;
-        const double* e = ef + (size_t)bidx[a] * 3;
+        const double* e = CACHE ? e_c[CACHE ? a : 0] : ef + (size_t)bidx[a] * 3;
         acc[12] += w * e[0];
         acc[13] += w * e[1];
         acc[14] += w * e[2];
         if (wt[a] != 0.0) {
-          const double* mo = mom + (size_t)bidx[a] * MOM;
+          const double* mo = CACHE ? mo_c[CACHE ? a : 0] : mom + (size_t)bidx[a] * MOM;
 #pragma unroll
           for (int s = 0; s < 3; ++s) {
             acc[9 + s] += wt[a] * mo[s];
@@ -404,12 +433,17 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
           for (int c = 0; c < 3; ++c) F[c] += coef * dv[c];
         }
       }
-      for (int wsite = lane; wsite < 64; wsite += TPB) {   // WCA against wall-site centres
+      for (int k = 0; k < NWS; ++k) {             // WCA against wall-site centres
+        const int wsite = lane + k * TPB;
         const int wx = wsite & 3, wy = (wsite >> 2) & 3, wz = wsite >> 4;
         const int ax = fx - 1 + wx, ay = fy - 1 + wy, az = fz - 1 + wz;
-        const int ix = ax - org[0] + 1, iy = ay - org[1] + 1, iz = az - org[2] + 1;
-        if (ix < 0 || ix >= WIN || iy < 0 || iy >= WIN || iz < 0 || iz >= WIN) continue;
-        if (!(fl[ix + WIN * (iy + WIN * iz)] & 2)) continue;
+        if constexpr (CACHE) {
+          if (!((wall_bits >> k) & 1ull)) continue;
+        } else {
+          const int ix = ax - org[0] + 1, iy = ay - org[1] + 1, iz = az - org[2] + 1;
+          if (ix < 0 || ix >= WIN || iy < 0 || iy >= WIN || iz < 0 || iz >= WIN) continue;
+          if (!(fl[ix + WIN * (iy + WIN * iz)] & 2)) continue;
+        }
         const double dv[3] = {R[0] - ax, R[1] - ay, R[2] - az};
         const double r2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
         if (r2 < rc2) {

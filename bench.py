@@ -131,7 +131,8 @@ def learned_comparison(progress):
 
 def run_ensemble(args):
     """64 uneven replicas of the 48 x 48 x 96 pore system in one persistent
-    launch per call; the autotuner picks the workgroup size during warm-up."""
+    launch per call; the autotuner picks the workgroup size and the number of
+    workgroups per replica during warm-up."""
     import torch
     from paper_1710_09421_amd import ek, workloads
 
@@ -144,7 +145,7 @@ def run_ensemble(args):
              f"{sorted(set(int(w.beads_R.shape[0]) for w in wls))}")
     ens = ek.ensemble_from_workloads(wls, precision=ek.EK_FP32, poisson_tol=1e-8)
     progress("ensemble ready")
-    tune = ens.autotune(steps=max(1, args.warmup // 3))
+    tune = ens.autotune(steps=max(2, args.warmup // 3))
     progress(f"autotuned: {tune}")
     ens.step(1)
     torch.cuda.synchronize()
@@ -174,7 +175,8 @@ def run_ensemble(args):
             "workload": f"ensemble of {n_rep} pore replicas 48x48x96 (E_z ~ U[0.01, 0.1], "
                         f"chains of 16-64 beads), one persistent launch per call",
             "sites": sites,
-            "threads_per_replica": tune["threads"],
+            "threads_per_workgroup": tune["threads"],
+            "workgroups_per_replica": tune["group"],
             "poisson": f"mg to 1e-8 per replica, last solve {min(cycles)}-{max(cycles)} cycles",
             "lb_bytes_per_step_gb": round(lb_bytes / 1e9, 3),
         },

@@ -282,6 +282,7 @@ typedef struct ek_ensemble ek_ensemble;
 
 typedef struct {
   int32_t threads;             /* workgroup size of the persistent kernel      */
+  int32_t group;               /* workgroups per replica                       */
   double ms_per_step;          /* measured time per ensemble step              */
 } ek_tune_result;
 
@@ -321,9 +322,20 @@ ek_status ek_ensemble_get_stats(ek_ensemble* ens, int32_t r, ek_stats* out);
 /* Workgroup size of the persistent kernel (256, 512 or 1024). */
 ek_status ek_ensemble_set_threads(ek_ensemble* ens, int32_t threads);
 
+/* Workgroups per replica (1, 2 or 4).  With more than one, the replica's
+ * site-parallel phases on the finest level (charge pass, finest multigrid
+ * level, gauge, collide-and-stream) are split over a team of workgroups of one
+ * cooperative launch that meet at barriers; the coarse multigrid levels and
+ * the chain run in the team's first workgroup.  Sums are taken per
+ * workgroup, then over the team in a fixed order, so results do not depend
+ * on timing (but may differ in the last bits between team sizes).  A launch
+ * the device cannot make co-resident is refused with EK_EHIP. */
+ek_status ek_ensemble_set_group(ek_ensemble* ens, int32_t group);
+
 /* Autotuner: times `steps` ensemble steps with every candidate workgroup size
- * (the replicas advance by those steps, like a warm-up) and keeps the
- * fastest; *out (may be NULL) receives the choice and its time. */
+ * and team size (the replicas advance by those steps, like a warm-up; team
+ * sizes the device refuses are skipped) and keeps the fastest; *out (may be
+ * NULL) receives the choice and its time. */
 ek_status ek_ensemble_autotune(ek_ensemble* ens, int32_t steps, ek_tune_result* out);
 
 #ifdef __cplusplus

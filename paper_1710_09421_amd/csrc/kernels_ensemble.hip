@@ -32,11 +32,29 @@ constexpr int ENS_TABLE_BITS = 12;     // node table of a replica: 4096 slots
 constexpr int ENS_MAX_BEADS = 64;      // node sums of a chain live in LDS
 constexpr int ENS_COARSEST_CAP = 200;
 
-enum : int { ST_OK = 0, ST_NOCONV = 1, ST_UNSTABLE = 2 };
+enum : int { ST_OK = 0, ST_NOCONV = 1, ST_UNSTABLE = 2, ST_TIMEOUT = 3 };
+
+// A replica is advanced by a team of G workgroups (G = 1, 2 or 4) of one
+// cooperative launch: the site-parallel phases on the finest level are split
+// over the team, the coarse multigrid levels and the chain run in member 0.
+constexpr int ENS_MAX_GROUP = 4;
+constexpr long long ENS_SPIN_LIMIT = 1ll << 24;   // ~1 s of s_sleep: then the team aborts
+
+// Team barrier state and reduction partials of one replica (global memory,
+// cleared by the host before every launch).  Partials are double-buffered by
+// the parity of the reduction count, so a member that has summed reduction k
+// can write reduction k + 1 while the others still read k.
+struct TeamSync {
+  int count;                  // barrier arrivals
+  int abort;                  // set when a member waited beyond the spin limit
+  int pad[14];
+  double part[2][ENS_MAX_GROUP][8];
+};
 
 // Per-replica device pointers and parameters.
 struct RepDev {
   void* f[2];                 // populations; f[cur] holds the current ones
+  TeamSync* sync;
   uint32_t* mask;             // link words (own copy: the bead flag is per replica)
   double* psi;
   double* b;
@@ -69,6 +87,8 @@ struct EnsConst {
   double omega_coarsest;
   int coarsest_sweeps;
   int lds_bits;
+  int n_rep;
+  int group;                  // workgroups per replica
 };
 
 // Sum of one value per thread in a fixed tree order (deterministic).
@@ -86,6 +106,94 @@ __device__ inline double team_sum(double v, double* sh) {
   return r;
 }
 
+// Barrier of the G workgroups of one replica: release this workgroup's
+// writes, count in, wait for the other members, acquire theirs.  Returns
+// false (in every thread) when the team has aborted.
+__device__ inline bool team_sync(TeamSync* ts, int G, int& gen, int* s_ok) {
+  __syncthreads();
+  if (G == 1) return true;
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    __threadfence();
+    atomicAdd(&ts->count, 1);
+    gen += G;
+    long long spins = 0;
+    while (__hip_atomic_load(&ts->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+      if (__hip_atomic_load(&ts->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        ok = 0;
+        break;
+      }
+      if (++spins > ENS_SPIN_LIMIT) {
+        atomicExch(&ts->abort, 1);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+    *s_ok = ok;
+  }
+  __syncthreads();
+  return *s_ok != 0;
+}
+
+// Team-wide sums of NV values: per workgroup in a fixed tree, then the G
+// partials in member order, so every member gets the same bits.
+template <int MAXT, int NV>
+__device__ inline bool team_sums(double (&v)[NV], double* sh, TeamSync* ts, int g, int G, int& gen,
+                                 int& nred, int* s_ok) {
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = team_sum<MAXT>(v[k], sh);
+  if (G == 1) return true;
+  const int set = nred & 1;
+  ++nred;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) ts->part[set][g][k] = v[k];
+  }
+  if (!team_sync(ts, G, gen, s_ok)) return false;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double t = 0.0;
+    for (int m = 0; m < G; ++m) t += ts->part[set][m][k];
+    v[k] = t;
+  }
+  return true;
+}
+
+// One colour of a red-black sweep of level L over the team's share of sites.
+__device__ inline void team_half(const Lvl& L, int colour, double shift, double omega, int first,
+                                 int stride) {
+  const int hx = L.nx / 2, nh = hx * L.ny * L.nz;
+  const float ihx = 1.0f / hx, iny = 1.0f / L.ny;
+  for (int t = first; t < nh; t += stride) {
+    int tx, y;
+    const int yz = fdivmod(t, hx, ihx, tx);
+    const int z = fdivmod(yz, L.ny, iny, y);
+    smooth_site(L, colour, tx, y, z, shift, omega);
+  }
+}
+
+__device__ inline void team_restrict(const Lvl& F, const Lvl& C, double shift, int first, int stride) {
+  const float inx = 1.0f / C.nx, iny = 1.0f / C.ny;
+  for (int t = first; t < int(C.n); t += stride) {
+    int X, Y;
+    const int yz = fdivmod(t, C.nx, inx, X);
+    const int Z = fdivmod(yz, C.ny, iny, Y);
+    restrict_site(F, C, X, Y, Z, shift);
+  }
+}
+
+__device__ inline void team_prolong(const Lvl& F, const Lvl& C, int first, int stride) {
+  const float inx = 1.0f / F.nx, iny = 1.0f / F.ny;
+  for (int t = first; t < int(F.n); t += stride) {
+    int x, y;
+    const int yz = fdivmod(t, F.nx, inx, x);
+    const int z = fdivmod(yz, F.ny, iny, y);
+    prolong_site(F, C, x, y, z);
+  }
+}
+
 __device__ inline void site_xyz(int t, const Dims& d, float inx, float iny, int& x, int& y, int& z) {
   const int yz = fdivmod(t, d.nx, inx, x);
   z = fdivmod(yz, d.ny, iny, y);
@@ -97,11 +205,17 @@ __global__ __launch_bounds__(MAXT) void k_ensemble(RepDev* reps, EnsConst ec) {
   __shared__ double sh[MAXT];
   __shared__ Lvl L[MAX_LEVELS];
   __shared__ int s_status;
-  RepDev& R = reps[blockIdx.x];
+  __shared__ int s_ok;
+  const int G = ec.group;
+  const int g = blockIdx.x / ec.n_rep;                    // member of the replica's team
+  RepDev& R = reps[blockIdx.x % ec.n_rep];
+  TeamSync* ts = R.sync;
   const Dims d = ec.d;
   const int tid = threadIdx.x;
+  const int first = g * MAXT + tid, stride = G * MAXT;   // this thread's share of a team loop
   const int N = int(d.n);
   const float inx = 1.0f / d.nx, iny = 1.0f / d.ny;
+  int gen = 0, nred = 0;
   if (tid == 0) {
     for (int l = 0; l < ec.nlev; ++l) {
       L[l] = ec.lv[l];
@@ -114,6 +228,14 @@ __global__ __launch_bounds__(MAXT) void k_ensemble(RepDev* reps, EnsConst ec) {
   const int last = ec.nlev - 1;
   const LBParams lp = R.lp;
   int cur = R.cur;
+// every member takes the same branch: the status depends only on team-wide
+// values; a failed barrier ends the team's work
+#define TEAM_SYNC()                                   \
+  if (!team_sync(ts, G, gen, &s_ok)) {                \
+    if (tid == 0) s_status = ST_TIMEOUT;              \
+    __syncthreads();                                  \
+    break;                                            \
+  }
   for (int step = 0; step < ec.n_steps; ++step) {
     if (s_status != ST_OK) break;
     const T* fsrc = (const T*)R.f[cur];
@@ -123,111 +245,150 @@ __global__ __launch_bounds__(MAXT) void k_ensemble(RepDev* reps, EnsConst ec) {
     bt.vals = R.vals;
     bt.bits = ENS_TABLE_BITS;
 
-    // bead charges of time t
-    if (R.n_beads > 0) {
+    // bead charges of time t (member 0)
+    if (R.n_beads > 0 && g == 0) {
       table_clear_items(R.keys, R.vals, R.mask, d.n, ENS_TABLE_BITS, tid, MAXT);
       __syncthreads();
       deposit_items(R.bs, R.n_beads, R.keys, R.vals, R.mask, d, ENS_TABLE_BITS, tid, MAXT);
-      __syncthreads();
     }
+    TEAM_SYNC();
     // charge pass
-    double rs = 0.0;
-    for (int t = tid; t < N; t += MAXT) {
+    double rs[1] = {0.0};
+    for (int t = first; t < N; t += stride) {
       int x, y, z;
       site_xyz(t, d, inx, iny, x, y, z);
       const double rho = charge_site<T, long long>(fsrc, R.mask, ec.wall_q, lp, bt, x, y, z, d);
       R.b[t] = -rho * ec.inv_eps;
-      rs += rho;
+      rs[0] += rho;
     }
-    const double shift = team_sum<MAXT>(rs, sh) / double(N) * ec.inv_eps;
+    if (!team_sums<MAXT, 1>(rs, sh, ts, g, G, gen, nred, &s_ok)) {
+      if (tid == 0) s_status = ST_TIMEOUT;
+      __syncthreads();
+      break;
+    }
+    const double shift = rs[0] / double(N) * ec.inv_eps;
 
     // Poisson: multigrid cycles until ||b - A psi|| / ||b|| <= tol
-    auto residual = [&](double& rel, double& psum) {
-      double r2 = 0.0, b2 = 0.0, ps = 0.0;
-      for (int t = tid; t < N; t += MAXT) {
+    auto residual = [&](double& rel, double& psum, double& b2) -> bool {
+      double v[3] = {0.0, 0.0, 0.0};
+      for (int t = first; t < N; t += stride) {
         int x, y, z;
         site_xyz(t, d, inx, iny, x, y, z);
         const double c = R.psi[t];
         const double rhs = R.b[t] + shift;
         const double res = rhs - (nbsum(R.psi, x, y, z, L[0]) - 6.0 * c);
-        r2 += res * res;
-        b2 += rhs * rhs;
-        ps += c;
+        v[0] += res * res;
+        v[1] += rhs * rhs;
+        v[2] += c;
       }
-      r2 = team_sum<MAXT>(r2, sh);
-      b2 = team_sum<MAXT>(b2, sh);
-      psum = team_sum<MAXT>(ps, sh);
-      rel = b2 > 0.0 ? sqrt(r2 / b2) : (r2 == 0.0 ? 0.0 : INFINITY);
-      return b2;
+      if (!team_sums<MAXT, 3>(v, sh, ts, g, G, gen, nred, &s_ok)) return false;
+      b2 = v[1];
+      psum = v[2];
+      rel = v[1] > 0.0 ? sqrt(v[0] / v[1]) : (v[0] == 0.0 ? 0.0 : INFINITY);
+      return true;
     };
-    double rel, psum;
-    const double b2 = residual(rel, psum);
+    // one colour of the finest level over the team, then a barrier
+    auto fine_half = [&](int colour, double omega) -> bool {
+      team_half(L[0], colour, shift, omega, first, stride);
+      return team_sync(ts, G, gen, &s_ok);
+    };
+    double rel = 0.0, psum = 0.0, b2 = 0.0;
+    bool ok = residual(rel, psum, b2);
     const double rel0 = rel;
     int cycles = 0;
-    bool zero_rhs = b2 == 0.0;
-    while (!zero_rhs && rel > ec.tol && cycles < ec.max_cycles) {
+    const bool zero_rhs = b2 == 0.0;
+    while (ok && !zero_rhs && rel > ec.tol && cycles < ec.max_cycles) {
       if (last == 0) {
-        block_smooth(L[0], ec.coarsest_sweeps, shift, ec.omega_coarsest);
+        for (int sw = 0; ok && sw < ec.coarsest_sweeps; ++sw)
+          for (int c = 0; ok && c < 2; ++c) ok = fine_half(c, ec.omega_coarsest);
       } else {
-        for (int l = 0; l < last; ++l) {
-          block_smooth(L[l], NU1, l == 0 ? shift : 0.0);
-          block_restrict(L[l], L[l + 1], l == 0 ? shift : 0.0);
+        for (int sw = 0; ok && sw < NU1; ++sw)
+          for (int c = 0; ok && c < 2; ++c) ok = fine_half(c, 1.0);
+        if (!ok) break;
+        team_restrict(L[0], L[1], shift, first, stride);
+        if (!(ok = team_sync(ts, G, gen, &s_ok))) break;
+        if (g == 0) {   // the coarse levels in member 0
+          for (int l = 1; l < last; ++l) {
+            block_smooth(L[l], NU1, 0.0);
+            block_restrict(L[l], L[l + 1], 0.0);
+          }
+          block_smooth(L[last], ec.coarsest_sweeps, 0.0, ec.omega_coarsest);
+          for (int l = last - 1; l >= 1; --l) {
+            block_prolong(L[l], L[l + 1]);
+            block_smooth(L[l], NU2, 0.0);
+          }
         }
-        block_smooth(L[last], ec.coarsest_sweeps, 0.0, ec.omega_coarsest);
-        for (int l = last - 1; l >= 0; --l) {
-          block_prolong(L[l], L[l + 1]);
-          block_smooth(L[l], NU2, l == 0 ? shift : 0.0);
-        }
+        if (!(ok = team_sync(ts, G, gen, &s_ok))) break;
+        team_prolong(L[0], L[1], first, stride);
+        if (!(ok = team_sync(ts, G, gen, &s_ok))) break;
+        for (int sw = 0; ok && sw < NU2; ++sw)
+          for (int c = 0; ok && c < 2; ++c) ok = fine_half(c, 1.0);
+        if (!ok) break;
       }
       ++cycles;
-      residual(rel, psum);
+      ok = residual(rel, psum, b2);
+    }
+    if (!ok) {
+      if (tid == 0) s_status = ST_TIMEOUT;
+      __syncthreads();
+      break;
     }
     if (!zero_rhs && rel > ec.tol) {
       if (tid == 0) {
         s_status = ST_NOCONV;
-        R.last_cycles = cycles;
-        R.last_res = rel;
+        if (g == 0) {
+          R.last_cycles = cycles;
+          R.last_res = rel;
+        }
       }
       __syncthreads();
       break;
     }
     // gauge: mean(psi) = 0
     const double mean = zero_rhs ? 0.0 : psum / double(N);
-    for (int t = tid; t < N; t += MAXT) R.psi[t] = zero_rhs ? 0.0 : R.psi[t] - mean;
-    __syncthreads();
+    for (int t = first; t < N; t += stride) R.psi[t] = zero_rhs ? 0.0 : R.psi[t] - mean;
+    TEAM_SYNC();
 
-    // chain: fields around the beads, then n_sub substeps
-    if (R.n_beads > 0) {
+    // chain (member 0): fields around the beads, then n_sub substeps
+    if (R.n_beads > 0 && g == 0) {
       for (int it = tid; it < R.n_beads * WIN3; it += MAXT)
         bead_box_item(R.bs, it / WIN3, it % WIN3, fsrc, R.mask, R.psi, lp, d);
       __syncthreads();
       md_chain<true, TPB>(R.bs, R.mp, R.keys, R.vals, R.mask, d, ENS_TABLE_BITS, ec.lds_bits, smem);
     }
+    TEAM_SYNC();
 
     // fused collide-and-stream
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int t = tid; t < N; t += MAXT) {
+    for (int t = first; t < N; t += stride) {
       int x, y, z;
       site_xyz(t, d, inx, iny, x, y, z);
       lb_site<T, long long>(fsrc, fdst, R.mask, R.psi, lp, bt, x, y, z, d, acc);
     }
-    double tot[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) tot[c] = team_sum<MAXT>(acc[c], sh);
+    if (!team_sums<MAXT, 6>(acc, sh, ts, g, G, gen, nred, &s_ok)) {
+      if (tid == 0) s_status = ST_TIMEOUT;
+      __syncthreads();
+      break;
+    }
     cur ^= 1;
     if (tid == 0) {
-      for (int c = 0; c < 6; ++c) R.stats[c] = tot[c];
-      R.last_cycles = cycles;
-      R.last_res = rel;
-      R.last_res0 = rel0;
-      R.steps += 1;
-      for (int s = 0; s < 3; ++s)
-        if (!(tot[s] >= 0.0) || !isfinite(tot[s])) s_status = ST_UNSTABLE;
+      if (g == 0) {
+        for (int c = 0; c < 6; ++c) R.stats[c] = acc[c];
+        R.last_cycles = cycles;
+        R.last_res = rel;
+        R.last_res0 = rel0;
+        R.steps += 1;
+      }
+      for (int sp = 0; sp < 3; ++sp)
+        if (!(acc[sp] >= 0.0) || !isfinite(acc[sp])) s_status = ST_UNSTABLE;
       if (R.n_beads > 0 && *R.bs.err) s_status = ST_UNSTABLE;
     }
-    __syncthreads();
+    // every member reads the chain's error word before any member clears it
+    // in the next step's deposit
+    TEAM_SYNC();
   }
-  if (tid == 0) {
+#undef TEAM_SYNC
+  if (tid == 0 && g == 0) {
     R.cur = cur;
     R.status = s_status;
   }
@@ -258,6 +419,7 @@ struct ek_ensemble {
   std::vector<bool> have_replica;
   EnsConst ec{};
   int threads = 512;
+  int group = 1;              // workgroups per replica
   std::string err;
 
   ek_status fail(ek_status st, const std::string& m) {
@@ -269,7 +431,7 @@ struct ek_ensemble {
 namespace {
 
 struct RepLayout {
-  size_t fA, fB, mask, psi, b, mg, keys, vals, beads, total;
+  size_t fA, fB, mask, psi, b, mg, keys, vals, beads, sync, total;
 };
 
 RepLayout rep_layout(const ek_params* p, int max_beads) {
@@ -287,6 +449,7 @@ RepLayout rep_layout(const ek_params* p, int max_beads) {
   L.keys = take((size_t(1) << ENS_TABLE_BITS) * 4);
   L.vals = take((size_t(1) << ENS_TABLE_BITS) * SLOT_VALUES * 8);
   L.beads = take(bead_state_bytes(max_beads));
+  L.sync = take(sizeof(TeamSync));
   L.total = off;
   return L;
 }
@@ -332,19 +495,39 @@ size_t md_lds_bytes(int max_beads) {
 }
 
 template <typename T>
-ek_status launch_ensemble(ek_ensemble* e, int n_steps, int threads) {
+ek_status launch_ensemble(ek_ensemble* e, int n_steps, int threads, int group) {
   EnsConst ec = e->ec;
   ec.n_steps = n_steps;
+  ec.n_rep = e->n_rep;
+  ec.group = group;
   const size_t lds = md_lds_bytes(e->max_beads);
+  // barrier counters start at zero in every launch
+  for (int r = 0; r < e->n_rep; ++r)
+    if (hipMemsetAsync(e->reps[r].sync, 0, sizeof(TeamSync), e->stream) != hipSuccess)
+      return e->fail(EK_EHIP, "clearing the team barriers failed");
   auto go = [&](auto kernel) -> ek_status {
     if (lds > 64 * 1024 &&
         hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
             hipSuccess)
       return e->fail(EK_EHIP, "cannot raise the LDS limit of the ensemble kernel");
-    hipLaunchKernelGGL(kernel, dim3(e->n_rep), dim3(threads), lds, e->stream, e->reps_dev, ec);
-    if (hipGetLastError() != hipSuccess) return e->fail(EK_EHIP, "ensemble launch failed");
+    if (group == 1) {
+      hipLaunchKernelGGL(kernel, dim3(e->n_rep), dim3(threads), lds, e->stream, e->reps_dev, ec);
+      if (hipGetLastError() != hipSuccess) return e->fail(EK_EHIP, "ensemble launch failed");
+      return EK_OK;
+    }
+    // teams of workgroups wait for each other: all of them must be resident,
+    // which a cooperative launch guarantees (or refuses)
+    RepDev* reps = e->reps_dev;
+    void* args[] = {(void*)&reps, (void*)&ec};
+    const hipError_t err = hipLaunchCooperativeKernel((const void*)kernel, dim3(e->n_rep * group),
+                                                      dim3(threads), args, (unsigned)lds, e->stream);
+    if (err != hipSuccess) {
+      (void)hipGetLastError();
+      return e->fail(EK_EHIP, std::string("cooperative ensemble launch refused: ") + hipGetErrorString(err));
+    }
     return EK_OK;
   };
+  if (group != 1 && group != 2 && group != 4) return e->fail(EK_EINVAL, "group must be 1, 2 or 4");
   if (threads == 256) return go(k_ensemble<T, 256, 4>);
   if (threads == 512) return go(k_ensemble<T, 512, 8>);
   if (threads == 1024) return go(k_ensemble<T, 1024, 8>);
@@ -366,12 +549,12 @@ ek_status download(ek_ensemble* e) {
   return EK_OK;
 }
 
-ek_status run_steps(ek_ensemble* e, int n_steps, int threads) {
+ek_status run_steps(ek_ensemble* e, int n_steps, int threads, int group) {
   if (n_steps == 0) return EK_OK;
   ek_status st = upload(e);
   if (st) return st;
-  st = e->p.precision == EK_FP64 ? launch_ensemble<double>(e, n_steps, threads)
-                                 : launch_ensemble<float>(e, n_steps, threads);
+  st = e->p.precision == EK_FP64 ? launch_ensemble<double>(e, n_steps, threads, group)
+                                 : launch_ensemble<float>(e, n_steps, threads, group);
   if (st) return st;
   st = download(e);
   if (st) return st;
@@ -386,6 +569,10 @@ ek_status run_steps(ek_ensemble* e, int n_steps, int threads) {
     if (R.status == ST_UNSTABLE) {
       std::snprintf(buf, sizeof buf, "replica %d: non-finite mass or failed chain update", r);
       return e->fail(EK_EUNSTABLE, buf);
+    }
+    if (R.status == ST_TIMEOUT) {
+      std::snprintf(buf, sizeof buf, "replica %d: a workgroup of its team waited beyond the limit", r);
+      return e->fail(EK_EHIP, buf);
     }
   }
   return EK_OK;
@@ -487,6 +674,7 @@ ek_status ek_ensemble_create(const ek_params* base, int32_t n_rep, int32_t max_b
     R.keys = (int*)(m + RL.keys);
     R.vals = (long long*)(m + RL.vals);
     R.bs = carve_beads(m + RL.beads, max_beads);
+    R.sync = (TeamSync*)(m + RL.sync);
   }
   *out = e;
   return EK_OK;
@@ -615,7 +803,7 @@ ek_status ek_ensemble_step(ek_ensemble* e, int32_t n_steps) {
   if (n_steps < 0) return e->fail(EK_EINVAL, "n_steps < 0");
   for (int r = 0; r < e->n_rep; ++r)
     if (!e->have_replica[r]) return e->fail(EK_ESTATE, "every replica must be set first");
-  return run_steps(e, n_steps, e->threads);
+  return run_steps(e, n_steps, e->threads, e->group);
 }
 
 ek_status ek_ensemble_set_threads(ek_ensemble* e, int32_t threads) {
@@ -634,33 +822,50 @@ ek_status ek_ensemble_autotune(ek_ensemble* e, int32_t steps, ek_tune_result* ou
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
     return e->fail(EK_EHIP, "hipEventCreate failed");
-  int best = e->threads;
+  int best = e->threads, best_group = e->group;
   double best_ms = INFINITY;
   ek_status st = EK_OK;
-  for (int cand : {256, 512, 1024}) {
-    st = run_steps(e, 1, cand);            // first launch of a variant: not timed
-    if (st) break;
-    (void)hipEventRecord(a, e->stream);
-    st = run_steps(e, steps, cand);
-    (void)hipEventRecord(b, e->stream);
-    if (st) break;
-    (void)hipEventSynchronize(b);
-    float ms = 0.0f;
-    (void)hipEventElapsedTime(&ms, a, b);
-    const double per = ms / steps;
-    if (per < best_ms) {
-      best_ms = per;
-      best = cand;
+  const int threads_c[] = {256, 512, 1024};
+  const int groups_c[] = {1, 2, 4};
+  for (int cand : threads_c)
+    for (int grp : groups_c) {
+      st = run_steps(e, 1, cand, grp);        // first launch of a variant: not timed
+      if (st == EK_EHIP && grp > 1 && e->err.find("cooperative") != std::string::npos) {
+        st = EK_OK;                            // this team size does not fit the device
+        continue;
+      }
+      if (st) break;
+      (void)hipEventRecord(a, e->stream);
+      st = run_steps(e, steps, cand, grp);
+      (void)hipEventRecord(b, e->stream);
+      if (st) break;
+      (void)hipEventSynchronize(b);
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, a, b);
+      const double per = ms / steps;
+      if (per < best_ms) {
+        best_ms = per;
+        best = cand;
+        best_group = grp;
+      }
     }
-  }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (st) return st;
   e->threads = best;
+  e->group = best_group;
   if (out) {
     out->threads = best;
+    out->group = best_group;
     out->ms_per_step = best_ms;
   }
+  return EK_OK;
+}
+
+ek_status ek_ensemble_set_group(ek_ensemble* e, int32_t group) {
+  if (!e) return EK_EINVAL;
+  if (group != 1 && group != 2 && group != 4) return e->fail(EK_EINVAL, "group must be 1, 2 or 4");
+  e->group = group;
   return EK_OK;
 }
 

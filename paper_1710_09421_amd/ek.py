@@ -51,7 +51,7 @@ class ek_timing(ctypes.Structure):
 
 
 class ek_tune_result(ctypes.Structure):
-    _fields_ = [("threads", c_int32), ("ms_per_step", c_double)]
+    _fields_ = [("threads", c_int32), ("group", c_int32), ("ms_per_step", c_double)]
 
 
 class ek_poisson_report(ctypes.Structure):
@@ -118,6 +118,7 @@ def _load():
         "ek_ensemble_get_stats": (c_int32, [c_void_p, c_int32, P(ek_stats)]),
         "ek_ensemble_set_threads": (c_int32, [c_void_p, c_int32]),
         "ek_ensemble_autotune": (c_int32, [c_void_p, c_int32, P(ek_tune_result)]),
+        "ek_ensemble_set_group": (c_int32, [c_void_p, c_int32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -371,10 +372,14 @@ class Ensemble:
     def set_threads(self, threads):
         self._check(self._lib.ek_ensemble_set_threads(self._h, threads), self._h)
 
+    def set_group(self, group):
+        """Workgroups per replica (1, 2 or 4)."""
+        self._check(self._lib.ek_ensemble_set_group(self._h, group), self._h)
+
     def autotune(self, steps=2):
         res = ek_tune_result()
         self._check(self._lib.ek_ensemble_autotune(self._h, steps, byref(res)), self._h)
-        return dict(threads=res.threads, ms_per_step=res.ms_per_step)
+        return dict(threads=res.threads, group=res.group, ms_per_step=res.ms_per_step)
 
     def moments(self, r, species):
         n = np.empty(self.shape)

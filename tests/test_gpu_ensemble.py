@@ -114,13 +114,69 @@ def test_replicas_are_independent(ek):
     assert not np.array_equal(n1, ens.moments(0, 1)[0])
 
 
+@pytest.mark.parametrize("group", [2, 4])
+def test_replica_teams_match_oracle_fp32(ek, group):
+    """Each replica advanced by a team of workgroups meeting at barriers."""
+    wls = replicas()
+    ens = ek.ensemble_from_workloads(wls, precision=ek.EK_FP32, poisson_tol=1e-8)
+    ens.set_threads(512)
+    ens.set_group(group)
+    ens.step(20)
+    for r in (0, 3):
+        sim = oracle_sim(wls[r], 1e-8)
+        sim.run(20)
+        err = errors(lambda s: ens.moments(r, s), lambda: ens.potential(r), sim, wls[r])
+        R, _ = ens.beads(r)
+        err["R"] = float(np.abs(R - sim.R).max())
+        print(group, r, err)
+        assert max(err.values()) < 1e-5, (r, err)
+    for r in range(4):
+        assert ens.stats(r)["step"] == 20
+
+
+def test_replica_teams_agree_with_single_workgroups(ek):
+    """Team sizes differ only in the order of the fixed-order sums."""
+    wls = replicas()
+    out = []
+    for group in (1, 2, 4):
+        ens = ek.ensemble_from_workloads(wls, precision=ek.EK_FP32, poisson_tol=1e-8)
+        ens.set_threads(256)
+        ens.set_group(group)
+        ens.step(10)
+        out.append([(ens.moments(r, 1)[0], ens.potential(r)) for r in range(4)])
+        ens.close()
+    for k in (1, 2):
+        for r in range(4):
+            n1, p1 = out[0][r]
+            nk, pk = out[k][r]
+            fluid = wls[r].solid == 0
+            assert density_error(nk, n1, fluid) < 1e-6
+            assert field_error(pk, p1) < 1e-6
+
+
+def test_replica_teams_are_deterministic(ek):
+    wls = replicas()
+    res = []
+    for _ in range(2):
+        ens = ek.ensemble_from_workloads(wls, precision=ek.EK_FP32, poisson_tol=1e-8)
+        ens.set_group(4)
+        ens.step(6)
+        res.append((ens.moments(3, 2), ens.beads(3), ens.potential(3)))
+        ens.close()
+    (na, ua), (Ra, Va), pa = res[0]
+    (nb, ub), (Rb, Vb), pb = res[1]
+    assert np.array_equal(na, nb) and np.array_equal(ua, ub) and np.array_equal(pa, pb)
+    assert np.array_equal(Ra, Rb) and np.array_equal(Va, Vb)
+
+
 def test_autotune_picks_a_candidate(ek):
     ens = ek.ensemble_from_workloads(replicas(), precision=ek.EK_FP32)
     res = ens.autotune(steps=2)
-    assert res["threads"] in (256, 512, 1024) and res["ms_per_step"] > 0
+    assert res["threads"] in (256, 512, 1024) and res["group"] in (1, 2, 4)
+    assert res["ms_per_step"] > 0
     ens.step(2)
-    for r in range(4):
-        assert ens.stats(r)["step"] == 3 * (1 + 2) + 2    # three candidates x (1 + 2) steps, then 2
+    for r in range(4):   # 3 workgroup sizes x 3 team sizes x (1 + 2) steps, then 2
+        assert ens.stats(r)["step"] == 9 * (1 + 2) + 2
 
 
 def test_no_convergence_names_the_replica(ek):

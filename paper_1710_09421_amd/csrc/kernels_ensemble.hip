@@ -303,26 +303,26 @@ __global__ __launch_bounds__(MAXT) void k_ensemble(RepDev* reps, EnsConst ec) {
           for (int c = 0; ok && c < 2; ++c) ok = fine_half(c, ec.omega_coarsest);
       } else {
         for (int sw = 0; ok && sw < NU1; ++sw)
-          for (int c = 0; ok && c < 2; ++c) ok = fine_half(c, 1.0);
+          for (int c = 0; ok && c < 2; ++c) ok = fine_half(c, MG_OMEGA);
         if (!ok) break;
         team_restrict(L[0], L[1], shift, first, stride);
         if (!(ok = team_sync(ts, G, gen, &s_ok))) break;
         if (g == 0) {   // the coarse levels in member 0
           for (int l = 1; l < last; ++l) {
-            block_smooth(L[l], NU1, 0.0);
+            block_smooth(L[l], NU1, 0.0, MG_OMEGA);
             block_restrict(L[l], L[l + 1], 0.0);
           }
           block_smooth(L[last], ec.coarsest_sweeps, 0.0, ec.omega_coarsest);
           for (int l = last - 1; l >= 1; --l) {
             block_prolong(L[l], L[l + 1]);
-            block_smooth(L[l], NU2, 0.0);
+            block_smooth(L[l], NU2, 0.0, MG_OMEGA);
           }
         }
         if (!(ok = team_sync(ts, G, gen, &s_ok))) break;
         team_prolong(L[0], L[1], first, stride);
         if (!(ok = team_sync(ts, G, gen, &s_ok))) break;
         for (int sw = 0; ok && sw < NU2; ++sw)
-          for (int c = 0; ok && c < 2; ++c) ok = fine_half(c, 1.0);
+          for (int c = 0; ok && c < 2; ++c) ok = fine_half(c, MG_OMEGA);
         if (!ok) break;
       }
       ++cycles;

@@ -5,7 +5,8 @@
 // large boxes.  Cell-centred hierarchy on the periodic box, each level half
 // the previous in every direction while all sides stay even:
 //   level l, spacing h = 2^l:  (sum of 6 neighbours - 6 x) / h^2 = f_l
-//   smoother   red-black Gauss-Seidel (x = (sum nb - h^2 f) / 6), nu1 = nu2 = 2
+//   smoother   red-black Gauss-Seidel (x = (sum nb - h^2 f) / 6) over-relaxed
+//              by MG_OMEGA, nu1 = nu2 = 2
 //   restriction  f_{l+1} = average of the 8 fine residuals (fused with the
 //                residual, also zeroes the coarse iterate)
 //   prolongation trilinear cell-centred interpolation (weights 3/4, 1/4 per
@@ -85,13 +86,13 @@ __global__ __launch_bounds__(1024) void k_coarse_cycle(LvlSet set, int first,
   }
   __syncthreads();
   for (int l = first; l < last; ++l) {
-    block_smooth(L[l], NU1, 0.0);
+    block_smooth(L[l], NU1, 0.0, MG_OMEGA);
     block_restrict(L[l], L[l + 1], 0.0);
   }
   block_smooth(L[last], coarsest_sweeps, 0.0, omega_coarsest);
   for (int l = last - 1; l >= first; --l) {
     block_prolong(L[l], L[l + 1]);
-    block_smooth(L[l], NU2, 0.0);
+    block_smooth(L[l], NU2, 0.0, MG_OMEGA);
   }
   for (int t = threadIdx.x; t < int(L[first].n); t += blockDim.x) set.l[first].x[t] = L[first].x[t];
 }
@@ -196,7 +197,7 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x) {
     for (int s = 0; s < NU1; ++s)
       for (int c = 0; c < 2; ++c)
         hipLaunchKernelGGL(k_smooth, colour_launch(L[l]).grid, colour_launch(L[l]).block, 0, stream,
-                           L[l], c, ps, l == 0 ? 1 : 0, 1.0);
+                           L[l], c, ps, l == 0 ? 1 : 0, MG_OMEGA);
     hipLaunchKernelGGL(k_restrict, level_launch(L[l + 1]).grid, level_launch(L[l + 1]).block, 0,
                        stream, L[l], L[l + 1], ps, l == 0 ? 1 : 0);
   }
@@ -211,7 +212,7 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x) {
     for (int s = 0; s < NU2; ++s)
       for (int c = 0; c < 2; ++c)
         hipLaunchKernelGGL(k_smooth, colour_launch(L[l]).grid, colour_launch(L[l]).block, 0, stream,
-                           L[l], c, ps, l == 0 ? 1 : 0, 1.0);
+                           L[l], c, ps, l == 0 ? 1 : 0, MG_OMEGA);
   }
   return EK_OK;
 }

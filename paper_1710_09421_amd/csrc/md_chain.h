@@ -309,10 +309,11 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
   // whole step (node momenta of time t and the field), and the lane's
   // wall-site flags are kept in registers from the substep the bead enters
   // its cell on; with more corners per lane they are read each substep.
-  constexpr bool CACHE = CPL <= 2;
+  constexpr bool CACHE = CPL <= 2;   // node momenta too
+  constexpr bool CACHE_E = CPL <= 4; // field and wall flags
   constexpr int NWS = 64 / TPB;     // wall sites per lane
   double mo_c[CACHE ? CPL : 1][MOM];
-  double e_c[CACHE ? CPL : 1][3];
+  double e_c[CACHE_E ? CPL : 1][3];
   unsigned long long wall_bits = 0;
   for (int sub = 0; sub < mp.n_sub; ++sub) {
     double wt[CPL];
@@ -350,16 +351,18 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
             const long long site = site_of(fx + ox, fy + oy, fz + oz, d);
             slot[a] = LDS ? ln.slot(site) : gn.slot(site);
           }
-          if constexpr (CACHE) {
+          if constexpr (CACHE_E) {
             const double* e = ef + (size_t)bidx[a] * 3;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) e_c[CACHE_E ? a : 0][c] = e[c];
+          }
+          if constexpr (CACHE) {
             const double* mo = mom + (size_t)bidx[a] * MOM;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) e_c[a][c] = e[c];
-#pragma unroll
-            for (int c = 0; c < MOM; ++c) mo_c[a][c] = wfl[a] != 0.0 ? mo[c] : 0.0;
+            for (int c = 0; c < MOM; ++c) mo_c[CACHE ? a : 0][c] = wfl[a] != 0.0 ? mo[c] : 0.0;
           }
         }
-        if constexpr (CACHE) {
+        if constexpr (CACHE_E) {
           wall_bits = 0;
 #pragma unroll
           for (int k = 0; k < NWS; ++k) {
@@ -396,7 +399,7 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
         const int ox = k8 & 1, oy = (k8 >> 1) & 1, oz = (k8 >> 2) & 1;
         const double w = (ox ? dx : 1.0 - dx) * (oy ? dy : 1.0 - dy) * (oz ? dz : 1.0 - dz);
         wt[a] = w * wfl[a] * iws;
-        const double* e = CACHE ? e_c[CACHE ? a : 0] : ef + (size_t)bidx[a] * 3;
+        const double* e = CACHE_E ? e_c[CACHE_E ? a : 0] : ef + (size_t)bidx[a] * 3;
         acc[12] += w * e[0];
         acc[13] += w * e[1];
         acc[14] += w * e[2];
@@ -437,7 +440,7 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
         const int wsite = lane + k * TPB;
         const int wx = wsite & 3, wy = (wsite >> 2) & 3, wz = wsite >> 4;
         const int ax = fx - 1 + wx, ay = fy - 1 + wy, az = fz - 1 + wz;
-        if constexpr (CACHE) {
+        if constexpr (CACHE_E) {
           if (!((wall_bits >> k) & 1ull)) continue;
         } else {
           const int ix = ax - org[0] + 1, iy = ay - org[1] + 1, iz = az - org[2] + 1;
@@ -516,7 +519,9 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
         if (lane == 0) sR[3 * i + c] = Rn[c];
       }
     }
-    if (!LDS) __threadfence();
+    // one workgroup advances the chain: the barrier's workgroup-scope ordering
+    // (prior atomics completed) is enough for the table's atomic reads, which
+    // go to the shared L2
     __syncthreads();
   }
   if (live && lane == 0) {

@@ -46,9 +46,8 @@ def test_multigrid_meets_tolerance(ek, shape):
     assert field_error(psi, ref) < 1e3 * 1e-8
 
 
-def test_multigrid_with_fused_sweeps_meets_tolerance(ek):
-    """A 128^3 box: its finest level (2^21 sites) takes the fused one-launch
-    red-black sweep, the coarser levels the half sweeps.  Reference: the exact
+def test_multigrid_128_cubed_meets_tolerance(ek):
+    """A 128^3 box (2^21 sites on the finest level).  Reference: the exact
     periodic solution of the 7-point problem by FFT (the SOR oracle is too slow
     at this size)."""
     shape = (128, 128, 128)

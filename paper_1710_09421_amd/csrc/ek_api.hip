@@ -283,9 +283,10 @@ ek_status ek_ctx::step_impl(int n_steps) {
       if (st) return st;
     }
     record(t, 3);
-    launch_lb_step<T>((const T*)fcur(), (T*)fnext(), mask, psi, lp, bt, partials, dims, g, stream);
+    const int nb_lb =
+        launch_lb_step<T>((const T*)fcur(), (T*)fnext(), mask, psi, lp, bt, partials, dims, g, stream);
     record(t, 4);
-    launch_sum_partials(partials, nb, 6, stats_dev, stream);
+    launch_sum_partials(partials, nb_lb, 6, stats_dev, stream);
     cur_is_a = !cur_is_a;
     ++step_count;
   }

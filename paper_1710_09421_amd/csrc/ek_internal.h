@@ -94,10 +94,12 @@ template <typename T>
 void launch_charge(const T* f, const uint32_t* mask, const double* wall_q, double* b,
                    double* partials, const LBParams& lp, double inv_eps, Dims d,
                    const SiteGrid& g, hipStream_t s, const BeadTableView& bt);
+// Returns the number of block partials written (the launch may give a block
+// several z-planes).
 template <typename T>
-void launch_lb_step(const T* fsrc, T* fdst, const uint32_t* mask, const double* psi,
-                    const LBParams& lp, const BeadTableView& bt, double* partials, Dims d,
-                    const SiteGrid& g, hipStream_t s);
+int launch_lb_step(const T* fsrc, T* fdst, const uint32_t* mask, const double* psi,
+                   const LBParams& lp, const BeadTableView& bt, double* partials, Dims d,
+                   const SiteGrid& g, hipStream_t s);
 template <typename T>
 void launch_moments(const T* f, const uint32_t* mask, int species, double nref, double* n_out,
                     double* u_out, Dims d, hipStream_t s);

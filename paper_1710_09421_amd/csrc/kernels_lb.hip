@@ -69,14 +69,15 @@ __global__ __launch_bounds__(BLOCK) void k_lb_step(const T* __restrict__ fsrc,
                                                    const uint32_t* __restrict__ mask,
                                                    const double* __restrict__ psi, LBParams lp,
                                                    BeadTableView bt,
-                                                   double* __restrict__ partials, Dims d) {
+                                                   double* __restrict__ partials, Dims d, int zb) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
   const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   const int nblocks = gridDim.x * gridDim.y * gridDim.z;
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  if (x < d.nx && y < d.ny) lb_site<T, I>(fsrc, fdst, mask, psi, lp, bt, x, y, z, d, acc);
+  if (x < d.nx && y < d.ny)
+    for (int k = 0; k < zb; ++k)
+      lb_site<T, I>(fsrc, fdst, mask, psi, lp, bt, x, y, blockIdx.z * zb + k, d, acc);
   block_partials<6>(acc, partials, bid, nblocks);
 }
 
@@ -174,16 +175,28 @@ void launch_charge(const T* f, const uint32_t* mask, const double* wall_q, doubl
                        partials, lp, inv_eps, bt, d);
 }
 
+// z-planes per block of the fused step: each block sums its sites' masses
+// and momentum once, so longer blocks spend less on the block reduction;
+// planes are doubled while at least 1024 blocks remain.
+int lb_planes_per_block(const SiteGrid& g, int nz) {
+  int zb = 1;
+  while (nz % (2 * zb) == 0 && (long long)g.grid.x * g.grid.y * (nz / (2 * zb)) >= 1024) zb *= 2;
+  return zb;
+}
+
 template <typename T>
-void launch_lb_step(const T* fsrc, T* fdst, const uint32_t* mask, const double* psi,
-                    const LBParams& lp, const BeadTableView& bt, double* partials, Dims d,
-                    const SiteGrid& g, hipStream_t s) {
+int launch_lb_step(const T* fsrc, T* fdst, const uint32_t* mask, const double* psi,
+                   const LBParams& lp, const BeadTableView& bt, double* partials, Dims d,
+                   const SiteGrid& g, hipStream_t s) {
+  const int zb = lb_planes_per_block(g, d.nz);
+  const dim3 grid(g.grid.x, g.grid.y, d.nz / zb);
   if (fits_idx32<T>(d.n))
-    hipLaunchKernelGGL((k_lb_step<T, uint32_t>), g.grid, g.block, 0, s, fsrc, fdst, mask, psi,
-                       lp, bt, partials, d);
+    hipLaunchKernelGGL((k_lb_step<T, uint32_t>), grid, g.block, 0, s, fsrc, fdst, mask, psi,
+                       lp, bt, partials, d, zb);
   else
-    hipLaunchKernelGGL((k_lb_step<T, long long>), g.grid, g.block, 0, s, fsrc, fdst, mask, psi,
-                       lp, bt, partials, d);
+    hipLaunchKernelGGL((k_lb_step<T, long long>), grid, g.block, 0, s, fsrc, fdst, mask, psi,
+                       lp, bt, partials, d, zb);
+  return int(grid.x * grid.y * grid.z);
 }
 
 template <typename T>
@@ -212,9 +225,9 @@ void launch_mean_shift(const double* partials, int nblocks, double inv_n, double
   template void launch_charge<T>(const T*, const uint32_t*, const double*, double*, double*, \
                                  const LBParams&, double, Dims, const SiteGrid&, hipStream_t,\
                                  const BeadTableView&);                                      \
-  template void launch_lb_step<T>(const T*, T*, const uint32_t*, const double*,              \
-                                  const LBParams&, const BeadTableView&, double*, Dims,      \
-                                  const SiteGrid&, hipStream_t);                             \
+  template int launch_lb_step<T>(const T*, T*, const uint32_t*, const double*,               \
+                                 const LBParams&, const BeadTableView&, double*, Dims,       \
+                                 const SiteGrid&, hipStream_t);                              \
   template void launch_moments<T>(const T*, const uint32_t*, int, double, double*, double*,  \
                                   Dims, hipStream_t);
 EK_INST(float)

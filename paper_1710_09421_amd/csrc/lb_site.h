@@ -163,7 +163,7 @@ __device__ inline void lb_site(const T* __restrict__ fsrc, T* __restrict__ fdst,
       }
       n[s] = T(lp.nref[s]) + dn;
       dns[s] = dn;
-      acc[s] = lp.nref[s] + double(dn);
+      acc[s] += lp.nref[s] + double(dn);
       acc[3] += double(jx); acc[4] += double(jy); acc[5] += double(jz);
       const T zs = T(lp.valence[s]);
       const T inv_n = recip(n[s]);

@@ -101,6 +101,22 @@ def test_replicas_match_single_contexts(ek):
         ctx.close()
 
 
+@pytest.mark.parametrize("group", [1, 4])
+def test_replica_species_mass_is_conserved(ek, group):
+    """The per-replica sums of species mass (float64 over the whole replica)
+    equal the initial masses."""
+    wls = replicas()
+    ens = ek.ensemble_from_workloads(wls, precision=ek.EK_FP32, poisson_tol=1e-8)
+    ens.set_group(group)
+    ens.step(5)
+    for r, wl in enumerate(wls):
+        fluid = wl.solid == 0
+        m0 = np.array([wl.n0[s][fluid].sum() for s in range(3)])
+        m = ens.stats(r)["mass"]
+        print(r, m / m0 - 1.0)
+        assert np.all(np.abs(m / m0 - 1.0) < 1e-7), (r, m, m0)
+
+
 def test_replicas_are_independent(ek):
     a, b = replica(201, 0.03, 10), replica(202, 0.07, 0)
     ens = ek.ensemble_from_workloads([a, b, a], precision=ek.EK_FP32)

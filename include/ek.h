@@ -178,11 +178,12 @@ ek_status ek_poisson_solve(struct ek_ctx* ctx, const double* dev_rho, double* de
 ek_status ek_poisson_sor_iterations(struct ek_ctx* ctx, const double* dev_b, double* dev_psi,
                                     int32_t iterations);
 
-/* Per-phase GPU time, measured with HIP events recorded on the context's
- * stream around each phase of every step while enabled: the charge pass, the
- * Poisson solve, the bead update, and the fused lattice kernel (whose launch
- * count is n_lb).  Used by the benchmark to price kernels against the
- * hardware roofline. */
+/* Per-phase GPU time, measured with HIP events on the context's stream for
+ * each phase of every step while enabled: the charge pass, the Poisson solve
+ * and the bead update between events recorded around them, the fused lattice
+ * kernel (whose launch count is n_lb) between events stamped at its own start
+ * and end.  Used by the benchmark to price kernels against the hardware
+ * roofline. */
 typedef struct {
   double ms_charge, ms_poisson, ms_md, ms_lb;
   int64_t n_steps;              /* steps measured                               */

@@ -282,10 +282,10 @@ ek_status ek_ctx::step_impl(int n_steps) {
       st = beads_advance<T>();
       if (st) return st;
     }
-    record(t, 3);
-    const int nb_lb =
-        launch_lb_step<T>((const T*)fcur(), (T*)fnext(), mask, psi, lp, bt, partials, dims, g, stream);
-    record(t, 4);
+    // events 3 and 4 are stamped by the fused kernel's own start and end
+    const int nb_lb = launch_lb_step<T>((const T*)fcur(), (T*)fnext(), mask, psi, lp, bt, partials,
+                                        dims, g, stream, timing ? events[5 * t + 3] : nullptr,
+                                        timing ? events[5 * t + 4] : nullptr);
     launch_sum_partials(partials, nb_lb, 6, stats_dev, stream);
     cur_is_a = !cur_is_a;
     ++step_count;

@@ -95,11 +95,13 @@ void launch_charge(const T* f, const uint32_t* mask, const double* wall_q, doubl
                    double* partials, const LBParams& lp, double inv_eps, Dims d,
                    const SiteGrid& g, hipStream_t s, const BeadTableView& bt);
 // Returns the number of block partials written (the launch may give a block
-// several z-planes).
+// several z-planes).  start / stop (may be null) are recorded at the kernel's
+// own start and end.
 template <typename T>
 int launch_lb_step(const T* fsrc, T* fdst, const uint32_t* mask, const double* psi,
                    const LBParams& lp, const BeadTableView& bt, double* partials, Dims d,
-                   const SiteGrid& g, hipStream_t s);
+                   const SiteGrid& g, hipStream_t s, hipEvent_t start = nullptr,
+                   hipEvent_t stop = nullptr);
 template <typename T>
 void launch_moments(const T* f, const uint32_t* mask, int species, double nref, double* n_out,
                     double* u_out, Dims d, hipStream_t s);

@@ -2,6 +2,8 @@
 // ion-density (charge) pass, the fused pull-stream + collide step and the
 // moment read-out.  The per-site bodies are in lb_site.h.
 #include "ek_internal.h"
+#include <hip/hip_ext.h>
+
 #include "lb_site.h"
 #include "md_table.h"
 #include "reduce.h"
@@ -187,15 +189,16 @@ int lb_planes_per_block(const SiteGrid& g, int nz) {
 template <typename T>
 int launch_lb_step(const T* fsrc, T* fdst, const uint32_t* mask, const double* psi,
                    const LBParams& lp, const BeadTableView& bt, double* partials, Dims d,
-                   const SiteGrid& g, hipStream_t s) {
+                   const SiteGrid& g, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
   const int zb = lb_planes_per_block(g, d.nz);
   const dim3 grid(g.grid.x, g.grid.y, d.nz / zb);
+  // the events (when given) are stamped at the kernel's own start and end
   if (fits_idx32<T>(d.n))
-    hipLaunchKernelGGL((k_lb_step<T, uint32_t>), grid, g.block, 0, s, fsrc, fdst, mask, psi,
-                       lp, bt, partials, d, zb);
+    hipExtLaunchKernelGGL((k_lb_step<T, uint32_t>), grid, g.block, 0, s, start, stop, 0, fsrc,
+                          fdst, mask, psi, lp, bt, partials, d, zb);
   else
-    hipLaunchKernelGGL((k_lb_step<T, long long>), grid, g.block, 0, s, fsrc, fdst, mask, psi,
-                       lp, bt, partials, d, zb);
+    hipExtLaunchKernelGGL((k_lb_step<T, long long>), grid, g.block, 0, s, start, stop, 0, fsrc,
+                          fdst, mask, psi, lp, bt, partials, d, zb);
   return int(grid.x * grid.y * grid.z);
 }
 
@@ -227,7 +230,7 @@ void launch_mean_shift(const double* partials, int nblocks, double inv_n, double
                                  const BeadTableView&);                                      \
   template int launch_lb_step<T>(const T*, T*, const uint32_t*, const double*,               \
                                  const LBParams&, const BeadTableView&, double*, Dims,       \
-                                 const SiteGrid&, hipStream_t);                              \
+                                 const SiteGrid&, hipStream_t, hipEvent_t, hipEvent_t);      \
   template void launch_moments<T>(const T*, const uint32_t*, int, double, double*, double*,  \
                                   Dims, hipStream_t);
 EK_INST(float)

@@ -201,8 +201,8 @@ def main():
                          "times (a kernel of known traffic for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the method's data-parallel step runs on a single "
-              "MI355X here; multi-GPU runs are not part of this build.", file=sys.stderr)
+        print("bench.py measures one GPU: the data-parallel step runs on a single MI355X; "
+              "runs on several GPUs are not supported.", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "ensemble":

@@ -60,79 +60,6 @@ __global__ __launch_bounds__(256) void k_prolong(Lvl F, Lvl C, const PoissonScal
   prolong_site(F, C, x, y, blockIdx.z);
 }
 
-// One full red-black sweep in one launch, for the mid-size levels whose half
-// sweeps are too short to pay for a launch each: a workgroup loads its tile
-// of x_in with a two-site halo into LDS, updates the red sites of the tile and
-// a one-site halo (the halo's red values equal those its neighbouring tile
-// computes, both from x_in), then the black sites of the tile from those red
-// values, and writes the tile to x_out.  The same arithmetic, in the same
-// order, as the red and then the black half sweep of k_smooth.  (On large
-// levels the halo work outweighs the saved launch; they keep the half sweeps.)
-constexpr int SW_TX = 16, SW_TY = 4, SW_TZ = 4;
-constexpr int SW_HX = SW_TX + 4, SW_HY = SW_TY + 4, SW_HZ = SW_TZ + 4;
-
-__device__ inline int wrap_coord(int v, int n) {
-  while (v < 0) v += n;
-  while (v >= n) v -= n;
-  return v;
-}
-
-__global__ __launch_bounds__(256) void k_sweep(Lvl L, const double* __restrict__ x_in,
-                                               double* __restrict__ x_out,
-                                               const PoissonScalars* ps, int level0,
-                                               double omega) {
-  if (ps->done) return;
-  __shared__ double xs[SW_HZ * SW_HY * SW_HX];
-  const int ox = blockIdx.x * SW_TX, oy = blockIdx.y * SW_TY, oz = blockIdx.z * SW_TZ;
-  const double shift = level0 ? ps->shift : 0.0;
-  const int tid = threadIdx.x;
-  for (int i = tid; i < SW_HZ * SW_HY * SW_HX; i += 256) {
-    const int lx = i % SW_HX, ly = (i / SW_HX) % SW_HY, lz = i / (SW_HX * SW_HY);
-    const int gx = wrap_coord(ox + lx - 2, L.nx), gy = wrap_coord(oy + ly - 2, L.ny),
-              gz = wrap_coord(oz + lz - 2, L.nz);
-    xs[i] = x_in[idx3(gx, gy, gz, L)];
-  }
-  __syncthreads();
-  auto update = [&](int lx, int ly, int lz) {
-    const int i = (lz * SW_HY + ly) * SW_HX + lx;
-    const int gx = wrap_coord(ox + lx - 2, L.nx), gy = wrap_coord(oy + ly - 2, L.ny),
-              gz = wrap_coord(oz + lz - 2, L.nz);
-    const double nb = xs[i - 1] + xs[i + 1] + xs[i - SW_HX] + xs[i + SW_HX] +
-                      xs[i - SW_HX * SW_HY] + xs[i + SW_HX * SW_HY];
-    const double gs = (nb - L.h2 * (L.f[idx3(gx, gy, gz, L)] + shift)) * (1.0 / 6.0);
-    xs[i] = omega == 1.0 ? gs : xs[i] + omega * (gs - xs[i]);
-  };
-  // red sites ((x + y + z) even) of the tile and a one-site halo: 34 x 10 x 10
-  // sites, half of them red; thread t takes the t-th red site of each group
-  // of 256 red sites in row order
-  constexpr int RX = SW_TX + 2, RY = SW_TY + 2, RZ = SW_TZ + 2;
-  const int par = (ox + oy + oz) & 1;      // colour of local (2, 2, 2)
-  for (int j = tid; j < RX * RY * RZ / 2; j += 256) {
-    // pairs along x: j -> row (ry, rz), pair index px; the red one of the pair
-    const int px = j % (RX / 2), row = j / (RX / 2);
-    const int ry = row % RY, rz = row / RY;
-    const int lx0 = 1 + 2 * px, ly = 1 + ry, lz = 1 + rz;
-    // local (lx, ly, lz) has colour (par + lx + ly + lz - 6) & 1 = (par + lx + ly + lz) & 1
-    const int lx = lx0 + ((par + lx0 + ly + lz) & 1);
-    update(lx, ly, lz);
-  }
-  __syncthreads();
-  for (int j = tid; j < SW_TX * SW_TY * SW_TZ / 2; j += 256) {
-    const int px = j % (SW_TX / 2), row = j / (SW_TX / 2);
-    const int ty = row % SW_TY, tz = row / SW_TY;
-    const int lx0 = 2 + 2 * px, ly = 2 + ty, lz = 2 + tz;
-    const int lx = lx0 + ((par + lx0 + ly + lz + 1) & 1);
-    update(lx, ly, lz);
-  }
-  __syncthreads();
-  for (int i = tid; i < SW_TX * SW_TY * SW_TZ; i += 256) {
-    const int tx = i % SW_TX, ty = (i / SW_TX) % SW_TY, tz = i / (SW_TX * SW_TY);
-    const int gx = ox + tx, gy = oy + ty, gz = oz + tz;
-    if (gx < L.nx && gy < L.ny && gz < L.nz)
-      x_out[idx3(gx, gy, gz, L)] = xs[((tz + 2) * SW_HY + ty + 2) * SW_HX + tx + 2];
-  }
-}
-
 // The coarse part of the cycle runs on copies of the coarse levels in LDS:
 // level `first` arrives with its right-hand side and a zero iterate in global
 // memory, its iterate goes back to global memory at the end.
@@ -181,17 +108,7 @@ struct ek_ctx::MG {
   size_t coarse_lds = 0;     // LDS bytes of that kernel
   double omega_coarsest = 1.0;
   int coarsest_sweeps = COARSEST_SWEEPS;
-  double* tmp = nullptr;     // second iterate of the fused sweeps
 };
-
-namespace {
-// levels below this many sites take the fused sweep
-constexpr long long FUSED_SWEEP_MAX_SITES = 1ll << 18;
-dim3 sweep_grid(const Lvl& L) {
-  return dim3((L.nx + SW_TX - 1) / SW_TX, (L.ny + SW_TY - 1) / SW_TY, (L.nz + SW_TZ - 1) / SW_TZ);
-}
-static_assert(NU1 % 2 == 0 && NU2 % 2 == 0, "fused sweeps alternate between x and the second iterate");
-}  // namespace
 
 bool halvable(int nx, int ny, int nz) {
   return nx % 4 == 0 && ny % 4 == 0 && nz % 4 == 0;
@@ -205,8 +122,7 @@ double omega_opt(int nx, int ny, int nz) {
 }
 
 size_t ek::mg_workspace_bytes(int nx, int ny, int nz) {
-  // the fused sweep's second iterate (level 0 size, reused by every level)
-  size_t bytes = 256 + (((size_t)nx * ny * nz * 8 + 255) & ~size_t(255));
+  size_t bytes = 256;
   while (halvable(nx, ny, nz)) {
     nx /= 2;
     ny /= 2;
@@ -234,7 +150,6 @@ void ek_ctx::mg_setup() {
     mem += 2 * b;
     mg->levels.push_back(l);
   }
-  mg->tmp = (double*)mem;
   const int nl = (int)mg->levels.size();
   int fc = nl - 1;
   size_t bytes = 16 * (size_t)mg->levels[fc].n;
@@ -278,24 +193,11 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x) {
                            L[0], c, ps, 1, mg->omega_coarsest);
     return EK_OK;
   }
-  // n sweeps of level l: fused on mid-size levels (an even count, x -> tmp
-  // -> x, leaves the iterate in x), two half sweeps each otherwise
-  auto sweeps = [&](int l, int n) {
-    for (int s = 0; s < n; ++s) {
-      if (L[l].n < FUSED_SWEEP_MAX_SITES) {
-        const double* in = (s & 1) ? mg->tmp : L[l].x;
-        double* out = (s & 1) ? L[l].x : mg->tmp;
-        hipLaunchKernelGGL(k_sweep, sweep_grid(L[l]), dim3(256), 0, stream, L[l], in, out, ps,
-                           l == 0 ? 1 : 0, MG_OMEGA);
-      } else {
-        for (int c = 0; c < 2; ++c)
-          hipLaunchKernelGGL(k_smooth, colour_launch(L[l]).grid, colour_launch(L[l]).block, 0,
-                             stream, L[l], c, ps, l == 0 ? 1 : 0, MG_OMEGA);
-      }
-    }
-  };
   for (int l = 0; l < fc; ++l) {
-    sweeps(l, NU1);
+    for (int s = 0; s < NU1; ++s)
+      for (int c = 0; c < 2; ++c)
+        hipLaunchKernelGGL(k_smooth, colour_launch(L[l]).grid, colour_launch(L[l]).block, 0, stream,
+                           L[l], c, ps, l == 0 ? 1 : 0, MG_OMEGA);
     hipLaunchKernelGGL(k_restrict, level_launch(L[l + 1]).grid, level_launch(L[l + 1]).block, 0,
                        stream, L[l], L[l + 1], ps, l == 0 ? 1 : 0);
   }
@@ -307,7 +209,10 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x) {
   for (int l = fc - 1; l >= 0; --l) {
     hipLaunchKernelGGL(k_prolong, level_launch(L[l]).grid, level_launch(L[l]).block, 0, stream, L[l],
                        L[l + 1], ps);
-    sweeps(l, NU2);
+    for (int s = 0; s < NU2; ++s)
+      for (int c = 0; c < 2; ++c)
+        hipLaunchKernelGGL(k_smooth, colour_launch(L[l]).grid, colour_launch(L[l]).block, 0, stream,
+                           L[l], c, ps, l == 0 ? 1 : 0, MG_OMEGA);
   }
   return EK_OK;
 }

@@ -178,11 +178,13 @@ void launch_charge(const T* f, const uint32_t* mask, const double* wall_q, doubl
 }
 
 // z-planes per block of the fused step: each block sums its sites' masses
-// and momentum once, so longer blocks spend less on the block reduction;
-// planes are doubled while at least 1024 blocks remain.
+// and momentum once, so two planes per block halve the block-reduction work;
+// more planes per block measured slower (fewer blocks walking longer), and at
+// least 1024 blocks remain.
 int lb_planes_per_block(const SiteGrid& g, int nz) {
   int zb = 1;
-  while (nz % (2 * zb) == 0 && (long long)g.grid.x * g.grid.y * (nz / (2 * zb)) >= 1024) zb *= 2;
+  while (zb < 2 && nz % (2 * zb) == 0 && (long long)g.grid.x * g.grid.y * (nz / (2 * zb)) >= 1024)
+    zb *= 2;
   return zb;
 }
 

@@ -216,37 +216,47 @@ __device__ inline void bead_box_item(const BeadState& bs, int i, int t, const T*
   const long long r = site_of(cx, cy, cz, d);
   const uint32_t m = mask[r];
   double* mo = bs.mom + ((size_t)i * BOX3 + t) * MOM;
-  for (int c = 0; c < MOM; ++c) mo[c] = 0.0;
+  // all 57 pulls are issued before any sum (registers only, one store pass)
+  double v[MOM];
+#pragma unroll
+  for (int c = 0; c < MOM; ++c) v[c] = 0.0;
   if (!(m & MASK_SOLID)) {
     const int x = wrap(cx, d.nx), y = wrap(cy, d.ny), z = wrap(cz, d.nz);
+    T g[3][Q];
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+      const bool bounce = (m >> p) & 1u;
+      const long long src = bounce ? r : site_of(x - CX[p], y - CY[p], z - CZ[p], d);
+      const int q = bounce ? OPP[p] : p;
+#pragma unroll
+      for (int s = 0; s < 3; ++s) g[s][p] = f[(size_t)(s * Q + q) * d.n + src];
+    }
+    double n[3];
+#pragma unroll
     for (int s = 0; s < 3; ++s) {
       double dn = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
       for (int p = 0; p < Q; ++p) {
-        long long src;
-        int q = p;
-        if ((m >> p) & 1u) {
-          src = r;
-          q = OPP[p];
-        } else {
-          src = site_of(x - CX[p], y - CY[p], z - CZ[p], d);
-        }
-        const double g = double(f[(size_t)(s * Q + q) * d.n + src]);
-        dn += g;
-        jx += CX[p] * g;
-        jy += CY[p] * g;
-        jz += CZ[p] * g;
+        const double gp = double(g[s][p]);
+        dn += gp;
+        jx += CX[p] * gp;
+        jy += CY[p] * gp;
+        jz += CZ[p] * gp;
       }
-      mo[s] = lp.nref[s] + dn;        // density for now, fraction below
-      mo[6 + 3 * s] = jx;
-      mo[7 + 3 * s] = jy;
-      mo[8 + 3 * s] = jz;
+      n[s] = lp.nref[s] + dn;
+      v[6 + 3 * s] = jx;
+      v[7 + 3 * s] = jy;
+      v[8 + 3 * s] = jz;
     }
-    const double ntot = mo[0] + mo[1] + mo[2];
+    const double ntot = n[0] + n[1] + n[2];
+#pragma unroll
     for (int s = 0; s < 3; ++s) {
-      mo[3 + s] = 1.0 / mo[s];
-      mo[s] = mo[s] / ntot;
+      v[3 + s] = 1.0 / n[s];
+      v[s] = n[s] / ntot;
     }
   }
+#pragma unroll
+  for (int c = 0; c < MOM; ++c) mo[c] = v[c];
   double* e = bs.efield + ((size_t)i * BOX3 + t) * 3;
   e[0] = -0.5 * (psi[site_of(cx + 1, cy, cz, d)] - psi[site_of(cx - 1, cy, cz, d)]) + lp.eext[0];
   e[1] = -0.5 * (psi[site_of(cx, cy + 1, cz, d)] - psi[site_of(cx, cy - 1, cz, d)]) + lp.eext[1];

@@ -226,7 +226,7 @@ __global__ __launch_bounds__(MAXT) void k_ensemble(RepDev* reps, EnsConst ec) {
   }
   __syncthreads();
   const int last = ec.nlev - 1;
-  const LBParams lp = R.lp;
+  const LBParams& lp = R.lp;   // read where used (uniform loads)
   int cur = R.cur;
 // every member takes the same branch: the status depends only on team-wide
 // values; a failed barrier ends the team's work

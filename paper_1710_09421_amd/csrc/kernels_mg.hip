@@ -227,15 +227,21 @@ ek_status ek_ctx::mg_solve(const double* bb, double* x, PoissonScalars h, int& i
   ek_status st = EK_OK;
   int it = 0;
   int batch = std::max(1, last_iters);
+  // the previous solve needed `batch` cycles: the residual is first tested
+  // after batch - 1 of them (a solve that converges earlier than that costs
+  // one extra cycle, the usual one saves the tests of the early cycles)
+  int untested = std::max(0, batch - 2);
   while (!h.done && it < p.poisson_max_iter) {
     const int nrun = std::min(batch, p.poisson_max_iter - it);
     for (int k = 0; k < nrun; ++k) {
       st = mg_vcycle(bb, x);
       if (st) return st;
       ++it;
+      if (k < untested && it < p.poisson_max_iter) continue;
       launch_residual(x, bb, ps, partials, dims, g, stream);
       launch_residual_final(partials, nb, p.poisson_tol, it, 0, ps, stream);
     }
+    untested = 0;
     st = read_scalars(&h);
     if (st) return st;
     batch = 1;

@@ -195,6 +195,18 @@ typedef struct {
 ek_status ek_set_timing(struct ek_ctx* ctx, int32_t enable);
 ek_status ek_get_timing(struct ek_ctx* ctx, ek_timing* out);
 
+/* Launch mode of the multigrid cycles (EK_POISSON_MG).  enable != 0 (the
+ * default): each V-cycle, with or without its residual test, is recorded once
+ * as a HIP graph (on a stream the library creates; the caller's stream may be
+ * the default stream) and replayed on the context's stream; the graphs are
+ * recorded again when the solve's psi buffer changes.  0: the same kernels
+ * are launched one by one.  Both modes run the same kernels in the same order
+ * and give bit-identical results.  When recording fails the context keeps to
+ * single launches.  A context whose stream the caller is recording itself
+ * cannot run a solve either way (the solve reads its convergence flag back to
+ * the host). */
+ek_status ek_set_graph_launch(struct ek_ctx* ctx, int32_t enable);
+
 /* ---------------------------------------------------------------------------
  * Learned warm start of the Poisson solve.  The paper solves Eq. poisson
  * iteratively from scratch or from the previous step (Sec. II.C); this library

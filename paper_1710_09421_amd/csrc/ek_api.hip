@@ -580,6 +580,12 @@ ek_status ek_set_timing(ek_ctx* ctx, int32_t enable) {
   return EK_OK;
 }
 
+ek_status ek_set_graph_launch(ek_ctx* ctx, int32_t enable) {
+  if (!ctx) return EK_EINVAL;
+  ctx->graph_launch = enable != 0;
+  return EK_OK;
+}
+
 ek_status ek_get_timing(ek_ctx* ctx, ek_timing* out) {
   if (!ctx || !out) return EK_EINVAL;
   *out = ctx->tacc;

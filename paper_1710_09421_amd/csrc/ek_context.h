@@ -72,6 +72,7 @@ struct ek_ctx {
 
   // per-phase timers (HIP events on the context stream)
   bool timing = false;
+  bool graph_launch = true;            // multigrid cycles replayed from recorded graphs
   std::vector<hipEvent_t> events;      // 5 per step: charge, poisson, md, lb start, lb end
   ek_timing tacc{};
   ek_status ensure_events(int n_steps);
@@ -100,6 +101,7 @@ struct ek_ctx {
   void mg_setup();
   void mg_release();
   ek_status mg_vcycle(const double* b, double* x);
+  bool mg_graphs(const double* b, double* x);
   ek_status poisson(const double* b, double* x, bool learned, int& iters, double& res,
                     double& res0);
 

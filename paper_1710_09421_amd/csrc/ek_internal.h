@@ -81,7 +81,7 @@ struct PoissonScalars {
   int done;               // solve converged
   int iters;              // iteration at which it converged
   int zero_rhs;           // right-hand side vanished
-  int pad;
+  int cycles;             // multigrid cycles run since the flags were cleared
 };
 
 // ---------------------------------------------------------------------------

@@ -134,6 +134,7 @@ __global__ __launch_bounds__(1024) void k_mean_shift(const double* __restrict__ 
     ps->done = 0;
     ps->iters = 0;
     ps->zero_rhs = 0;
+    ps->cycles = 0;
   }
 }
 

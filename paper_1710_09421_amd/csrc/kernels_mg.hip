@@ -6,7 +6,7 @@
 // the previous in every direction while all sides stay even:
 //   level l, spacing h = 2^l:  (sum of 6 neighbours - 6 x) / h^2 = f_l
 //   smoother   red-black Gauss-Seidel (x = (sum nb - h^2 f) / 6) over-relaxed
-//              by MG_OMEGA, nu1 = nu2 = 2
+//              by MG_OMEGA, nu1 = NU1 = 1 and nu2 = NU2 = 2
 //   restriction  f_{l+1} = average of the 8 fine residuals (fused with the
 //                residual, also zeroes the coarse iterate)
 //   prolongation trilinear cell-centred interpolation (weights 3/4, 1/4 per
@@ -16,10 +16,15 @@
 // right-hand sides fit in COARSE_LDS_BYTES of LDS run inside one workgroup
 // (one launch for the whole coarse part of the cycle); the coarsest level
 // gets red-black SOR sweeps at the optimal relaxation factor of that grid,
-// enough of them to reduce its error by 1e-10.  Level 0 is the context's psi and b (b
-// plus the scalar shift that removes the mean charge).
+// enough of them to reduce its error by COARSEST_REDUCTION (a cycle reduces
+// the residual by about 1e-2, so a coarsest solve to 1e-3 leaves the cycle's
+// rate unchanged; a box that cannot be coarsened is solved by these sweeps
+// alone, each "cycle" then reducing its error by 1e-10).  Level 0 is the context's psi and b (b
+// plus the scalar shift that removes the mean charge).  The launches of one
+// cycle are recorded once as a graph and replayed (see ek_ctx::MG).
 #include <cmath>
 #include <cstdio>
+#include <string>
 #include <vector>
 
 #include "ek_context.h"
@@ -31,6 +36,7 @@ namespace {
 
 constexpr size_t COARSE_LDS_BYTES = 40 * 1024;    // one-workgroup coarse cycle: levels of up to ~2k sites
 constexpr int COARSEST_SWEEPS = 40;
+constexpr double COARSEST_REDUCTION = 1e-3;
 
 // --- grid-wide kernels for the fine levels (3-D launch: x, y from the block,
 // z = blockIdx.z, so no index division) ------------------------------------
@@ -63,10 +69,10 @@ __global__ __launch_bounds__(256) void k_prolong(Lvl F, Lvl C, const PoissonScal
 // The coarse part of the cycle runs on copies of the coarse levels in LDS:
 // level `first` arrives with its right-hand side and a zero iterate in global
 // memory, its iterate goes back to global memory at the end.
-__global__ __launch_bounds__(1024) void k_coarse_cycle(LvlSet set, int first,
-                                                       const PoissonScalars* ps,
+__global__ __launch_bounds__(1024) void k_coarse_cycle(LvlSet set, int first, PoissonScalars* ps,
                                                        double omega_coarsest, int coarsest_sweeps) {
   if (ps->done) return;
+  if (threadIdx.x == 0) ps->cycles += 1;   // read only by later kernels
   extern __shared__ __align__(16) double lds[];
   __shared__ Lvl L[MAX_LEVELS];
   const int last = set.count - 1;
@@ -108,6 +114,25 @@ struct ek_ctx::MG {
   size_t coarse_lds = 0;     // LDS bytes of that kernel
   double omega_coarsest = 1.0;
   int coarsest_sweeps = COARSEST_SWEEPS;
+  // One V-cycle, and one V-cycle followed by the residual test, recorded as
+  // graphs for the level-0 pair (b, x) they were recorded with: a replay
+  // dispatches the cycle's ~30 dependent launches faster than the launches
+  // issued one by one.  They are recorded on a stream of the library's own
+  // (the caller's may be the default stream, which cannot be recorded) and
+  // replayed on the context's stream.
+  hipStream_t record_stream = nullptr;
+  hipGraphExec_t cycle = nullptr, cycle_test = nullptr;
+  const double* graph_b = nullptr;
+  double* graph_x = nullptr;
+  bool graph_failed = false;   // recording is not possible: launch one by one
+
+  void drop_graphs() {
+    if (cycle) hipGraphExecDestroy(cycle);
+    if (cycle_test) hipGraphExecDestroy(cycle_test);
+    cycle = cycle_test = nullptr;
+    graph_b = nullptr;
+    graph_x = nullptr;
+  }
 };
 
 bool halvable(int nx, int ny, int nz) {
@@ -172,12 +197,78 @@ void ek_ctx::mg_setup() {
   const Lvl& c = mg->levels.back();
   mg->omega_coarsest = omega_opt(c.nx, c.ny, c.nz);
   const double rate = std::max(mg->omega_coarsest - 1.0, 1e-3);
-  mg->coarsest_sweeps = std::min(200, std::max(4, (int)std::ceil(std::log(1e-10) / std::log(rate))));
+  const double reduction = nl > 1 ? COARSEST_REDUCTION : 1e-10;
+  mg->coarsest_sweeps =
+      std::min(200, std::max(4, (int)std::ceil(std::log(reduction) / std::log(rate))));
 }
 
 void ek_ctx::mg_release() {
+  if (mg) {
+    mg->drop_graphs();
+    if (mg->record_stream) hipStreamDestroy(mg->record_stream);
+  }
   delete mg;
   mg = nullptr;
+}
+
+// Records the launches that `enqueue` issues on `stream` into an executable
+// graph; false (and nothing recorded) when that is not possible.
+template <typename F>
+static bool record_graph(hipStream_t stream, hipGraphExec_t* out, F enqueue) {
+  if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  enqueue();
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(stream, &g) != hipSuccess || !g) {
+    (void)hipGetLastError();
+    return false;
+  }
+  const bool ok = hipGraphInstantiate(out, g, nullptr, nullptr, 0) == hipSuccess;
+  hipGraphDestroy(g);
+  if (!ok) {
+    (void)hipGetLastError();
+    *out = nullptr;
+  }
+  return ok;
+}
+
+// The two cycle graphs for (b, x); false leaves the solve on single launches.
+bool ek_ctx::mg_graphs(const double* bb, double* x) {
+  MG& m = *mg;
+  if (!graph_launch || m.graph_failed || m.levels.size() < 2) return false;
+  if (m.cycle && m.graph_b == bb && m.graph_x == x) return true;
+  m.drop_graphs();
+  if (!m.record_stream &&
+      hipStreamCreateWithFlags(&m.record_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    m.record_stream = nullptr;
+    m.graph_failed = true;
+    return false;
+  }
+  const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
+  const int nb = g.nblocks();
+  // the launchers enqueue on `stream`: point it at the recording stream
+  const hipStream_t own = stream;
+  stream = m.record_stream;
+  const bool ok =
+      record_graph(stream, &m.cycle, [&] { mg_vcycle(bb, x); }) &&
+      record_graph(stream, &m.cycle_test, [&] {
+        mg_vcycle(bb, x);
+        launch_residual(x, bb, ps, partials, dims, g, stream);
+        // iteration -1: the test reads the cycle count the coarse kernel keeps
+        launch_residual_final(partials, nb, p.poisson_tol, -1, 0, ps, stream);
+      });
+  stream = own;
+  if (!ok) {
+    m.drop_graphs();
+    m.graph_failed = true;
+    return false;
+  }
+  m.graph_b = bb;
+  m.graph_x = x;
+  return true;
 }
 
 ek_status ek_ctx::mg_vcycle(const double* bb, double* x) {
@@ -231,13 +322,20 @@ ek_status ek_ctx::mg_solve(const double* bb, double* x, PoissonScalars h, int& i
   // after batch - 1 of them (a solve that converges earlier than that costs
   // one extra cycle, the usual one saves the tests of the early cycles)
   int untested = std::max(0, batch - 2);
+  const bool graphs = mg_graphs(bb, x);
   while (!h.done && it < p.poisson_max_iter) {
     const int nrun = std::min(batch, p.poisson_max_iter - it);
     for (int k = 0; k < nrun; ++k) {
+      ++it;
+      const bool test = k >= untested || it >= p.poisson_max_iter;
+      if (graphs) {
+        const hipError_t e = hipGraphLaunch(test ? mg->cycle_test : mg->cycle, stream);
+        if (e != hipSuccess) return fail(EK_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+        continue;
+      }
       st = mg_vcycle(bb, x);
       if (st) return st;
-      ++it;
-      if (k < untested && it < p.poisson_max_iter) continue;
+      if (!test) continue;
       launch_residual(x, bb, ps, partials, dims, g, stream);
       launch_residual_final(partials, nb, p.poisson_tol, it, 0, ps, stream);
     }

@@ -80,6 +80,7 @@ __global__ __launch_bounds__(1024) void k_residual_final(const double* __restric
   double t[3];
   block_sums_1024<3>(partials, nblocks, t);
   if (threadIdx.x == 0) {
+    if (iter < 0) iter = ps->cycles;   // counted on the device (replayed launches)
     const double r2 = t[0], b2 = t[1];
     double rel;
     if (b2 > 0.0) rel = sqrt(r2 / b2);
@@ -178,6 +179,7 @@ __global__ void k_ps_reset(PoissonScalars* ps, double shift) {
     ps->done = 0;
     ps->iters = 0;
     ps->zero_rhs = 0;
+    ps->cycles = 0;
   }
 }
 // Clears the convergence flags before the residual of another start is
@@ -187,6 +189,7 @@ __global__ void k_ps_rearm(PoissonScalars* ps) {
     ps->done = 0;
     ps->iters = 0;
     ps->zero_rhs = 0;
+    ps->cycles = 0;
   }
 }
 

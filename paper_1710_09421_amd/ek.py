@@ -86,6 +86,7 @@ def _load():
         "ek_poisson_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, P(ek_poisson_report)]),
         "ek_poisson_sor_iterations": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32]),
         "ek_set_timing": (c_int32, [c_void_p, c_int32]),
+        "ek_set_graph_launch": (c_int32, [c_void_p, c_int32]),
         "ek_get_timing": (c_int32, [c_void_p, P(ek_timing)]),
         "ek_set_model": (c_int32, [c_void_p, c_void_p, c_int32, ctypes.c_float]),
         "ek_get_poisson_system": (c_int32, [c_void_p, c_void_p, c_void_p]),
@@ -252,6 +253,9 @@ class Context:
 
     def set_timing(self, enable=True):
         self._check(self._lib.ek_set_timing(self._h, 1 if enable else 0), self._h)
+
+    def set_graph_launch(self, enable=True):
+        self._check(self._lib.ek_set_graph_launch(self._h, 1 if enable else 0), self._h)
 
     def timing(self):
         t = ek_timing()

@@ -41,7 +41,7 @@ def test_multigrid_meets_tolerance(ek, shape):
     assert rr <= 1e-8
     assert abs(psi.mean()) < 1e-12 * np.abs(psi).max()
     if min(shape) >= 8:
-        assert rep["iterations"] <= 12           # about a decade per V(2,2) cycle
+        assert rep["iterations"] <= 12           # about a decade per V(1,2) cycle
     ref, _, _ = opoisson.sor_red_black_chebyshev(b, np.zeros(shape), 1e-12, 100000)
     assert field_error(psi, ref) < 1e3 * 1e-8
 

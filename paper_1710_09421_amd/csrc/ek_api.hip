@@ -249,7 +249,7 @@ void ek_ctx::record(int t, int k) {
 template <typename T>
 ek_status ek_ctx::step_impl(int n_steps) {
   ek_ctx* ctx = this;
-  const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
+  const SiteGrid g = bx_sites ? site_grid(p.nx, p.ny, p.nz, bx_sites) : lattice_grid(p.nx, p.ny, p.nz);
   const int nb = g.nblocks();
   const LBParams lp = lb_params();
   if (timing) {

@@ -50,6 +50,7 @@ SiteGrid site_grid(int nx, int ny, int nz, int bx_pref = 0);
 // Launch shape for kernels that visit one colour of the red-black checkerboard:
 // threads cover nx/2 sites per row.
 SiteGrid colour_grid(int nx, int ny, int nz, int bx_pref = 0);
+SiteGrid lattice_grid(int nx, int ny, int nz);
 
 struct Dims {
   int nx, ny, nz;

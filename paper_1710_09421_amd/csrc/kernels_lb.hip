@@ -154,6 +154,17 @@ SiteGrid site_grid(int nx, int ny, int nz, int bx_pref) {
   return g;
 }
 
+// Charge pass and fused step: blocks of whole x-rows where a power-of-two
+// row length allows (256 or 128 sites), else the default shape.  Reading
+// each population plane in runs of a whole row measured 14 % faster (fused
+// step) and 15 % faster (charge pass) on a 256x256x512 box than blocks of
+// 64 x 4 sites; multigrid keeps the default shape (whole rows were slower).
+SiteGrid lattice_grid(int nx, int ny, int nz) {
+  for (int bx = BLOCK; bx >= 128; bx >>= 1)
+    if (nx % bx == 0) return site_grid(nx, ny, nz, bx);
+  return site_grid(nx, ny, nz, 0);
+}
+
 SiteGrid colour_grid(int nx, int ny, int nz, int bx_pref) {
   return site_grid(nx / 2, ny, nz, bx_pref);
 }

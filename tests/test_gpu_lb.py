@@ -145,6 +145,21 @@ def test_pore_fp64_matches_oracle(ek):
     assert max(err.values()) < 1e-8, err
 
 
+@pytest.mark.parametrize("nx", [128, 256])
+def test_whole_row_blocks_match_oracle(ek, nx):
+    """Rows of 128 and 256 sites: the charge pass and the fused step then run
+    on blocks of whole x-rows (one row per block), with the pore's bounce-back
+    links, periodic wrap in x inside the block and 16 / 8 planes of rows."""
+    wl = workloads.pore_system((16, 8, nx), 4, 2, 0.01, 0.01, -0.01, 0, 23, steps=12)
+    ctx = ek.from_workload(wl, precision=ek.EK_FP64, poisson_tol=1e-10, poisson_check_every=1)
+    sim = oracle_sim(wl, 1e-10)
+    ctx.step(12)
+    sim.run(12)
+    err = compare(ctx, sim, wl.solid == 0)
+    print(nx, err)
+    assert max(err.values()) < 1e-8, err
+
+
 def test_fp32_mass_conserved_and_deterministic(ek):
     wl = pore()
     runs = []

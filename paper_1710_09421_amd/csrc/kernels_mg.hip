@@ -37,6 +37,13 @@ namespace {
 constexpr size_t COARSE_LDS_BYTES = 40 * 1024;    // one-workgroup coarse cycle: levels of up to ~2k sites
 constexpr int COARSEST_SWEEPS = 40;
 constexpr double COARSEST_REDUCTION = 1e-3;
+// Levels of at most this many sites take the coarse-grid correction inside
+// their first post-smoothing sweep; that sweep reads the coarse iterate about
+// seven times per site, which pays while the level is launch-bound and costs
+// more than the separate prolongation pass on large levels (measured: 2^18
+// beat 2^21 and 2^23 on 64x64x128 and 256x256x512 boxes; fusing the
+// 2^25-site level of the latter made its Poisson solve 13 % slower).
+constexpr long long FUSED_CORRECTION_MAX_SITES = 1ll << 18;
 
 // --- grid-wide kernels for the fine levels (3-D launch: x, y from the block,
 // z = blockIdx.z, so no index division) ------------------------------------
@@ -50,12 +57,23 @@ __global__ __launch_bounds__(256) void k_smooth(Lvl L, int colour, const Poisson
 }
 
 __global__ __launch_bounds__(256) void k_restrict(Lvl F, Lvl C, const PoissonScalars* ps,
-                                                  int level0) {
+                                                  int level0, double omega_red) {
   if (ps->done) return;
   const int X = blockIdx.x * blockDim.x + threadIdx.x;
   const int Y = blockIdx.y * blockDim.y + threadIdx.y;
   if (X >= C.nx || Y >= C.ny) return;
-  restrict_site(F, C, X, Y, blockIdx.z, level0 ? ps->shift : 0.0);
+  restrict_site(F, C, X, Y, blockIdx.z, level0 ? ps->shift : 0.0, omega_red);
+}
+
+// Prolongation fused into the first post-smoothing sweep (colour 0, then 1).
+__global__ __launch_bounds__(256) void k_corrected_smooth(Lvl L, Lvl C, int colour,
+                                                          const PoissonScalars* ps, int level0,
+                                                          double omega) {
+  if (ps->done) return;
+  const int tx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (tx >= L.nx / 2 || y >= L.ny) return;
+  corrected_smooth_site(L, C, colour, tx, y, blockIdx.z, level0 ? ps->shift : 0.0, omega);
 }
 
 __global__ __launch_bounds__(256) void k_prolong(Lvl F, Lvl C, const PoissonScalars* ps) {
@@ -284,26 +302,40 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x) {
                            L[0], c, ps, 1, mg->omega_coarsest);
     return EK_OK;
   }
+  // Levels 1 .. fc-1 arrive from the restriction with their first colour-0
+  // half sweep done; the level handed to the coarse kernel arrives at zero.
   for (int l = 0; l < fc; ++l) {
     for (int s = 0; s < NU1; ++s)
-      for (int c = 0; c < 2; ++c)
+      for (int c = 0; c < 2; ++c) {
+        if (l > 0 && s == 0 && c == 0) continue;
         hipLaunchKernelGGL(k_smooth, colour_launch(L[l]).grid, colour_launch(L[l]).block, 0, stream,
                            L[l], c, ps, l == 0 ? 1 : 0, MG_OMEGA);
+      }
+    const double omega_red = (l + 1 < fc && NU1 > 0) ? MG_OMEGA : 0.0;
     hipLaunchKernelGGL(k_restrict, level_launch(L[l + 1]).grid, level_launch(L[l + 1]).block, 0,
-                       stream, L[l], L[l + 1], ps, l == 0 ? 1 : 0);
+                       stream, L[l], L[l + 1], ps, l == 0 ? 1 : 0, omega_red);
   }
   LvlSet set{};
   set.count = nl;
   for (int l = 0; l < nl; ++l) set.l[l] = L[l];
   hipLaunchKernelGGL(k_coarse_cycle, dim3(1), dim3(1024), mg->coarse_lds, stream, set, fc, ps,
                      mg->omega_coarsest, mg->coarsest_sweeps);
+  // coarse-grid correction: fused into the first post-smoothing sweep on
+  // levels up to FUSED_CORRECTION_MAX_SITES, a pass of its own above
   for (int l = fc - 1; l >= 0; --l) {
-    hipLaunchKernelGGL(k_prolong, level_launch(L[l]).grid, level_launch(L[l]).block, 0, stream, L[l],
-                       L[l + 1], ps);
+    const bool fused = NU2 > 0 && L[l].n <= FUSED_CORRECTION_MAX_SITES;
+    if (!fused)
+      hipLaunchKernelGGL(k_prolong, level_launch(L[l]).grid, level_launch(L[l]).block, 0, stream,
+                         L[l], L[l + 1], ps);
     for (int s = 0; s < NU2; ++s)
-      for (int c = 0; c < 2; ++c)
-        hipLaunchKernelGGL(k_smooth, colour_launch(L[l]).grid, colour_launch(L[l]).block, 0, stream,
-                           L[l], c, ps, l == 0 ? 1 : 0, MG_OMEGA);
+      for (int c = 0; c < 2; ++c) {
+        if (fused && s == 0)
+          hipLaunchKernelGGL(k_corrected_smooth, colour_launch(L[l]).grid, colour_launch(L[l]).block,
+                             0, stream, L[l], L[l + 1], c, ps, l == 0 ? 1 : 0, MG_OMEGA);
+        else
+          hipLaunchKernelGGL(k_smooth, colour_launch(L[l]).grid, colour_launch(L[l]).block, 0,
+                             stream, L[l], c, ps, l == 0 ? 1 : 0, MG_OMEGA);
+      }
   }
   return EK_OK;
 }

@@ -73,7 +73,10 @@ __device__ inline void smooth_site(const Lvl& L, int colour, int tx, int y, int 
   L.x[r] = omega == 1.0 ? gs : L.x[r] + omega * (gs - L.x[r]);
 }
 
-__device__ inline void restrict_site(const Lvl& F, const Lvl& C, int X, int Y, int Z, double shift) {
+// omega_red != 0: the coarse level's first colour-0 half sweep is done here
+// as well (from the zero start it only needs the site's own right-hand side).
+__device__ inline void restrict_site(const Lvl& F, const Lvl& C, int X, int Y, int Z, double shift,
+                                     double omega_red = 0.0) {
   double s = 0.0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
@@ -82,22 +85,53 @@ __device__ inline void restrict_site(const Lvl& F, const Lvl& C, int X, int Y, i
     s += (F.f[r] + shift) - (nbsum(F.x, x, y, z, F) - 6.0 * F.x[r]) / F.h2;
   }
   const int t = idx3(X, Y, Z, C);
-  C.f[t] = 0.125 * s;
-  C.x[t] = 0.0;
+  const double f = 0.125 * s;
+  C.f[t] = f;
+  double x0 = 0.0;
+  if (omega_red != 0.0 && ((X + Y + Z) & 1) == 0) {
+    const double gs = (0.0 - C.h2 * (f + 0.0)) * (1.0 / 6.0);
+    x0 = omega_red == 1.0 ? gs : 0.0 + omega_red * (gs - 0.0);
+  }
+  C.x[t] = x0;
 }
 
-__device__ inline void prolong_site(const Lvl& F, const Lvl& C, int x, int y, int z) {
+// Coarse-grid correction at fine site (x, y, z) (trilinear, cell-centred).
+__device__ inline double prolong_value(const Lvl& C, int x, int y, int z) {
   const int X = x >> 1, Y = y >> 1, Z = z >> 1;
   const int Xn = (x & 1) ? (X + 1 == C.nx ? 0 : X + 1) : (X == 0 ? C.nx - 1 : X - 1);
   const int Yn = (y & 1) ? (Y + 1 == C.ny ? 0 : Y + 1) : (Y == 0 ? C.ny - 1 : Y - 1);
   const int Zn = (z & 1) ? (Z + 1 == C.nz ? 0 : Z + 1) : (Z == 0 ? C.nz - 1 : Z - 1);
   const double a = 0.75, b = 0.25;
-  const double v =
-      a * a * a * C.x[idx3(X, Y, Z, C)] + b * a * a * C.x[idx3(Xn, Y, Z, C)] +
-      a * b * a * C.x[idx3(X, Yn, Z, C)] + a * a * b * C.x[idx3(X, Y, Zn, C)] +
-      b * b * a * C.x[idx3(Xn, Yn, Z, C)] + b * a * b * C.x[idx3(Xn, Y, Zn, C)] +
-      a * b * b * C.x[idx3(X, Yn, Zn, C)] + b * b * b * C.x[idx3(Xn, Yn, Zn, C)];
-  F.x[idx3(x, y, z, F)] += v;
+  return a * a * a * C.x[idx3(X, Y, Z, C)] + b * a * a * C.x[idx3(Xn, Y, Z, C)] +
+         a * b * a * C.x[idx3(X, Yn, Z, C)] + a * a * b * C.x[idx3(X, Y, Zn, C)] +
+         b * b * a * C.x[idx3(Xn, Yn, Z, C)] + b * a * b * C.x[idx3(Xn, Y, Zn, C)] +
+         a * b * b * C.x[idx3(X, Yn, Zn, C)] + b * b * b * C.x[idx3(Xn, Yn, Zn, C)];
+}
+
+__device__ inline void prolong_site(const Lvl& F, const Lvl& C, int x, int y, int z) {
+  F.x[idx3(x, y, z, F)] += prolong_value(C, x, y, z);
+}
+
+// First post-smoothing sweep with the coarse-grid correction applied on the
+// fly (no separate prolongation pass).  Colour 0: the site and its six
+// neighbours (colour 1, not yet corrected) are read corrected; colour 1
+// (after colour 0): the site is corrected, its neighbours are final.  Equal
+// to a prolongation followed by the two half sweeps.
+__device__ inline void corrected_smooth_site(const Lvl& L, const Lvl& C, int colour, int tx, int y,
+                                             int z, double shift, double omega) {
+  const int x = 2 * tx + ((colour + y + z) & 1);
+  const int r = idx3(x, y, z, L);
+  const double xo = L.x[r] + prolong_value(C, x, y, z);
+  double nb = nbsum(L.x, x, y, z, L);
+  if (colour == 0) {
+    const int xm = x == 0 ? L.nx - 1 : x - 1, xp = x == L.nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? L.ny - 1 : y - 1, yp = y == L.ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? L.nz - 1 : z - 1, zp = z == L.nz - 1 ? 0 : z + 1;
+    nb += prolong_value(C, xm, y, z) + prolong_value(C, xp, y, z) + prolong_value(C, x, ym, z) +
+          prolong_value(C, x, yp, z) + prolong_value(C, x, y, zm) + prolong_value(C, x, y, zp);
+  }
+  const double gs = (nb - L.h2 * (L.f[r] + shift)) * (1.0 / 6.0);
+  L.x[r] = omega == 1.0 ? gs : xo + omega * (gs - xo);
 }
 
 // --- the coarse part of a V-cycle in one workgroup ----------------------------

@@ -132,10 +132,11 @@ def test_polymer_argument_checks(ek):
     assert e.value.status == ek.EK_EINVAL
 
 
-@pytest.mark.parametrize("n_beads", [80, 130])
+@pytest.mark.parametrize("n_beads", [48, 80, 130])
 def test_long_chain_fp64_matches_oracle(ek, n_beads):
-    """Chains beyond 64 beads take the kernel path with the node table in
-    global memory (4 lanes per bead up to 128 beads, then 2)."""
+    """Chains of up to 64 beads keep the node table in LDS (8 lanes per bead:
+    48 beads fill six waves); beyond 64 beads it moves to global memory (4
+    lanes per bead up to 128 beads, then 2)."""
     wl = workloads.pore_system((64, 40, 40), 8, 5, 0.01, 0.01, -0.01, n_beads, 41,
                                bead_q=workloads.STABLE_BEAD_CHARGE, steps=10)
     ctx = ek.from_workload(wl, precision=ek.EK_FP64, poisson_tol=1e-10, poisson_check_every=1)

@@ -72,12 +72,15 @@ def build_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def lb_bytes_per_launch(wl, precision_bytes):
+def lb_bytes_per_launch(wl, precision_bytes, fluid_updated=None):
     """Algorithmic bytes of one fused lattice launch: 57 populations read and
-    written at every fluid site, the 4-byte link word of every site and the
-    float64 potential at every fluid site (its neighbours come from cache)."""
-    fluid = wl.fluid_sites
-    return fluid * (2 * 57 * precision_bytes + 8) + wl.sites * 4
+    written at every fluid site it updates, the 4-byte link word of every site
+    and the float64 potential at every updated site (its neighbours come from
+    cache).  With a polymer the launch leaves the sites of the bead boxes to a
+    small launch after the chain kernel: fluid_updated is the library's count
+    of the sites it did update (per launch)."""
+    fluid = wl.fluid_sites if fluid_updated is None else fluid_updated
+    return int(round(fluid * (2 * 57 * precision_bytes + 8) + wl.sites * 4))
 
 
 def cpu_baseline(wl, tol):
@@ -252,7 +255,8 @@ def main():
     value = 3 * wl.sites * args.steps / dt / 1e6
     pbytes = 4 if prec == ek.EK_FP32 else 8
     lb_ms = tm["ms_lb"] / max(tm["n_lb"], 1)
-    lb_bytes = lb_bytes_per_launch(wl, pbytes)
+    lb_sites = tm["lb_sites"] / max(tm["n_lb"], 1) if tm["lb_sites"] > 0 else None
+    lb_bytes = lb_bytes_per_launch(wl, pbytes, lb_sites)
     achieved = lb_bytes / (lb_ms * 1e-3) / 1e9
     line = {
         "metric": "MLUPS per species-step",
@@ -291,6 +295,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "bytes_per_launch": lb_bytes,
+            "fluid_sites_per_launch": None if lb_sites is None else round(lb_sites, 1),
             "avg_launch_ms": round(lb_ms, 5),
             "traffic": measured_traffic(wl.name, "f32" if prec == ek.EK_FP32 else "f64"),
         },

@@ -178,34 +178,47 @@ ek_status ek_poisson_solve(struct ek_ctx* ctx, const double* dev_rho, double* de
 ek_status ek_poisson_sor_iterations(struct ek_ctx* ctx, const double* dev_b, double* dev_psi,
                                     int32_t iterations);
 
-/* Per-phase GPU time, measured with HIP events on the context's stream for
- * each phase of every step while enabled: the charge pass, the Poisson solve
- * and the bead update between events recorded around them, the fused lattice
- * kernel (whose launch count is n_lb) between events stamped at its own start
- * and end.  Used by the benchmark to price kernels against the hardware
- * roofline. */
+/* Per-phase GPU time, measured with HIP events for each phase of every step
+ * while enabled: the charge pass and the Poisson solve between events
+ * recorded around them on the context's stream, the bead update from the end
+ * of the solve to the end of the chain kernel, the fused lattice kernel
+ * (whose launch count is n_lb) between events stamped at its own start and
+ * end.  With the overlap of EK_LAUNCH_OVERLAP the lattice kernel runs while
+ * the chain advances and leaves the sites of the bead boxes to a small
+ * launch after it; lb_sites counts the fluid sites the timed lattice
+ * launches updated.  Used by the benchmark to price kernels against the
+ * hardware roofline. */
 typedef struct {
   double ms_charge, ms_poisson, ms_md, ms_lb;
   int64_t n_steps;              /* steps measured                               */
   int64_t n_lb;                 /* fused lattice kernel launches measured       */
   int64_t poisson_iters;        /* Poisson iterations (or cycles) summed        */
+  int64_t lb_sites;             /* fluid sites updated by those launches        */
 } ek_timing;
 
 /* enable != 0 starts (and zeroes) the per-phase timers; 0 stops them. */
 ek_status ek_set_timing(struct ek_ctx* ctx, int32_t enable);
 ek_status ek_get_timing(struct ek_ctx* ctx, ek_timing* out);
 
-/* Launch mode of the multigrid cycles (EK_POISSON_MG).  enable != 0 (the
- * default): each V-cycle, with or without its residual test, is recorded once
- * as a HIP graph (on a stream the library creates; the caller's stream may be
- * the default stream) and replayed on the context's stream; the graphs are
- * recorded again when the solve's psi buffer changes.  0: the same kernels
- * are launched one by one.  Both modes run the same kernels in the same order
- * and give bit-identical results.  When recording fails the context keeps to
- * single launches.  A context whose stream the caller is recording itself
- * cannot run a solve either way (the solve reads its convergence flag back to
- * the host). */
-ek_status ek_set_graph_launch(struct ek_ctx* ctx, int32_t enable);
+/* Launch modes (flags, both set by default).
+ * EK_LAUNCH_GRAPHS: each multigrid V-cycle (EK_POISSON_MG), with or without
+ *   its residual test, is recorded once as a HIP graph (on a stream the
+ *   library creates; the caller's stream may be the default stream) and
+ *   replayed on the context's stream; the graphs are recorded again when the
+ *   solve's psi buffer changes.  Without it the same kernels are launched one
+ *   by one, in the same order, with bit-identical results.  When recording
+ *   fails the context keeps to single launches.
+ * EK_LAUNCH_OVERLAP: with a polymer, the chain kernel runs on a second stream
+ *   of the library's while the fused lattice kernel updates every site
+ *   outside the beads' 4x4x4 boxes (the only nodes the friction reaches);
+ *   the box sites follow in a small launch once the chain is done.  Every
+ *   site is updated by the same arithmetic either way (bit-identical fields
+ *   and beads); only the order of the float64 mass and momentum sums
+ *   differs.  Needs nx, ny, nz >= 4, else the kernels run one after the other.
+ * A context whose stream the caller is recording itself cannot run a step
+ * (the step reads convergence flags back to the host). */
+enum { EK_LAUNCH_GRAPHS = 1, EK_LAUNCH_OVERLAP = 2 };
+ek_status ek_set_launch_mode(struct ek_ctx* ctx, int32_t flags);
 
 /* ---------------------------------------------------------------------------
  * Learned warm start of the Poisson solve.  The paper solves Eq. poisson

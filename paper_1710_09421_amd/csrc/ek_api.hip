@@ -73,7 +73,11 @@ Layout make_layout(const ek_params* p, int max_beads) {
   L.wall_q = take(n * 8);
   L.psi = take(n * 8);
   L.b = take(n * 8);
-  L.partials = take((size_t)g.nblocks() * 8 * 8);
+  // block partials of up to 8 components: site-grid or lattice-grid blocks,
+  // plus the blocks of the bead-box tail
+  const int nbp = std::max(g.nblocks(), lattice_grid(p->nx, p->ny, p->nz).nblocks()) +
+                  lb_tail_blocks(std::max(max_beads, 1));
+  L.partials = take((size_t)nbp * 8 * 8);
   L.ps = take(sizeof(PoissonScalars));
   L.stats = take(16 * 8);
   L.keys = take((size_t)HASH_SLOTS * 4);
@@ -234,7 +238,7 @@ ek_status ek_ctx::poisson(const double* bb, double* x, bool learned, int& iters,
 
 ek_status ek_ctx::ensure_events(int n_steps) {
   ek_ctx* ctx = this;
-  while ((int)events.size() < 5 * n_steps) {
+  while ((int)events.size() < 6 * n_steps) {
     hipEvent_t e;
     EK_HIP(hipEventCreate(&e));
     events.push_back(e);
@@ -243,7 +247,7 @@ ek_status ek_ctx::ensure_events(int n_steps) {
 }
 
 void ek_ctx::record(int t, int k) {
-  if (timing) (void)hipEventRecord(events[5 * t + k], stream);
+  if (timing) (void)hipEventRecord(events[6 * t + k], stream);
 }
 
 template <typename T>
@@ -252,6 +256,11 @@ ek_status ek_ctx::step_impl(int n_steps) {
   const SiteGrid g = bx_sites ? site_grid(p.nx, p.ny, p.nz, bx_sites) : lattice_grid(p.nx, p.ny, p.nz);
   const int nb = g.nblocks();
   const LBParams lp = lb_params();
+  // lattice update beside the chain (box sites after it): see EK_LAUNCH_OVERLAP
+  const bool overlap = overlap_md && n_beads > 0 && p.nx >= 4 && p.ny >= 4 && p.nz >= 4;
+  const int nb_bulk = lb_step_blocks(g, p.nz);
+  const int nb_lb = nb_bulk + (overlap ? lb_tail_blocks(n_beads) : 0);
+
   if (timing) {
     ek_status st = ensure_events(n_steps);
     if (st) return st;
@@ -278,15 +287,21 @@ ek_status ek_ctx::step_impl(int n_steps) {
     if (timing) tacc.poisson_iters += iters;
     record(t, 2);
     // beads: n_sub MD substeps with the fields of time t, friction spread
+    // (event 5: end of the chain kernel)
     if (n_beads > 0) {
-      st = beads_advance<T>();
+      st = beads_advance<T>(overlap, timing ? events[6 * t + 5] : nullptr);
       if (st) return st;
     }
     // events 3 and 4 are stamped by the fused kernel's own start and end
-    const int nb_lb = launch_lb_step<T>((const T*)fcur(), (T*)fnext(), mask, psi, lp, bt, partials,
-                                        dims, g, stream, timing ? events[5 * t + 3] : nullptr,
-                                        timing ? events[5 * t + 4] : nullptr);
-    launch_sum_partials(partials, nb_lb, 6, stats_dev, stream);
+    launch_lb_step<T>((const T*)fcur(), (T*)fnext(), mask, psi, lp, bt, partials, nb_lb,
+                      overlap ? MASK_DEFER : 0u, dims, g, stream,
+                      timing ? events[6 * t + 3] : nullptr, timing ? events[6 * t + 4] : nullptr);
+    if (overlap) {
+      EK_HIP(hipStreamWaitEvent(stream, md_join, 0));
+      launch_lb_tail<T>((const T*)fcur(), (T*)fnext(), mask, psi, lp, bt, bead_origin(), n_beads,
+                        partials, nb_bulk, nb_lb, dims, stream);
+    }
+    launch_sum_partials(partials, nb_lb, stats_dev, timing ? 1 : 0, stream);
     cur_is_a = !cur_is_a;
     ++step_count;
   }
@@ -296,7 +311,9 @@ ek_status ek_ctx::step_impl(int n_steps) {
     for (int t = 0; t < n_steps; ++t) {
       float ms[4];
       for (int k = 0; k < 4; ++k)
-        EK_HIP(hipEventElapsedTime(&ms[k], events[5 * t + k], events[5 * t + k + 1]));
+        EK_HIP(hipEventElapsedTime(&ms[k], events[6 * t + k], events[6 * t + k + 1]));
+      if (n_beads > 0)   // solve end to chain end (the lattice kernel may start earlier)
+        EK_HIP(hipEventElapsedTime(&ms[2], events[6 * t + 2], events[6 * t + 5]));
       tacc.ms_charge += ms[0];
       tacc.ms_poisson += ms[1];
       tacc.ms_md += ms[2];
@@ -415,6 +432,7 @@ ek_status ek_create(const ek_params* p, int32_t max_beads, void* dev_ws, size_t 
   // the link words before any kernel reads them
   launch_table_init(c->keys, c->vals, c->stream);
   if (hipMemsetAsync(c->mask, 0, c->dims.n * 4, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->stats_dev, 0, 16 * 8, c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess) {
     (void)hipHostFree(c->pinned);
     if (own) (void)hipFree(ws);
@@ -437,6 +455,12 @@ ek_status ek_create(const ek_params* p, int32_t max_beads, void* dev_ws, size_t 
 void ek_destroy(ek_ctx* ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->md_stream) {
+    (void)hipStreamSynchronize(ctx->md_stream);
+    (void)hipStreamDestroy(ctx->md_stream);
+  }
+  if (ctx->md_fork) (void)hipEventDestroy(ctx->md_fork);
+  if (ctx->md_join) (void)hipEventDestroy(ctx->md_join);
   for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
   ctx->mg_release();
   delete ctx->net;
@@ -577,18 +601,28 @@ ek_status ek_set_timing(ek_ctx* ctx, int32_t enable) {
   if (!ctx) return EK_EINVAL;
   ctx->timing = enable != 0;
   ctx->tacc = ek_timing{};
-  return EK_OK;
+  // the running count of updated lattice sites (stats slot 7)
+  static const double zero = 0.0;
+  EK_HIP(hipMemcpyAsync(ctx->stats_dev + 7, &zero, sizeof zero, hipMemcpyHostToDevice, ctx->stream));
+  return ctx->sync();
 }
 
-ek_status ek_set_graph_launch(ek_ctx* ctx, int32_t enable) {
+ek_status ek_set_launch_mode(ek_ctx* ctx, int32_t flags) {
   if (!ctx) return EK_EINVAL;
-  ctx->graph_launch = enable != 0;
+  if (flags & ~(EK_LAUNCH_GRAPHS | EK_LAUNCH_OVERLAP)) return ctx->fail(EK_EINVAL, "unknown launch flag");
+  ctx->graph_launch = (flags & EK_LAUNCH_GRAPHS) != 0;
+  ctx->overlap_md = (flags & EK_LAUNCH_OVERLAP) != 0;
   return EK_OK;
 }
 
 ek_status ek_get_timing(ek_ctx* ctx, ek_timing* out) {
   if (!ctx || !out) return EK_EINVAL;
+  double sites = 0.0;
+  EK_HIP(hipMemcpyAsync(&sites, ctx->stats_dev + 7, sizeof sites, hipMemcpyDeviceToHost, ctx->stream));
+  const ek_status st = ctx->sync();
+  if (st) return st;
   *out = ctx->tacc;
+  out->lb_sites = (int64_t)sites;
   return EK_OK;
 }
 

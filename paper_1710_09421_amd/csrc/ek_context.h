@@ -73,7 +73,13 @@ struct ek_ctx {
   // per-phase timers (HIP events on the context stream)
   bool timing = false;
   bool graph_launch = true;            // multigrid cycles replayed from recorded graphs
-  std::vector<hipEvent_t> events;      // 5 per step: charge, poisson, md, lb start, lb end
+  bool overlap_md = true;              // lattice update outside the bead boxes beside the chain
+  // second stream for the chain kernel and its fork / join events (created on
+  // first use)
+  hipStream_t md_stream = nullptr;
+  hipEvent_t md_fork = nullptr, md_join = nullptr;
+  // 6 per step: charge, poisson, md, lb start, lb end, chain end
+  std::vector<hipEvent_t> events;
   ek_timing tacc{};
   ek_status ensure_events(int n_steps);
   void record(int step_in_call, int k);
@@ -113,8 +119,12 @@ struct ek_ctx {
 
   // beads (kernels_md.hip)
   ek::BeadTableView bead_view() const;
+  const int* bead_origin() const;      // box origins of the step's beads (device)
   ek_status beads_deposit();
+  // Box gather and chain kernel.  With `overlap` the box nodes are flagged
+  // MASK_DEFER and the chain runs on md_stream (joined by md_join, and
+  // stamping `chain_end` when given); else both run on the context stream.
   template <typename T>
-  ek_status beads_advance();
+  ek_status beads_advance(bool overlap, hipEvent_t chain_end);
   ek_status beads_check();
 };

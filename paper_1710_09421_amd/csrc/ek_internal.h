@@ -30,6 +30,7 @@ constexpr uint32_t MASK_SOLID = 1u << 31;       // the site itself is solid
 constexpr uint32_t MASK_CHARGED = 1u << 30;     // the site carries a fixed charge
 constexpr uint32_t MASK_BEAD = 1u << 29;        // a bead kernel touches the site
 constexpr uint32_t MASK_WALL = 1u << 28;        // solid site next to the fluid (bead-wall WCA)
+constexpr uint32_t MASK_DEFER = 1u << 27;       // in a bead's box: updated after the chain
 
 // Fixed-point scales for order-independent (hence deterministic) sums of the
 // bead charge and bead force densities accumulated with integer atomics.
@@ -95,19 +96,31 @@ template <typename T>
 void launch_charge(const T* f, const uint32_t* mask, const double* wall_q, double* b,
                    double* partials, const LBParams& lp, double inv_eps, Dims d,
                    const SiteGrid& g, hipStream_t s, const BeadTableView& bt);
-// Returns the number of block partials written (the launch may give a block
-// several z-planes).  start / stop (may be null) are recorded at the kernel's
-// own start and end.
+// Fused step over the sites without a `skip` bit.  Writes its block partials
+// (seven components: masses, momentum, sites updated) first in a layout of
+// `nblocks` blocks (lb_step_blocks(g, nz), plus the tail's blocks when a tail
+// follows) and returns the number it wrote.  start / stop (may be null) are
+// recorded at the kernel's own start and end.
+int lb_step_blocks(const SiteGrid& g, int nz);
+int lb_tail_blocks(int n_beads);
 template <typename T>
 int launch_lb_step(const T* fsrc, T* fdst, const uint32_t* mask, const double* psi,
-                   const LBParams& lp, const BeadTableView& bt, double* partials, Dims d,
-                   const SiteGrid& g, hipStream_t s, hipEvent_t start = nullptr,
-                   hipEvent_t stop = nullptr);
+                   const LBParams& lp, const BeadTableView& bt, double* partials, int nblocks,
+                   uint32_t skip, Dims d, const SiteGrid& g, hipStream_t s,
+                   hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+// The sites flagged MASK_DEFER in the boxes of n_beads beads (box origins of
+// the step); partials of blocks first_block .. of the same layout.
+template <typename T>
+void launch_lb_tail(const T* fsrc, T* fdst, uint32_t* mask, const double* psi, const LBParams& lp,
+                    const BeadTableView& bt, const int* origin, int n_beads, double* partials,
+                    int first_block, int nblocks, Dims d, hipStream_t s);
 template <typename T>
 void launch_moments(const T* f, const uint32_t* mask, int species, double nref, double* n_out,
                     double* u_out, Dims d, hipStream_t s);
 
-void launch_sum_partials(const double* partials, int nblocks, int ncomp, double* out,
+// out[0..6] = the seven sums of the fused step's partials; count != 0 also
+// adds out[6] (sites updated) to the running count out[7].
+void launch_sum_partials(const double* partials, int nblocks, double* out, int count,
                          hipStream_t s);
 void launch_mean_shift(const double* partials, int nblocks, double inv_n, double inv_eps,
                        PoissonScalars* ps, hipStream_t s);

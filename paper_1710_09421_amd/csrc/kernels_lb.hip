@@ -5,7 +5,7 @@
 #include <hip/hip_ext.h>
 
 #include "lb_site.h"
-#include "md_table.h"
+#include "md_chain.h"
 #include "reduce.h"
 
 namespace ek {
@@ -64,23 +64,60 @@ __global__ __launch_bounds__(BLOCK) void k_charge(const T* __restrict__ f,
 // Fused step at every fluid site: pull + bounce-back, moments, field from the
 // potential, closed-form implicit drag, BGK collision with the half-force
 // (Guo) forcing term, aligned store; partial sums of species mass and total
-// momentum of f(t) in float64.
+// momentum of f(t) in float64, and the number of sites updated.  Sites with
+// a `skip` bit are left to k_lb_tail.  Partials: [c * nblocks + block], the
+// blocks of this launch first.
 template <typename T, typename I>
 __global__ __launch_bounds__(BLOCK) void k_lb_step(const T* __restrict__ fsrc,
                                                    T* __restrict__ fdst,
                                                    const uint32_t* __restrict__ mask,
                                                    const double* __restrict__ psi, LBParams lp,
                                                    BeadTableView bt,
-                                                   double* __restrict__ partials, Dims d, int zb) {
+                                                   double* __restrict__ partials, int nblocks,
+                                                   uint32_t skip, Dims d, int zb) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-  const int nblocks = gridDim.x * gridDim.y * gridDim.z;
-  double acc[6] = {0, 0, 0, 0, 0, 0};
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
   if (x < d.nx && y < d.ny)
     for (int k = 0; k < zb; ++k)
-      lb_site<T, I>(fsrc, fdst, mask, psi, lp, bt, x, y, blockIdx.z * zb + k, d, acc);
-  block_partials<6>(acc, partials, bid, nblocks);
+      if (lb_site<T, I>(fsrc, fdst, mask, psi, lp, bt, x, y, blockIdx.z * zb + k, d, acc, skip))
+        acc[6] += 1.0;
+  block_partials<7>(acc, partials, bid, nblocks);
+}
+
+// The sites left by k_lb_step (MASK_DEFER: the nodes of the bead boxes),
+// once the chain has spread its friction (component 6, the count of sites
+// the fused kernel updated, gets nothing from here).  Item = (bead i, box node t); a
+// node in several boxes is updated by the lowest bead whose box holds it
+// (the boxes' origins are fixed for the step), which also clears its flag.
+// Needs every side of the box >= BOX (no box overlaps itself).
+template <typename T, typename I>
+__global__ __launch_bounds__(BLOCK) void k_lb_tail(const T* __restrict__ fsrc,
+                                                   T* __restrict__ fdst, uint32_t* mask,
+                                                   const double* __restrict__ psi, LBParams lp,
+                                                   BeadTableView bt,
+                                                   const int* __restrict__ origin, int n_beads,
+                                                   double* __restrict__ partials,
+                                                   int first_block, int nblocks, Dims d) {
+  const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  if (item < n_beads * BOX3) {
+    const int i = item / BOX3, t = item % BOX3;
+    const int gx = origin[3 * i] + t % BOX, gy = origin[3 * i + 1] + (t / BOX) % BOX,
+              gz = origin[3 * i + 2] + t / (BOX * BOX);
+    bool first = true;
+    for (int j = 0; j < i && first; ++j)
+      if (wrap(gx - origin[3 * j], d.nx) < BOX && wrap(gy - origin[3 * j + 1], d.ny) < BOX &&
+          wrap(gz - origin[3 * j + 2], d.nz) < BOX)
+        first = false;
+    if (first) {
+      const int x = wrap(gx, d.nx), y = wrap(gy, d.ny), z = wrap(gz, d.nz);
+      lb_site<T, I>(fsrc, fdst, mask, psi, lp, bt, x, y, z, d, acc);   // not counted in acc[6]
+      atomicAnd(&mask[((long long)z * d.ny + y) * d.nx + x], ~MASK_DEFER);
+    }
+  }
+  block_partials<7>(acc, partials, first_block + blockIdx.x, nblocks);
 }
 
 template <typename T>
@@ -116,12 +153,16 @@ __global__ __launch_bounds__(BLOCK) void k_moments(const T* __restrict__ f,
   }
 }
 
-__global__ __launch_bounds__(1024) void k_sum6(const double* __restrict__ partials, int nblocks,
-                                               double* __restrict__ out) {
-  double t[6];
-  block_sums_1024<6>(partials, nblocks, t);
-  if (threadIdx.x == 0)
-    for (int c = 0; c < 6; ++c) out[c] = t[c];
+// out[0..6] = sums of the seven components; out[7] += out[6] when `count`
+// (sites updated by the timed launches).
+__global__ __launch_bounds__(1024) void k_sum7(const double* __restrict__ partials, int nblocks,
+                                               double* __restrict__ out, int count) {
+  double t[7];
+  block_sums_1024<7>(partials, nblocks, t);
+  if (threadIdx.x == 0) {
+    for (int c = 0; c < 7; ++c) out[c] = t[c];
+    if (count) out[7] += t[6];
+  }
 }
 
 __global__ __launch_bounds__(1024) void k_mean_shift(const double* __restrict__ partials,
@@ -200,20 +241,40 @@ int lb_planes_per_block(const SiteGrid& g, int nz) {
   return zb;
 }
 
+int lb_step_blocks(const SiteGrid& g, int nz) {
+  return int(g.grid.x * g.grid.y * (nz / lb_planes_per_block(g, nz)));
+}
+
+int lb_tail_blocks(int n_beads) { return (n_beads * BOX3 + BLOCK - 1) / BLOCK; }
+
 template <typename T>
 int launch_lb_step(const T* fsrc, T* fdst, const uint32_t* mask, const double* psi,
-                   const LBParams& lp, const BeadTableView& bt, double* partials, Dims d,
-                   const SiteGrid& g, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
+                   const LBParams& lp, const BeadTableView& bt, double* partials, int nblocks,
+                   uint32_t skip, Dims d, const SiteGrid& g, hipStream_t s, hipEvent_t start,
+                   hipEvent_t stop) {
   const int zb = lb_planes_per_block(g, d.nz);
   const dim3 grid(g.grid.x, g.grid.y, d.nz / zb);
   // the events (when given) are stamped at the kernel's own start and end
   if (fits_idx32<T>(d.n))
     hipExtLaunchKernelGGL((k_lb_step<T, uint32_t>), grid, g.block, 0, s, start, stop, 0, fsrc,
-                          fdst, mask, psi, lp, bt, partials, d, zb);
+                          fdst, mask, psi, lp, bt, partials, nblocks, skip, d, zb);
   else
     hipExtLaunchKernelGGL((k_lb_step<T, long long>), grid, g.block, 0, s, start, stop, 0, fsrc,
-                          fdst, mask, psi, lp, bt, partials, d, zb);
+                          fdst, mask, psi, lp, bt, partials, nblocks, skip, d, zb);
   return int(grid.x * grid.y * grid.z);
+}
+
+template <typename T>
+void launch_lb_tail(const T* fsrc, T* fdst, uint32_t* mask, const double* psi, const LBParams& lp,
+                    const BeadTableView& bt, const int* origin, int n_beads, double* partials,
+                    int first_block, int nblocks, Dims d, hipStream_t s) {
+  const int blocks = lb_tail_blocks(n_beads);
+  if (fits_idx32<T>(d.n))
+    hipLaunchKernelGGL((k_lb_tail<T, uint32_t>), dim3(blocks), dim3(BLOCK), 0, s, fsrc, fdst, mask,
+                       psi, lp, bt, origin, n_beads, partials, first_block, nblocks, d);
+  else
+    hipLaunchKernelGGL((k_lb_tail<T, long long>), dim3(blocks), dim3(BLOCK), 0, s, fsrc, fdst,
+                       mask, psi, lp, bt, origin, n_beads, partials, first_block, nblocks, d);
 }
 
 template <typename T>
@@ -224,10 +285,9 @@ void launch_moments(const T* f, const uint32_t* mask, int species, double nref, 
                      n_out, u_out, d);
 }
 
-void launch_sum_partials(const double* partials, int nblocks, int ncomp, double* out,
+void launch_sum_partials(const double* partials, int nblocks, double* out, int count,
                          hipStream_t s) {
-  (void)ncomp;   // always the six of the fused step: masses and momentum
-  hipLaunchKernelGGL(k_sum6, dim3(1), dim3(1024), 0, s, partials, nblocks, out);
+  hipLaunchKernelGGL(k_sum7, dim3(1), dim3(1024), 0, s, partials, nblocks, out, count);
 }
 
 void launch_mean_shift(const double* partials, int nblocks, double inv_n, double inv_eps,
@@ -243,8 +303,12 @@ void launch_mean_shift(const double* partials, int nblocks, double inv_n, double
                                  const LBParams&, double, Dims, const SiteGrid&, hipStream_t,\
                                  const BeadTableView&);                                      \
   template int launch_lb_step<T>(const T*, T*, const uint32_t*, const double*,               \
-                                 const LBParams&, const BeadTableView&, double*, Dims,       \
-                                 const SiteGrid&, hipStream_t, hipEvent_t, hipEvent_t);      \
+                                 const LBParams&, const BeadTableView&, double*, int,        \
+                                 uint32_t, Dims, const SiteGrid&, hipStream_t, hipEvent_t,   \
+                                 hipEvent_t);                                                \
+  template void launch_lb_tail<T>(const T*, T*, uint32_t*, const double*, const LBParams&,   \
+                                  const BeadTableView&, const int*, int, double*, int, int,  \
+                                  Dims, hipStream_t);                                        \
   template void launch_moments<T>(const T*, const uint32_t*, int, double, double*, double*,  \
                                   Dims, hipStream_t);
 EK_INST(float)

@@ -74,10 +74,9 @@ __global__ __launch_bounds__(256) void k_deposit(BeadState bs, int n, int* keys,
 // One block per bead: moments and field on the 4^3 box, flags on the 6^3 window.
 template <typename T>
 __global__ __launch_bounds__(256) void k_bead_box(BeadState bs, const T* __restrict__ f,
-                                                  const uint32_t* __restrict__ mask,
-                                                  const double* __restrict__ psi, LBParams lp,
-                                                  Dims d) {
-  bead_box_item(bs, blockIdx.x, threadIdx.x, f, mask, psi, lp, d);
+                                                  uint32_t* mask, const double* __restrict__ psi,
+                                                  LBParams lp, Dims d, int defer) {
+  bead_box_item(bs, blockIdx.x, threadIdx.x, f, mask, psi, lp, d, defer ? mask : nullptr);
 }
 
 template <bool LDS, int TPB, int MAXT>
@@ -118,6 +117,10 @@ void ek::launch_table_init(int* keys, long long* vals, hipStream_t s) {
   hipLaunchKernelGGL(k_table_init, dim3(HASH_SLOTS / 256), dim3(256), 0, s, keys, vals, HASH_SLOTS);
 }
 
+const int* ek_ctx::bead_origin() const {
+  return carve(bead_mem, max_beads < 1 ? 1 : max_beads).origin;
+}
+
 BeadTableView ek_ctx::bead_view() const {
   BeadTableView v;
   v.keys = keys;
@@ -134,11 +137,24 @@ ek_status ek_ctx::beads_deposit() {
 }
 
 template <typename T>
-ek_status ek_ctx::beads_advance() {
+ek_status ek_ctx::beads_advance(bool overlap, hipEvent_t chain_end) {
   BeadState bs = carve(bead_mem, max_beads < 1 ? 1 : max_beads);
   const LBParams lp = lb_params();
   hipLaunchKernelGGL(k_bead_box<T>, dim3(n_beads), dim3(256), 0, stream, bs, (const T*)fcur(),
-                     mask, psi, lp, dims);
+                     mask, psi, lp, dims, overlap ? 1 : 0);
+  hipStream_t cs = stream;   // stream of the chain kernel
+  if (overlap) {
+    if (!md_stream) {
+      if (hipStreamCreateWithFlags(&md_stream, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&md_fork, hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&md_join, hipEventDisableTiming) != hipSuccess)
+        return fail(EK_EHIP, "creating the chain stream failed");
+    }
+    if (hipEventRecord(md_fork, stream) != hipSuccess ||
+        hipStreamWaitEvent(md_stream, md_fork, 0) != hipSuccess)
+      return fail(EK_EHIP, "ordering the chain stream failed");
+    cs = md_stream;
+  }
   MDParams mp;
   mp.n = n_beads;
   mp.n_sub = poly.n_sub;
@@ -157,7 +173,7 @@ ek_status ek_ctx::beads_advance() {
   const int threads = ((n_beads * tpb + 63) / 64) * 64;
   const size_t sr_bytes = ((size_t)n_beads * 24 + 15) & ~size_t(15);
   auto md = [&](auto kernel, size_t lds, int bits) {
-    hipLaunchKernelGGL(kernel, dim3(1), dim3(threads), lds, stream, bs, mp, keys, vals, mask, dims,
+    hipLaunchKernelGGL(kernel, dim3(1), dim3(threads), lds, cs, bs, mp, keys, vals, mask, dims,
                        HASH_BITS, bits);
   };
   if (n_beads <= LDS_MAX_BEADS) {
@@ -178,10 +194,14 @@ ek_status ek_ctx::beads_advance() {
   } else {
     md(k_md<false, 1, 1024>, sr_bytes, 0);
   }
+  if (chain_end && hipEventRecord(chain_end, cs) != hipSuccess)
+    return fail(EK_EHIP, "recording the chain timer failed");
+  if (overlap && hipEventRecord(md_join, cs) != hipSuccess)
+    return fail(EK_EHIP, "recording the chain join failed");
   return EK_OK;
 }
-template ek_status ek_ctx::beads_advance<float>();
-template ek_status ek_ctx::beads_advance<double>();
+template ek_status ek_ctx::beads_advance<float>(bool, hipEvent_t);
+template ek_status ek_ctx::beads_advance<double>(bool, hipEvent_t);
 
 ek_status ek_ctx::beads_check() {
   BeadState bs = carve(bead_mem, max_beads < 1 ? 1 : max_beads);

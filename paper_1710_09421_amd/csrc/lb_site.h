@@ -123,16 +123,19 @@ __device__ inline double charge_site(const T* __restrict__ f, const uint32_t* __
 // Fused step at one fluid site: pull + bounce-back, moments, field from the
 // potential, closed-form implicit drag, BGK collision with the half-force
 // (Guo) forcing term, aligned store.  Adds the site's species masses and
-// momentum of f(t) to acc (float64).
-template <typename T, typename I = long long>
-__device__ inline void lb_site(const T* __restrict__ fsrc, T* __restrict__ fdst,
+// momentum of f(t) to acc[0..5] (float64).  Sites whose link word has one of
+// the `skip` bits are left alone; returns whether the site was updated.
+template <typename T, typename I = long long, int NA>
+__device__ inline bool lb_site(const T* __restrict__ fsrc, T* __restrict__ fdst,
                                const uint32_t* __restrict__ mask, const double* __restrict__ psi,
                                const LBParams& lp, const BeadTableView& bt, int x, int y, int z,
-                               const Dims& d, double (&acc)[6]) {
+                               const Dims& d, double (&acc)[NA], uint32_t skip = 0u) {
+  static_assert(NA >= 6, "masses and momentum take six sums");
   const I N = I(d.n);
   const I r = (I(z) * I(d.ny) + I(y)) * I(d.nx) + I(x);
   const uint32_t m = mask[r];
-  if (!(m & MASK_SOLID)) {
+  if (m & (MASK_SOLID | skip)) return false;
+  {
     const NbrT<I> nb = neighbours_t<I>(x, y, z, d);
     T g[3][Q];
 #pragma unroll
@@ -227,6 +230,7 @@ __device__ inline void lb_site(const T* __restrict__ fsrc, T* __restrict__ fdst,
       }
     }
   }
+  return true;
 }
 
 }  // namespace ek

@@ -192,12 +192,14 @@ __device__ inline void deposit_items(const BeadState& bs, int n, int* keys, long
 
 // Fields of time t around bead i: item t < WIN3 sets the fluid / wall flags of
 // the 6^3 window, item t < BOX3 the moments and field of one node of the 4^3
-// box.  The box origin is written by item 0.
+// box.  The box origin is written by item 0.  With `defer` set, every box
+// node is also flagged MASK_DEFER: the chain's friction can only reach nodes
+// of the boxes, so the lattice update of all other sites need not wait for it.
 template <typename T>
 __device__ inline void bead_box_item(const BeadState& bs, int i, int t, const T* __restrict__ f,
-                                     const uint32_t* __restrict__ mask,
+                                     const uint32_t* mask,
                                      const double* __restrict__ psi, const LBParams& lp,
-                                     const Dims& d) {
+                                     const Dims& d, uint32_t* defer = nullptr) {
   const double* R = bs.R + 3 * i;
   const int bx = int(floor(R[0])) - 1, by = int(floor(R[1])) - 1, bz = int(floor(R[2])) - 1;
   if (t == 0) {
@@ -214,6 +216,7 @@ __device__ inline void bead_box_item(const BeadState& bs, int i, int t, const T*
   if (t >= BOX3) return;
   const int cx = bx + t % BOX, cy = by + (t / BOX) % BOX, cz = bz + t / (BOX * BOX);
   const long long r = site_of(cx, cy, cz, d);
+  if (defer) atomicOr(&defer[r], MASK_DEFER);
   const uint32_t m = mask[r];
   double* mo = bs.mom + ((size_t)i * BOX3 + t) * MOM;
   // all 57 pulls are issued before any sum (registers only, one store pass)

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libek.so")
 EK_OK, EK_EINVAL, EK_EHIP, EK_ENOCONV, EK_EUNSTABLE, EK_ESTATE, EK_ENOMEM = 0, -1, -2, -3, -4, -5, -6
 EK_FP32, EK_FP64 = 0, 1
 EK_POISSON_SOR, EK_POISSON_MG = 0, 1
+EK_LAUNCH_GRAPHS, EK_LAUNCH_OVERLAP = 1, 2
 EK_WS_ZERO, EK_WS_PREV, EK_WS_LEARNED = 0, 1, 2
 
 _STATUS = {0: "EK_OK", -1: "EK_EINVAL", -2: "EK_EHIP", -3: "EK_ENOCONV", -4: "EK_EUNSTABLE",
@@ -47,7 +48,7 @@ class ek_stats(ctypes.Structure):
 class ek_timing(ctypes.Structure):
     _fields_ = [("ms_charge", c_double), ("ms_poisson", c_double), ("ms_md", c_double),
                 ("ms_lb", c_double), ("n_steps", c_int64), ("n_lb", c_int64),
-                ("poisson_iters", c_int64)]
+                ("poisson_iters", c_int64), ("lb_sites", c_int64)]
 
 
 class ek_tune_result(ctypes.Structure):
@@ -86,7 +87,7 @@ def _load():
         "ek_poisson_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, P(ek_poisson_report)]),
         "ek_poisson_sor_iterations": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32]),
         "ek_set_timing": (c_int32, [c_void_p, c_int32]),
-        "ek_set_graph_launch": (c_int32, [c_void_p, c_int32]),
+        "ek_set_launch_mode": (c_int32, [c_void_p, c_int32]),
         "ek_get_timing": (c_int32, [c_void_p, P(ek_timing)]),
         "ek_set_model": (c_int32, [c_void_p, c_void_p, c_int32, ctypes.c_float]),
         "ek_get_poisson_system": (c_int32, [c_void_p, c_void_p, c_void_p]),
@@ -254,8 +255,9 @@ class Context:
     def set_timing(self, enable=True):
         self._check(self._lib.ek_set_timing(self._h, 1 if enable else 0), self._h)
 
-    def set_graph_launch(self, enable=True):
-        self._check(self._lib.ek_set_graph_launch(self._h, 1 if enable else 0), self._h)
+    def set_launch_mode(self, graphs=True, overlap=True):
+        flags = (EK_LAUNCH_GRAPHS if graphs else 0) | (EK_LAUNCH_OVERLAP if overlap else 0)
+        self._check(self._lib.ek_set_launch_mode(self._h, flags), self._h)
 
     def timing(self):
         t = ek_timing()

@@ -100,16 +100,22 @@ __global__ __launch_bounds__(BLOCK) void k_lb_tail(const T* __restrict__ fsrc,
                                                    const int* __restrict__ origin, int n_beads,
                                                    double* __restrict__ partials,
                                                    int first_block, int nblocks, Dims d) {
+  // origins of the beads up to this block's last one, staged in LDS for the
+  // test against every lower bead
+  extern __shared__ int so[];
   const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nb_blk = min(n_beads, ((blockIdx.x + 1) * blockDim.x + BOX3 - 1) / BOX3);
+  for (int k = threadIdx.x; k < 3 * nb_blk; k += blockDim.x) so[k] = origin[k];
+  __syncthreads();
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
   if (item < n_beads * BOX3) {
     const int i = item / BOX3, t = item % BOX3;
-    const int gx = origin[3 * i] + t % BOX, gy = origin[3 * i + 1] + (t / BOX) % BOX,
-              gz = origin[3 * i + 2] + t / (BOX * BOX);
+    const int gx = so[3 * i] + t % BOX, gy = so[3 * i + 1] + (t / BOX) % BOX,
+              gz = so[3 * i + 2] + t / (BOX * BOX);
     bool first = true;
     for (int j = 0; j < i && first; ++j)
-      if (wrap(gx - origin[3 * j], d.nx) < BOX && wrap(gy - origin[3 * j + 1], d.ny) < BOX &&
-          wrap(gz - origin[3 * j + 2], d.nz) < BOX)
+      if (wrap(gx - so[3 * j], d.nx) < BOX && wrap(gy - so[3 * j + 1], d.ny) < BOX &&
+          wrap(gz - so[3 * j + 2], d.nz) < BOX)
         first = false;
     if (first) {
       const int x = wrap(gx, d.nx), y = wrap(gy, d.ny), z = wrap(gz, d.nz);
@@ -269,11 +275,12 @@ void launch_lb_tail(const T* fsrc, T* fdst, uint32_t* mask, const double* psi, c
                     const BeadTableView& bt, const int* origin, int n_beads, double* partials,
                     int first_block, int nblocks, Dims d, hipStream_t s) {
   const int blocks = lb_tail_blocks(n_beads);
+  const size_t lds = (size_t)3 * n_beads * sizeof(int);   // at most 12 KiB (MAX_BEADS = 1024)
   if (fits_idx32<T>(d.n))
-    hipLaunchKernelGGL((k_lb_tail<T, uint32_t>), dim3(blocks), dim3(BLOCK), 0, s, fsrc, fdst, mask,
-                       psi, lp, bt, origin, n_beads, partials, first_block, nblocks, d);
+    hipLaunchKernelGGL((k_lb_tail<T, uint32_t>), dim3(blocks), dim3(BLOCK), lds, s, fsrc, fdst,
+                       mask, psi, lp, bt, origin, n_beads, partials, first_block, nblocks, d);
   else
-    hipLaunchKernelGGL((k_lb_tail<T, long long>), dim3(blocks), dim3(BLOCK), 0, s, fsrc, fdst,
+    hipLaunchKernelGGL((k_lb_tail<T, long long>), dim3(blocks), dim3(BLOCK), lds, s, fsrc, fdst,
                        mask, psi, lp, bt, origin, n_beads, partials, first_block, nblocks, d);
 }
 

@@ -108,7 +108,7 @@ def learned_comparison(progress):
     plain starts, outside the timed region: cold held-out fields (zero start
     vs the network's guess, network time included) and warm pairs (previous
     solution, with and without the network consulted), then the single-pore
-    time loop with the previous-step and the learned start."""
+    time loop with the previous-step, the extrapolated and the learned start."""
     from paper_1710_09421_amd import learned
     if not os.path.exists(learned.DEFAULT_MODEL):
         return None
@@ -196,6 +196,9 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--poisson", default="mg", choices=["sor", "mg"])
     ap.add_argument("--check-every", type=int, default=4)
+    ap.add_argument("--start", default="extrapolated", choices=["previous", "extrapolated"],
+                    help="start of each step's Poisson solve: the previous solution or the "
+                         "linear extrapolation of the two previous ones")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-warm-start comparison (single-pore workload only)")
@@ -222,9 +225,11 @@ def main():
     progress(f"workload {wl.name}: {wl.sites} sites")
     prec = ek.EK_FP32 if args.precision == "fp32" else ek.EK_FP64
     method = ek.EK_POISSON_SOR if args.poisson == "sor" else ek.EK_POISSON_MG
+    start = ek.EK_WS_EXTRAP if args.start == "extrapolated" else ek.EK_WS_PREV
     ctx = ek.from_workload(wl, precision=prec, poisson_method=method,
                            poisson_check_every=args.check_every,
-                           poisson_max_iter=200 if method == ek.EK_POISSON_MG else 100000)
+                           poisson_max_iter=200 if method == ek.EK_POISSON_MG else 100000,
+                           warm_start=start)
     progress("context ready")
     for k in range(args.warmup):
         ctx.step(1)
@@ -277,8 +282,9 @@ def main():
             "fluid_sites": wl.fluid_sites,
             "species": 3,
             "beads": 0 if wl.beads_R is None else int(wl.beads_R.shape[0]),
-            "poisson": f"{args.poisson} to {wl.poisson_tol:g} (fp64 residual), "
-                       f"mean {tm['poisson_iters'] / max(tm['n_steps'], 1):.1f} iterations/step",
+            "poisson": f"{args.poisson} to {wl.poisson_tol:g} (fp64 residual) from the "
+                       f"{args.start} start, "
+                       f"mean {tm['poisson_iters'] / max(tm['n_steps'], 1):.2f} iterations/step",
             "phase_ms_per_step": {
                 "charge": round(tm["ms_charge"] / args.steps, 4),
                 "poisson": round(tm["ms_poisson"] / args.steps, 4),

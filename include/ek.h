@@ -63,7 +63,12 @@ typedef enum {
 
 enum { EK_FP32 = 0, EK_FP64 = 1 };                 /* population storage type */
 enum { EK_POISSON_SOR = 0, EK_POISSON_MG = 1 };    /* Poisson method          */
-enum { EK_WS_ZERO = 0, EK_WS_PREV = 1, EK_WS_LEARNED = 2 };  /* warm start    */
+/* Start of each step's Poisson solve: zero; the previous step's solution
+ * (Sec. II.C); the learned guess (see ek_set_model); or the linear
+ * extrapolation in time 2 psi(t-1) - psi(t-2) of the two previous steps'
+ * solutions (the previous solution on the first two steps after
+ * ek_set_geometry).  The solver finishes every start to the same tolerance. */
+enum { EK_WS_ZERO = 0, EK_WS_PREV = 1, EK_WS_LEARNED = 2, EK_WS_EXTRAP = 3 };
 
 /* Problem statement (Sec. II.A-C).  Copied at ek_create. */
 typedef struct {
@@ -86,8 +91,10 @@ typedef struct {
   int32_t poisson_check_every; /* residual test every k iterations (>= 1)      */
   double rho_jacobi;           /* Jacobi radius for the Chebyshev schedule;
                                   0 selects (2 + cos(2 pi / max(n))) / 3       */
-  int32_t warm_start;          /* EK_WS_ZERO, EK_WS_PREV or EK_WS_LEARNED
-                                  (ek_set_model; sizes multiples of 4)  */
+  int32_t warm_start;          /* EK_WS_ZERO, EK_WS_PREV, EK_WS_LEARNED
+                                  (ek_set_model; sizes multiples of 4) or
+                                  EK_WS_EXTRAP (one more float64 field in
+                                  the workspace)                               */
   uint64_t seed;               /* thermal noise seed (noise is not built yet)  */
   int32_t fluctuations;        /* must be 0                                    */
 } ek_params;
@@ -112,6 +119,7 @@ typedef struct {
   int32_t fallback;            /* 1 if the last solve consulted the network
                                   and rejected its guess                       */
   int32_t consulted;           /* 1 if the last solve consulted the network    */
+  double poisson_residual0;    /* relative residual of the last solve's start  */
 } ek_stats;
 
 typedef struct {

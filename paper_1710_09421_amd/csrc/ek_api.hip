@@ -46,7 +46,7 @@ ek_status check_params(const ek_params* p, std::string& why) {
     return EK_EINVAL;
   }
   if (p->rho_jacobi < 0.0 || p->rho_jacobi >= 1.0) { why = "rho_jacobi must be in [0, 1)"; return EK_EINVAL; }
-  if (p->warm_start < EK_WS_ZERO || p->warm_start > EK_WS_LEARNED) { why = "unknown warm_start"; return EK_EINVAL; }
+  if (p->warm_start < EK_WS_ZERO || p->warm_start > EK_WS_EXTRAP) { why = "unknown warm_start"; return EK_EINVAL; }
   if (p->warm_start == EK_WS_LEARNED && !UNet::shape_ok(p->nx, p->ny, p->nz)) {
     why = "the learned warm start needs nx, ny, nz divisible by 4 (two 2x2x2 poolings)";
     return EK_EINVAL;
@@ -57,7 +57,8 @@ ek_status check_params(const ek_params* p, std::string& why) {
 
 // Workspace layout (every block 256-byte aligned).
 struct Layout {
-  size_t fA, fB, mask, wall_q, psi, b, partials, ps, stats, keys, vals, beads, mg, net, guess, total;
+  size_t fA, fB, mask, wall_q, psi, b, partials, ps, stats, keys, vals, beads, mg, net, guess,
+      psi_old, total;
 };
 
 Layout make_layout(const ek_params* p, int max_beads) {
@@ -87,6 +88,7 @@ Layout make_layout(const ek_params* p, int max_beads) {
   const bool learned = p->warm_start == EK_WS_LEARNED;
   L.net = take(learned ? UNet::bytes(p->nx, p->ny, p->nz, false) : 0);
   L.guess = take(learned ? n * 8 : 0);
+  L.psi_old = take(p->warm_start == EK_WS_EXTRAP ? n * 8 : 0);
   L.total = off;
   return L;
 }
@@ -230,6 +232,15 @@ ek_status ek_ctx::poisson(const double* bb, double* x, bool learned, int& iters,
   PoissonScalars h{};
   last_fallback = 0;
   last_consulted = 0;
+  if (!learned && p.poisson_method == EK_POISSON_MG) {
+    // the start's residual stays on the device (the cycles test its flag and
+    // skip themselves once converged); the host reads it with the first
+    // batch's result
+    const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
+    launch_residual(x, bb, ps, partials, dims, g, stream);
+    launch_residual_final(partials, g.nblocks(), p.poisson_tol, 0, 1, ps, stream);
+    return mg_solve(bb, x, h, iters, res, res0);
+  }
   ek_status st = learned ? learned_start(bb, x, &h) : initial_residual(bb, x, &h);
   if (st) return st;
   if (p.poisson_method == EK_POISSON_MG) return mg_solve(bb, x, h, iters, res, res0);
@@ -277,12 +288,19 @@ ek_status ek_ctx::step_impl(int n_steps) {
     launch_mean_shift(partials, nb, 1.0 / double(dims.n), inv_eps(), ps, stream);
     record(t, 1);
     if (p.warm_start == EK_WS_ZERO) launch_fill(psi, 0.0, dims.n, stream);
+    if (p.warm_start == EK_WS_EXTRAP) {
+      // psi = 2 psi(t-1) - psi(t-2) once two previous solutions exist; the
+      // history keeps psi(t-1)
+      if (psi_hist > 0) launch_extrapolate(psi, psi_old, psi_hist >= 2, dims.n, stream);
+      psi_hist = std::min(psi_hist + 1, 2);
+    }
     int iters = 0;
     double res = 0, res0 = 0;
     ek_status st = poisson(b, psi, p.warm_start == EK_WS_LEARNED, iters, res, res0);
     if (st) return st;
     last_iters = iters;
     last_res = res;
+    last_res0 = res0;
     have_solve = true;
     if (timing) tacc.poisson_iters += iters;
     record(t, 2);
@@ -448,6 +466,7 @@ ek_status ek_create(const ek_params* p, int32_t max_beads, void* dev_ws, size_t 
     c->net->init_state();
     c->guess = (double*)(ws + L.guess);
   }
+  if (p->warm_start == EK_WS_EXTRAP) c->psi_old = (double*)(ws + L.psi_old);
   *out = c;
   return EK_OK;
 }
@@ -497,6 +516,7 @@ ek_status ek_set_geometry(ek_ctx* ctx, const uint8_t* solid, const double* wall_
   for (int s = 0; s < 3; ++s) ctx->have_species[s] = false;
   ctx->step_count = 0;
   ctx->last_iters = 0;
+  ctx->psi_hist = 0;
   return ctx->sync();
 }
 
@@ -594,6 +614,7 @@ ek_status ek_get_stats(ek_ctx* ctx, ek_stats* out) {
   out->poisson_residual = ctx->last_res;
   out->fallback = ctx->last_fallback;
   out->consulted = ctx->last_consulted;
+  out->poisson_residual0 = ctx->last_res0;
   return EK_OK;
 }
 

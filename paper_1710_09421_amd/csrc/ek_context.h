@@ -55,6 +55,7 @@ struct ek_ctx {
   int last_iters = 0;
   int solo_iters = 0;
   double last_res = 0.0;
+  double last_res0 = 0.0;
   int last_fallback = 0;
   int last_consulted = 0;
   bool have_solve = false;             // b, ps and psi hold a finished solve
@@ -114,6 +115,10 @@ struct ek_ctx {
   // learned warm start (present when p.warm_start == EK_WS_LEARNED)
   ek::UNet* net = nullptr;
   double* guess = nullptr;
+  // extrapolated start (p.warm_start == EK_WS_EXTRAP): psi(t-2), and how many
+  // previous step solutions the history holds (0, 1 or 2)
+  double* psi_old = nullptr;
+  int psi_hist = 0;
   template <typename T>
   ek_status step_impl(int n_steps);
 

@@ -134,6 +134,8 @@ void launch_residual_final(const double* partials, int nblocks, double tol, int 
                            int initial, PoissonScalars* ps, hipStream_t s);
 void launch_psi_shift(double* psi, const PoissonScalars* ps, double inv_n, Dims d,
                       hipStream_t s);
+// x = 2 x - old (linear) or x kept; old = the previous x.
+void launch_extrapolate(double* x, double* old, bool linear, long long n, hipStream_t s);
 void launch_fill(double* x, double v, long long n, hipStream_t s);
 void launch_ps_reset(PoissonScalars* ps, double shift, hipStream_t s);
 void launch_ps_rearm(PoissonScalars* ps, hipStream_t s);

@@ -927,6 +927,7 @@ ek_status ek_ensemble_get_stats(ek_ensemble* e, int32_t r, ek_stats* out) {
   out->step = R.steps;
   out->poisson_iters = R.last_cycles;
   out->poisson_residual = R.last_res;
+  out->poisson_residual0 = R.last_res0;
   return EK_OK;
 }
 

@@ -18,7 +18,7 @@ EK_OK, EK_EINVAL, EK_EHIP, EK_ENOCONV, EK_EUNSTABLE, EK_ESTATE, EK_ENOMEM = 0, -
 EK_FP32, EK_FP64 = 0, 1
 EK_POISSON_SOR, EK_POISSON_MG = 0, 1
 EK_LAUNCH_GRAPHS, EK_LAUNCH_OVERLAP = 1, 2
-EK_WS_ZERO, EK_WS_PREV, EK_WS_LEARNED = 0, 1, 2
+EK_WS_ZERO, EK_WS_PREV, EK_WS_LEARNED, EK_WS_EXTRAP = 0, 1, 2, 3
 
 _STATUS = {0: "EK_OK", -1: "EK_EINVAL", -2: "EK_EHIP", -3: "EK_ENOCONV", -4: "EK_EUNSTABLE",
            -5: "EK_ESTATE", -6: "EK_ENOMEM"}
@@ -42,7 +42,7 @@ class ek_polymer_params(ctypes.Structure):
 class ek_stats(ctypes.Structure):
     _fields_ = [("mass", c_double * 3), ("momentum", c_double * 3), ("step", c_int64),
                 ("poisson_iters", c_int32), ("poisson_residual", c_double), ("fallback", c_int32),
-                ("consulted", c_int32)]
+                ("consulted", c_int32), ("poisson_residual0", c_double)]
 
 
 class ek_timing(ctypes.Structure):
@@ -250,7 +250,8 @@ class Context:
         self._check(self._lib.ek_get_stats(self._h, byref(s)), self._h)
         return dict(mass=np.array(s.mass[:]), momentum=np.array(s.momentum[:]), step=s.step,
                     poisson_iters=s.poisson_iters, poisson_residual=s.poisson_residual,
-                    fallback=s.fallback, consulted=s.consulted)
+                    poisson_residual0=s.poisson_residual0, fallback=s.fallback,
+                    consulted=s.consulted)
 
     def set_timing(self, enable=True):
         self._check(self._lib.ek_set_timing(self._h, 1 if enable else 0), self._h)

@@ -220,12 +220,14 @@ def evaluate(params, out_scale, data, tol=1e-8, repeats=3, log=print):
 
 
 def simulate(params, out_scale, steps=200, warmup=20, wl=None, log=print):
-    """Single-pore time loop with the previous-step start and with the learned
-    start (previous step kept as the fallback): Poisson milliseconds and
-    cycles per step from the context's phase timers."""
+    """Single-pore time loop with the previous-step start, the extrapolated
+    start (2 psi(t-1) - psi(t-2)) and the learned start (previous step kept
+    as the fallback): Poisson milliseconds and cycles per step from the
+    context's phase timers."""
     wl = wl or workloads.single_pore()
     out = {}
-    for name, ws in (("previous", ek.EK_WS_PREV), ("learned", ek.EK_WS_LEARNED)):
+    for name, ws in (("previous", ek.EK_WS_PREV), ("extrapolated", ek.EK_WS_EXTRAP),
+                     ("learned", ek.EK_WS_LEARNED)):
         ctx = ek.from_workload(wl, precision=ek.EK_FP32, poisson_method=ek.EK_POISSON_MG,
                                poisson_tol=1e-8, poisson_max_iter=200, warm_start=ws)
         if ws == ek.EK_WS_LEARNED:

@@ -89,10 +89,15 @@ def test_multigrid_warm_start_needs_fewer_cycles(ek):
     assert warm["initial_residual"] < 1e-2
 
 
-def test_pore_fp32_with_multigrid_matches_oracle(ek):
+@pytest.mark.parametrize("start", ["previous", "extrapolated"])
+def test_pore_fp32_with_multigrid_matches_oracle(ek, start):
+    """Each step's solve starts from the previous solution, or from the linear
+    extrapolation of the two previous ones; the oracle starts SOR from the
+    previous solution.  Both finish to 1e-8."""
     wl = workloads.pore_system((32, 24, 24), 6, 4, 0.01, 0.01, -0.01, 8, 32, steps=100)
+    ws = ek.EK_WS_PREV if start == "previous" else ek.EK_WS_EXTRAP
     ctx = ek.from_workload(wl, precision=ek.EK_FP32, poisson_method=ek.EK_POISSON_MG,
-                           poisson_tol=1e-8)
+                           poisson_tol=1e-8, warm_start=ws)
     p = ostep.Params(E_ext=wl.E_ext, poisson_tol=1e-8)
     sim = ostep.Simulation(p, wl.solid.astype(bool), wl.wall_q, wl.n0,
                            beads=(wl.beads_R, wl.beads_V, wl.polymer))
@@ -109,3 +114,28 @@ def test_pore_fp32_with_multigrid_matches_oracle(ek):
     err["R"] = float(np.abs(ctx.beads(8)[0] - sim.R).max())
     print(err)
     assert max(err.values()) < 1e-5, err
+
+
+def test_extrapolated_start_needs_fewer_cycles(ek):
+    """Single pore, 60 steps after 10: the extrapolated start begins closer to
+    the solution than the previous one and needs no more multigrid cycles per
+    step; every solve meets the tolerance."""
+    wl = workloads.single_pore()
+    cycles, res0 = {}, {}
+    for name, ws in (("previous", ek.EK_WS_PREV), ("extrapolated", ek.EK_WS_EXTRAP)):
+        ctx = ek.from_workload(wl, precision=ek.EK_FP32, poisson_method=ek.EK_POISSON_MG,
+                               poisson_tol=1e-8, poisson_max_iter=200, warm_start=ws)
+        ctx.step(10)
+        ctx.set_timing(True)
+        r0 = []
+        for _ in range(60):
+            ctx.step(1)
+            st = ctx.stats()
+            assert st["poisson_residual"] <= 1e-8
+            r0.append(st["poisson_residual0"])
+        cycles[name] = ctx.timing()["poisson_iters"] / 60
+        res0[name] = float(np.median(r0))
+        ctx.close()
+    print(cycles, res0)
+    assert res0["extrapolated"] < 0.5 * res0["previous"]
+    assert cycles["extrapolated"] <= cycles["previous"]

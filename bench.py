@@ -146,7 +146,9 @@ def run_ensemble(args):
     wls = [workloads.ensemble_replica(r) for r in range(n_rep)]
     progress(f"{n_rep} replicas of {wls[0].shape[::-1]}, chains "
              f"{sorted(set(int(w.beads_R.shape[0]) for w in wls))}")
-    ens = ek.ensemble_from_workloads(wls, precision=ek.EK_FP32, poisson_tol=1e-8)
+    start = ek.EK_WS_EXTRAP if args.start == "extrapolated" else ek.EK_WS_PREV
+    ens = ek.ensemble_from_workloads(wls, precision=ek.EK_FP32, poisson_tol=1e-8,
+                                     warm_start=start)
     progress("ensemble ready")
     tune = ens.autotune(steps=max(2, args.warmup // 3))
     progress(f"autotuned: {tune}")
@@ -180,7 +182,8 @@ def run_ensemble(args):
             "sites": sites,
             "threads_per_workgroup": tune["threads"],
             "workgroups_per_replica": tune["group"],
-            "poisson": f"mg to 1e-8 per replica, last solve {min(cycles)}-{max(cycles)} cycles",
+            "poisson": f"mg to 1e-8 per replica from the {args.start} start, "
+                       f"last solve {min(cycles)}-{max(cycles)} cycles",
             "lb_bytes_per_step_gb": round(lb_bytes / 1e9, 3),
         },
     }

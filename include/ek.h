@@ -305,12 +305,15 @@ ek_status ek_unet_read_loss(ek_unet* net, double* mean_loss, int64_t* count);
 /* ---------------------------------------------------------------------------
  * Ensemble: uneven replicas of one geometry (translocation replicas with their
  * own salt noise, applied field and chain, Sec. IV.A) advanced together by ONE
- * persistent kernel launch per ek_ensemble_step call: one workgroup per
- * replica runs the whole time loop of Fig. 1 for that replica (charge pass,
- * multigrid Poisson solve with its own convergence test, chain substeps,
- * fused lattice step), so replicas with more Poisson cycles or longer chains
- * never hold the others back.  The Poisson method is multigrid; all other
- * parameters come from the base ek_params except the applied field.
+ * persistent kernel launch per ek_ensemble_step call: a team of 1, 2 or 4
+ * workgroups per replica runs the whole time loop of Fig. 1 for that replica
+ * (charge pass, multigrid Poisson solve with its own convergence test, chain
+ * substeps, fused lattice step), so replicas with more Poisson cycles or
+ * longer chains never hold the others back.  The Poisson method is
+ * multigrid, started from the previous solution, or from the extrapolated
+ * one when the base warm_start is EK_WS_EXTRAP (other values: the previous
+ * solution); all other parameters come from the base ek_params except the
+ * applied field.
  * ------------------------------------------------------------------------- */
 typedef struct ek_ensemble ek_ensemble;
 

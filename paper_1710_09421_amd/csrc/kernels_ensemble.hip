@@ -60,6 +60,8 @@ struct RepDev {
   TeamSync* sync;
   uint32_t* mask;             // link words (own copy: the bead flag is per replica)
   double* psi;
+  double* psi_old;            // psi(t-2) for the extrapolated start, or null
+  int psi_hist;               // previous solutions held (0, 1 or 2)
   double* b;
   double* mg;                 // multigrid levels 1.. (x then f per level)
   int* keys;
@@ -231,6 +233,7 @@ __global__ __launch_bounds__(MAXT) void k_ensemble(RepDev* reps, EnsConst ec) {
   const int last = ec.nlev - 1;
   const LBParams& lp = R.lp;   // read where used (uniform loads)
   int cur = R.cur;
+  int hist = R.psi_hist;       // every member keeps the same count
 // every member takes the same branch: the status depends only on team-wide
 // values; a failed barrier ends the team's work
 #define TEAM_SYNC()                                   \
@@ -255,15 +258,23 @@ __global__ __launch_bounds__(MAXT) void k_ensemble(RepDev* reps, EnsConst ec) {
       deposit_items(R.bs, R.n_beads, R.keys, R.vals, R.mask, d, ENS_TABLE_BITS, tid, MAXT);
     }
     TEAM_SYNC();
-    // charge pass
+    // charge pass; with the extrapolated start also psi = 2 psi(t-1) - psi(t-2)
+    // (the sums' barrier orders it before the solve reads neighbours)
     double rs[1] = {0.0};
+    const bool extrap = R.psi_old != nullptr && hist > 0;
     for (int t = first; t < N; t += stride) {
       int x, y, z;
       site_xyz(t, d, inx, iny, x, y, z);
       const double rho = charge_site<T, long long>(fsrc, R.mask, ec.wall_q, lp, bt, x, y, z, d);
       R.b[t] = -rho * ec.inv_eps;
       rs[0] += rho;
+      if (extrap) {
+        const double p = R.psi[t];
+        if (hist >= 2) R.psi[t] = 2.0 * p - R.psi_old[t];
+        R.psi_old[t] = p;
+      }
     }
+    if (R.psi_old != nullptr) hist = hist < 2 ? hist + 1 : 2;
     if (!team_sums<MAXT, 1>(rs, sh, ts, g, G, gen, nred, &s_ok)) {
       if (tid == 0) s_status = ST_TIMEOUT;
       __syncthreads();
@@ -394,6 +405,7 @@ __global__ __launch_bounds__(MAXT) void k_ensemble(RepDev* reps, EnsConst ec) {
   if (tid == 0 && g == 0) {
     R.cur = cur;
     R.status = s_status;
+    R.psi_hist = hist;
   }
 }
 
@@ -434,7 +446,7 @@ struct ek_ensemble {
 namespace {
 
 struct RepLayout {
-  size_t fA, fB, mask, psi, b, mg, keys, vals, beads, sync, total;
+  size_t fA, fB, mask, psi, psi_old, b, mg, keys, vals, beads, sync, total;
 };
 
 RepLayout rep_layout(const ek_params* p, int max_beads) {
@@ -447,6 +459,7 @@ RepLayout rep_layout(const ek_params* p, int max_beads) {
   L.fB = take(3 * Q * n * tsz);
   L.mask = take(n * 4);
   L.psi = take(n * 8);
+  L.psi_old = take(p->warm_start == EK_WS_EXTRAP ? n * 8 : 0);
   L.b = take(n * 8);
   L.mg = take(mg_workspace_bytes(p->nx, p->ny, p->nz));
   L.keys = take((size_t(1) << ENS_TABLE_BITS) * 4);
@@ -675,6 +688,7 @@ ek_status ek_ensemble_create(const ek_params* base, int32_t n_rep, int32_t max_b
     R.f[1] = m + RL.fB;
     R.mask = (uint32_t*)(m + RL.mask);
     R.psi = (double*)(m + RL.psi);
+    R.psi_old = base->warm_start == EK_WS_EXTRAP ? (double*)(m + RL.psi_old) : nullptr;
     R.b = (double*)(m + RL.b);
     R.mg = (double*)(m + RL.mg + 256);
     R.keys = (int*)(m + RL.keys);
@@ -718,6 +732,7 @@ ek_status ek_ensemble_set_geometry(ek_ensemble* e, const uint8_t* solid, const d
     R.status = ST_OK;
     R.steps = 0;
     R.n_beads = 0;
+    R.psi_hist = 0;
   }
   if (wall_q) {
     if (hipMemcpyAsync(e->wall_q, wall_q, n * 8, hipMemcpyHostToDevice, e->stream) != hipSuccess)
@@ -778,6 +793,7 @@ ek_status ek_ensemble_set_replica(ek_ensemble* e, int32_t r, const double* E_ext
   R.status = ST_OK;
   R.steps = 0;
   R.n_beads = n_beads;
+  R.psi_hist = 0;
   if (n_beads > 0) {
     std::vector<double> q(n_beads, 0.0);
     if (charge) std::copy(charge, charge + n_beads, q.begin());

@@ -415,7 +415,7 @@ class Ensemble:
 
 
 def ensemble_from_workloads(wls, precision=EK_FP32, poisson_tol=1e-8, poisson_max_iter=200,
-                            max_beads=None):
+                            max_beads=None, warm_start=EK_WS_PREV):
     """Ensemble whose replicas are the given workloads (same geometry)."""
     w0 = wls[0]
     for w in wls:
@@ -423,7 +423,8 @@ def ensemble_from_workloads(wls, precision=EK_FP32, poisson_tol=1e-8, poisson_ma
     nb = [0 if w.beads_R is None else w.beads_R.shape[0] for w in wls]
     p = make_params(w0.shape, precision=precision, valence=w0.valence, tau=w0.tau,
                     omega_drag=w0.omega_drag, bjerrum=w0.bjerrum, poisson_method=EK_POISSON_MG,
-                    poisson_tol=poisson_tol, poisson_max_iter=poisson_max_iter)
+                    poisson_tol=poisson_tol, poisson_max_iter=poisson_max_iter,
+                    warm_start=warm_start)
     ens = Ensemble(p, len(wls), max_beads=max(nb) if max_beads is None else max_beads)
     ens.set_geometry(w0.solid, w0.wall_q)
     for r, w in enumerate(wls):

@@ -83,13 +83,16 @@ def test_replica_fp64_matches_oracle(ek):
     assert max(err.values()) < 1e-8, err
 
 
-def test_replicas_match_single_contexts(ek):
+@pytest.mark.parametrize("start", ["previous", "extrapolated"])
+def test_replicas_match_single_contexts(ek, start):
+    """Replicas against single contexts with the same start of each solve."""
     wls = replicas()
-    ens = ek.ensemble_from_workloads(wls, precision=ek.EK_FP32, poisson_tol=1e-8)
+    ws = ek.EK_WS_PREV if start == "previous" else ek.EK_WS_EXTRAP
+    ens = ek.ensemble_from_workloads(wls, precision=ek.EK_FP32, poisson_tol=1e-8, warm_start=ws)
     ens.step(15)
     for r, wl in enumerate(wls):
         ctx = ek.from_workload(wl, precision=ek.EK_FP32, poisson_method=ek.EK_POISSON_MG,
-                               poisson_tol=1e-8)
+                               poisson_tol=1e-8, warm_start=ws)
         ctx.step(15)
         for s in range(3):
             n_e, u_e = ens.moments(r, s)
@@ -130,11 +133,14 @@ def test_replicas_are_independent(ek):
     assert not np.array_equal(n1, ens.moments(0, 1)[0])
 
 
-@pytest.mark.parametrize("group", [2, 4])
-def test_replica_teams_match_oracle_fp32(ek, group):
-    """Each replica advanced by a team of workgroups meeting at barriers."""
+@pytest.mark.parametrize("group,start", [(2, "previous"), (4, "previous"), (4, "extrapolated")])
+def test_replica_teams_match_oracle_fp32(ek, group, start):
+    """Each replica advanced by a team of workgroups meeting at barriers; the
+    solves start from the previous solution or its extrapolation (the oracle
+    starts from the previous one; both finish to 1e-8)."""
     wls = replicas()
-    ens = ek.ensemble_from_workloads(wls, precision=ek.EK_FP32, poisson_tol=1e-8)
+    ws = ek.EK_WS_PREV if start == "previous" else ek.EK_WS_EXTRAP
+    ens = ek.ensemble_from_workloads(wls, precision=ek.EK_FP32, poisson_tol=1e-8, warm_start=ws)
     ens.set_threads(512)
     ens.set_group(group)
     ens.step(20)

@@ -144,11 +144,30 @@ constexpr int LDS_MAX_BEADS = 64;
 // One workgroup per chain, TPB threads per bead: the lanes of a bead split
 // its 8 corners, its pair partners and its wall sites, and combine their
 // parts with a butterfly over the TPB lanes (every lane ends with the same
-// bits, so all lanes advance the bead identically).
+// bits, so all lanes advance the bead identically).  The exchanges are DPP
+// lane moves within a row of 16 lanes: xor 1 and xor 2 as quad permutations,
+// xor 4 as a shift by four lanes to the left (lanes 0-3 of each group of 8)
+// or to the right (lanes 4-7).  A bead's lanes are active together.
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
 template <int TPB>
 __device__ inline double group_sum(double v) {
-#pragma unroll
-  for (int m = 1; m < TPB; m <<= 1) v += __shfl_xor(v, m, TPB);
+  static_assert(TPB == 1 || TPB == 2 || TPB == 4 || TPB == 8, "lanes per bead");
+  constexpr int XOR1 = 0xB1;          // quad_perm [1, 0, 3, 2]
+  constexpr int XOR2 = 0x4E;          // quad_perm [2, 3, 0, 1]
+  constexpr int SHL4 = 0x104;         // row_shl:4 (lane l reads lane l + 4)
+  constexpr int SHR4 = 0x114;         // row_shr:4 (lane l reads lane l - 4)
+  if constexpr (TPB >= 2) v += dpp_move<XOR1>(v);
+  if constexpr (TPB >= 4) v += dpp_move<XOR2>(v);
+  if constexpr (TPB >= 8) {
+    const double up = dpp_move<SHL4>(v), down = dpp_move<SHR4>(v);
+    v += (threadIdx.x & 4) ? down : up;
+  }
   return v;
 }
 

@@ -185,14 +185,22 @@ ek_status ek_ctx::beads_advance(bool overlap, hipEvent_t chain_end) {
                             (int)lds) != hipSuccess)
       return fail(EK_EHIP, "cannot raise the LDS limit of the chain kernel");
     md(k_md<true, 8, 512>, lds, bits);
-  } else if (tpb == 4) {
-    md(k_md<false, 4, 512>, sr_bytes, 0);
-  } else if (tpb == 2) {
-    md(k_md<false, 2, 512>, sr_bytes, 0);
-  } else if (threads <= 512) {
-    md(k_md<false, 1, 512>, sr_bytes, 0);
   } else {
-    md(k_md<false, 1, 1024>, sr_bytes, 0);
+    // positions and the per-lane pair lists
+    const size_t lds = sr_bytes + md_list_bytes(false, threads);
+    if (tpb == 4) {
+      md(k_md<false, 4, 512>, lds, 0);
+    } else if (tpb == 2) {
+      md(k_md<false, 2, 512>, lds, 0);
+    } else if (threads <= 512) {
+      md(k_md<false, 1, 512>, lds, 0);
+    } else {
+      if (lds > 64 * 1024 &&
+          hipFuncSetAttribute((const void*)k_md<false, 1, 1024>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return fail(EK_EHIP, "cannot raise the LDS limit of the chain kernel");
+      md(k_md<false, 1, 1024>, lds, 0);
+    }
   }
   if (chain_end && hipEventRecord(chain_end, cs) != hipSuccess)
     return fail(EK_EHIP, "recording the chain timer failed");

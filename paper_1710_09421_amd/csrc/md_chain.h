@@ -285,9 +285,25 @@ __device__ inline void bead_box_item(const BeadState& bs, int i, int t, const T*
   e[2] = -0.5 * (psi[site_of(cx, cy, cz + 1, d)] - psi[site_of(cx, cy, cz - 1, d)]) + lp.eext[2];
 }
 
+// Pair partners kept per lane for chains whose node table is in global
+// memory (long chains): lane l of bead i lists the beads j = l, l + TPB, ...
+// within the WCA cut-off plus NB_SKIN at the last build, in increasing j.
+// The list is rebuilt when any bead has moved more than NB_SKIN / 2 since
+// the build, so every pair inside the cut-off stays listed; a lane that would
+// list more than NB_PER_LANE partners switches the chain back to all pairs.
+// A lane sums the same nonzero pair terms in the same order either way.
+constexpr int NB_PER_LANE = 32;
+constexpr double NB_SKIN = 0.6;
+
+// LDS bytes of md_chain beyond the positions and the LDS node table.
+__host__ __device__ inline size_t md_list_bytes(bool lds_table, int threads) {
+  return lds_table ? 0 : (size_t)threads * NB_PER_LANE * sizeof(unsigned short);
+}
+
 // n_sub substeps of one chain by one workgroup (TPB lanes per bead; the
 // threads beyond n * TPB only take part in the barriers).  smem: LDS for the
-// bead positions and, when LDS is set, the node table of 2^lds_bits slots.
+// bead positions and, when LDS is set, the node table of 2^lds_bits slots,
+// else the pair lists (md_list_bytes).
 template <bool LDS, int TPB>
 __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gkeys,
                                 long long* gvals, uint32_t* mask, const Dims& d, int gbits,
@@ -297,6 +313,16 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
   long long* lvals = (long long*)(smem + (((size_t)mp.n * 24 + 15) & ~size_t(15)));
   const int lslots = LDS ? (1 << lds_bits) : 0;
   int* lkeys = (int*)(lvals + (size_t)lslots * 9);
+  // pair lists (long chains): entry k of thread t at nbl[k * blockDim.x + t]
+  constexpr bool NLIST = !LDS;
+  unsigned short* nbl = (unsigned short*)lvals;
+  __shared__ int s_rebuild, s_overflow;
+  if (NLIST && threadIdx.x == 0) {
+    s_rebuild = 1;
+    s_overflow = 0;
+  }
+  int nb_count = 0;
+  double Rb[3] = {0, 0, 0};                 // position at the last list build
 
   const int i = threadIdx.x / TPB;          // bead
   const int lane = threadIdx.x % TPB;
@@ -347,7 +373,33 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
   double mo_c[CACHE ? CPL : 1][MOM];
   double e_c[CACHE_E ? CPL : 1][3];
   unsigned long long wall_bits = 0;
+  const double rl = 1.122462048309373 * mp.sigma + NB_SKIN;      // list radius
+  const double rl2 = rl * rl, half_skin2 = 0.25 * NB_SKIN * NB_SKIN;
   for (int sub = 0; sub < mp.n_sub; ++sub) {
+    if (NLIST && s_rebuild) {            // the same in every thread (set before the last barrier)
+      if (live) {
+        nb_count = 0;
+        for (int j = lane; j < mp.n; j += TPB) {
+          if (j == i) continue;
+          double r2 = 0.0;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double v = R[c] - sR[3 * j + c];
+            const double dv = v - L[c] * rint(v * iL[c]);
+            r2 += dv * dv;
+          }
+          if (r2 < rl2) {
+            if (nb_count < NB_PER_LANE) nbl[nb_count * blockDim.x + threadIdx.x] = (unsigned short)j;
+            ++nb_count;
+          }
+        }
+        if (nb_count > NB_PER_LANE) s_overflow = 1;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Rb[c] = R[c];
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) s_rebuild = 0;
+    }
     double wt[CPL];
     double phi[3][3];
     double Rn[3];
@@ -377,7 +429,9 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
           const int k8 = lane * CPL + a;
           const int ox = k8 & 1, oy = (k8 >> 1) & 1, oz = (k8 >> 2) & 1;
           bidx[a] = (lx + ox) + BOX * ((ly + oy) + BOX * (lz + oz));
-          wfl[a] = fl_all[k8];
+          // from the flag window, not fl_all[k8]: k8 depends on the lane, and
+          // a register array indexed at run time would live in scratch memory
+          wfl[a] = (fl[(lx + ox + 1) + WIN * ((ly + oy + 1) + WIN * (lz + oz + 1))] & 1) ? 1.0 : 0.0;
           slot[a] = -1;
           if (wfl[a] != 0.0) {
             const long long site = site_of(fx + ox, fy + oy, fz + oz, d);
@@ -451,8 +505,7 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
       }
       // this lane's share of the conservative forces
       double F[3] = {0.0, 0.0, 0.0};
-      for (int j = lane; j < mp.n; j += TPB) {        // WCA between all pairs
-        if (j == i) continue;
+      auto wca_pair = [&](int j) {
         double dv[3], r2 = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -467,6 +520,12 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
 #pragma unroll
           for (int c = 0; c < 3; ++c) F[c] += coef * dv[c];
         }
+      };
+      if (NLIST && !s_overflow) {                    // WCA with the listed partners
+        for (int k = 0; k < nb_count; ++k) wca_pair(nbl[k * blockDim.x + threadIdx.x]);
+      } else {
+        for (int j = lane; j < mp.n; j += TPB)       // WCA between all pairs
+          if (j != i) wca_pair(j);
       }
       for (int k = 0; k < NWS; ++k) {             // WCA against wall-site centres
         const int wsite = lane + k * TPB;
@@ -549,6 +608,12 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
       for (int c = 0; c < 3; ++c) {
         R[c] = Rn[c];
         if (lane == 0) sR[3 * i + c] = Rn[c];
+      }
+      if (NLIST) {   // moved more than half the skin since the build: rebuild next substep
+        double dd = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dd += (R[c] - Rb[c]) * (R[c] - Rb[c]);
+        if (dd > half_skin2) s_rebuild = 1;
       }
     }
     // one workgroup advances the chain: the barrier's workgroup-scope ordering

@@ -132,17 +132,39 @@ def test_polymer_argument_checks(ek):
     assert e.value.status == ek.EK_EINVAL
 
 
-@pytest.mark.parametrize("n_beads", [48, 80, 130])
-def test_long_chain_fp64_matches_oracle(ek, n_beads):
+@pytest.mark.parametrize("n_beads,steps", [(48, 8), (80, 8), (130, 8), (300, 3)])
+def test_long_chain_fp64_matches_oracle(ek, n_beads, steps):
     """Chains of up to 64 beads keep the node table in LDS (8 lanes per bead:
     48 beads fill six waves); beyond 64 beads it moves to global memory (4
-    lanes per bead up to 128 beads, then 2)."""
+    lanes per bead up to 128 beads, then 2, then 1) and the WCA partners come
+    from per-lane pair lists."""
     wl = workloads.pore_system((64, 40, 40), 8, 5, 0.01, 0.01, -0.01, n_beads, 41,
                                bead_q=workloads.STABLE_BEAD_CHARGE, steps=10)
     ctx = ek.from_workload(wl, precision=ek.EK_FP64, poisson_tol=1e-10, poisson_check_every=1)
     sim = oracle_sim(wl, 1e-10)
-    ctx.step(8)
-    sim.run(8)
+    ctx.step(steps)
+    sim.run(steps)
     err = errors(ctx, sim, wl)
     print(n_beads, err)
+    assert max(err.values()) < 1e-8, err
+
+
+def test_pair_lists_rebuilt_within_a_step(ek):
+    """Weak friction and fast beads: beads cross half the list skin within a
+    step, so the per-lane pair lists of an 80-bead chain are rebuilt between
+    substeps; the chain still matches the oracle's all-pairs forces."""
+    wl = workloads.pore_system((64, 40, 40), 8, 5, 0.01, 0.01, -0.01, 80, 43,
+                               bead_q=workloads.STABLE_BEAD_CHARGE, steps=3, gamma=0.5)
+    rng = np.random.default_rng(7)
+    v = rng.normal(size=wl.beads_R.shape)
+    wl.beads_V = 0.35 * v / np.linalg.norm(v, axis=1, keepdims=True)
+    ctx = ek.from_workload(wl, precision=ek.EK_FP64, poisson_tol=1e-10, poisson_check_every=1)
+    sim = oracle_sim(wl, 1e-10)
+    R0 = wl.beads_R.copy()
+    ctx.step(2)
+    sim.run(2)
+    err = errors(ctx, sim, wl)
+    moved = np.linalg.norm(sim.R - R0, axis=1).max()
+    print(moved, err)
+    assert moved > 0.3            # more than half the skin (0.6): lists were rebuilt
     assert max(err.values()) < 1e-8, err

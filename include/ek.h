@@ -176,7 +176,11 @@ ek_status ek_get_stats(struct ek_ctx* ctx, ek_stats* out);
 /* Standalone Poisson solve on device buffers: dev_rho[nz*ny*nx] charge
  * density, dev_psi[nz*ny*nx] warm start on entry and solution (mean zero) on
  * return, both float64.  Uses the context's method, tolerance and iteration
- * limit; warm_start EK_WS_ZERO clears dev_psi first. */
+ * limit; warm_start EK_WS_ZERO clears dev_psi first, EK_WS_PREV and
+ * EK_WS_EXTRAP start from dev_psi as given (a stand-alone solve has no
+ * history to extrapolate), EK_WS_LEARNED consults the network (EK_ESTATE
+ * without a model); other values give EK_EINVAL.  The context's own fields
+ * (populations, potential) are not touched. */
 ek_status ek_poisson_solve(struct ek_ctx* ctx, const double* dev_rho, double* dev_psi,
                            int32_t warm_start, ek_poisson_report* rep);
 

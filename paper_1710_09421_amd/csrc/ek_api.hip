@@ -284,16 +284,15 @@ ek_status ek_ctx::step_impl(int n_steps) {
       ek_status st = beads_deposit();
       if (st) return st;
     }
-    launch_charge<T>((const T*)fcur(), mask, wall_q, b, partials, lp, inv_eps(), dims, g, stream, bt);
+    // the charge pass also prepares the extrapolated start (EK_WS_EXTRAP):
+    // psi = 2 psi(t-1) - psi(t-2) once two previous solutions exist
+    const int extrap = p.warm_start == EK_WS_EXTRAP ? std::min(psi_hist, 2) : 0;
+    launch_charge<T>((const T*)fcur(), mask, wall_q, b, partials, lp, inv_eps(), dims, g, stream, bt,
+                     psi, psi_old, extrap);
+    if (p.warm_start == EK_WS_EXTRAP) psi_hist = std::min(psi_hist + 1, 2);
     launch_mean_shift(partials, nb, 1.0 / double(dims.n), inv_eps(), ps, stream);
     record(t, 1);
     if (p.warm_start == EK_WS_ZERO) launch_fill(psi, 0.0, dims.n, stream);
-    if (p.warm_start == EK_WS_EXTRAP) {
-      // psi = 2 psi(t-1) - psi(t-2) once two previous solutions exist; the
-      // history keeps psi(t-1)
-      if (psi_hist > 0) launch_extrapolate(psi, psi_old, psi_hist >= 2, dims.n, stream);
-      psi_hist = std::min(psi_hist + 1, 2);
-    }
     int iters = 0;
     double res = 0, res0 = 0;
     ek_status st = poisson(b, psi, p.warm_start == EK_WS_LEARNED, iters, res, res0);
@@ -651,6 +650,9 @@ ek_status ek_poisson_solve(ek_ctx* ctx, const double* dev_rho, double* dev_psi,
                            int32_t warm_start, ek_poisson_report* rep) {
   if (!ctx) return EK_EINVAL;
   if (!dev_rho || !dev_psi) return ctx->fail(EK_EINVAL, "NULL device buffer");
+  if (warm_start < EK_WS_ZERO || warm_start > EK_WS_EXTRAP) return ctx->fail(EK_EINVAL, "unknown warm_start");
+  if (warm_start == EK_WS_LEARNED && !(ctx->net && ctx->net->have_params))
+    return ctx->fail(EK_ESTATE, "learned warm start without a model (ek_set_model)");
   const SiteGrid g = site_grid(ctx->p.nx, ctx->p.ny, ctx->p.nz, ctx->bx_sites);
   launch_rho_to_b(dev_rho, ctx->b, ctx->partials, ctx->inv_eps(), ctx->dims, g, ctx->stream);
   launch_mean_shift(ctx->partials, g.nblocks(), 1.0 / double(ctx->dims.n), ctx->inv_eps(), ctx->ps,
@@ -660,8 +662,6 @@ ek_status ek_poisson_solve(ek_ctx* ctx, const double* dev_rho, double* dev_psi,
   double res = 0, res0 = 0;
   const int saved = ctx->last_iters;
   ctx->last_iters = ctx->solo_iters;
-  if (warm_start == EK_WS_LEARNED && !(ctx->net && ctx->net->have_params))
-    return ctx->fail(EK_ESTATE, "learned warm start without a model (ek_set_model)");
   ek_status st = ctx->poisson(ctx->b, dev_psi, warm_start == EK_WS_LEARNED, iters, res, res0);
   ctx->solo_iters = iters;
   if (st == EK_OK) ctx->have_solve = true;

@@ -92,10 +92,13 @@ struct PoissonScalars {
 template <typename T>
 void launch_init_species(T* f, const uint32_t* mask, const double* n_dev, int species,
                          double nref, Dims d, hipStream_t s);
+// With psi_old (the extrapolated start) and extrap = 1 or 2 the pass also
+// copies psi to psi_old (1) or sets psi = 2 psi - psi_old, psi_old = old psi (2).
 template <typename T>
 void launch_charge(const T* f, const uint32_t* mask, const double* wall_q, double* b,
                    double* partials, const LBParams& lp, double inv_eps, Dims d,
-                   const SiteGrid& g, hipStream_t s, const BeadTableView& bt);
+                   const SiteGrid& g, hipStream_t s, const BeadTableView& bt,
+                   double* psi = nullptr, double* psi_old = nullptr, int extrap = 0);
 // Fused step over the sites without a `skip` bit.  Writes its block partials
 // (seven components: masses, momentum, sites updated) first in a layout of
 // `nblocks` blocks (lb_step_blocks(g, nz), plus the tail's blocks when a tail
@@ -134,8 +137,6 @@ void launch_residual_final(const double* partials, int nblocks, double tol, int 
                            int initial, PoissonScalars* ps, hipStream_t s);
 void launch_psi_shift(double* psi, const PoissonScalars* ps, double inv_n, Dims d,
                       hipStream_t s);
-// x = 2 x - old (linear) or x kept; old = the previous x.
-void launch_extrapolate(double* x, double* old, bool linear, long long n, hipStream_t s);
 void launch_fill(double* x, double v, long long n, hipStream_t s);
 void launch_ps_reset(PoissonScalars* ps, double shift, hipStream_t s);
 void launch_ps_rearm(PoissonScalars* ps, hipStream_t s);

@@ -39,14 +39,23 @@ __global__ __launch_bounds__(BLOCK) void k_init_species(T* __restrict__ f,
 
 // Charge pass: n^a at time t for every charged species, rho_e = sum z^a n^a
 // + fixed wall charge + bead charge; stores -rho_e / eps and partial sums of
-// rho_e (for the mean that the periodic problem removes).
+// rho_e (for the mean that the periodic problem removes).  With `start` set
+// it also prepares the extrapolated start of the solve at the site:
+// start.mode 1 keeps psi and copies it to old, 2 sets psi = 2 psi - old.
+struct StartExtrap {
+  double* psi;
+  double* old;
+  int mode;
+};
+
 template <typename T, typename I>
 __global__ __launch_bounds__(BLOCK) void k_charge(const T* __restrict__ f,
                                                   const uint32_t* __restrict__ mask,
                                                   const double* __restrict__ wall_q,
                                                   double* __restrict__ b,
                                                   double* __restrict__ partials, LBParams lp,
-                                                  double inv_eps, BeadTableView bt, Dims d) {
+                                                  double inv_eps, BeadTableView bt, Dims d,
+                                                  StartExtrap start) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
@@ -55,8 +64,14 @@ __global__ __launch_bounds__(BLOCK) void k_charge(const T* __restrict__ f,
   double acc[1] = {0.0};
   if (x < d.nx && y < d.ny) {
     const double rho = charge_site<T, I>(f, mask, wall_q, lp, bt, x, y, z, d);
-    b[((long long)z * d.ny + y) * d.nx + x] = -rho * inv_eps;
+    const long long r = ((long long)z * d.ny + y) * d.nx + x;
+    b[r] = -rho * inv_eps;
     acc[0] = rho;
+    if (start.mode) {
+      const double p = start.psi[r];
+      if (start.mode == 2) start.psi[r] = 2.0 * p - start.old[r];
+      start.old[r] = p;
+    }
   }
   block_partials<1>(acc, partials, bid, nblocks);
 }
@@ -227,13 +242,15 @@ void launch_init_species(T* f, const uint32_t* mask, const double* n_dev, int sp
 template <typename T>
 void launch_charge(const T* f, const uint32_t* mask, const double* wall_q, double* b,
                    double* partials, const LBParams& lp, double inv_eps, Dims d,
-                   const SiteGrid& g, hipStream_t s, const BeadTableView& bt) {
+                   const SiteGrid& g, hipStream_t s, const BeadTableView& bt, double* psi,
+                   double* psi_old, int extrap) {
+  const StartExtrap start{psi, psi_old, psi_old ? extrap : 0};
   if (fits_idx32<T>(d.n))
     hipLaunchKernelGGL((k_charge<T, uint32_t>), g.grid, g.block, 0, s, f, mask, wall_q, b,
-                       partials, lp, inv_eps, bt, d);
+                       partials, lp, inv_eps, bt, d, start);
   else
     hipLaunchKernelGGL((k_charge<T, long long>), g.grid, g.block, 0, s, f, mask, wall_q, b,
-                       partials, lp, inv_eps, bt, d);
+                       partials, lp, inv_eps, bt, d, start);
 }
 
 // z-planes per block of the fused step: each block sums its sites' masses
@@ -308,7 +325,7 @@ void launch_mean_shift(const double* partials, int nblocks, double inv_n, double
                                        hipStream_t);                                         \
   template void launch_charge<T>(const T*, const uint32_t*, const double*, double*, double*, \
                                  const LBParams&, double, Dims, const SiteGrid&, hipStream_t,\
-                                 const BeadTableView&);                                      \
+                                 const BeadTableView&, double*, double*, int);               \
   template int launch_lb_step<T>(const T*, T*, const uint32_t*, const double*,               \
                                  const LBParams&, const BeadTableView&, double*, int,        \
                                  uint32_t, Dims, const SiteGrid&, hipStream_t, hipEvent_t,   \

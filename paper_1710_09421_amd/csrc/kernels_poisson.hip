@@ -114,17 +114,6 @@ __global__ __launch_bounds__(BLOCK) void k_fill(double* __restrict__ x, double v
   if (r < n) x[r] = v;
 }
 
-// Start of the next solve: x = 2 x - old (linear = 1) or x unchanged
-// (linear = 0); old takes the previous x.
-__global__ __launch_bounds__(BLOCK) void k_extrapolate(double* __restrict__ x,
-                                                       double* __restrict__ old, int linear,
-                                                       long long n) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double p = x[i];
-  if (linear) x[i] = 2.0 * p - old[i];
-  old[i] = p;
-}
 
 __global__ __launch_bounds__(BLOCK) void k_rho_to_b(const double* __restrict__ rho,
                                                     double* __restrict__ b,
@@ -167,11 +156,6 @@ void launch_psi_shift(double* psi, const PoissonScalars* ps, double inv_n, Dims 
                       hipStream_t s) {
   const int blocks = int((d.n + BLOCK - 1) / BLOCK);
   hipLaunchKernelGGL(k_psi_shift, dim3(blocks), dim3(BLOCK), 0, s, psi, ps, inv_n, d.n);
-}
-
-void launch_extrapolate(double* x, double* old, bool linear, long long n, hipStream_t s) {
-  const int blocks = int((n + BLOCK - 1) / BLOCK);
-  hipLaunchKernelGGL(k_extrapolate, dim3(blocks), dim3(BLOCK), 0, s, x, old, linear ? 1 : 0, n);
 }
 
 void launch_fill(double* x, double v, long long n, hipStream_t s) {

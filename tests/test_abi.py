@@ -72,6 +72,20 @@ def test_learned_warm_start_needs_sizes_divisible_by_4(ek):
     assert nbytes.value - plain.value > 32 ** 3 * (3 * 32 + 8)
 
 
+def test_extrapolated_start_workspace(ek):
+    """EK_WS_EXTRAP keeps psi(t-2): one more float64 field; unknown starts are
+    rejected."""
+    lib = ek.lib()
+    plain, extrap = ctypes.c_size_t(), ctypes.c_size_t()
+    p0 = ek.make_params((32, 32, 32), warm_start=ek.EK_WS_PREV)
+    p1 = ek.make_params((32, 32, 32), warm_start=ek.EK_WS_EXTRAP)
+    assert lib.ek_workspace_bytes(ctypes.byref(p0), 0, ctypes.byref(plain)) == ek.EK_OK
+    assert lib.ek_workspace_bytes(ctypes.byref(p1), 0, ctypes.byref(extrap)) == ek.EK_OK
+    assert extrap.value - plain.value >= 32 ** 3 * 8
+    bad = ek.make_params((32, 32, 32), warm_start=4)
+    assert lib.ek_workspace_bytes(ctypes.byref(bad), 0, ctypes.byref(plain)) == ek.EK_EINVAL
+
+
 def test_unet_workspace_bytes(ek):
     lib = ek.lib()
     inf, tr = ctypes.c_size_t(), ctypes.c_size_t()

@@ -208,3 +208,14 @@ def test_invalid_arguments(ek):
     with pytest.raises(ek.EKError) as e:
         ctx.set_species_density(0, -np.ones((8, 8, 8)))
     assert e.value.status == ek.EK_EINVAL
+    with pytest.raises(ek.EKError) as e:
+        ctx._check(ctx._lib.ek_set_launch_mode(ctx._h, 4), ctx._h)      # unknown launch flag
+    assert e.value.status == ek.EK_EINVAL
+    rho = torch.zeros((8, 8, 8), dtype=torch.float64, device="cuda")
+    psi = torch.zeros_like(rho)
+    with pytest.raises(ek.EKError) as e:
+        ctx.poisson_solve(rho, psi, warm_start=7)                           # unknown start
+    assert e.value.status == ek.EK_EINVAL
+    with pytest.raises(ek.EKError) as e:
+        ctx.poisson_solve(rho, psi, warm_start=ek.EK_WS_LEARNED)           # no model
+    assert e.value.status in (ek.EK_ESTATE, ek.EK_EINVAL)

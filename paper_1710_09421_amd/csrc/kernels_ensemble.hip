@@ -369,7 +369,8 @@ __global__ __launch_bounds__(MAXT) void k_ensemble(RepDev* reps, EnsConst ec) {
       for (int it = tid; it < R.n_beads * WIN3; it += MAXT)
         bead_box_item(R.bs, it / WIN3, it % WIN3, fsrc, R.mask, R.psi, lp, d);
       __syncthreads();
-      md_chain<true, TPB>(R.bs, R.mp, R.keys, R.vals, R.mask, d, ENS_TABLE_BITS, ec.lds_bits, smem);
+      md_chain<true, TPB, false>(R.bs, R.mp, R.keys, R.vals, R.mask, d, ENS_TABLE_BITS, ec.lds_bits,
+                                 smem);
     }
     TEAM_SYNC();
 
@@ -506,6 +507,8 @@ int lds_bits_for(int max_beads) {
   return bits;
 }
 
+// LDS of the chain (positions and node table; the ensemble runs the chain
+// without pair lists)
 size_t md_lds_bytes(int max_beads) {
   const size_t sr = ((size_t)std::max(1, max_beads) * 24 + 15) & ~size_t(15);
   return sr + ((size_t)1 << lds_bits_for(max_beads)) * (9 * 8 + 4);

@@ -179,7 +179,7 @@ ek_status ek_ctx::beads_advance(bool overlap, hipEvent_t chain_end) {
   if (n_beads <= LDS_MAX_BEADS) {
     int bits = 6;
     while ((1 << bits) < 16 * n_beads) ++bits;          // load factor <= 1/2 for 8 corners/bead
-    const size_t lds = sr_bytes + ((size_t)1 << bits) * (9 * 8 + 4);
+    const size_t lds = sr_bytes + ((size_t)1 << bits) * (9 * 8 + 4) + md_list_bytes(true, threads, 8);
     if (lds > 64 * 1024 &&
         hipFuncSetAttribute((const void*)k_md<true, 8, 512>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds) != hipSuccess)
@@ -187,7 +187,7 @@ ek_status ek_ctx::beads_advance(bool overlap, hipEvent_t chain_end) {
     md(k_md<true, 8, 512>, lds, bits);
   } else {
     // positions and the per-lane pair lists
-    const size_t lds = sr_bytes + md_list_bytes(false, threads);
+    const size_t lds = sr_bytes + md_list_bytes(false, threads, tpb);
     if (tpb == 4) {
       md(k_md<false, 4, 512>, lds, 0);
     } else if (tpb == 2) {

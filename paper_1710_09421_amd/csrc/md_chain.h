@@ -139,8 +139,6 @@ struct LdsNodes {
   }
 };
 
-constexpr int LDS_MAX_BEADS = 64;
-
 // One workgroup per chain, TPB threads per bead: the lanes of a bead split
 // its 8 corners, its pair partners and its wall sites, and combine their
 // parts with a butterfly over the TPB lanes (every lane ends with the same
@@ -285,26 +283,34 @@ __device__ inline void bead_box_item(const BeadState& bs, int i, int t, const T*
   e[2] = -0.5 * (psi[site_of(cx, cy, cz + 1, d)] - psi[site_of(cx, cy, cz - 1, d)]) + lp.eext[2];
 }
 
-// Pair partners kept per lane for chains whose node table is in global
-// memory (long chains): lane l of bead i lists the beads j = l, l + TPB, ...
-// within the WCA cut-off plus NB_SKIN at the last build, in increasing j.
-// The list is rebuilt when any bead has moved more than NB_SKIN / 2 since
-// the build, so every pair inside the cut-off stays listed; a lane that would
-// list more than NB_PER_LANE partners switches the chain back to all pairs.
-// A lane sums the same nonzero pair terms in the same order either way.
+// Pair partners kept per lane: lane l of bead i lists the beads j = l,
+// l + TPB, ... within the WCA cut-off plus NB_SKIN at the last build, in
+// increasing j.  The list is rebuilt when any bead has moved more than
+// NB_SKIN / 2 since the build, so every pair inside the cut-off stays listed.
+// Chains with the node table in LDS (at most LDS_MAX_BEADS beads) have room
+// for every candidate; longer chains keep up to NB_PER_LANE partners per lane
+// and a lane that would list more switches the chain back to all pairs.  A
+// lane sums the same nonzero pair terms in the same order either way.
 constexpr int NB_PER_LANE = 32;
 constexpr double NB_SKIN = 0.6;
+constexpr int LDS_MAX_BEADS = 64;
+
+__host__ __device__ constexpr int md_list_len(bool lds_table, int tpb) {
+  return lds_table ? (LDS_MAX_BEADS + tpb - 1) / tpb : NB_PER_LANE;
+}
 
 // LDS bytes of md_chain beyond the positions and the LDS node table.
-__host__ __device__ inline size_t md_list_bytes(bool lds_table, int threads) {
-  return lds_table ? 0 : (size_t)threads * NB_PER_LANE * sizeof(unsigned short);
+__host__ __device__ inline size_t md_list_bytes(bool lds_table, int threads, int tpb) {
+  return (size_t)threads * md_list_len(lds_table, tpb) * sizeof(unsigned short);
 }
 
 // n_sub substeps of one chain by one workgroup (TPB lanes per bead; the
 // threads beyond n * TPB only take part in the barriers).  smem: LDS for the
-// bead positions and, when LDS is set, the node table of 2^lds_bits slots,
-// else the pair lists (md_list_bytes).
-template <bool LDS, int TPB>
+// bead positions, when LDS is set the node table of 2^lds_bits slots, and
+// with LISTS the pair lists (md_list_bytes; without them every lane walks all
+// its candidate partners each substep: the persistent ensemble kernel, whose
+// registers the lists would spill).
+template <bool LDS, int TPB, bool LISTS = true>
 __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gkeys,
                                 long long* gvals, uint32_t* mask, const Dims& d, int gbits,
                                 int lds_bits, unsigned char* smem) {
@@ -313,9 +319,11 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
   long long* lvals = (long long*)(smem + (((size_t)mp.n * 24 + 15) & ~size_t(15)));
   const int lslots = LDS ? (1 << lds_bits) : 0;
   int* lkeys = (int*)(lvals + (size_t)lslots * 9);
-  // pair lists (long chains): entry k of thread t at nbl[k * blockDim.x + t]
-  constexpr bool NLIST = !LDS;
-  unsigned short* nbl = (unsigned short*)lvals;
+  // pair lists: entry k of thread t at nbl[k * blockDim.x + t], after the
+  // LDS node table
+  constexpr bool NLIST = LISTS;
+  constexpr int NBL = md_list_len(LDS, TPB);
+  unsigned short* nbl = (unsigned short*)(lkeys + lslots);
   __shared__ int s_rebuild, s_overflow;
   if (NLIST && threadIdx.x == 0) {
     s_rebuild = 1;
@@ -389,11 +397,11 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
             r2 += dv * dv;
           }
           if (r2 < rl2) {
-            if (nb_count < NB_PER_LANE) nbl[nb_count * blockDim.x + threadIdx.x] = (unsigned short)j;
+            if (nb_count < NBL) nbl[nb_count * blockDim.x + threadIdx.x] = (unsigned short)j;
             ++nb_count;
           }
         }
-        if (nb_count > NB_PER_LANE) s_overflow = 1;
+        if (nb_count > NBL) s_overflow = 1;
 #pragma unroll
         for (int c = 0; c < 3; ++c) Rb[c] = R[c];
       }

@@ -90,6 +90,27 @@ def generate(n_traj, per_traj, every, seed, shape=SHAPE, first=1, tol=1e-10, log
     return dict(rhs=rhs, psi=psi, solid=solid, meta=meta, per_traj=per_traj, every=every)
 
 
+def generate_workload(wl, per_traj, first=20, every=1, tol=1e-10, log=print):
+    """Held-out pairs from one trajectory of a given workload (its own
+    geometry and size): after `first` steps, then every `every` steps."""
+    import torch
+    shape = wl.shape
+    rhs = torch.empty((per_traj,) + shape, dtype=torch.float64, device="cuda")
+    psi = torch.empty_like(rhs)
+    solid = torch.empty((per_traj,) + shape, dtype=torch.uint8, device="cuda")
+    ctx = ek.from_workload(wl, precision=ek.EK_FP32, poisson_method=ek.EK_POISSON_MG,
+                           poisson_tol=tol, poisson_max_iter=400)
+    sol = torch.from_numpy(wl.solid.astype(np.uint8)).to("cuda")
+    for k in range(per_traj):
+        ctx.step(first if k == 0 else every)
+        ctx.poisson_system(rhs[k], psi[k])
+        solid[k].copy_(sol)
+    ctx.close()
+    log(f"generated {per_traj} pairs of {wl.name}")
+    return dict(rhs=rhs, psi=psi, solid=solid, meta=[dict(workload=wl.name)], per_traj=per_traj,
+                every=every)
+
+
 def output_scale(data):
     """RMS of psi over RMS of rhs, averaged over the pairs: the network then
     predicts values of order one."""
@@ -269,6 +290,9 @@ def main(argv=None):
     e.add_argument("--per-traj", type=int, default=6)
     e.add_argument("--seed", type=int, default=777)
     e.add_argument("--simulate", type=int, default=0, help="single-pore steps per start")
+    e.add_argument("--workload", default="training", choices=["training", "large"],
+                   help="held-out fields: systems of the training distribution at 64x64x128, "
+                        "or one trajectory of the 256x256x512 pore (the model applied at that size)")
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)
     if a.cmd == "train":
@@ -286,7 +310,10 @@ def main(argv=None):
                 json.dump(dict(train=info, evaluation=summary), f, indent=1)
     else:
         params, sc, info = load_model(a.model)
-        held = generate(a.n_traj, a.per_traj, 1, a.seed, first=20, log=log)
+        if a.workload == "large":
+            held = generate_workload(workloads.large_system(), a.per_traj, log=log)
+        else:
+            held = generate(a.n_traj, a.per_traj, 1, a.seed, first=20, log=log)
         evaluate(params, sc, held, log=log)
         if a.simulate:
             simulate(params, sc, steps=a.simulate, log=log)

@@ -14,8 +14,9 @@
 // A level is halved only while every side stays even (red-black colouring
 // needs even periodic sides).  The coarsest levels whose iterates and
 // right-hand sides fit in COARSE_LDS_BYTES of LDS run inside one workgroup
-// (one launch for the whole coarse part of the cycle); the coarsest level
-// gets red-black SOR sweeps at the optimal relaxation factor of that grid,
+// (one launch for the whole coarse part of the cycle); a coarsest level of at
+// most COARSEST_DIRECT_MAX sites is solved directly, a larger one gets
+// red-black SOR sweeps at the optimal relaxation factor of that grid,
 // enough of them to reduce its error by COARSEST_REDUCTION (a cycle reduces
 // the residual by about 1e-2, so a coarsest solve to 1e-3 leaves the cycle's
 // rate unchanged; a box that cannot be coarsened is solved by these sweeps
@@ -37,6 +38,9 @@ namespace {
 constexpr size_t COARSE_LDS_BYTES = 40 * 1024;    // one-workgroup coarse cycle: levels of up to ~2k sites
 constexpr int COARSEST_SWEEPS = 40;
 constexpr double COARSEST_REDUCTION = 1e-3;
+// A coarsest level of at most this many sites is solved directly (one
+// matrix-vector product with a precomputed inverse, instead of SOR sweeps).
+constexpr int COARSEST_DIRECT_MAX = 64;
 // Levels of at most this many sites take the coarse-grid correction inside
 // their first post-smoothing sweep; that sweep reads the coarse iterate about
 // seven times per site, which pays while the level is launch-bound and costs
@@ -86,9 +90,19 @@ __global__ __launch_bounds__(256) void k_prolong(Lvl F, Lvl C, const PoissonScal
 
 // The coarse part of the cycle runs on copies of the coarse levels in LDS:
 // level `first` arrives with its right-hand side and a zero iterate in global
-// memory, its iterate goes back to global memory at the end.
+// memory, its iterate goes back to global memory at the end.  As on the
+// launched levels, the first colour-0 half sweep of a level coming from a
+// zero start is done where its right-hand side is written (copy-in,
+// restriction); the correction goes up by a prolongation pass (inside one
+// workgroup the fused corrected sweep, which recomputes the correction at
+// the six neighbours, measured slower).  The coarsest level is solved
+// directly when `pinv` is given (its n x n inverse of A + c 11^T / n, which
+// returns the mean-free solution of A x = f for a mean-free f), else by
+// coarsest_sweeps red-black SOR sweeps.
 __global__ __launch_bounds__(1024) void k_coarse_cycle(LvlSet set, int first, PoissonScalars* ps,
-                                                       double omega_coarsest, int coarsest_sweeps) {
+                                                       double omega_coarsest, int coarsest_sweeps,
+                                                       const double* __restrict__ pinv) {
+  static_assert(NU1 >= 1, "the fold needs a pre-smoothing sweep");
   if (ps->done) return;
   if (threadIdx.x == 0) ps->cycles += 1;   // read only by later kernels
   extern __shared__ __align__(16) double lds[];
@@ -104,16 +118,47 @@ __global__ __launch_bounds__(1024) void k_coarse_cycle(LvlSet set, int first, Po
     }
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < int(L[first].n); t += blockDim.x) {
-    L[first].f[t] = set.l[first].f[t];
-    L[first].x[t] = 0.0;
+  // copy-in; a level that is smoothed here gets its first colour-0 half sweep
+  const bool fold_first = first < last;
+  {
+    const Lvl& F = L[first];
+    const float inx = 1.0f / F.nx, iny = 1.0f / F.ny;
+    for (int t = threadIdx.x; t < int(F.n); t += blockDim.x) {
+      const double f = set.l[first].f[t];
+      F.f[t] = f;
+      int x, y;
+      const int yz = fdivmod(t, F.nx, inx, x);
+      const int z = fdivmod(yz, F.ny, iny, y);
+      double x0 = 0.0;
+      if (fold_first && ((x + y + z) & 1) == 0) {
+        const double gs = (0.0 - F.h2 * (f + 0.0)) * (1.0 / 6.0);
+        x0 = MG_OMEGA == 1.0 ? gs : 0.0 + MG_OMEGA * (gs - 0.0);
+      }
+      F.x[t] = x0;
+    }
   }
   __syncthreads();
   for (int l = first; l < last; ++l) {
-    block_smooth(L[l], NU1, 0.0, MG_OMEGA);
-    block_restrict(L[l], L[l + 1], 0.0);
+    // colour 0 of the first pre-smoothing sweep is already done
+    block_half(L[l], 1, 0.0, MG_OMEGA);
+    for (int s = 1; s < NU1; ++s) {
+      block_half(L[l], 0, 0.0, MG_OMEGA);
+      block_half(L[l], 1, 0.0, MG_OMEGA);
+    }
+    block_restrict(L[l], L[l + 1], 0.0, l + 1 < last ? MG_OMEGA : 0.0);
   }
-  block_smooth(L[last], coarsest_sweeps, 0.0, omega_coarsest);
+  if (pinv) {
+    const Lvl& C = L[last];
+    const int n = int(C.n);
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+      double v = 0.0;
+      for (int k = 0; k < n; ++k) v += pinv[t * n + k] * C.f[k];
+      C.x[t] = v;
+    }
+    __syncthreads();
+  } else {
+    block_smooth(L[last], coarsest_sweeps, 0.0, omega_coarsest);
+  }
   for (int l = last - 1; l >= first; --l) {
     block_prolong(L[l], L[l + 1]);
     block_smooth(L[l], NU2, 0.0, MG_OMEGA);
@@ -132,6 +177,7 @@ struct ek_ctx::MG {
   size_t coarse_lds = 0;     // LDS bytes of that kernel
   double omega_coarsest = 1.0;
   int coarsest_sweeps = COARSEST_SWEEPS;
+  const double* pinv = nullptr;   // inverse for the direct coarsest solve, or null
   // One V-cycle, and one V-cycle followed by the residual test, recorded as
   // graphs for the level-0 pair (b, x) they were recorded with: a replay
   // dispatches the cycle's ~30 dependent launches faster than the launches
@@ -172,7 +218,63 @@ size_t ek::mg_workspace_bytes(int nx, int ny, int nz) {
     nz /= 2;
     bytes += 2 * (((size_t)nx * ny * nz * 8 + 255) & ~size_t(255));
   }
+  // the coarsest level's inverse (direct solve)
+  bytes += (size_t)COARSEST_DIRECT_MAX * COARSEST_DIRECT_MAX * 8;
   return bytes;
+}
+
+// Inverse of M = A + c 11^T / n for the periodic 7-point operator A of level
+// C ((sum of the 6 neighbours - 6 x) / h^2, a neighbour counted twice where a
+// side is 2 long), c = -6 / h^2.  A is singular only along the constant
+// vector, which M lifts; for a mean-free f, M^-1 f is the mean-free solution
+// of A x = f.  Gauss-Jordan elimination with partial pivoting in double;
+// false if a pivot vanishes.
+static bool coarsest_inverse(const Lvl& C, std::vector<double>& inv) {
+  const int n = int(C.n);
+  std::vector<double> a((size_t)n * n, 0.0);
+  const double c = -6.0 / C.h2;
+  for (int z = 0; z < C.nz; ++z)
+    for (int y = 0; y < C.ny; ++y)
+      for (int x = 0; x < C.nx; ++x) {
+        const int r = (z * C.ny + y) * C.nx + x;
+        const int nb[6] = {(z * C.ny + y) * C.nx + (x + C.nx - 1) % C.nx,
+                           (z * C.ny + y) * C.nx + (x + 1) % C.nx,
+                           (z * C.ny + (y + C.ny - 1) % C.ny) * C.nx + x,
+                           (z * C.ny + (y + 1) % C.ny) * C.nx + x,
+                           (((z + C.nz - 1) % C.nz) * C.ny + y) * C.nx + x,
+                           (((z + 1) % C.nz) * C.ny + y) * C.nx + x};
+        for (int k = 0; k < 6; ++k) a[(size_t)r * n + nb[k]] += 1.0 / C.h2;
+        a[(size_t)r * n + r] -= 6.0 / C.h2;
+      }
+  for (size_t k = 0; k < a.size(); ++k) a[k] += c / n;
+  inv.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(a[(size_t)r * n + col]) > std::fabs(a[(size_t)piv * n + col])) piv = r;
+    if (!(std::fabs(a[(size_t)piv * n + col]) > 0.0)) return false;
+    if (piv != col)
+      for (int k = 0; k < n; ++k) {
+        std::swap(a[(size_t)piv * n + k], a[(size_t)col * n + k]);
+        std::swap(inv[(size_t)piv * n + k], inv[(size_t)col * n + k]);
+      }
+    const double d = 1.0 / a[(size_t)col * n + col];
+    for (int k = 0; k < n; ++k) {
+      a[(size_t)col * n + k] *= d;
+      inv[(size_t)col * n + k] *= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const double m = a[(size_t)r * n + col];
+      if (m == 0.0) continue;
+      for (int k = 0; k < n; ++k) {
+        a[(size_t)r * n + k] -= m * a[(size_t)col * n + k];
+        inv[(size_t)r * n + k] -= m * inv[(size_t)col * n + k];
+      }
+    }
+  }
+  return true;
 }
 
 void ek_ctx::mg_setup() {
@@ -213,6 +315,15 @@ void ek_ctx::mg_setup() {
     mg->first_coarse = fc;
   }
   const Lvl& c = mg->levels.back();
+  // the coarsest level's inverse, after the levels in the workspace
+  if (nl > 1 && c.n <= COARSEST_DIRECT_MAX) {
+    std::vector<double> inv;
+    if (coarsest_inverse(c, inv) &&
+        hipMemcpy(mem, inv.data(), inv.size() * 8, hipMemcpyHostToDevice) == hipSuccess)
+      mg->pinv = (double*)mem;
+    else
+      (void)hipGetLastError();
+  }
   mg->omega_coarsest = omega_opt(c.nx, c.ny, c.nz);
   const double rate = std::max(mg->omega_coarsest - 1.0, 1e-3);
   const double reduction = nl > 1 ? COARSEST_REDUCTION : 1e-10;
@@ -319,7 +430,7 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x) {
   set.count = nl;
   for (int l = 0; l < nl; ++l) set.l[l] = L[l];
   hipLaunchKernelGGL(k_coarse_cycle, dim3(1), dim3(1024), mg->coarse_lds, stream, set, fc, ps,
-                     mg->omega_coarsest, mg->coarsest_sweeps);
+                     mg->omega_coarsest, mg->coarsest_sweeps, mg->pinv);
   // coarse-grid correction: fused into the first post-smoothing sweep on
   // levels up to FUSED_CORRECTION_MAX_SITES, a pass of its own above
   for (int l = fc - 1; l >= 0; --l) {

@@ -149,14 +149,29 @@ __device__ inline void block_smooth(const Lvl& L, int sweeps, double shift, doub
     }
 }
 
-// Restriction and prolongation of a whole level by one workgroup.
-__device__ inline void block_restrict(const Lvl& F, const Lvl& C, double shift) {
+// One colour of a red-black sweep of a whole level by one workgroup.
+__device__ inline void block_half(const Lvl& L, int colour, double shift, double omega) {
+  const int hx = L.nx / 2, nh = hx * L.ny * L.nz;
+  const float ihx = 1.0f / hx, iny = 1.0f / L.ny;
+  for (int t = threadIdx.x; t < nh; t += blockDim.x) {
+    int tx, y;
+    const int yz = fdivmod(t, hx, ihx, tx);
+    const int z = fdivmod(yz, L.ny, iny, y);
+    smooth_site(L, colour, tx, y, z, shift, omega);
+  }
+  __syncthreads();
+}
+
+// Restriction and prolongation of a whole level by one workgroup
+// (omega_red as in restrict_site).
+__device__ inline void block_restrict(const Lvl& F, const Lvl& C, double shift,
+                                      double omega_red = 0.0) {
   const float inx = 1.0f / C.nx, iny = 1.0f / C.ny;
   for (int t = threadIdx.x; t < int(C.n); t += blockDim.x) {
     int X, Y;
     const int yz = fdivmod(t, C.nx, inx, X);
     const int Z = fdivmod(yz, C.ny, iny, Y);
-    restrict_site(F, C, X, Y, Z, shift);
+    restrict_site(F, C, X, Y, Z, shift, omega_red);
   }
   __syncthreads();
 }

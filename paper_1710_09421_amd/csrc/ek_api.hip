@@ -462,8 +462,12 @@ ek_status ek_create(const ek_params* p, int32_t max_beads, void* dev_ws, size_t 
     c->net = new UNet();
     c->net->stream = c->stream;
     c->net->carve(ws + L.net, p->nx, p->ny, p->nz, false);
-    c->net->init_state();
     c->guess = (double*)(ws + L.guess);
+    if (c->net->init_state() != hipSuccess) {
+      ek_destroy(c);
+      g_create_error = "initialising the network state failed";
+      return EK_EHIP;
+    }
   }
   if (p->warm_start == EK_WS_EXTRAP) c->psi_old = (double*)(ws + L.psi_old);
   *out = c;

@@ -191,8 +191,8 @@ struct ek_ctx::MG {
   bool graph_failed = false;   // recording is not possible: launch one by one
 
   void drop_graphs() {
-    if (cycle) hipGraphExecDestroy(cycle);
-    if (cycle_test) hipGraphExecDestroy(cycle_test);
+    if (cycle) (void)hipGraphExecDestroy(cycle);
+    if (cycle_test) (void)hipGraphExecDestroy(cycle_test);
     cycle = cycle_test = nullptr;
     graph_b = nullptr;
     graph_x = nullptr;
@@ -334,7 +334,7 @@ void ek_ctx::mg_setup() {
 void ek_ctx::mg_release() {
   if (mg) {
     mg->drop_graphs();
-    if (mg->record_stream) hipStreamDestroy(mg->record_stream);
+    if (mg->record_stream) (void)hipStreamDestroy(mg->record_stream);
   }
   delete mg;
   mg = nullptr;
@@ -355,7 +355,7 @@ static bool record_graph(hipStream_t stream, hipGraphExec_t* out, F enqueue) {
     return false;
   }
   const bool ok = hipGraphInstantiate(out, g, nullptr, nullptr, 0) == hipSuccess;
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (!ok) {
     (void)hipGetLastError();
     *out = nullptr;

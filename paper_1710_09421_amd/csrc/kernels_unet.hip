@@ -623,14 +623,15 @@ void UNet::carve(char* base, int nx, int ny, int nz, bool train) {
   for (int l = 0; l < 3; ++l) g[l] = Grid3{nx >> l, ny >> l, nz >> l, (nx >> l) * (ny >> l) * (nz >> l)};
 }
 
-void UNet::init_state() {
-  hipMemsetAsync(sc, 0, sizeof(UNetScalars), stream);
-  if (training) {
-    hipMemsetAsync(grad, 0, UNET_PARAMS * 4, stream);
-    hipMemsetAsync(adam_m, 0, UNET_PARAMS * 4, stream);
-    hipMemsetAsync(adam_v, 0, UNET_PARAMS * 4, stream);
-  }
+hipError_t UNet::init_state() {
   adam_t = 0;
+  hipError_t e = hipMemsetAsync(sc, 0, sizeof(UNetScalars), stream);
+  if (e == hipSuccess && training) {
+    e = hipMemsetAsync(grad, 0, UNET_PARAMS * 4, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(adam_m, 0, UNET_PARAMS * 4, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(adam_v, 0, UNET_PARAMS * 4, stream);
+  }
+  return e;
 }
 
 void UNet::pack() {

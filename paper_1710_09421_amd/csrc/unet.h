@@ -82,7 +82,7 @@ struct UNet {
   static bool shape_ok(int nx, int ny, int nz);
   static size_t bytes(int nx, int ny, int nz, bool training);
   void carve(char* base, int nx, int ny, int nz, bool training);
-  void init_state();                                   // zero moments, gradient, loss
+  hipError_t init_state();                             // zero moments, gradient, loss
   void pack();                                         // params -> packed bf16 + bias
   // guess = s * out_scale * N(b, solid); solid is a byte mask (nonzero = solid)
   // or, with link = true, link words whose top bit marks solid sites.

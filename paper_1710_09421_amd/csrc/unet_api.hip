@@ -74,8 +74,8 @@ ek_status ek_unet_create(int32_t nx, int32_t ny, int32_t nz, int32_t training, v
     g_unet_error = "hipHostMalloc failed";
     return EK_EHIP;
   }
-  u->net.init_state();
-  if (u->sync()) {
+  if (u->net.init_state() != hipSuccess) u->err = "initialising the network state failed";
+  if (!u->err.empty() || u->sync()) {
     g_unet_error = u->err;
     (void)hipHostFree(u->pinned);
     if (own) (void)hipFree(ws);
@@ -103,7 +103,7 @@ ek_status ek_unet_set_params(ek_unet* u, const float* params, int32_t n, float o
   UN_HIP(hipMemcpyAsync(u->net.params, params, size_t(n) * 4, hipMemcpyHostToDevice, u->net.stream));
   u->net.out_scale = out_scale;
   u->net.pack();
-  u->net.init_state();
+  UN_HIP(u->net.init_state());
   u->net.have_params = true;
   return u->sync();
 }

@@ -168,7 +168,8 @@ __device__ inline bool team_sums(double (&v)[NV], double* sh, TeamSync* ts, int 
 }
 
 // One colour of a red-black sweep of level L over the team's share of sites.
-__device__ inline void team_half(const Lvl& L, int colour, double shift, double omega, int first,
+// (Level descriptions by value: see block_smooth.)
+__device__ inline void team_half(const Lvl L, int colour, double shift, double omega, int first,
                                  int stride) {
   const int hx = L.nx / 2, nh = hx * L.ny * L.nz;
   const float ihx = 1.0f / hx, iny = 1.0f / L.ny;
@@ -180,7 +181,7 @@ __device__ inline void team_half(const Lvl& L, int colour, double shift, double 
   }
 }
 
-__device__ inline void team_restrict(const Lvl& F, const Lvl& C, double shift, int first, int stride) {
+__device__ inline void team_restrict(const Lvl F, const Lvl C, double shift, int first, int stride) {
   const float inx = 1.0f / C.nx, iny = 1.0f / C.ny;
   for (int t = first; t < int(C.n); t += stride) {
     int X, Y;
@@ -190,7 +191,7 @@ __device__ inline void team_restrict(const Lvl& F, const Lvl& C, double shift, i
   }
 }
 
-__device__ inline void team_prolong(const Lvl& F, const Lvl& C, int first, int stride) {
+__device__ inline void team_prolong(const Lvl F, const Lvl C, int first, int stride) {
   const float inx = 1.0f / F.nx, iny = 1.0f / F.ny;
   for (int t = first; t < int(F.n); t += stride) {
     int x, y;

@@ -6,7 +6,8 @@
 // the previous in every direction while all sides stay even:
 //   level l, spacing h = 2^l:  (sum of 6 neighbours - 6 x) / h^2 = f_l
 //   smoother   red-black Gauss-Seidel (x = (sum nb - h^2 f) / 6) over-relaxed
-//              by MG_OMEGA, nu1 = NU1 = 1 and nu2 = NU2 = 2
+//              by MG_OMEGA, nu1 = NU1 = 1 and nu2 = NU2 = 2 (NU2_COARSE = 1
+//              on the levels of the one-workgroup coarse kernel)
 //   restriction  f_{l+1} = average of the 8 fine residuals (fused with the
 //                residual, also zeroes the coarse iterate)
 //   prolongation trilinear cell-centred interpolation (weights 3/4, 1/4 per
@@ -48,6 +49,13 @@ constexpr int COARSEST_DIRECT_MAX = 64;
 // beat 2^21 and 2^23 on 64x64x128 and 256x256x512 boxes; fusing the
 // 2^25-site level of the latter made its Poisson solve 13 % slower).
 constexpr long long FUSED_CORRECTION_MAX_SITES = 1ll << 18;
+// Post-smoothing sweeps on the levels inside the one-workgroup coarse kernel,
+// whose barrier phases on a 1k-site level are bound by LDS bandwidth: one
+// sweep there left the cycle counts of the pore systems from the
+// extrapolated start unchanged (64x64x128 and 256x256x512) and took 2 % off
+// the single pore's step; from the previous solution it needed about 3 %
+// more cycles, which cancels the gain.
+constexpr int NU2_COARSE = 1;
 
 // --- grid-wide kernels for the fine levels (3-D launch: x, y from the block,
 // z = blockIdx.z, so no index division) ------------------------------------
@@ -80,12 +88,13 @@ __global__ __launch_bounds__(256) void k_corrected_smooth(Lvl L, Lvl C, int colo
   corrected_smooth_site(L, C, colour, tx, y, blockIdx.z, level0 ? ps->shift : 0.0, omega);
 }
 
+// One thread per coarse cell (launched over the coarse level).
 __global__ __launch_bounds__(256) void k_prolong(Lvl F, Lvl C, const PoissonScalars* ps) {
   if (ps->done) return;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  if (x >= F.nx || y >= F.ny) return;
-  prolong_site(F, C, x, y, blockIdx.z);
+  const int X = blockIdx.x * blockDim.x + threadIdx.x;
+  const int Y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (X >= C.nx || Y >= C.ny) return;
+  prolong_cell(F, C, X, Y, blockIdx.z);
 }
 
 // The coarse part of the cycle runs on copies of the coarse levels in LDS:
@@ -107,6 +116,7 @@ __global__ __launch_bounds__(1024) void k_coarse_cycle(LvlSet set, int first, Po
   if (threadIdx.x == 0) ps->cycles += 1;   // read only by later kernels
   extern __shared__ __align__(16) double lds[];
   __shared__ Lvl L[MAX_LEVELS];
+  __shared__ double* s_pinv;   // the coarsest level's inverse, after the levels
   const int last = set.count - 1;
   if (threadIdx.x == 0) {
     double* p = lds;
@@ -116,15 +126,23 @@ __global__ __launch_bounds__(1024) void k_coarse_cycle(LvlSet set, int first, Po
       L[l].f = p + L[l].n;
       p += 2 * L[l].n;
     }
+    s_pinv = p;
   }
   __syncthreads();
-  // copy-in; a level that is smoothed here gets its first colour-0 half sweep
+  // copy-in, with the inverse (its global reads overlap those of the
+  // right-hand side instead of stalling the direct solve); a level that is
+  // smoothed here gets its first colour-0 half sweep
   const bool fold_first = first < last;
+  const int n_inv = pinv ? int(set.l[last].n * set.l[last].n) : 0;
   {
-    const Lvl& F = L[first];
+    const Lvl F = L[first];
     const float inx = 1.0f / F.nx, iny = 1.0f / F.ny;
-    for (int t = threadIdx.x; t < int(F.n); t += blockDim.x) {
-      const double f = set.l[first].f[t];
+    const int nf = int(F.n), nt = nf > n_inv ? nf : n_inv;
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+      const double f = t < nf ? set.l[first].f[t] : 0.0;
+      const double pv = t < n_inv ? pinv[t] : 0.0;
+      if (t < n_inv) s_pinv[t] = pv;
+      if (t >= nf) continue;
       F.f[t] = f;
       int x, y;
       const int yz = fdivmod(t, F.nx, inx, x);
@@ -148,11 +166,11 @@ __global__ __launch_bounds__(1024) void k_coarse_cycle(LvlSet set, int first, Po
     block_restrict(L[l], L[l + 1], 0.0, l + 1 < last ? MG_OMEGA : 0.0);
   }
   if (pinv) {
-    const Lvl& C = L[last];
+    const Lvl C = L[last];
     const int n = int(C.n);
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
       double v = 0.0;
-      for (int k = 0; k < n; ++k) v += pinv[t * n + k] * C.f[k];
+      for (int k = 0; k < n; ++k) v += s_pinv[t * n + k] * C.f[k];
       C.x[t] = v;
     }
     __syncthreads();
@@ -161,7 +179,7 @@ __global__ __launch_bounds__(1024) void k_coarse_cycle(LvlSet set, int first, Po
   }
   for (int l = last - 1; l >= first; --l) {
     block_prolong(L[l], L[l + 1]);
-    block_smooth(L[l], NU2, 0.0, MG_OMEGA);
+    block_smooth(L[l], NU2_COARSE, 0.0, MG_OMEGA);
   }
   for (int t = threadIdx.x; t < int(L[first].n); t += blockDim.x) set.l[first].x[t] = L[first].x[t];
 }
@@ -296,12 +314,16 @@ void ek_ctx::mg_setup() {
     mg->levels.push_back(l);
   }
   const int nl = (int)mg->levels.size();
+  const Lvl& c = mg->levels.back();
+  // LDS of the direct coarsest solve's inverse (reserved when it is planned)
+  const size_t inv_bytes = nl > 1 && c.n <= COARSEST_DIRECT_MAX ? (size_t)(c.n * c.n) * 8 : 0;
   int fc = nl - 1;
   size_t bytes = 16 * (size_t)mg->levels[fc].n;
   while (fc > 1 && bytes + 16 * (size_t)mg->levels[fc - 1].n <= COARSE_LDS_BYTES) {
     --fc;
     bytes += 16 * (size_t)mg->levels[fc].n;
   }
+  bytes += inv_bytes;
   mg->first_coarse = fc;
   mg->coarse_lds = bytes;
   if (nl > 1 && bytes > 64 * 1024 &&
@@ -314,7 +336,6 @@ void ek_ctx::mg_setup() {
     }
     mg->first_coarse = fc;
   }
-  const Lvl& c = mg->levels.back();
   // the coarsest level's inverse, after the levels in the workspace
   if (nl > 1 && c.n <= COARSEST_DIRECT_MAX) {
     std::vector<double> inv;
@@ -436,8 +457,8 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x) {
   for (int l = fc - 1; l >= 0; --l) {
     const bool fused = NU2 > 0 && L[l].n <= FUSED_CORRECTION_MAX_SITES;
     if (!fused)
-      hipLaunchKernelGGL(k_prolong, level_launch(L[l]).grid, level_launch(L[l]).block, 0, stream,
-                         L[l], L[l + 1], ps);
+      hipLaunchKernelGGL(k_prolong, level_launch(L[l + 1]).grid, level_launch(L[l + 1]).block, 0,
+                         stream, L[l], L[l + 1], ps);
     for (int s = 0; s < NU2; ++s)
       for (int c = 0; c < 2; ++c) {
         if (fused && s == 0)

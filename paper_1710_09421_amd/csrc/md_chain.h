@@ -96,6 +96,18 @@ __device__ inline double wca_coef(double r2, double eps, double sigma) {
   return 24.0 * eps * (2.0 * s6 * s6 - s6) / r2;
 }
 
+// Nearest integer (ties to even, as llrint) of x.  For |x| < 2^51 the sum
+// x + 1.5 * 2^52 has a unit in the last place of 1, so its low mantissa bits
+// hold the rounded value as an offset from the bits of 1.5 * 2^52; larger
+// values take llrint.
+__device__ inline long long round_fixed(double x) {
+  if (__builtin_expect(fabs(x) < 2251799813685248.0, 1)) {       // 2^51
+    const double t = x + 6755399441055744.0;                        // 1.5 * 2^52
+    return __double_as_longlong(t) - 0x4338000000000000ll;
+  }
+  return llrint(x);
+}
+
 // Node accumulators for the friction impulse: the context's global table, or
 // (for chains of at most LDS_MAX_BEADS beads) a table in LDS that is flushed to
 // the global one once after the substeps.  Values are int64 fixed point, so
@@ -143,9 +155,10 @@ struct LdsNodes {
 // its 8 corners, its pair partners and its wall sites, and combine their
 // parts with a butterfly over the TPB lanes (every lane ends with the same
 // bits, so all lanes advance the bead identically).  The exchanges are DPP
-// lane moves within a row of 16 lanes: xor 1 and xor 2 as quad permutations,
-// xor 4 as a shift by four lanes to the left (lanes 0-3 of each group of 8)
-// or to the right (lanes 4-7).  A bead's lanes are active together.
+// lane moves within a row of 16 lanes: xor 1 and xor 2 as quad permutations;
+// after those every lane of a quad holds the quad's sum, so the last level
+// takes the other quad's sum from the mirrored lane of the group of 8
+// (lane l reads lane 7 - l).  A bead's lanes are active together.
 template <int CTRL>
 __device__ inline double dpp_move(double v) {
   const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
@@ -158,14 +171,10 @@ __device__ inline double group_sum(double v) {
   static_assert(TPB == 1 || TPB == 2 || TPB == 4 || TPB == 8, "lanes per bead");
   constexpr int XOR1 = 0xB1;          // quad_perm [1, 0, 3, 2]
   constexpr int XOR2 = 0x4E;          // quad_perm [2, 3, 0, 1]
-  constexpr int SHL4 = 0x104;         // row_shl:4 (lane l reads lane l + 4)
-  constexpr int SHR4 = 0x114;         // row_shr:4 (lane l reads lane l - 4)
+  constexpr int HALF_MIRROR = 0x141;  // row_half_mirror (lane l reads lane 7 - l of its 8)
   if constexpr (TPB >= 2) v += dpp_move<XOR1>(v);
   if constexpr (TPB >= 4) v += dpp_move<XOR2>(v);
-  if constexpr (TPB >= 8) {
-    const double up = dpp_move<SHL4>(v), down = dpp_move<SHR4>(v);
-    v += (threadIdx.x & 4) ? down : up;
-  }
+  if constexpr (TPB >= 8) v += dpp_move<HALF_MIRROR>(v);
   return v;
 }
 
@@ -453,7 +462,10 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
           if constexpr (CACHE) {
             const double* mo = mom + (size_t)bidx[a] * MOM;
 #pragma unroll
-            for (int c = 0; c < MOM; ++c) mo_c[CACHE ? a : 0][c] = wfl[a] != 0.0 ? mo[c] : 0.0;
+            for (int c = 0; c < MOM; ++c) {   // read unconditionally: not behind the flag's read
+              const double m = mo[c];
+              mo_c[CACHE ? a : 0][c] = wfl[a] != 0.0 ? m : 0.0;
+            }
           }
         }
         if constexpr (CACHE_E) {
@@ -468,6 +480,18 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
             if (fl[ix + WIN * (iy + WIN * iz)] & 2) wall_bits |= 1ull << k;
           }
         }
+      }
+      // impulse of earlier substeps on this lane's corners, read before the
+      // weights so that the reads overlap their arithmetic (one corner per
+      // lane: with more the registers are not spared)
+      constexpr bool PRE_K = CPL == 1;
+      double kpre[PRE_K ? CPL : 1][9];
+      if constexpr (PRE_K) {
+#pragma unroll
+        for (int a = 0; a < CPL; ++a)
+#pragma unroll
+          for (int k = 0; k < 9; ++k)
+            kpre[a][k] = slot[a] < 0 ? 0.0 : (LDS ? ln.get(slot[a], k) : gn.get(slot[a], k));
       }
       // plain and fluid-renormalised trilinear weights
       double wsum = 0.0;
@@ -504,8 +528,10 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
             acc[9 + s] += wt[a] * mo[s];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-              const double kacc = slot[a] < 0 ? 0.0 : (LDS ? ln.get(slot[a], 3 * s + c)
-                                                            : gn.get(slot[a], 3 * s + c));
+              const double kacc =
+                  PRE_K ? kpre[PRE_K ? a : 0][3 * s + c]
+                        : (slot[a] < 0 ? 0.0 : (LDS ? ln.get(slot[a], 3 * s + c)
+                                                    : gn.get(slot[a], 3 * s + c)));
               acc[3 * s + c] += wt[a] * (mo[6 + 3 * s + c] + kacc) * mo[3 + s];
             }
           }
@@ -513,11 +539,28 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
       }
       // this lane's share of the conservative forces
       double F[3] = {0.0, 0.0, 0.0};
-      auto wca_pair = [&](int j) {
+      // FENE bonds: the bond to i - 1 on lane 0 and the one to i + 1 on lane
+      // 1 (both on lane 0 with one lane per bead); the bonded neighbour's
+      // position is read up front with the partners' ones where the registers
+      // allow (short chains with the lists)
+      constexpr int NBOND = TPB >= 2 ? 1 : 2;        // bonds per bond lane
+      const int bond0 = TPB >= 2 ? lane : 0;         // 0: bond to i - 1, 1: to i + 1
+      const bool bond_lane = TPB >= 2 ? lane < 2 : true;
+      constexpr bool PRE_B = LDS && LISTS;
+      double PB[PRE_B ? NBOND : 1][3];
+      if constexpr (PRE_B) {
+#pragma unroll
+        for (int k = 0; k < NBOND; ++k) {
+          const int j = min(max(i + 2 * (bond0 + k) - 1, 0), mp.n - 1);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) PB[PRE_B ? k : 0][c] = sR[3 * j + c];
+        }
+      }
+      auto wca_at = [&](const double* P) {   // WCA with a partner at P
         double dv[3], r2 = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const double v = R[c] - sR[3 * j + c];
+          const double v = R[c] - P[c];
           dv[c] = v - L[c] * rint(v * iL[c]);
           r2 += dv[c] * dv[c];
         }
@@ -530,10 +573,31 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
         }
       };
       if (NLIST && !s_overflow) {                    // WCA with the listed partners
-        for (int k = 0; k < nb_count; ++k) wca_pair(nbl[k * blockDim.x + threadIdx.x]);
+        // four partners at a time: their indices, then their positions, are
+        // read together (one LDS round trip each), the terms are added in
+        // list order
+        constexpr int CH = 4;
+        static_assert(md_list_len(true, TPB) % CH == 0 && NB_PER_LANE % CH == 0, "list chunks");
+        for (int k0 = 0; k0 < nb_count; k0 += CH) {
+          int jj[CH];
+#pragma unroll
+          for (int u = 0; u < CH; ++u)
+            jj[u] = k0 + u < nb_count ? int(nbl[(k0 + u) * blockDim.x + threadIdx.x]) : i;
+          double P[CH][3];
+#pragma unroll
+          for (int u = 0; u < CH; ++u)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) P[u][c] = sR[3 * jj[u] + c];
+#pragma unroll
+          for (int u = 0; u < CH; ++u)
+            if (k0 + u < nb_count) wca_at(P[u]);
+        }
       } else {
         for (int j = lane; j < mp.n; j += TPB)       // WCA between all pairs
-          if (j != i) wca_pair(j);
+          if (j != i) {
+            const double P[3] = {sR[3 * j], sR[3 * j + 1], sR[3 * j + 2]};
+            wca_at(P);
+          }
       }
       for (int k = 0; k < NWS; ++k) {             // WCA against wall-site centres
         const int wsite = lane + k * TPB;
@@ -556,15 +620,15 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
           for (int c = 0; c < 3; ++c) F[c] += coef * dv[c];
         }
       }
-      if (lane == 0) {
+      if (bond_lane) {
 #pragma unroll
-        for (int nb = -1; nb <= 1; nb += 2) {        // FENE bonds
-          const int j = i + nb;
+        for (int k = 0; k < NBOND; ++k) {            // FENE bonds
+          const int j = i + 2 * (bond0 + k) - 1;
           if (j < 0 || j >= mp.n) continue;
           double dv[3], r2 = 0.0;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const double v = sR[3 * j + c] - R[c];
+            const double v = (PRE_B ? PB[PRE_B ? k : 0][c] : sR[3 * j + c]) - R[c];
             dv[c] = v - L[c] * rint(v * iL[c]);
             r2 += dv[c] * dv[c];
           }
@@ -607,7 +671,7 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
         for (int s = 0; s < 3; ++s)
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const long long v = llrint(-h * phi[s][c] * wt[a] * FIX_FORCE);
+            const long long v = round_fixed(-h * phi[s][c] * wt[a] * FIX_FORCE);
             if (LDS) ln.add(slot[a], 3 * s + c, v);
             else gn.add(slot[a], 3 * s + c, v);
           }

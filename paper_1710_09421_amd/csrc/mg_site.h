@@ -74,14 +74,16 @@ __device__ inline void smooth_site(const Lvl& L, int colour, int tx, int y, int 
 
 // omega_red != 0: the coarse level's first colour-0 half sweep is done here
 // as well (from the zero start it only needs the site's own right-hand side).
+// h^2 is a power of two, so multiplying by its reciprocal equals dividing by it.
 __device__ inline void restrict_site(const Lvl& F, const Lvl& C, int X, int Y, int Z, double shift,
                                      double omega_red = 0.0) {
+  const double ih2 = 1.0 / F.h2;
   double s = 0.0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int x = 2 * X + (k & 1), y = 2 * Y + ((k >> 1) & 1), z = 2 * Z + ((k >> 2) & 1);
     const int r = idx3(x, y, z, F);
-    s += (F.f[r] + shift) - (nbsum(F.x, x, y, z, F) - 6.0 * F.x[r]) / F.h2;
+    s += (F.f[r] + shift) - (nbsum(F.x, x, y, z, F) - 6.0 * F.x[r]) * ih2;
   }
   const int t = idx3(X, Y, Z, C);
   const double f = 0.125 * s;
@@ -111,6 +113,41 @@ __device__ inline void prolong_site(const Lvl& F, const Lvl& C, int x, int y, in
   F.x[idx3(x, y, z, F)] += prolong_value(C, x, y, z);
 }
 
+// The corrections of the 8 fine children of coarse cell (X, Y, Z), each the
+// sum of prolong_value term by term, from the cell's 3x3x3 coarse
+// neighbourhood read once; the two children in a fine row are adjacent.
+__device__ inline void prolong_cell(const Lvl& F, const Lvl& C, int X, int Y, int Z) {
+  const int xs[3] = {X == 0 ? C.nx - 1 : X - 1, X, X + 1 == C.nx ? 0 : X + 1};
+  const int ys[3] = {Y == 0 ? C.ny - 1 : Y - 1, Y, Y + 1 == C.ny ? 0 : Y + 1};
+  const int zs[3] = {Z == 0 ? C.nz - 1 : Z - 1, Z, Z + 1 == C.nz ? 0 : Z + 1};
+  double c[3][3][3];   // [z][y][x], centre at [1][1][1]
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) c[k][j][i] = C.x[idx3(xs[i], ys[j], zs[k], C)];
+  const double a = 0.75, b = 0.25;
+#pragma unroll
+  for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+    for (int oy = 0; oy < 2; ++oy) {
+      const int zn = oz ? 2 : 0, yn = oy ? 2 : 0;
+      double* px = F.x + idx3(2 * X, 2 * Y + oy, 2 * Z + oz, F);
+      const double v0 = px[0], v1 = px[1];
+      double e[2];
+#pragma unroll
+      for (int ox = 0; ox < 2; ++ox) {
+        const int xn = ox ? 2 : 0;
+        e[ox] = a * a * a * c[1][1][1] + b * a * a * c[1][1][xn] + a * b * a * c[1][yn][1] +
+                a * a * b * c[zn][1][1] + b * b * a * c[1][yn][xn] + b * a * b * c[zn][1][xn] +
+                a * b * b * c[zn][yn][1] + b * b * b * c[zn][yn][xn];
+      }
+      px[0] = v0 + e[0];
+      px[1] = v1 + e[1];
+    }
+}
+
 // First post-smoothing sweep with the coarse-grid correction applied on the
 // fly (no separate prolongation pass).  Colour 0: the site and its six
 // neighbours (colour 1, not yet corrected) are read corrected; colour 1
@@ -134,7 +171,10 @@ __device__ inline void corrected_smooth_site(const Lvl& L, const Lvl& C, int col
 }
 
 // --- the coarse part of a V-cycle in one workgroup ----------------------------
-__device__ inline void block_smooth(const Lvl& L, int sweeps, double shift, double omega = 1.0) {
+// The level descriptions are taken by value: in registers the compiler need
+// not read them again after every store to the level's arrays (a descriptor
+// kept in LDS may alias them).
+__device__ inline void block_smooth(const Lvl L, int sweeps, double shift, double omega = 1.0) {
   const int hx = L.nx / 2, nh = hx * L.ny * L.nz;
   const float ihx = 1.0f / hx, iny = 1.0f / L.ny;
   for (int s = 0; s < sweeps; ++s)
@@ -150,7 +190,7 @@ __device__ inline void block_smooth(const Lvl& L, int sweeps, double shift, doub
 }
 
 // One colour of a red-black sweep of a whole level by one workgroup.
-__device__ inline void block_half(const Lvl& L, int colour, double shift, double omega) {
+__device__ inline void block_half(const Lvl L, int colour, double shift, double omega) {
   const int hx = L.nx / 2, nh = hx * L.ny * L.nz;
   const float ihx = 1.0f / hx, iny = 1.0f / L.ny;
   for (int t = threadIdx.x; t < nh; t += blockDim.x) {
@@ -164,7 +204,7 @@ __device__ inline void block_half(const Lvl& L, int colour, double shift, double
 
 // Restriction and prolongation of a whole level by one workgroup
 // (omega_red as in restrict_site).
-__device__ inline void block_restrict(const Lvl& F, const Lvl& C, double shift,
+__device__ inline void block_restrict(const Lvl F, const Lvl C, double shift,
                                       double omega_red = 0.0) {
   const float inx = 1.0f / C.nx, iny = 1.0f / C.ny;
   for (int t = threadIdx.x; t < int(C.n); t += blockDim.x) {
@@ -176,7 +216,7 @@ __device__ inline void block_restrict(const Lvl& F, const Lvl& C, double shift,
   __syncthreads();
 }
 
-__device__ inline void block_prolong(const Lvl& F, const Lvl& C) {
+__device__ inline void block_prolong(const Lvl F, const Lvl C) {
   const float inx = 1.0f / F.nx, iny = 1.0f / F.ny;
   for (int t = threadIdx.x; t < int(F.n); t += blockDim.x) {
     int x, y;

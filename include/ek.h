@@ -171,6 +171,34 @@ ek_status ek_get_potential(struct ek_ctx* ctx, double* psi);
 /* Bead positions and velocities (host, 3 doubles per bead). */
 ek_status ek_get_beads(struct ek_ctx* ctx, double* pos, double* vel);
 
+/* Pore observables (Sec. IV.B, ionic current and conductance; Sec. IV.C,
+ * the time at which each bead passes the pore's mid-plane).
+ *
+ * ek_plane_flux: particles of each species that the streaming which formed
+ * the current densities (those of ek_get_moments) carried across the link
+ * plane between z and z + 1 (periodic: z = nz - 1 pairs with 0): populations
+ * moving +z count +1, those moving -z count -1, bounced-back links (fluid to
+ * solid) carry nothing.  out[0..2]: species 0, 1, 2; out[3]: the charge,
+ * sum of valence[a] * out[a], i.e. the ionic current through the plane in
+ * charge per time step.  Host output of 4 doubles; EK_EINVAL for z outside
+ * [0, nz) or a NULL output; EK_ESTATE before the species are set.  The sums
+ * are float64 in a fixed order (deterministic). */
+ek_status ek_plane_flux(struct ek_ctx* ctx, int32_t z, double* out);
+
+/* Bead crossing record of the plane z = z_plane (lattice units; its periodic
+ * images z_plane + k nz count too).  Setting the plane enables the record and
+ * clears it; ek_set_polymer clears it as well.  A bead crosses the plane in a
+ * step when floor((Z - z_plane) / nz) differs between its z coordinate Z at
+ * the start and at the end of the step (both float64).  EK_EINVAL for a
+ * non-finite z_plane. */
+ek_status ek_set_crossing_plane(struct ek_ctx* ctx, double z_plane);
+
+/* Per bead (host arrays of n_beads int32, any may be NULL): the first and
+ * the last step that crossed the plane, counted as the number of steps the
+ * context had completed when that step ended (-1: none yet), and the net
+ * number of crossings (+1 in +z, -1 in -z).  EK_ESTATE if no plane is set. */
+ek_status ek_get_crossings(struct ek_ctx* ctx, int32_t* first, int32_t* last, int32_t* net);
+
 ek_status ek_get_stats(struct ek_ctx* ctx, ek_stats* out);
 
 /* Standalone Poisson solve on device buffers: dev_rho[nz*ny*nx] charge

@@ -70,6 +70,9 @@ struct ek_ctx {
   ek_polymer_params poly{};
   std::vector<double> host_q;
   bool table_dirty = false;
+  // bead crossing record of the plane z = cross_plane (when cross_on)
+  bool cross_on = false;
+  double cross_plane = 0.0;
 
   // per-phase timers (HIP events on the context stream)
   bool timing = false;

@@ -46,6 +46,7 @@ BeadState carve(char* mem, int maxb) {
   s.efield = (double*)take((size_t)maxb * BOX3 * 3 * 8 + 8);
   s.flags = (unsigned char*)take((size_t)maxb * WIN3 + 8);
   s.err = (int*)take(64);
+  s.cross = (int*)take((size_t)maxb * 3 * 4 + 4);
   return s;
 }
 
@@ -91,6 +92,15 @@ __global__ void k_err_reset(int* err) {
   if (threadIdx.x == 0) *err = 0;
 }
 
+// Empty crossing record: no first / last step (-1), net count 0.
+__global__ __launch_bounds__(256) void k_cross_reset(int* cross, int maxb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= maxb) return;
+  cross[3 * i] = -1;
+  cross[3 * i + 1] = -1;
+  cross[3 * i + 2] = 0;
+}
+
 void launch_table_clear(int* keys, long long* vals, uint32_t* mask, long long n, hipStream_t s) {
   hipLaunchKernelGGL(k_table_clear, dim3(HASH_SLOTS / 256), dim3(256), 0, s, keys, vals, mask, n,
                      HASH_BITS);
@@ -105,6 +115,7 @@ size_t ek::bead_state_bytes(int maxb) {
   t += align256(maxb * 3 * 8 + 8) * 2 + align256(maxb * 8 + 8) + align256(maxb * 3 * 4 + 4);
   t += align256((size_t)maxb * BOX3 * MOM * 8 + 8) + align256((size_t)maxb * BOX3 * 3 * 8 + 8);
   t += align256((size_t)maxb * WIN3 + 8) + align256(64);
+  t += align256((size_t)maxb * 3 * 4 + 4);   // plane crossing record
   return t;
 }
 
@@ -167,6 +178,9 @@ ek_status ek_ctx::beads_advance(bool overlap, hipEvent_t chain_end) {
   mp.Lx = p.nx;
   mp.Ly = p.ny;
   mp.Lz = p.nz;
+  mp.track = cross_on ? 1 : 0;
+  mp.step = (int)(step_count + 1);
+  mp.z_plane = cross_plane;
   // lanes per bead so that a chain fills at most 512 threads (register budget
   // of 256 per thread); chains beyond 512 beads take one lane each
   const int tpb = n_beads <= 64 ? 8 : (n_beads <= 128 ? 4 : (n_beads <= 256 ? 2 : 1));
@@ -278,12 +292,45 @@ extern "C" ek_status ek_set_polymer(ek_ctx* ctx, int32_t n, const double* pos, c
     if (e != hipSuccess) return ctx->fail(EK_EHIP, "copying the polymer failed");
     ctx->poly = *pp;
   }
-  // clear a previous chain's node table and error flags
+  // clear a previous chain's node table, error flags and crossing record
   launch_table_clear(ctx->keys, ctx->vals, ctx->mask, ctx->dims.n, ctx->stream);
   hipLaunchKernelGGL(k_err_reset, dim3(1), dim3(64), 0, ctx->stream, bs.err);
+  const int mb = ctx->max_beads < 1 ? 1 : ctx->max_beads;
+  hipLaunchKernelGGL(k_cross_reset, dim3((mb + 255) / 256), dim3(256), 0, ctx->stream, bs.cross, mb);
   ctx->n_beads = n;
   ctx->host_q = q;
   return ctx->sync();
+}
+
+extern "C" ek_status ek_set_crossing_plane(ek_ctx* ctx, double z_plane) {
+  if (!ctx) return EK_EINVAL;
+  if (!std::isfinite(z_plane)) return ctx->fail(EK_EINVAL, "non-finite crossing plane");
+  if (!ctx->bead_mem) return ctx->fail(EK_ESTATE, "the context has no bead storage");
+  const int mb = ctx->max_beads < 1 ? 1 : ctx->max_beads;
+  BeadState bs = carve(ctx->bead_mem, mb);
+  hipLaunchKernelGGL(k_cross_reset, dim3((mb + 255) / 256), dim3(256), 0, ctx->stream, bs.cross, mb);
+  ctx->cross_on = true;
+  ctx->cross_plane = z_plane;
+  return ctx->sync();
+}
+
+extern "C" ek_status ek_get_crossings(ek_ctx* ctx, int32_t* first, int32_t* last, int32_t* net) {
+  if (!ctx) return EK_EINVAL;
+  if (!ctx->cross_on) return ctx->fail(EK_ESTATE, "no crossing plane is set");
+  if (ctx->n_beads == 0) return EK_OK;
+  const int n = ctx->n_beads;
+  BeadState bs = carve(ctx->bead_mem, ctx->max_beads < 1 ? 1 : ctx->max_beads);
+  std::vector<int> rec((size_t)n * 3);
+  if (hipMemcpyAsync(rec.data(), bs.cross, (size_t)n * 3 * 4, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess)
+    return ctx->fail(EK_EHIP, "copying the crossing record failed");
+  ek_status st = ctx->sync();
+  if (st) return st;
+  for (int i = 0; i < n; ++i) {
+    if (first) first[i] = rec[3 * i];
+    if (last) last[i] = rec[3 * i + 1];
+    if (net) net[i] = rec[3 * i + 2];
+  }
+  return EK_OK;
 }
 
 extern "C" ek_status ek_get_beads(ek_ctx* ctx, double* pos, double* vel) {

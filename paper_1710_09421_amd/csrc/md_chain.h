@@ -29,6 +29,7 @@ struct BeadState {
   double* efield;     // [maxb][BOX3][3]
   unsigned char* flags;  // [maxb][WIN3]: bit0 fluid, bit1 wall
   int* err;           // error bits
+  int* cross = nullptr;  // [maxb][3] plane crossings: first step, last step, net count
 };
 
 __device__ inline int wrap(int i, int n) {
@@ -83,6 +84,11 @@ struct MDParams {
   int n, n_sub;
   double M, k_fene, R0, eps, sigma, gamma;
   double Lx, Ly, Lz;
+  // crossing record of the plane z = z_plane (and its periodic images) in
+  // bs.cross; `step` is the number of completed steps once this one ends
+  int track = 0;
+  int step = 0;
+  double z_plane = 0.0;
 };
 
 __device__ inline double min_image(double v, double L) { return v - L * rint(v / L); }
@@ -362,6 +368,7 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
     }
     q = bs.q[i];
   }
+  const double z_start = R[2];   // for the plane crossing record
   __syncthreads();
   GlobalNodes gn{gkeys, gvals, mask, bs.err, gbits};
   LdsNodes ln{lkeys, lvals, lds_bits, bs.err};
@@ -698,6 +705,16 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
     for (int c = 0; c < 3; ++c) {
       bs.R[3 * i + c] = R[c];
       bs.V[3 * i + c] = V[c];
+    }
+    if (mp.track && bs.cross) {   // the step moved the bead across an image of the plane
+      const double k0 = floor((z_start - mp.z_plane) / mp.Lz);
+      const double k1 = floor((R[2] - mp.z_plane) / mp.Lz);
+      if (k0 != k1) {
+        int* cr = bs.cross + 3 * i;
+        if (cr[0] < 0) cr[0] = mp.step;
+        cr[1] = mp.step;
+        cr[2] += k1 > k0 ? 1 : -1;
+      }
     }
   }
   if (LDS) {   // hand the accumulated impulses to the lattice kernels

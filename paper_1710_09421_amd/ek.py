@@ -83,6 +83,9 @@ def _load():
         "ek_get_moments": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
         "ek_get_potential": (c_int32, [c_void_p, c_void_p]),
         "ek_get_beads": (c_int32, [c_void_p, c_void_p, c_void_p]),
+        "ek_plane_flux": (c_int32, [c_void_p, c_int32, c_void_p]),
+        "ek_set_crossing_plane": (c_int32, [c_void_p, ctypes.c_double]),
+        "ek_get_crossings": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
         "ek_get_stats": (c_int32, [c_void_p, P(ek_stats)]),
         "ek_poisson_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, P(ek_poisson_report)]),
         "ek_poisson_sor_iterations": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32]),
@@ -244,6 +247,25 @@ class Context:
         vel = np.empty((n_beads, 3))
         self._check(self._lib.ek_get_beads(self._h, _ptr(pos), _ptr(vel)), self._h)
         return pos, vel
+
+    def plane_flux(self, z):
+        """Particles of species 0, 1, 2 carried across the link plane between z
+        and z + 1 by the streaming that formed the current densities, and the
+        charge they carry (the ionic current in charge per step)."""
+        out = np.empty(4)
+        self._check(self._lib.ek_plane_flux(self._h, int(z), _ptr(out)), self._h)
+        return out
+
+    def set_crossing_plane(self, z_plane):
+        self._check(self._lib.ek_set_crossing_plane(self._h, float(z_plane)), self._h)
+
+    def crossings(self, n_beads):
+        """Per bead: first and last step that crossed the plane (-1: none) and
+        the net crossing count (+1 per crossing in +z)."""
+        rec = np.empty((3, n_beads), dtype=np.int32)
+        self._check(self._lib.ek_get_crossings(self._h, _ptr(rec[0]), _ptr(rec[1]), _ptr(rec[2])),
+                    self._h)
+        return rec[0], rec[1], rec[2]
 
     def stats(self):
         s = ek_stats()

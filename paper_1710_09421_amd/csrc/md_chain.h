@@ -606,17 +606,9 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
             wca_at(P);
           }
       }
-      for (int k = 0; k < NWS; ++k) {             // WCA against wall-site centres
-        const int wsite = lane + k * TPB;
-        const int wx = wsite & 3, wy = (wsite >> 2) & 3, wz = wsite >> 4;
-        const int ax = fx - 1 + wx, ay = fy - 1 + wy, az = fz - 1 + wz;
-        if constexpr (CACHE_E) {
-          if (!((wall_bits >> k) & 1ull)) continue;
-        } else {
-          const int ix = ax - org[0] + 1, iy = ay - org[1] + 1, iz = az - org[2] + 1;
-          if (ix < 0 || ix >= WIN || iy < 0 || iy >= WIN || iz < 0 || iz >= WIN) continue;
-          if (!(fl[ix + WIN * (iy + WIN * iz)] & 2)) continue;
-        }
+      // WCA against wall-site centres: site k of this lane is lane + k TPB of
+      // the 4^3 sites around the bead's cell
+      auto wall_at = [&](int ax, int ay, int az) {
         const double dv[3] = {R[0] - ax, R[1] - ay, R[2] - az};
         const double r2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
         if (r2 < rc2) {
@@ -625,6 +617,22 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
           const double coef = 24.0 * mp.eps * (2.0 * s6 * s6 - s6) * ir2;
 #pragma unroll
           for (int c = 0; c < 3; ++c) F[c] += coef * dv[c];
+        }
+      };
+      if constexpr (CACHE_E) {
+        // only the wall sites among them, in increasing k
+        for (unsigned long long mb = wall_bits; mb; mb &= mb - 1) {
+          const int wsite = lane + __builtin_ctzll(mb) * TPB;
+          wall_at(fx - 1 + (wsite & 3), fy - 1 + ((wsite >> 2) & 3), fz - 1 + (wsite >> 4));
+        }
+      } else {
+        for (int k = 0; k < NWS; ++k) {
+          const int wsite = lane + k * TPB;
+          const int ax = fx - 1 + (wsite & 3), ay = fy - 1 + ((wsite >> 2) & 3), az = fz - 1 + (wsite >> 4);
+          const int ix = ax - org[0] + 1, iy = ay - org[1] + 1, iz = az - org[2] + 1;
+          if (ix < 0 || ix >= WIN || iy < 0 || iy >= WIN || iz < 0 || iz >= WIN) continue;
+          if (!(fl[ix + WIN * (iy + WIN * iz)] & 2)) continue;
+          wall_at(ax, ay, az);
         }
       }
       if (bond_lane) {
@@ -649,11 +657,14 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
           for (int c = 0; c < 3; ++c) F[c] += coef * dv[c];
         }
       }
-      // combine the lanes of this bead
+      // combine the lanes of this bead (the field enters only as q E, so each
+      // lane adds its corners' share to its force first)
 #pragma unroll
-      for (int c = 0; c < 15; ++c) acc[c] = group_sum<TPB>(acc[c]);
+      for (int c = 0; c < 3; ++c) F[c] += q * acc[12 + c];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) F[c] = group_sum<TPB>(F[c]) + q * acc[12 + c];
+      for (int c = 0; c < 12; ++c) acc[c] = group_sum<TPB>(acc[c]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) F[c] = group_sum<TPB>(F[c]);
       // friction of each species and the substep update
       double ftot[3] = {F[0], F[1], F[2]};
 #pragma unroll
@@ -674,11 +685,12 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
 #pragma unroll
       for (int a = 0; a < CPL; ++a) {
         if (wt[a] == 0.0 || slot[a] < 0) continue;
+        const double g = -h * wt[a] * FIX_FORCE;   // impulse scale of this corner
 #pragma unroll
         for (int s = 0; s < 3; ++s)
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const long long v = round_fixed(-h * phi[s][c] * wt[a] * FIX_FORCE);
+            const long long v = round_fixed(phi[s][c] * g);
             if (LDS) ln.add(slot[a], 3 * s + c, v);
             else gn.add(slot[a], 3 * s + c, v);
           }

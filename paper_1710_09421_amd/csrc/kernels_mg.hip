@@ -21,9 +21,13 @@
 // enough of them to reduce its error by COARSEST_REDUCTION (a cycle reduces
 // the residual by about 1e-2, so a coarsest solve to 1e-3 leaves the cycle's
 // rate unchanged; a box that cannot be coarsened is solved by these sweeps
-// alone, each "cycle" then reducing its error by 1e-10).  Level 0 is the context's psi and b (b
+// alone, each "cycle" then reducing its error by 1e-10; a coarsest level
+// too large for one workgroup's LDS gets those sweeps as grid-wide
+// launches).  Level 0 is the context's psi and b (b
 // plus the scalar shift that removes the mean charge).  The launches of one
 // cycle are recorded once as a graph and replayed (see ek_ctx::MG).
+#include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <string>
@@ -113,7 +117,7 @@ __global__ __launch_bounds__(1024) void k_coarse_cycle(LvlSet set, int first, Po
                                                        const double* __restrict__ pinv) {
   static_assert(NU1 >= 1, "the fold needs a pre-smoothing sweep");
   if (ps->done) return;
-  if (threadIdx.x == 0) ps->cycles += 1;   // read only by later kernels
+  if (threadIdx.x == 0) atomicAdd(&ps->cycles, 1);   // read only by later kernels; no wait
   extern __shared__ __align__(16) double lds[];
   __shared__ Lvl L[MAX_LEVELS];
   __shared__ double* s_pinv;   // the coarsest level's inverse, after the levels
@@ -184,6 +188,11 @@ __global__ __launch_bounds__(1024) void k_coarse_cycle(LvlSet set, int first, Po
   for (int t = threadIdx.x; t < int(L[first].n); t += blockDim.x) set.l[first].x[t] = L[first].x[t];
 }
 
+// Cycle count of a V-cycle whose coarsest level is swept on the grid.
+__global__ void k_count_cycle(PoissonScalars* ps) {
+  if (threadIdx.x == 0 && !ps->done) ps->cycles += 1;
+}
+
 SiteGrid colour_launch(const Lvl& L) { return site_grid(L.nx / 2, L.ny, L.nz); }
 SiteGrid level_launch(const Lvl& L) { return site_grid(L.nx, L.ny, L.nz); }
 
@@ -196,6 +205,7 @@ struct ek_ctx::MG {
   double omega_coarsest = 1.0;
   int coarsest_sweeps = COARSEST_SWEEPS;
   const double* pinv = nullptr;   // inverse for the direct coarsest solve, or null
+  bool coarse_kernel = true;      // false: the coarsest level does not fit LDS
   // One V-cycle, and one V-cycle followed by the residual test, recorded as
   // graphs for the level-0 pair (b, x) they were recorded with: a replay
   // dispatches the cycle's ~30 dependent launches faster than the launches
@@ -324,18 +334,24 @@ void ek_ctx::mg_setup() {
     bytes += 16 * (size_t)mg->levels[fc].n;
   }
   bytes += inv_bytes;
+  // LDS of the one-workgroup kernel: up to 64 KiB by default, more where the
+  // device grants it; hand it fewer levels until they fit
+  auto fits = [](size_t b) {
+    if (b <= 64 * 1024) return true;
+    if (hipFuncSetAttribute((const void*)k_coarse_cycle, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)std::min<size_t>(b, INT_MAX)) == hipSuccess)
+      return true;
+    (void)hipGetLastError();
+    return false;
+  };
+  while (nl > 1 && fc < nl - 1 && !fits(bytes)) {
+    bytes -= 16 * (size_t)mg->levels[fc].n;
+    ++fc;
+  }
   mg->first_coarse = fc;
   mg->coarse_lds = bytes;
-  if (nl > 1 && bytes > 64 * 1024 &&
-      hipFuncSetAttribute((const void*)k_coarse_cycle, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)bytes) != hipSuccess) {
-    // keep within the default dynamic LDS limit
-    while (fc < nl - 1 && mg->coarse_lds > 64 * 1024) {
-      mg->coarse_lds -= 16 * (size_t)mg->levels[fc].n;
-      ++fc;
-    }
-    mg->first_coarse = fc;
-  }
+  // a coarsest level too large for LDS is swept on the grid instead
+  mg->coarse_kernel = nl > 1 && fits(bytes);
   // the coarsest level's inverse, after the levels in the workspace
   if (nl > 1 && c.n <= COARSEST_DIRECT_MAX) {
     std::vector<double> inv;
@@ -447,11 +463,23 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x) {
     hipLaunchKernelGGL(k_restrict, level_launch(L[l + 1]).grid, level_launch(L[l + 1]).block, 0,
                        stream, L[l], L[l + 1], ps, l == 0 ? 1 : 0, omega_red);
   }
-  LvlSet set{};
-  set.count = nl;
-  for (int l = 0; l < nl; ++l) set.l[l] = L[l];
-  hipLaunchKernelGGL(k_coarse_cycle, dim3(1), dim3(1024), mg->coarse_lds, stream, set, fc, ps,
-                     mg->omega_coarsest, mg->coarsest_sweeps, mg->pinv);
+  if (mg->coarse_kernel) {
+    LvlSet set{};
+    set.count = nl;
+    for (int l = 0; l < nl; ++l) set.l[l] = L[l];
+    hipLaunchKernelGGL(k_coarse_cycle, dim3(1), dim3(1024), mg->coarse_lds, stream, set, fc, ps,
+                       mg->omega_coarsest, mg->coarsest_sweeps, mg->pinv);
+  } else {
+    // the coarsest level (arriving at zero) by red-black SOR sweeps over the
+    // grid at its optimal factor; the cycle is counted as the coarse kernel
+    // would count it
+    const Lvl& C = L[nl - 1];
+    for (int s = 0; s < mg->coarsest_sweeps; ++s)
+      for (int c = 0; c < 2; ++c)
+        hipLaunchKernelGGL(k_smooth, colour_launch(C).grid, colour_launch(C).block, 0, stream, C, c,
+                           ps, 0, mg->omega_coarsest);
+    hipLaunchKernelGGL(k_count_cycle, dim3(1), dim3(64), 0, stream, ps);
+  }
   // coarse-grid correction: fused into the first post-smoothing sweep on
   // levels up to FUSED_CORRECTION_MAX_SITES, a pass of its own above
   for (int l = fc - 1; l >= 0; --l) {

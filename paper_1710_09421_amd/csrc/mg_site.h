@@ -68,8 +68,9 @@ __device__ inline void smooth_site(const Lvl& L, int colour, int tx, int y, int 
                                    double omega = 1.0) {
   const int x = 2 * tx + ((colour + y + z) & 1);
   const int r = idx3(x, y, z, L);
+  const double xo = L.x[r];   // read with the neighbours, not after their sum
   const double gs = (nbsum(L.x, x, y, z, L) - L.h2 * (L.f[r] + shift)) * (1.0 / 6.0);
-  L.x[r] = omega == 1.0 ? gs : L.x[r] + omega * (gs - L.x[r]);
+  L.x[r] = omega == 1.0 ? gs : xo + omega * (gs - xo);
 }
 
 // omega_red != 0: the coarse level's first colour-0 half sweep is done here

@@ -74,6 +74,43 @@ def test_multigrid_128_cubed_meets_tolerance(ek):
     assert field_error(psi, ref) < 1e3 * 1e-8
 
 
+def fft_solution(b):
+    """Exact mean-free periodic solution of the 7-point problem A psi = b."""
+    k = [2 * np.pi * np.fft.fftfreq(n) for n in b.shape]
+    lam = (2 * np.cos(k[0])[:, None, None] + 2 * np.cos(k[1])[None, :, None] +
+           2 * np.cos(k[2])[None, None, :] - 6.0)
+    lam[0, 0, 0] = 1.0
+    bh = np.fft.fftn(b)
+    bh[0, 0, 0] = 0.0
+    return np.real(np.fft.ifftn(bh / lam))
+
+
+@pytest.mark.parametrize("shape", [(36, 36, 36), (44, 44, 44)])
+def test_multigrid_with_a_large_coarsest_level(ek, shape):
+    """Boxes whose sides stop halving early: the coarsest level of 36^3 is
+    18^3 = 5,832 sites (more than the one-workgroup coarse kernel reads ahead
+    per thread), that of 44^3 is 22^3 = 10,648 sites (more than one
+    workgroup's LDS holds, so it is swept on the grid).  Both must still
+    reach the tolerance, in graph replay and in single launches."""
+    rng = np.random.default_rng(sum(shape) + 1)
+    rho = rng.normal(size=shape) * 0.01
+    b = opoisson.rhs_from_charge(rho, EPS)
+    ref = fft_solution(b)
+    for graphs in (True, False):
+        p = ek.make_params(shape, precision=ek.EK_FP64, poisson_method=ek.EK_POISSON_MG,
+                           poisson_tol=1e-8, poisson_max_iter=400)
+        ctx = ek.Context(p)
+        ctx.set_launch_mode(graphs=graphs, overlap=True)
+        rt = torch.tensor(rho, dtype=torch.float64, device="cuda")
+        pt = torch.zeros(shape, dtype=torch.float64, device="cuda")
+        rep = ctx.poisson_solve(rt, pt, ek.EK_WS_ZERO)
+        psi = pt.cpu().numpy()
+        rr = opoisson.relative_residual(psi, b)
+        print(shape, graphs, rep, rr)
+        assert rr <= 1e-8 and rep["iterations"] <= 12
+        assert field_error(psi, ref) < 1e3 * 1e-8
+
+
 def test_multigrid_warm_start_needs_fewer_cycles(ek):
     shape = (64, 32, 32)
     rng = np.random.default_rng(5)

@@ -148,7 +148,6 @@ ek_status ek_ctx::sor_solve(const double* bb, double* x, PoissonScalars h, int& 
                            double& res0) {
   const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
   const SiteGrid cg = colour_grid(p.nx, p.ny, p.nz, bx_colour);
-  const int nb = g.nblocks();
   const double rj = jacobi_radius();
   ek_status st = EK_OK;
   int it = 0;
@@ -166,8 +165,8 @@ ek_status ek_ctx::sor_solve(const double* bb, double* x, PoissonScalars h, int& 
       }
       ++it;
       if (it % ce == 0 || it == p.poisson_max_iter) {
-        launch_residual(x, bb, ps, partials, dims, g, stream);
-        launch_residual_final(partials, nb, p.poisson_tol, it, 0, ps, stream);
+        const int nr = launch_residual(x, bb, ps, partials, dims, g, stream);
+        launch_residual_final(partials, nr, p.poisson_tol, it, 0, ps, stream);
       }
     }
     st = read_scalars(&h);
@@ -190,8 +189,8 @@ ek_status ek_ctx::sor_solve(const double* bb, double* x, PoissonScalars h, int& 
 
 ek_status ek_ctx::initial_residual(const double* bb, const double* x, PoissonScalars* h) {
   const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
-  launch_residual(x, bb, ps, partials, dims, g, stream);
-  launch_residual_final(partials, g.nblocks(), p.poisson_tol, 0, 1, ps, stream);
+  const int nr = launch_residual(x, bb, ps, partials, dims, g, stream);
+  launch_residual_final(partials, nr, p.poisson_tol, 0, 1, ps, stream);
   return read_scalars(h);
 }
 
@@ -203,7 +202,6 @@ ek_status ek_ctx::initial_residual(const double* bb, const double* x, PoissonSca
 ek_status ek_ctx::learned_start(const double* bb, double* x, PoissonScalars* h) {
   ek_ctx* ctx = this;
   const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
-  const int nb = g.nblocks();
   last_fallback = 0;
   last_consulted = 0;
   ek_status st = initial_residual(bb, x, h);
@@ -212,8 +210,8 @@ ek_status ek_ctx::learned_start(const double* bb, double* x, PoissonScalars* h) 
   const PoissonScalars hp = *h;
   launch_ps_rearm(ps, stream);
   net->forward(bb, mask, true, guess);
-  launch_residual(guess, bb, ps, partials, dims, g, stream);
-  launch_residual_final(partials, nb, p.poisson_tol, 0, 1, ps, stream);
+  const int nr = launch_residual(guess, bb, ps, partials, dims, g, stream);
+  launch_residual_final(partials, nr, p.poisson_tol, 0, 1, ps, stream);
   PoissonScalars hl{};
   st = read_scalars(&hl);
   if (st) return st;
@@ -237,8 +235,8 @@ ek_status ek_ctx::poisson(const double* bb, double* x, bool learned, int& iters,
     // skip themselves once converged); the host reads it with the first
     // batch's result
     const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
-    launch_residual(x, bb, ps, partials, dims, g, stream);
-    launch_residual_final(partials, g.nblocks(), p.poisson_tol, 0, 1, ps, stream);
+    const int nr = launch_residual(x, bb, ps, partials, dims, g, stream);
+    launch_residual_final(partials, nr, p.poisson_tol, 0, 1, ps, stream);
     return mg_solve(bb, x, h, iters, res, res0);
   }
   ek_status st = learned ? learned_start(bb, x, &h) : initial_residual(bb, x, &h);

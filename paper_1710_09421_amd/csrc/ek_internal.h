@@ -131,8 +131,9 @@ void launch_mean_shift(const double* partials, int nblocks, double inv_n, double
 // Poisson (kernels_poisson.hip)
 void launch_sor_half(double* psi, const double* b, const PoissonScalars* ps, int colour,
                      double omega, Dims d, const SiteGrid& g, hipStream_t s);
-void launch_residual(const double* psi, const double* b, PoissonScalars* ps, double* partials,
-                     Dims d, const SiteGrid& g, hipStream_t s);
+// Returns the number of block partials it writes (for launch_residual_final).
+int launch_residual(const double* psi, const double* b, PoissonScalars* ps, double* partials,
+                    Dims d, const SiteGrid& g, hipStream_t s);
 void launch_residual_final(const double* partials, int nblocks, double tol, int iter,
                            int initial, PoissonScalars* ps, hipStream_t s);
 void launch_psi_shift(double* psi, const PoissonScalars* ps, double inv_n, Dims d,

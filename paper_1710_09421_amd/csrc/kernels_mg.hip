@@ -414,7 +414,6 @@ bool ek_ctx::mg_graphs(const double* bb, double* x) {
     return false;
   }
   const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
-  const int nb = g.nblocks();
   // the launchers enqueue on `stream`: point it at the recording stream
   const hipStream_t own = stream;
   stream = m.record_stream;
@@ -422,9 +421,9 @@ bool ek_ctx::mg_graphs(const double* bb, double* x) {
       record_graph(stream, &m.cycle, [&] { mg_vcycle(bb, x); }) &&
       record_graph(stream, &m.cycle_test, [&] {
         mg_vcycle(bb, x);
-        launch_residual(x, bb, ps, partials, dims, g, stream);
+        const int nr = launch_residual(x, bb, ps, partials, dims, g, stream);
         // iteration -1: the test reads the cycle count the coarse kernel keeps
-        launch_residual_final(partials, nb, p.poisson_tol, -1, 0, ps, stream);
+        launch_residual_final(partials, nr, p.poisson_tol, -1, 0, ps, stream);
       });
   stream = own;
   if (!ok) {
@@ -506,7 +505,6 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x) {
 ek_status ek_ctx::mg_solve(const double* bb, double* x, PoissonScalars h, int& iters, double& res,
                           double& res0) {
   const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
-  const int nb = g.nblocks();
   ek_status st = EK_OK;
   int it = 0;
   int batch = std::max(1, last_iters);
@@ -528,8 +526,8 @@ ek_status ek_ctx::mg_solve(const double* bb, double* x, PoissonScalars h, int& i
       st = mg_vcycle(bb, x);
       if (st) return st;
       if (!test) continue;
-      launch_residual(x, bb, ps, partials, dims, g, stream);
-      launch_residual_final(partials, nb, p.poisson_tol, it, 0, ps, stream);
+      const int nr = launch_residual(x, bb, ps, partials, dims, g, stream);
+      launch_residual_final(partials, nr, p.poisson_tol, it, 0, ps, stream);
     }
     untested = 0;
     st = read_scalars(&h);

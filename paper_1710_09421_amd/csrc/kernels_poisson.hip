@@ -40,6 +40,11 @@ __global__ __launch_bounds__(BLOCK) void k_sor_half(double* __restrict__ psi,
   psi[r] = old + omega * ((nbsum - rhs) * (1.0 / 6.0) - old);
 }
 
+// z planes per block of the residual: a thread sums the sites of a short
+// column (more loads in flight, the z neighbours shared through the cache,
+// a quarter of the block reductions and partials)
+constexpr int RESIDUAL_PLANES = 4;
+
 // Partial sums of r^2, b^2 and psi with r = b - A psi (7-point operator).
 __global__ __launch_bounds__(BLOCK) void k_residual(const double* __restrict__ psi,
                                                     const double* __restrict__ b,
@@ -48,11 +53,13 @@ __global__ __launch_bounds__(BLOCK) void k_residual(const double* __restrict__ p
   if (ps->done) return;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
   const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   const int nblocks = gridDim.x * gridDim.y * gridDim.z;
   double acc[3] = {0.0, 0.0, 0.0};
-  if (x < d.nx && y < d.ny) {
+#pragma unroll
+  for (int k = 0; k < RESIDUAL_PLANES; ++k) {
+  const int z = blockIdx.z * RESIDUAL_PLANES + k;
+  if (x < d.nx && y < d.ny && z < d.nz) {
     const int xm = x == 0 ? d.nx - 1 : x - 1, xp = x == d.nx - 1 ? 0 : x + 1;
     const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
     const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
@@ -66,9 +73,10 @@ __global__ __launch_bounds__(BLOCK) void k_residual(const double* __restrict__ p
                        psi[zp * nxy + (long long)y * d.nx + x] - 6.0 * c;
     const double rhs = b[r] + ps->shift;
     const double res = rhs - lap;
-    acc[0] = res * res;
-    acc[1] = rhs * rhs;
-    acc[2] = c;
+    acc[0] += res * res;
+    acc[1] += rhs * rhs;
+    acc[2] += c;
+  }
   }
   block_partials<3>(acc, partials, bid, nblocks);
 }
@@ -141,9 +149,12 @@ void launch_sor_half(double* psi, const double* b, const PoissonScalars* ps, int
   hipLaunchKernelGGL(k_sor_half, g.grid, g.block, 0, s, psi, b, ps, colour, omega, d);
 }
 
-void launch_residual(const double* psi, const double* b, PoissonScalars* ps, double* partials,
-                     Dims d, const SiteGrid& g, hipStream_t s) {
-  hipLaunchKernelGGL(k_residual, g.grid, g.block, 0, s, psi, b, ps, partials, d);
+int launch_residual(const double* psi, const double* b, PoissonScalars* ps, double* partials,
+                    Dims d, const SiteGrid& g, hipStream_t s) {
+  dim3 grid = g.grid;
+  grid.z = (d.nz + RESIDUAL_PLANES - 1) / RESIDUAL_PLANES;
+  hipLaunchKernelGGL(k_residual, grid, g.block, 0, s, psi, b, ps, partials, d);
+  return int(grid.x * grid.y * grid.z);
 }
 
 void launch_residual_final(const double* partials, int nblocks, double tol, int iter,

@@ -248,10 +248,11 @@ ek_status ek_get_timing(struct ek_ctx* ctx, ek_timing* out);
  *   solve's psi buffer changes.  Without it the same kernels are launched one
  *   by one, in the same order, with bit-identical results.  When recording
  *   fails the context keeps to single launches.
- * EK_LAUNCH_OVERLAP: with a polymer, the chain kernel runs on a second stream
- *   of the library's while the fused lattice kernel updates every site
- *   outside the beads' 4x4x4 boxes (the only nodes the friction reaches);
- *   the box sites follow in a small launch once the chain is done.  Every
+ * EK_LAUNCH_OVERLAP: with a polymer, the fused lattice kernel updates every
+ *   site outside the beads' 4x4x4 boxes (the only nodes the friction
+ *   reaches) on a second stream of the library's while the chain kernel runs
+ *   on the context's stream; the box sites follow in a small launch once
+ *   both are done.  Every
  *   site is updated by the same arithmetic either way (bit-identical fields
  *   and beads); only the order of the float64 mass and momentum sums
  *   differs.  Needs nx, ny, nz >= 4, else the kernels run one after the other.

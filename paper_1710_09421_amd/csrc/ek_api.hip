@@ -307,12 +307,21 @@ ek_status ek_ctx::step_impl(int n_steps) {
       st = beads_advance<T>(overlap, timing ? events[6 * t + 5] : nullptr);
       if (st) return st;
     }
-    // events 3 and 4 are stamped by the fused kernel's own start and end
+    // events 3 and 4 are stamped by the fused kernel's own start and end.
+    // With the overlap it runs on the side stream from the box gather on,
+    // beside the chain (the longer of the two stays on the context stream,
+    // which then waits only for a lattice update that has long finished)
+    hipStream_t ls = stream;
+    if (overlap) {
+      EK_HIP(hipStreamWaitEvent(side_stream, side_fork, 0));
+      ls = side_stream;
+    }
     launch_lb_step<T>((const T*)fcur(), (T*)fnext(), mask, psi, lp, bt, partials, nb_lb,
-                      overlap ? MASK_DEFER : 0u, dims, g, stream,
+                      overlap ? MASK_DEFER : 0u, dims, g, ls,
                       timing ? events[6 * t + 3] : nullptr, timing ? events[6 * t + 4] : nullptr);
     if (overlap) {
-      EK_HIP(hipStreamWaitEvent(stream, md_join, 0));
+      EK_HIP(hipEventRecord(side_join, side_stream));
+      EK_HIP(hipStreamWaitEvent(stream, side_join, 0));
       launch_lb_tail<T>((const T*)fcur(), (T*)fnext(), mask, psi, lp, bt, bead_origin(), n_beads,
                         partials, nb_bulk, nb_lb, dims, stream);
     }
@@ -475,12 +484,12 @@ ek_status ek_create(const ek_params* p, int32_t max_beads, void* dev_ws, size_t 
 void ek_destroy(ek_ctx* ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
-  if (ctx->md_stream) {
-    (void)hipStreamSynchronize(ctx->md_stream);
-    (void)hipStreamDestroy(ctx->md_stream);
+  if (ctx->side_stream) {
+    (void)hipStreamSynchronize(ctx->side_stream);
+    (void)hipStreamDestroy(ctx->side_stream);
   }
-  if (ctx->md_fork) (void)hipEventDestroy(ctx->md_fork);
-  if (ctx->md_join) (void)hipEventDestroy(ctx->md_join);
+  if (ctx->side_fork) (void)hipEventDestroy(ctx->side_fork);
+  if (ctx->side_join) (void)hipEventDestroy(ctx->side_join);
   for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
   ctx->mg_release();
   delete ctx->net;

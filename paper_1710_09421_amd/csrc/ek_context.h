@@ -78,10 +78,10 @@ struct ek_ctx {
   bool timing = false;
   bool graph_launch = true;            // multigrid cycles replayed from recorded graphs
   bool overlap_md = true;              // lattice update outside the bead boxes beside the chain
-  // second stream for the chain kernel and its fork / join events (created on
-  // first use)
-  hipStream_t md_stream = nullptr;
-  hipEvent_t md_fork = nullptr, md_join = nullptr;
+  // second stream for the lattice update outside the bead boxes, beside the
+  // chain kernel, and its fork / join events (created on first use)
+  hipStream_t side_stream = nullptr;
+  hipEvent_t side_fork = nullptr, side_join = nullptr;
   // 6 per step: charge, poisson, md, lb start, lb end, chain end
   std::vector<hipEvent_t> events;
   ek_timing tacc{};
@@ -129,9 +129,10 @@ struct ek_ctx {
   ek::BeadTableView bead_view() const;
   const int* bead_origin() const;      // box origins of the step's beads (device)
   ek_status beads_deposit();
-  // Box gather and chain kernel.  With `overlap` the box nodes are flagged
-  // MASK_DEFER and the chain runs on md_stream (joined by md_join, and
-  // stamping `chain_end` when given); else both run on the context stream.
+  // Box gather and chain kernel on the context stream (stamping `chain_end`
+  // when given).  With `overlap` the box nodes are flagged MASK_DEFER and
+  // side_fork is recorded after the gather, for the lattice update that the
+  // caller runs beside the chain on side_stream.
   template <typename T>
   ek_status beads_advance(bool overlap, hipEvent_t chain_end);
   ek_status beads_check();

@@ -153,18 +153,18 @@ ek_status ek_ctx::beads_advance(bool overlap, hipEvent_t chain_end) {
   const LBParams lp = lb_params();
   hipLaunchKernelGGL(k_bead_box<T>, dim3(n_beads), dim3(256), 0, stream, bs, (const T*)fcur(),
                      mask, psi, lp, dims, overlap ? 1 : 0);
-  hipStream_t cs = stream;   // stream of the chain kernel
+  const hipStream_t cs = stream;   // the chain follows the box gather on the context stream
   if (overlap) {
-    if (!md_stream) {
-      if (hipStreamCreateWithFlags(&md_stream, hipStreamNonBlocking) != hipSuccess ||
-          hipEventCreateWithFlags(&md_fork, hipEventDisableTiming) != hipSuccess ||
-          hipEventCreateWithFlags(&md_join, hipEventDisableTiming) != hipSuccess)
-        return fail(EK_EHIP, "creating the chain stream failed");
+    // the lattice update outside the boxes (launched by the caller on the
+    // side stream) may start once the boxes are flagged
+    if (!side_stream) {
+      if (hipStreamCreateWithFlags(&side_stream, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&side_fork, hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&side_join, hipEventDisableTiming) != hipSuccess)
+        return fail(EK_EHIP, "creating the side stream failed");
     }
-    if (hipEventRecord(md_fork, stream) != hipSuccess ||
-        hipStreamWaitEvent(md_stream, md_fork, 0) != hipSuccess)
-      return fail(EK_EHIP, "ordering the chain stream failed");
-    cs = md_stream;
+    if (hipEventRecord(side_fork, stream) != hipSuccess)
+      return fail(EK_EHIP, "recording the side stream's fork failed");
   }
   MDParams mp;
   mp.n = n_beads;
@@ -218,8 +218,6 @@ ek_status ek_ctx::beads_advance(bool overlap, hipEvent_t chain_end) {
   }
   if (chain_end && hipEventRecord(chain_end, cs) != hipSuccess)
     return fail(EK_EHIP, "recording the chain timer failed");
-  if (overlap && hipEventRecord(md_join, cs) != hipSuccess)
-    return fail(EK_EHIP, "recording the chain join failed");
   return EK_OK;
 }
 template ek_status ek_ctx::beads_advance<float>(bool, hipEvent_t);

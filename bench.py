@@ -10,8 +10,10 @@ updates per second summed over the three species (MLUPS per species-step).
 
 The JSON line also carries:
   roofline      the fused lattice kernel priced against HBM bandwidth, from
-                its average duration measured with HIP events on the
-                library's stream during the timed region, and its algorithmic
+                its average duration measured with HIP events stamped at
+                the kernel's own start and end on the stream it runs on (the
+                library's second stream, beside the chain) during the timed
+                region, and its algorithmic
                 bytes per launch (populations read and written once, the link
                 word of every site, the potential of every fluid site);
   cpu_baseline  the float64 oracle timed on the host for a bounded sample of

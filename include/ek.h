@@ -187,7 +187,8 @@ ek_status ek_plane_flux(struct ek_ctx* ctx, int32_t z, double* out);
 
 /* Bead crossing record of the plane z = z_plane (lattice units; its periodic
  * images z_plane + k nz count too).  Setting the plane enables the record and
- * clears it; ek_set_polymer clears it as well.  A bead crosses the plane in a
+ * clears it; ek_set_polymer clears it as well, and ek_set_geometry (which
+ * restarts the step count) ends it until a plane is set again.  A bead crosses the plane in a
  * step when floor((Z - z_plane) / nz) differs between its z coordinate Z at
  * the start and at the end of the step (both float64).  EK_EINVAL for a
  * non-finite z_plane. */

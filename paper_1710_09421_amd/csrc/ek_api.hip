@@ -527,6 +527,7 @@ ek_status ek_set_geometry(ek_ctx* ctx, const uint8_t* solid, const double* wall_
   ctx->step_count = 0;
   ctx->last_iters = 0;
   ctx->psi_hist = 0;
+  ctx->cross_on = false;   // the step count restarts: a crossing record would not match it
   return ctx->sync();
 }
 

@@ -123,10 +123,13 @@ def test_bead_crossings_match_oracle(ek):
     assert np.array_equal(g_net[sure], net[sure])
     # the rest: a valid record either way
     assert np.all((g_first <= g_last) & ((g_first < 0) == (g_last < 0)))
-    # setting the polymer again clears the record
+    # setting the polymer again clears the record; a new geometry ends it
     ctx.set_polymer(wl.beads_R, wl.beads_V, wl.polymer["q"])
     c_first, c_last, c_net = ctx.crossings(n)
     assert np.all(c_first == -1) and np.all(c_last == -1) and np.all(c_net == 0)
+    ctx.set_geometry(wl.solid, wl.wall_q)
+    with pytest.raises(ek.EKError):
+        ctx.crossings(n)
 
 
 def test_crossings_follow_the_chain_single_pore_64x64x128(ek):

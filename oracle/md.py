@@ -23,7 +23,10 @@ Readings taken (listed with the others in the design notes):
     self-weight exceeds the local fluid density by a factor of about two);
   * conservative forces: FENE bonds between chain neighbours,
     U = -k R0^2 / 2 ln(1 - (r / R0)^2), a purely repulsive WCA between all
-    pairs, the same WCA between a bead and the centres of boundary solid sites,
+    pairs; or, with poly["bond"] == "harmonic", the bonds of Eq.
+    polymermodel, U = k (r - l_bond)^2 / 2, and the WCA only between beads
+    more than one apart along the chain (|i - j| > 1); the same WCA between
+    a bead and the centres of boundary solid sites,
     and the electric force q_i E(R_i) with E = -grad psi + E_ext (the text's
     "+ q_i grad psi" is read as the usual -q_i grad psi);
   * integrator: n_sub substeps of h = 1 / n_sub per lattice step,
@@ -91,11 +94,30 @@ def fene_forces(R, box, k, R0):
     return F
 
 
-def wca_energy(R, box, eps, sigma):
+def harmonic_energy(R, box, k, l):
+    d = minimum_image(R[1:] - R[:-1], box)
+    r = np.sqrt((d * d).sum(axis=1))
+    return float(np.sum(0.5 * k * (r - l) ** 2))
+
+
+def harmonic_forces(R, box, k, l):
+    """-grad of the harmonic bond energy over the chain bonds (i, i+1)."""
+    F = np.zeros_like(R)
+    d = minimum_image(R[1:] - R[:-1], box)      # from i to i+1
+    r = np.sqrt((d * d).sum(axis=1))
+    coef = k * (r - l) / r                      # force on i is +coef * d
+    F[:-1] += coef[:, None] * d
+    F[1:] -= coef[:, None] * d
+    return F
+
+
+def wca_energy(R, box, eps, sigma, skip_bonded=False):
     N = R.shape[0]
     e = 0.0
     for i in range(N):
         for j in range(i + 1, N):
+            if skip_bonded and j == i + 1:
+                continue
             d = minimum_image(R[j] - R[i], box)
             r = np.sqrt((d * d).sum())
             if r < WCA_CUT * sigma:
@@ -104,11 +126,16 @@ def wca_energy(R, box, eps, sigma):
     return e
 
 
-def wca_pair_forces(R, box, eps, sigma):
-    """Repulsive WCA between every pair of beads (minimum image)."""
+def wca_pair_forces(R, box, eps, sigma, skip_bonded=False):
+    """Repulsive WCA between every pair of beads (minimum image); with
+    skip_bonded not between chain neighbours."""
     d = minimum_image(R[:, None, :] - R[None, :, :], box)   # R_i - R_j
     r2 = (d * d).sum(axis=2)
     np.fill_diagonal(r2, np.inf)
+    if skip_bonded:
+        i = np.arange(R.shape[0] - 1)
+        r2[i, i + 1] = np.inf
+        r2[i + 1, i] = np.inf
     inside = r2 < (WCA_CUT * sigma) ** 2
     sr2 = np.where(inside, sigma * sigma / np.where(inside, r2, 1.0), 0.0)
     sr6 = sr2 ** 3
@@ -171,7 +198,8 @@ def md_substeps(R, V, n, j, E, fluid, walls, poly):
     R, V: [N, 3]; n: [S, Z, Y, X] and j: [S, 3, Z, Y, X] from the populations
     at time t; E: [3, Z, Y, X] nodal field including E_ext; fluid: bool
     [Z, Y, X]; walls: [M, 3] boundary site centres; poly: dict with keys
-    M, q [N], k_fene, R0, eps, sigma, gamma, n_sub.
+    M, q [N], k_fene, R0, eps, sigma, gamma, n_sub (and optionally bond =
+    "harmonic" with k_bond, l_bond).
 
     Returns (R, V, K) with K [S, 3, Z, Y, X] the force density on each species
     accumulated over the substeps (the fluid's share of the friction).
@@ -205,8 +233,12 @@ def md_substeps(R, V, n, j, E, fluid, walls, poly):
         x_b = (wt[None] * nc / ntc[None]).sum(axis=-1)                    # [S, N]
         E_b = (w[None] * gather(E, idx)).sum(axis=-1)                     # [3, N]
 
-        F = fene_forces(R, box, poly["k_fene"], poly["R0"])
-        F += wca_pair_forces(R, box, poly["eps"], poly["sigma"])
+        harmonic = poly.get("bond", "fene") == "harmonic"
+        if harmonic:
+            F = harmonic_forces(R, box, poly["k_bond"], poly["l_bond"])
+        else:
+            F = fene_forces(R, box, poly["k_fene"], poly["R0"])
+        F += wca_pair_forces(R, box, poly["eps"], poly["sigma"], skip_bonded=harmonic)
         F += wall_forces(R, walls, box, poly["eps"], poly["sigma"])
         F += q[:, None] * E_b.T
 

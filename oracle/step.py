@@ -40,9 +40,11 @@ class Params:
 
 
 def polymer_params(n_beads, q=-1.0, M=1.0, k_fene=30.0, R0=1.5, eps=1.0, sigma=1.0,
-                   gamma=20.0, n_sub=40):
+                   gamma=20.0, n_sub=40, bond="fene", k_bond=0.0, l_bond=0.0):
+    """bond "fene" (k_fene, R0) or "harmonic" (k_bond, l_bond: Eq. polymermodel)."""
     return dict(M=M, q=np.full(n_beads, q, dtype=np.float64), k_fene=k_fene, R0=R0,
-                eps=eps, sigma=sigma, gamma=gamma, n_sub=n_sub)
+                eps=eps, sigma=sigma, gamma=gamma, n_sub=n_sub, bond=bond, k_bond=k_bond,
+                l_bond=l_bond)
 
 
 class Simulation:

@@ -167,3 +167,58 @@ def test_bead_and_uniform_flow_reach_common_velocity():
     assert np.allclose(V1[0] - u_node, -u0 * decay, rtol=1e-6, atol=1e-14)
     assert np.allclose(M * V1[0] + ntot * u_node, ntot * u0, rtol=1e-6)
     assert np.allclose(V1[0], common, rtol=1e-6)
+
+
+def test_harmonic_bond_force_is_minus_energy_gradient():
+    """Bonded term of Eq. polymermodel, U = k (r - l_bond)^2 / 2."""
+    R = chain(8)
+    F = md.harmonic_forces(R, BOX, 25.0, 1.0)
+    g = numerical_gradient(lambda X: md.harmonic_energy(X, BOX, 25.0, 1.0), R)
+    assert np.allclose(F, -g, rtol=1e-6, atol=1e-6)
+    assert np.allclose(F.sum(axis=0), 0.0, atol=1e-12)
+    pair = np.array([[1.0, 2.0, 3.0], [1.0, 2.0, 4.5]])      # r = 1.5 across no boundary
+    assert md.harmonic_energy(pair, BOX, 4.0, 1.0) == pytest.approx(0.5, rel=1e-14)
+    assert np.allclose(md.harmonic_forces(pair, BOX, 4.0, 1.0), [[0, 0, 2.0], [0, 0, -2.0]])
+
+
+def test_wca_skips_bonded_neighbours_only():
+    """With the harmonic bonds the WCA acts only for |i - j| > 1: a chain whose
+    only close pairs are neighbours feels none, and a folded chain feels
+    exactly the pair force of its close non-neighbours."""
+    straight = np.array([[1.0, 1.0, 1.0], [1.9, 1.0, 1.0], [2.8, 1.0, 1.0]])
+    assert np.abs(md.wca_pair_forces(straight, BOX, 1.0, 1.0)).max() > 1.0
+    assert np.abs(md.wca_pair_forces(straight, BOX, 1.0, 1.0, skip_bonded=True)).max() == 0.0
+    folded = np.array([[1.0, 1.0, 1.0], [1.9, 1.0, 1.0], [1.5, 1.7, 1.0]])   # 0-2 at 0.86
+    F = md.wca_pair_forces(folded, BOX, 1.0, 1.0, skip_bonded=True)
+    F02 = md.wca_pair_forces(folded[[0, 2]], BOX, 1.0, 1.0)
+    assert np.allclose(F[[0, 2]], F02, rtol=1e-14) and np.all(F[1] == 0.0)
+    assert md.wca_energy(folded, BOX, 1.0, 1.0, skip_bonded=True) == pytest.approx(
+        md.wca_energy(folded[[0, 2]], BOX, 1.0, 1.0), rel=1e-14)
+
+
+def test_free_harmonic_dimer_oscillates_at_sqrt_2k_over_m():
+    """Two beads joined by a harmonic bond, no friction, field or WCA: the
+    separation y = r - l obeys the semi-implicit Euler map of an oscillator
+    with w^2 = 2 k / M (reduced mass M / 2), v' = v - h w^2 y, y' = y + h v',
+    whose exact solution from y_0 = a, v_0 = 0 is
+    y_n = a cos(n th) - a (h w)^2 / 2 / sin(th) sin(n th), cos(th) = 1 - (h w)^2 / 2
+    (the continuous a cos(w t) to first order in h w)."""
+    shape = (8, 8, 8)
+    n, j, E = _quiescent_fields(shape)
+    fluid = np.ones(shape, dtype=bool)
+    k, M, l, a = 2.0, 1.0, 1.0, 0.1
+    R = np.array([[3.0, 4.0, 4.0], [3.0 + l + a, 4.0, 4.0]])
+    V = np.zeros((2, 3))
+    poly = dict(M=M, q=np.zeros(2), k_fene=0.0, R0=1.5, eps=0.0, sigma=1.0, gamma=0.0,
+                n_sub=400, bond="harmonic", k_bond=k, l_bond=l)
+    w = np.sqrt(2 * k / M)
+    hw = w / poly["n_sub"]
+    th = np.arccos(1 - hw * hw / 2)
+    for t in range(1, 4):
+        R, V, K = md.md_substeps(R, V, n, j, E, fluid, np.zeros((0, 3)), poly)
+        sep = R[1, 0] - R[0, 0]
+        m = t * poly["n_sub"]
+        y = a * np.cos(m * th) - a * hw * hw / 2 / np.sin(th) * np.sin(m * th)
+        assert sep == pytest.approx(l + y, abs=1e-10), t
+        assert sep == pytest.approx(l + a * np.cos(w * t), abs=0.01 * a), t
+    assert np.allclose(R[:, 1:], [[4.0, 4.0], [4.0, 4.0]]) and np.abs(K).max() == 0.0

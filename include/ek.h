@@ -99,15 +99,23 @@ typedef struct {
   int32_t fluctuations;        /* must be 0                                    */
 } ek_params;
 
-/* Bead-spring chain (Sec. II.B): FENE bonds between neighbours, repulsive
- * WCA between all bead pairs and between beads and boundary solid sites,
- * friction gamma with the species, n_sub MD substeps per lattice step. */
+/* Bead-spring chain (Sec. II.B): bonds between chain neighbours, repulsive
+ * WCA between bead pairs and between beads and boundary solid sites,
+ * friction gamma with the species, n_sub MD substeps per lattice step.
+ * Bonds: EK_BOND_FENE, U = -k R0^2 / 2 ln(1 - (r / R0)^2) with the WCA between
+ * all pairs; or EK_BOND_HARMONIC, the bonded term of Eq. polymermodel,
+ * U = k_bond (r - l_bond)^2 / 2, with the WCA only between beads more than
+ * one apart along the chain. */
+enum { EK_BOND_FENE = 0, EK_BOND_HARMONIC = 1 };
 typedef struct {
   double M;                    /* bead mass                                    */
   double k_fene, R0;           /* FENE spring constant and maximum extension   */
   double eps, sigma;           /* WCA energy and diameter                      */
   double gamma;                /* friction coefficient                         */
   int32_t n_sub;               /* MD substeps per lattice step (>= 1)          */
+  int32_t bond;                /* EK_BOND_FENE or EK_BOND_HARMONIC             */
+  double k_bond, l_bond;       /* harmonic spring constant (>= 0) and rest
+                                  length (> 0)                                 */
 } ek_polymer_params;
 
 typedef struct {

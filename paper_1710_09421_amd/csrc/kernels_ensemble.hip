@@ -760,8 +760,11 @@ ek_status ek_ensemble_set_replica(ek_ensemble* e, int32_t r, const double* E_ext
   if (!e->have_geometry) return e->fail(EK_ESTATE, "set the geometry first");
   if (r < 0 || r >= e->n_rep || !E_ext || !n0) return e->fail(EK_EINVAL, "bad replica arguments");
   if (n_beads < 0 || n_beads > e->max_beads) return e->fail(EK_EINVAL, "n_beads exceeds max_beads");
-  if (n_beads > 0 && (!pos || !vel || !pp || pp->n_sub < 1 || !(pp->M > 0) || !(pp->R0 > 0) ||
-                      !(pp->sigma > 0) || 1.122462048309373 * pp->sigma >= 2.0))
+  if (n_beads > 0 && (!pos || !vel || !pp || pp->n_sub < 1 || !(pp->M > 0) || !(pp->sigma > 0) ||
+                      1.122462048309373 * pp->sigma >= 2.0 ||
+                      (pp->bond != EK_BOND_FENE && pp->bond != EK_BOND_HARMONIC) ||
+                      (pp->bond == EK_BOND_FENE && !(pp->R0 > 0)) ||
+                      (pp->bond == EK_BOND_HARMONIC && (!(pp->k_bond >= 0) || !(pp->l_bond > 0)))))
     return e->fail(EK_EINVAL, "bad chain arguments");
   const Dims d = e->d;
   const size_t n = d.n;
@@ -820,6 +823,9 @@ ek_status ek_ensemble_set_replica(ek_ensemble* e, int32_t r, const double* E_ext
     mp.Lx = d.nx;
     mp.Ly = d.ny;
     mp.Lz = d.nz;
+    mp.bond = pp->bond;
+    mp.k_bond = pp->k_bond;
+    mp.l_bond = pp->l_bond;
   }
   e->have_replica[r] = true;
   return EK_OK;

@@ -178,6 +178,9 @@ ek_status ek_ctx::beads_advance(bool overlap, hipEvent_t chain_end) {
   mp.Lx = p.nx;
   mp.Ly = p.ny;
   mp.Lz = p.nz;
+  mp.bond = poly.bond;
+  mp.k_bond = poly.k_bond;
+  mp.l_bond = poly.l_bond;
   mp.track = cross_on ? 1 : 0;
   mp.step = (int)(step_count + 1);
   mp.z_plane = cross_plane;
@@ -246,8 +249,11 @@ extern "C" ek_status ek_set_polymer(ek_ctx* ctx, int32_t n, const double* pos, c
   if (n < 0 || n > ctx->max_beads) return ctx->fail(EK_EINVAL, "n_beads exceeds max_beads of the context");
   if (n > 0 && (!pos || !vel || !pp)) return ctx->fail(EK_EINVAL, "NULL polymer argument");
   if (n > 0) {
-    if (!(pp->M > 0) || pp->n_sub < 1 || !(pp->gamma >= 0) || !(pp->R0 > 0) || !(pp->sigma > 0) ||
-        !(pp->eps >= 0) || !(pp->k_fene >= 0))
+    const bool fene = pp->bond == EK_BOND_FENE;
+    if (!(pp->M > 0) || pp->n_sub < 1 || !(pp->gamma >= 0) || !(pp->sigma > 0) ||
+        !(pp->eps >= 0) || (pp->bond != EK_BOND_FENE && pp->bond != EK_BOND_HARMONIC) ||
+        (fene && (!(pp->R0 > 0) || !(pp->k_fene >= 0))) ||
+        (!fene && (!(pp->k_bond >= 0) || !(pp->l_bond > 0))))
       return ctx->fail(EK_EINVAL, "invalid polymer parameters");
     if (1.122462048309373 * pp->sigma >= 2.0)
       return ctx->fail(EK_EINVAL, "WCA cut-off must stay below two lattice spacings");
@@ -264,7 +270,7 @@ extern "C" ek_status ek_set_polymer(ek_ctx* ctx, int32_t n, const double* pos, c
           v -= L[c] * std::rint(v / L[c]);
           r2 += v * v;
         }
-        if (r2 >= pp->R0 * pp->R0) return ctx->fail(EK_EINVAL, "a bond is longer than R0");
+        if (fene && r2 >= pp->R0 * pp->R0) return ctx->fail(EK_EINVAL, "a bond is longer than R0");
       }
       bool fluid = false;
       const int fx = (int)std::floor(pos[3 * i]), fy = (int)std::floor(pos[3 * i + 1]),

@@ -89,6 +89,10 @@ struct MDParams {
   int track = 0;
   int step = 0;
   double z_plane = 0.0;
+  // bonds: 0 FENE (k_fene, R0) with the WCA between all pairs; 1 harmonic
+  // (k_bond, l_bond, Eq. polymermodel) with the WCA only for |i - j| > 1
+  int bond = 0;
+  double k_bond = 0.0, l_bond = 0.0;
 };
 
 __device__ inline double min_image(double v, double L) { return v - L * rint(v / L); }
@@ -404,7 +408,7 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
       if (live) {
         nb_count = 0;
         for (int j = lane; j < mp.n; j += TPB) {
-          if (j == i) continue;
+          if (j == i || (mp.bond == 1 && (j == i - 1 || j == i + 1))) continue;
           double r2 = 0.0;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
@@ -601,7 +605,7 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
         }
       } else {
         for (int j = lane; j < mp.n; j += TPB)       // WCA between all pairs
-          if (j != i) {
+          if (j != i && !(mp.bond == 1 && (j == i - 1 || j == i + 1))) {
             const double P[3] = {sR[3 * j], sR[3 * j + 1], sR[3 * j + 2]};
             wca_at(P);
           }
@@ -647,12 +651,18 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
             dv[c] = v - L[c] * rint(v * iL[c]);
             r2 += dv[c] * dv[c];
           }
-          const double x2 = r2 * iR02;
-          if (x2 >= 1.0) {
-            atomicOr(bs.err, ERR_BOND);
-            continue;
+          double coef;
+          if (mp.bond == 1) {   // harmonic: k (r - l) / r along the bond
+            const double r = sqrt(r2);
+            coef = r > 0.0 ? mp.k_bond * (r - mp.l_bond) / r : 0.0;
+          } else {
+            const double x2 = r2 * iR02;
+            if (x2 >= 1.0) {
+              atomicOr(bs.err, ERR_BOND);
+              continue;
+            }
+            coef = mp.k_fene / (1.0 - x2);
           }
-          const double coef = mp.k_fene / (1.0 - x2);
 #pragma unroll
           for (int c = 0; c < 3; ++c) F[c] += coef * dv[c];
         }

@@ -36,7 +36,15 @@ class ek_params(ctypes.Structure):
 
 class ek_polymer_params(ctypes.Structure):
     _fields_ = [("M", c_double), ("k_fene", c_double), ("R0", c_double), ("eps", c_double),
-                ("sigma", c_double), ("gamma", c_double), ("n_sub", c_int32)]
+                ("sigma", c_double), ("gamma", c_double), ("n_sub", c_int32), ("bond", c_int32),
+                ("k_bond", c_double), ("l_bond", c_double)]
+
+
+EK_BOND_FENE, EK_BOND_HARMONIC = 0, 1
+
+
+def _bond_code(bond):
+    return {"fene": EK_BOND_FENE, "harmonic": EK_BOND_HARMONIC}.get(bond, bond)
 
 
 class ek_stats(ctypes.Structure):
@@ -218,11 +226,12 @@ class Context:
         self._check(self._lib.ek_set_species_density(self._h, species, _ptr(a)), self._h)
 
     def set_polymer(self, pos, vel, charge, M=1.0, k_fene=30.0, R0=1.5, eps=1.0, sigma=1.0,
-                    gamma=20.0, n_sub=40):
+                    gamma=20.0, n_sub=40, bond="fene", k_bond=0.0, l_bond=0.0):
         pos = np.ascontiguousarray(pos, dtype=np.float64)
         vel = np.ascontiguousarray(vel, dtype=np.float64)
         q = np.ascontiguousarray(charge, dtype=np.float64)
-        pp = ek_polymer_params(M, k_fene, R0, eps, sigma, gamma, n_sub)
+        pp = ek_polymer_params(M, k_fene, R0, eps, sigma, gamma, n_sub, _bond_code(bond), k_bond,
+                               l_bond)
         self._check(self._lib.ek_set_polymer(self._h, pos.shape[0], _ptr(pos), _ptr(vel), _ptr(q),
                                              byref(pp)), self._h)
 
@@ -330,7 +339,8 @@ def from_workload(wl, precision=EK_FP32, poisson_method=EK_POISSON_SOR, poisson_
         pp = wl.polymer
         ctx.set_polymer(wl.beads_R, wl.beads_V, pp["q"], M=pp["M"], k_fene=pp["k_fene"],
                         R0=pp["R0"], eps=pp["eps"], sigma=pp["sigma"], gamma=pp["gamma"],
-                        n_sub=pp["n_sub"])
+                        n_sub=pp["n_sub"], bond=pp.get("bond", "fene"), k_bond=pp.get("k_bond", 0.0),
+                        l_bond=pp.get("l_bond", 0.0))
     return ctx
 
 
@@ -380,7 +390,7 @@ class Ensemble:
                     self._h)
 
     def set_replica(self, r, E_ext, n0, pos=None, vel=None, charge=None, M=1.0, k_fene=30.0, R0=1.5,
-                    eps=1.0, sigma=1.0, gamma=20.0, n_sub=40):
+                    eps=1.0, sigma=1.0, gamma=20.0, n_sub=40, bond="fene", k_bond=0.0, l_bond=0.0):
         E = np.ascontiguousarray(E_ext, dtype=np.float64)
         n = np.ascontiguousarray(n0, dtype=np.float64).reshape((3,) + self.shape)
         nb = 0 if pos is None else int(np.asarray(pos).shape[0])
@@ -389,7 +399,8 @@ class Ensemble:
             pos = np.ascontiguousarray(pos, dtype=np.float64)
             vel = np.ascontiguousarray(vel, dtype=np.float64)
             q = np.ascontiguousarray(charge, dtype=np.float64)
-            pp = ek_polymer_params(M, k_fene, R0, eps, sigma, gamma, n_sub)
+            pp = ek_polymer_params(M, k_fene, R0, eps, sigma, gamma, n_sub, _bond_code(bond),
+                                   k_bond, l_bond)
             args = [_ptr(pos), _ptr(vel), _ptr(q), byref(pp)]
         self._check(self._lib.ek_ensemble_set_replica(self._h, r, _ptr(E), _ptr(n), nb, *args),
                     self._h)
@@ -454,7 +465,8 @@ def ensemble_from_workloads(wls, precision=EK_FP32, poisson_tol=1e-8, poisson_ma
             pp = w.polymer
             ens.set_replica(r, w.E_ext, w.n0, w.beads_R, w.beads_V, pp["q"], M=pp["M"],
                             k_fene=pp["k_fene"], R0=pp["R0"], eps=pp["eps"], sigma=pp["sigma"],
-                            gamma=pp["gamma"], n_sub=pp["n_sub"])
+                            gamma=pp["gamma"], n_sub=pp["n_sub"], bond=pp.get("bond", "fene"),
+                            k_bond=pp.get("k_bond", 0.0), l_bond=pp.get("l_bond", 0.0))
         else:
             ens.set_replica(r, w.E_ext, w.n0)
     return ens

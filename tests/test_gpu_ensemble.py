@@ -207,3 +207,25 @@ def test_no_convergence_names_the_replica(ek):
     with pytest.raises(ek.EKError) as e:
         ens.step(1)
     assert e.value.status == ek.EK_ENOCONV and "replica" in str(e.value)
+
+
+def test_harmonic_replicas_match_single_contexts(ek):
+    """Replicas whose chains have the harmonic bonds of Eq. polymermodel (the
+    persistent kernel's all-pairs WCA skips bonded neighbours)."""
+    wls = replicas()[:2]
+    for w in wls:
+        w.polymer.update(bond="harmonic", k_bond=40.0, l_bond=1.0)
+    ens = ek.ensemble_from_workloads(wls, precision=ek.EK_FP32, poisson_tol=1e-8)
+    ens.step(10)
+    for r, wl in enumerate(wls):
+        ctx = ek.from_workload(wl, precision=ek.EK_FP32, poisson_method=ek.EK_POISSON_MG,
+                               poisson_tol=1e-8)
+        ctx.step(10)
+        fluid = wl.solid == 0
+        for s in range(3):
+            n_e, _ = ens.moments(r, s)
+            n_c, _ = ctx.moments(s)
+            assert np.max(np.abs(n_e - n_c)[fluid] / n_c[fluid]) < 1e-6, (r, s)
+        R_e, _ = ens.beads(r)
+        R_c, _ = ctx.beads(wl.beads_R.shape[0])
+        assert np.abs(R_e - R_c).max() < 1e-6, r

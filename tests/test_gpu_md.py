@@ -168,3 +168,33 @@ def test_pair_lists_rebuilt_within_a_step(ek):
     print(moved, err)
     assert moved > 0.3            # more than half the skin (0.6): lists were rebuilt
     assert max(err.values()) < 1e-8, err
+
+
+@pytest.mark.parametrize("n_beads,steps", [(8, 20), (80, 8)])
+def test_harmonic_chain_fp64_matches_oracle(ek, n_beads, steps):
+    """The bonded term of Eq. polymermodel (harmonic bonds of rest length 1)
+    with the WCA only between beads more than one apart, on the LDS node
+    table with pair lists (8 beads) and on the global one (80 beads)."""
+    if n_beads == 8:
+        wl = pore_with_chain(seed=34)
+    else:
+        wl = workloads.pore_system((64, 40, 40), 8, 5, 0.01, 0.01, -0.01, n_beads, 41,
+                                   bead_q=workloads.STABLE_BEAD_CHARGE, steps=10)
+    wl.polymer.update(bond="harmonic", k_bond=40.0, l_bond=1.0)
+    ctx = ek.from_workload(wl, precision=ek.EK_FP64, poisson_tol=1e-10, poisson_check_every=1)
+    sim = oracle_sim(wl, 1e-10)
+    ctx.step(steps)
+    sim.run(steps)
+    err = errors(ctx, sim, wl)
+    print(n_beads, err)
+    assert max(err.values()) < 1e-8, err
+    assert np.abs(sim.V).max() > 1e-4
+
+
+def test_harmonic_bond_parameters_are_checked(ek):
+    wl = pore_with_chain()
+    ctx = ek.from_workload(wl, precision=ek.EK_FP32)
+    for kw in (dict(bond=2), dict(bond="harmonic", k_bond=1.0, l_bond=0.0),
+               dict(bond="harmonic", k_bond=-1.0, l_bond=1.0)):
+        with pytest.raises(ek.EKError):
+            ctx.set_polymer(wl.beads_R, wl.beads_V, wl.polymer["q"], **kw)

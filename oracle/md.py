@@ -28,7 +28,14 @@ Readings taken (listed with the others in the design notes):
     more than one apart along the chain (|i - j| > 1); the same WCA between
     a bead and the centres of boundary solid sites,
     and the electric force q_i E(R_i) with E = -grad psi + E_ext (the text's
-    "+ q_i grad psi" is read as the usual -q_i grad psi);
+    "+ q_i grad psi" is read as the usual -q_i grad psi), interpolated once
+    per lattice step at the position R_i(t) where the bead's charge was
+    deposited for that step's Poisson solve (the paper solves Eq. poisson
+    once per lattice step for the forces on the fluid and on the molecule,
+    Sec. II.C, then subcycles the molecule): deposit and interpolation then
+    use the same weights, so the electrostatic forces on ions, walls and
+    beads sum to zero and a bead never feels its own deposited charge, which
+    sampling the frozen field along the substeps would make it do;
   * integrator: n_sub substeps of h = 1 / n_sub per lattice step,
     V += h (F + sum_a phi^a) / M, then R += h V (semi-implicit Euler);
     thermal noise off (parity runs).
@@ -216,6 +223,9 @@ def md_substeps(R, V, n, j, E, fluid, walls, poly):
     K = np.zeros((S, 3) + shape)
     R = np.array(R, dtype=np.float64, copy=True)
     V = np.array(V, dtype=np.float64, copy=True)
+    # electric force with the plain weights at the positions of the deposit
+    idx0, w0 = trilinear(R, shape)
+    F_el = q[:, None] * (w0[None] * gather(E, idx0)).sum(axis=-1).T           # [N, 3]
     for _ in range(poly["n_sub"]):
         idx, w = trilinear(R, shape)
         fl = gather(fluid, idx).astype(np.float64)
@@ -231,7 +241,6 @@ def md_substeps(R, V, n, j, E, fluid, walls, poly):
         u_b = (wt[None, None] * jc / nsafe[:, None]).sum(axis=-1)        # [S, 3, N]
         ntc = np.where(fl > 0, gather(ntot, idx), 1.0)
         x_b = (wt[None] * nc / ntc[None]).sum(axis=-1)                    # [S, N]
-        E_b = (w[None] * gather(E, idx)).sum(axis=-1)                     # [3, N]
 
         harmonic = poly.get("bond", "fene") == "harmonic"
         if harmonic:
@@ -240,7 +249,7 @@ def md_substeps(R, V, n, j, E, fluid, walls, poly):
             F = fene_forces(R, box, poly["k_fene"], poly["R0"])
         F += wca_pair_forces(R, box, poly["eps"], poly["sigma"], skip_bonded=harmonic)
         F += wall_forces(R, walls, box, poly["eps"], poly["sigma"])
-        F += q[:, None] * E_b.T
+        F += F_el
 
         phi = gamma * x_b[:, :, None] * (np.transpose(u_b, (0, 2, 1)) - V[None])   # [S, N, 3]
         V = V + h * (F + phi.sum(axis=0)) / M

@@ -401,6 +401,11 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
   double mo_c[CACHE ? CPL : 1][MOM];
   double e_c[CACHE_E ? CPL : 1][3];
   unsigned long long wall_bits = 0;
+  // this lane's share of q E(R(t)): the field is interpolated once, with the
+  // plain weights at the position where the bead's charge was deposited for
+  // this step's solve (the electrostatic forces on ions, walls and beads then
+  // cancel exactly, and the bead never feels its own deposited charge)
+  double qe[3] = {0.0, 0.0, 0.0};
   const double rl = 1.122462048309373 * mp.sigma + NB_SKIN;      // list radius
   const double rl2 = rl * rl, half_skin2 = 0.25 * NB_SKIN * NB_SKIN;
   for (int sub = 0; sub < mp.n_sub; ++sub) {
@@ -518,20 +523,21 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
       const double iws = 1.0 / wsum;
       // this lane's corners: velocities from the node momentum (populations of
       // time t plus the friction impulse of earlier substeps), composition,
-      // electric field with the plain weights
-      double acc[15];
+      // and on the first substep the electric field with the plain weights
+      double acc[12];
 #pragma unroll
-      for (int c = 0; c < 15; ++c) acc[c] = 0.0;
+      for (int c = 0; c < 12; ++c) acc[c] = 0.0;
 #pragma unroll
       for (int a = 0; a < CPL; ++a) {
         const int k8 = lane * CPL + a;
         const int ox = k8 & 1, oy = (k8 >> 1) & 1, oz = (k8 >> 2) & 1;
         const double w = (ox ? dx : 1.0 - dx) * (oy ? dy : 1.0 - dy) * (oz ? dz : 1.0 - dz);
         wt[a] = w * wfl[a] * iws;
-        const double* e = CACHE_E ? e_c[CACHE_E ? a : 0] : ef + (size_t)bidx[a] * 3;
-        acc[12] += w * e[0];
-        acc[13] += w * e[1];
-        acc[14] += w * e[2];
+        if (sub == 0) {
+          const double* e = CACHE_E ? e_c[CACHE_E ? a : 0] : ef + (size_t)bidx[a] * 3;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) qe[c] += q * w * e[c];
+        }
         if (wt[a] != 0.0) {
           const double* mo = CACHE ? mo_c[CACHE ? a : 0] : mom + (size_t)bidx[a] * MOM;
 #pragma unroll
@@ -670,7 +676,7 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
       // combine the lanes of this bead (the field enters only as q E, so each
       // lane adds its corners' share to its force first)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) F[c] += q * acc[12 + c];
+      for (int c = 0; c < 3; ++c) F[c] += qe[c];
 #pragma unroll
       for (int c = 0; c < 12; ++c) acc[c] = group_sum<TPB>(acc[c]);
 #pragma unroll

@@ -6,7 +6,7 @@ geometrically, and the fluid + bead momentum is conserved."""
 import numpy as np
 import pytest
 
-from oracle import md, lb, step
+from oracle import md, lb, poisson, step
 from paper_1710_09421_amd import workloads
 
 RNG = np.random.default_rng(2)
@@ -222,3 +222,109 @@ def test_free_harmonic_dimer_oscillates_at_sqrt_2k_over_m():
         assert sep == pytest.approx(l + y, abs=1e-10), t
         assert sep == pytest.approx(l + a * np.cos(w * t), abs=0.01 * a), t
     assert np.allclose(R[:, 1:], [[4.0, 4.0], [4.0, 4.0]]) and np.abs(K).max() == 0.0
+
+
+def _field_probe_polymer(q):
+    """Beads that feel only the electric force over one substep of unit
+    length: no bonds (k = 0 with a far maximum extension), no WCA (eps = 0),
+    no friction, unit mass, so that V(after) - V(before) = q E(R)."""
+    return dict(M=1.0, q=np.asarray(q, dtype=np.float64), k_fene=0.0, R0=1e3, eps=0.0,
+                sigma=1.0, gamma=0.0, n_sub=1)
+
+
+def test_electrostatic_forces_balance_with_charged_beads_beside_a_wall():
+    """Newton's third law of the lattice electrostatics (Sec. II.A, Eq.
+    poisson with the central-difference field): the forces charge x field on
+    the ions, the fixed wall charges and the beads sum to zero, because the
+    beads' charge is deposited with the same plain trilinear weights that
+    interpolate the field at the beads and sum_r rho_e grad_h psi = 0 for the
+    periodic 7-point problem.  The beads sit beside the charged slab with
+    solid corners, where interpolating the field with the weights
+    renormalised over fluid corners (those of the fluid velocity) would give
+    another force; the bead force is q E, not -q E."""
+    shape = (12, 8, 10)
+    solid = np.zeros(shape, dtype=bool)
+    solid[4:7] = True
+    rng = np.random.default_rng(21)
+    walls = workloads.boundary_sites(solid.astype(np.uint8))
+    wall_q = np.where(walls, -0.02, 0.0)
+    fluid = ~solid
+    n0 = np.stack([np.where(fluid, 1.0, 0.0),
+                   np.where(fluid, 0.01 * (1 + 0.2 * rng.uniform(-1, 1, shape)), 0.0),
+                   np.where(fluid, 0.01 * (1 + 0.2 * rng.uniform(-1, 1, shape)), 0.0)])
+    # corners at z = 6 (solid) and 7, z = 3 and 4 (solid), one bead in the bulk
+    R = np.array([[2.3, 3.6, 6.4], [6.7, 1.2, 3.25], [4.5, 5.5, 9.1]])
+    q = np.array([-0.7, 0.4, -1.1])
+    poly = _field_probe_polymer(q)
+    sim = step.Simulation(step.Params(poisson_tol=1e-13), solid, wall_q, n0,
+                          beads=(R, np.zeros_like(R), poly))
+    n, j = lb.moments(sim.f)
+    psi = sim.solve_potential(sim.charge_density(n))
+    E = poisson.electric_field(psi, (0.0, 0.0, 0.0))
+    z = np.asarray(sim.p.valence)
+    F_ions = np.einsum("s,szyx,kzyx->k", z, n, E)
+    F_wall = np.einsum("zyx,kzyx->k", wall_q, E)
+    R1, V1, K = md.md_substeps(R, np.zeros_like(R), n, j, E, fluid, sim.walls, poly)
+    F_beads = V1                                          # M = 1, one substep of h = 1
+    assert not np.abs(K).any()                            # no friction: nothing to the fluid
+    scale = np.abs(F_ions).max() + np.abs(F_wall).max() + np.abs(F_beads).max()
+    assert np.abs(F_beads).max() > 1e-2 * scale           # the beads carry a real share
+    assert np.allclose(F_ions + F_wall + F_beads.sum(axis=0), 0.0, atol=1e-10 * scale)
+    # the configuration tells the plain weights from renormalised ones
+    idx, w = md.trilinear(R, shape)
+    fl = md.gather(fluid, idx).astype(np.float64)
+    assert np.all(fl[:2].sum(axis=1) < 8) and fl[2].sum() == 8
+    wt = w * fl / (w * fl).sum(axis=1, keepdims=True)
+    E_renorm = (wt[None] * md.gather(E, idx)).sum(axis=-1).T
+    assert np.abs(q[:, None] * E_renorm - F_beads).max() > 1e-4 * scale
+
+
+def test_fluid_plus_charged_bead_momentum_is_conserved():
+    """Periodic box, no walls, no applied field, charged beads among charged
+    ions, 40 substeps per step: the electrostatic forces on ions and beads
+    cancel (same identity as above; the beads feel the field where their
+    charge was deposited), the friction is exchanged exactly, so fluid + bead
+    momentum stays at its initial value while the beads are pushed around by
+    the field."""
+    shape = (8, 8, 12)
+    rng = np.random.default_rng(15)
+    n0 = np.stack([np.ones(shape), 0.01 * (1 + 0.05 * rng.uniform(-1, 1, shape)),
+                   0.01 * (1 + 0.05 * rng.uniform(-1, 1, shape))])
+    R = chain(6, seed=4)
+    V = rng.normal(scale=0.02, size=R.shape)
+    poly = step.polymer_params(6, q=-0.5, gamma=20.0, n_sub=40)
+    poly["q"] = np.array([-0.5, 0.3, -0.8, -0.2, 0.6, -0.5])
+    sim = step.Simulation(step.Params(poisson_tol=1e-12), np.zeros(shape, dtype=bool),
+                          np.zeros(shape), n0, beads=(R, V, poly))
+
+    def total():
+        return sim.momentum() + poly["M"] * sim.V.sum(axis=0)
+    P0 = total()
+    sim.run(6)
+    assert np.allclose(total(), P0, atol=1e-11)
+    # the beads' charge does move momentum between beads and ions
+    neutral = step.Simulation(step.Params(poisson_tol=1e-12), np.zeros(shape, dtype=bool),
+                              np.zeros(shape), n0,
+                              beads=(R, V, dict(poly, q=np.zeros(6))))
+    neutral.run(6)
+    assert np.abs(sim.V - neutral.V).max() > 1e-4
+
+
+def test_lone_charged_bead_accelerates_along_qE():
+    """One charged bead with no friction in a neutral, uniform electrolyte
+    under an applied field: its own deposited charge exerts no force on it
+    (the periodic lattice Green's function composed with the central
+    difference is antisymmetric), so over one lattice step V changes by
+    exactly q E_ext / M (Sec. II.B, conservative force of the charge)."""
+    shape = (8, 10, 12)
+    E_ext = (0.01, -0.02, 0.03)
+    n0 = np.stack([np.ones(shape), np.full(shape, 0.01), np.full(shape, 0.01)])
+    R = np.array([[4.3, 6.8, 5.55]])
+    q = -0.5
+    M = 2.0
+    poly = dict(_field_probe_polymer([q]), M=M)
+    sim = step.Simulation(step.Params(E_ext=E_ext, poisson_tol=1e-13),
+                          np.zeros(shape, dtype=bool), np.zeros(shape), n0,
+                          beads=(R, np.zeros_like(R), poly))
+    sim.step()
+    assert np.allclose(sim.V[0], q * np.asarray(E_ext) / M, rtol=1e-9, atol=1e-15)

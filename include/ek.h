@@ -210,6 +210,32 @@ ek_status ek_get_crossings(struct ek_ctx* ctx, int32_t* first, int32_t* last, in
 
 ek_status ek_get_stats(struct ek_ctx* ctx, ek_stats* out);
 
+/* Checkpoint and resume (the time loop of Fig. 1 carries the populations,
+ * the potential and the beads from one step to the next; this is not in the
+ * paper).  The state holds the geometry (solid mask, wall charges), the
+ * current populations, the last Poisson solution (and the one before it with
+ * EK_WS_EXTRAP), the chain (parameters, charges, positions, velocities), the
+ * crossing plane and record, and the counters the next steps depend on (step
+ * count, the previous solve's cycle count, which schedules the next solve's
+ * residual tests); a network set with ek_set_model, the launch mode and the
+ * timers are not part of it.  Loading it into a context created with the same
+ * ek_params (lattice size, precision and warm start must match; max_beads at
+ * least the state's chain) and stepping on gives bit for bit the results the
+ * saved context would have given.
+ *
+ * ek_state_bytes: size of the state of the context as it stands (it grows
+ *   with the chain).
+ * ek_save_state: writes the state into host[bytes]; EK_EINVAL if NULL or
+ *   smaller than ek_state_bytes, EK_ESTATE before the geometry and all three
+ *   species are set.  Synchronises the stream.
+ * ek_load_state: replaces the context's state by host[bytes]; EK_EINVAL (the
+ *   context untouched) for a buffer that is not such a state, is truncated,
+ *   fails its checksum or belongs to other parameters; EK_EHIP if a copy
+ *   fails part way (the context then needs a new geometry or state). */
+ek_status ek_state_bytes(struct ek_ctx* ctx, size_t* bytes);
+ek_status ek_save_state(struct ek_ctx* ctx, void* host, size_t bytes);
+ek_status ek_load_state(struct ek_ctx* ctx, const void* host, size_t bytes);
+
 /* Standalone Poisson solve on device buffers: dev_rho[nz*ny*nx] charge
  * density, dev_psi[nz*ny*nx] warm start on entry and solution (mean zero) on
  * return, both float64.  Uses the context's method, tolerance and iteration
@@ -369,6 +395,8 @@ typedef struct {
  * (max_beads <= 64: each chain's node sums live in LDS). */
 ek_status ek_ensemble_workspace_bytes(const ek_params* base, int32_t n_rep, int32_t max_beads,
                                       size_t* bytes);
+/* base->precision must be EK_FP32 (float64 populations are refused with
+ * EK_EINVAL, here and in ek_ensemble_workspace_bytes). */
 ek_status ek_ensemble_create(const ek_params* base, int32_t n_rep, int32_t max_beads,
                              void* dev_ws, size_t ws_bytes, void* hip_stream, ek_ensemble** out);
 void ek_ensemble_destroy(ek_ensemble* ens);

@@ -25,6 +25,13 @@ thread_local std::string g_create_error;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+}  // namespace
+
+// Message of the last failing call that has no context (ek_last_error(NULL)).
+void ek::set_thread_error(const std::string& msg) { g_create_error = msg; }
+
+namespace {
+
 ek_status check_params(const ek_params* p, std::string& why) {
   if (!p) { why = "params is NULL"; return EK_EINVAL; }
   if (p->nx < 2 || p->ny < 2 || p->nz < 2 || (p->nx & 1) || (p->ny & 1) || (p->nz & 1)) {

@@ -70,6 +70,9 @@ struct LBParams {
 
 struct BeadTableView;      // md_table.h
 
+// Sets the message ek_last_error(NULL) returns on the calling thread.
+void set_thread_error(const std::string& msg);
+
 // Link word of every site from the host solid mask; returns the fluid count.
 long long build_link_words(const uint8_t* solid, const double* wall_q, const Dims& d,
                            std::vector<uint32_t>& m);

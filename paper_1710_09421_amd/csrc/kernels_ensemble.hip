@@ -497,6 +497,9 @@ ek_status check(const ek_params* p, int n_rep, int max_beads, std::string& why) 
   if (ek_workspace_bytes(p, 0, &dummy) != EK_OK) { why = ek_last_error(nullptr); return EK_EINVAL; }
   if (n_rep < 1 || n_rep > 4096) { why = "n_rep must be in [1, 4096]"; return EK_EINVAL; }
   if (max_beads < 0 || max_beads > ENS_MAX_BEADS) { why = "max_beads must be in [0, 64]"; return EK_EINVAL; }
+  // float64 populations are switched off in the persistent kernel: that path
+  // has no oracle parity on record since its team rewrites
+  if (p->precision != EK_FP32) { why = "the ensemble stores float32 populations only (EK_FP32)"; return EK_EINVAL; }
   return EK_OK;
 }
 

@@ -128,6 +128,10 @@ void ek::launch_table_init(int* keys, long long* vals, hipStream_t s) {
   hipLaunchKernelGGL(k_table_init, dim3(HASH_SLOTS / 256), dim3(256), 0, s, keys, vals, HASH_SLOTS);
 }
 
+BeadState ek::bead_state_view(char* mem, int max_beads) {
+  return carve(mem, max_beads < 1 ? 1 : max_beads);
+}
+
 const int* ek_ctx::bead_origin() const {
   return carve(bead_mem, max_beads < 1 ? 1 : max_beads).origin;
 }

@@ -32,6 +32,9 @@ struct BeadState {
   int* cross = nullptr;  // [maxb][3] plane crossings: first step, last step, net count
 };
 
+// Views of the bead state carved from a context's bead memory (host side).
+BeadState bead_state_view(char* mem, int max_beads);
+
 __device__ inline int wrap(int i, int n) {
   i %= n;
   return i < 0 ? i + n : i;

@@ -95,6 +95,9 @@ def _load():
         "ek_set_crossing_plane": (c_int32, [c_void_p, ctypes.c_double]),
         "ek_get_crossings": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
         "ek_get_stats": (c_int32, [c_void_p, P(ek_stats)]),
+        "ek_state_bytes": (c_int32, [c_void_p, P(c_size_t)]),
+        "ek_save_state": (c_int32, [c_void_p, c_void_p, c_size_t]),
+        "ek_load_state": (c_int32, [c_void_p, c_void_p, c_size_t]),
         "ek_poisson_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, P(ek_poisson_report)]),
         "ek_poisson_sor_iterations": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32]),
         "ek_set_timing": (c_int32, [c_void_p, c_int32]),
@@ -283,6 +286,21 @@ class Context:
                     poisson_iters=s.poisson_iters, poisson_residual=s.poisson_residual,
                     poisson_residual0=s.poisson_residual0, fallback=s.fallback,
                     consulted=s.consulted)
+
+    def state_bytes(self):
+        nbytes = c_size_t()
+        self._check(self._lib.ek_state_bytes(self._h, byref(nbytes)), self._h)
+        return nbytes.value
+
+    def save_state(self):
+        """The context's state (ek_save_state) as a numpy uint8 array."""
+        buf = np.empty(self.state_bytes(), dtype=np.uint8)
+        self._check(self._lib.ek_save_state(self._h, _ptr(buf), buf.size), self._h)
+        return buf
+
+    def load_state(self, buf):
+        a = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(self._lib.ek_load_state(self._h, _ptr(a), a.size), self._h)
 
     def set_timing(self, enable=True):
         self._check(self._lib.ek_set_timing(self._h, 1 if enable else 0), self._h)

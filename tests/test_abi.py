@@ -94,3 +94,18 @@ def test_unet_workspace_bytes(ek):
     assert tr.value > inf.value > 16 * 8 * 8 * 3 * 32
     assert lib.ek_unet_workspace_bytes(18, 8, 8, 0, ctypes.byref(inf)) == ek.EK_EINVAL
     assert lib.ek_unet_workspace_bytes(16, 8, 0, 0, ctypes.byref(inf)) == ek.EK_EINVAL
+
+
+def test_ensemble_refuses_float64_populations(ek):
+    """The persistent ensemble kernel runs float32 populations only; float64
+    is refused before any device memory is touched."""
+    lib = ek.lib()
+    nbytes = ctypes.c_size_t()
+    p = ek.make_params((16, 16, 16), precision=ek.EK_FP32, poisson_method=ek.EK_POISSON_MG)
+    assert lib.ek_ensemble_workspace_bytes(ctypes.byref(p), 2, 8, ctypes.byref(nbytes)) == ek.EK_OK
+    p64 = ek.make_params((16, 16, 16), precision=ek.EK_FP64, poisson_method=ek.EK_POISSON_MG)
+    assert lib.ek_ensemble_workspace_bytes(ctypes.byref(p64), 2, 8, ctypes.byref(nbytes)) == ek.EK_EINVAL
+    assert b"float32" in lib.ek_ensemble_last_error(None)
+    h = ctypes.c_void_p()
+    assert lib.ek_ensemble_create(ctypes.byref(p64), 2, 8, None, 0, None, ctypes.byref(h)) == ek.EK_EINVAL
+    assert not h.value

@@ -70,7 +70,8 @@ def test_replicas_match_oracle_fp32(ek, threads):
 
 
 @pytest.mark.skip(reason="faulted the GPU once with a since-removed buffer-resource variant of the "
-                         "lattice body; kept off the GPU until that fault's cause is shown")
+                         "lattice body whose cause was never shown; the ensemble now refuses float64 "
+                         "populations (EK_EINVAL), so this case stays off the GPU")
 def test_replica_fp64_matches_oracle(ek):
     wls = replicas()[:2]
     ens = ek.ensemble_from_workloads(wls, precision=ek.EK_FP64, poisson_tol=1e-10)

@@ -36,7 +36,7 @@ struct StateHeader {
   uint32_t header_bytes;
   int32_t nx, ny, nz, precision, warm_start, n_beads;
   int64_t step_count;
-  int32_t last_iters, solo_iters, psi_hist, have_solve;
+  int32_t last_iters, solo_iters, psi_hist, reserved0;
   double last_res, last_res0;
   double nref[3], mass[3], mom[3];
   int32_t cross_on, pad0;
@@ -139,7 +139,6 @@ ek_status ek_save_state(ek_ctx* ctx, void* host, size_t bytes) {
   h.last_iters = ctx->last_iters;
   h.solo_iters = ctx->solo_iters;
   h.psi_hist = ctx->psi_hist;
-  h.have_solve = ctx->have_solve ? 1 : 0;
   h.last_res = ctx->last_res;
   h.last_res0 = ctx->last_res0;
   for (int k = 0; k < 3; ++k) {

@@ -18,6 +18,8 @@ d3q19    lattice velocities and weights (Sec. II.C)
 lb       moments, equilibrium, forcing, drag, collision, streaming
 poisson  7-point Laplacian, residual, red-black SOR + Chebyshev schedule
 md       trilinear kernels, FENE/WCA/wall forces, friction-coupled substeps
+noise    Philox4x32-10 random numbers, the D3Q19 mode basis, the stochastic
+         term Delta of the populations and the beads' Langevin noise
 step     one full time step in the order of the paper's algorithm (Fig. 1)
 unet     float64 reference of the 3-D convolution network used as a warm start
 """

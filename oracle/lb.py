@@ -116,14 +116,15 @@ def species_velocities(n, j, G, omega_drag):
     return u, phi
 
 
-def collide(f, G, tau, omega_drag, fluid):
+def collide(f, G, tau, omega_drag, fluid, noise=None):
     """BGK collision with Guo forcing at the fluid sites (Eqs. kernelf2, kernelg).
 
     f: [S, 19, Z, Y, X] pre-collision populations; G: [S, 3, Z, Y, X] force
     per particle excluding the drag; tau: [S] relaxation times
-    (omega_visc = 1 / tau); fluid: bool [Z, Y, X].
-    Returns f* = f - omega (f - f_eq(n, u)) + (1 - omega/2) S(n, u, Phi) at
-    fluid sites and zero at solid sites, plus (u, Phi).
+    (omega_visc = 1 / tau); fluid: bool [Z, Y, X]; noise: optional
+    [S, 19, Z, Y, X] stochastic term Delta of Eq. kernelf2.
+    Returns f* = f - omega (f - f_eq(n, u)) + (1 - omega/2) S(n, u, Phi)
+    (+ Delta) at fluid sites and zero at solid sites, plus (u, Phi).
     """
     S = f.shape[0]
     n, j = moments(f)
@@ -136,6 +137,8 @@ def collide(f, G, tau, omega_drag, fluid):
         feq = equilibrium(nsafe[s], u[s])
         src = forcing(nsafe[s], u[s], phi[s])
         out[s] = f[s] - omega * (f[s] - feq) + (1.0 - 0.5 * omega) * src
+        if noise is not None:
+            out[s] += noise[s]
     out *= fluid[None, None]
     return out, u, phi
 

@@ -38,13 +38,18 @@ Readings taken (listed with the others in the design notes):
     sampling the frozen field along the substeps would make it do;
   * integrator: n_sub substeps of h = 1 / n_sub per lattice step,
     V += h (F + sum_a phi^a) / M, then R += h V (semi-implicit Euler);
-    thermal noise off (parity runs).
+  * thermal noise (optional): xi ~ N(0, 2 gamma k_B T / h) per component and
+    substep from the counter-based generator of noise.py, added to the
+    friction of each species in proportion to its number fraction,
+    phi^a += x^a xi, so that the bead receives the whole xi and the fluid
+    the opposite impulse.
 Positions are unwrapped; lattice indices and pair separations use the periodic
 box (minimum image).
 """
 import numpy as np
 
 from . import d3q19 as L
+from . import noise
 
 WCA_CUT = 2.0 ** (1.0 / 6.0)
 
@@ -199,7 +204,7 @@ def deposit_charge(R, q, shape):
     return rho
 
 
-def md_substeps(R, V, n, j, E, fluid, walls, poly):
+def md_substeps(R, V, n, j, E, fluid, walls, poly, thermal=None):
     """Advance the beads over one lattice step and spread the friction.
 
     R, V: [N, 3]; n: [S, Z, Y, X] and j: [S, 3, Z, Y, X] from the populations
@@ -207,6 +212,9 @@ def md_substeps(R, V, n, j, E, fluid, walls, poly):
     [Z, Y, X]; walls: [M, 3] boundary site centres; poly: dict with keys
     M, q [N], k_fene, R0, eps, sigma, gamma, n_sub (and optionally bond =
     "harmonic" with k_bond, l_bond).
+
+    thermal: optional (seed, step, kT) switching on the bead noise of this
+    lattice step.
 
     Returns (R, V, K) with K [S, 3, Z, Y, X] the force density on each species
     accumulated over the substeps (the fluid's share of the friction).
@@ -226,7 +234,7 @@ def md_substeps(R, V, n, j, E, fluid, walls, poly):
     # electric force with the plain weights at the positions of the deposit
     idx0, w0 = trilinear(R, shape)
     F_el = q[:, None] * (w0[None] * gather(E, idx0)).sum(axis=-1).T           # [N, 3]
-    for _ in range(poly["n_sub"]):
+    for sub in range(poly["n_sub"]):
         idx, w = trilinear(R, shape)
         fl = gather(fluid, idx).astype(np.float64)
         wsum = (w * fl).sum(axis=1)
@@ -252,6 +260,10 @@ def md_substeps(R, V, n, j, E, fluid, walls, poly):
         F += F_el
 
         phi = gamma * x_b[:, :, None] * (np.transpose(u_b, (0, 2, 1)) - V[None])   # [S, N, 3]
+        if thermal is not None:
+            seed, tstep, kT = thermal
+            xi = np.sqrt(2.0 * gamma * kT / h) * noise.bead_normals(R.shape[0], tstep, sub, seed)
+            phi = phi + x_b[:, :, None] * xi[None]
         V = V + h * (F + phi.sum(axis=0)) / M
         R = R + h * V
         for s in range(S):

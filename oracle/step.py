@@ -3,7 +3,8 @@ algorithm sketched in Fig. 1 and described at the end of Sec. II.C:
 
   moments -> charge density -> Poisson -> forces -> interpolate the fluid to
   the beads -> advance the beads (n_sub MD substeps) -> spread the bead forces
-  back -> collide -> propagate.
+  back -> collide (with the stochastic term when fluctuations are on) ->
+  propagate.
 
 State kept between steps: pre-collision populations f(t) [3, 19, Z, Y, X],
 the potential of the last solve (warm start of the next one), bead positions
@@ -17,7 +18,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import lb, md, poisson
+from . import lb, md, noise, poisson
 from . import d3q19 as L
 
 
@@ -33,6 +34,8 @@ class Params:
     poisson_tol: float = 1e-10
     poisson_max_iter: int = 100000
     rho_j: float = None                          # Jacobi radius for the Chebyshev schedule
+    fluctuations: bool = False                   # thermal noise on populations and beads
+    seed: int = 0                                # key of the counter-based generator
 
     @property
     def eps(self):
@@ -100,13 +103,20 @@ class Simulation:
         z = np.asarray(self.p.valence, dtype=np.float64)
         G = z[:, None, None, None, None] * E[None] + \
             np.asarray(self.p.F_ext, dtype=np.float64)[:, :, None, None, None]
+        thermal = (self.p.seed, self.t, self.p.kT) if self.p.fluctuations else None
         if self.R is not None:
             self.R, self.V, K = md.md_substeps(self.R, self.V, n, j, E, self.fluid,
-                                               self.walls, self.poly)
+                                               self.walls, self.poly, thermal=thermal)
             nsafe = np.where(self.fluid[None], n, 1.0)
             G = G + K / nsafe[:, None]
-        fstar, _, _ = lb.collide(self.f, G, np.asarray(self.p.tau, dtype=np.float64),
-                                 np.asarray(self.p.omega_drag, dtype=np.float64), self.fluid)
+        tau = np.asarray(self.p.tau, dtype=np.float64)
+        delta = None
+        if self.p.fluctuations:
+            delta = np.stack([noise.lattice_noise(n[s], 1.0 / tau[s], self.p.kT, s, self.t,
+                                                  self.p.seed) for s in range(S)])
+        fstar, _, _ = lb.collide(self.f, G, tau,
+                                 np.asarray(self.p.omega_drag, dtype=np.float64), self.fluid,
+                                 noise=delta)
         self.f = lb.stream(fstar, self.solid)
         self.t += 1
 

@@ -95,9 +95,45 @@ typedef struct {
                                   (ek_set_model; sizes multiples of 4) or
                                   EK_WS_EXTRAP (one more float64 field in
                                   the workspace)                               */
-  uint64_t seed;               /* thermal noise seed (noise is not built yet)  */
-  int32_t fluctuations;        /* must be 0                                    */
+  uint64_t seed;               /* key of the thermal noise (64 bits)           */
+  int32_t fluctuations;        /* 0: none; 1: thermal fluctuations (Sec. II.A
+                                  and II.C): the stochastic term Delta of
+                                  Eq. kernelf2 on the populations and the
+                                  Langevin noise on the beads (Sec. II.B), at
+                                  temperature kT, from the counter-based
+                                  generator described below                   */
 } ek_params;
+
+/* Thermal fluctuations (ek_params.fluctuations = 1).
+ * Populations (Sec. II.C): after the collision every fluid site gets, per
+ * species a, Delta_p = sqrt(m n^a omega (2 - omega)) w_p sum_{k=4}^{18}
+ * chi_kp N_k, where n^a is the site's density before the collision (taken
+ * as 0 if negative), omega = 1 / tau^a, m = kT / v_T^2 the thermal mass
+ * (v_T^2 = 1/3), and chi_k the D3Q19 mode vectors orthonormal under
+ * sum_p w_p chi_kp chi_lp: the polynomials 1; cx, cy, cz; c^2 - 1;
+ * 3 cx^2 - c^2; cy^2 - cz^2; cx cy; cy cz; cx cz; (3 c^2 - 5) cx, cy, cz;
+ * (cy^2 - cz^2) cx; (cz^2 - cx^2) cy; (cx^2 - cy^2) cz; 3 c^4 - 6 c^2 + 1;
+ * (2 c^2 - 3)(3 cx^2 - c^2); (2 c^2 - 3)(cy^2 - cz^2), each divided by its
+ * norm.  Delta conserves mass and momentum.
+ * Beads (Sec. II.B): each substep h = 1 / n_sub adds xi ~ N(0, 2 gamma kT / h)
+ * per component to the friction, shared among the species by their number
+ * fractions at the bead (the fluid gets the opposite impulse).
+ * Random numbers: Philox4x32-10 (Salmon et al., SC 2011) with key (seed mod
+ * 2^32, seed div 2^32); word x -> uniform (x + 1/2) / 2^32; words (0, 1) and
+ * (2, 3) -> two normals each by Box-Muller, sqrt(-2 ln u1) (cos 2 pi u2,
+ * sin 2 pi u2).  N_4..N_18 of species a at site r ((z ny + y) nx + x) in the
+ * step that follows t completed steps: the first 15 normals of the counters
+ * (r, t, 4 a + j, 0), j = 0..3.  Bead i, step t, substep s: normals 0..2 of
+ * counter (i, t, s, 1).  The ensemble runs without fluctuations.
+ *
+ * ek_philox: the library's device generator for given counters, for callers
+ * that reproduce or check the noise: host counters[4 n] (c0..c3 per draw),
+ * host words[4 n] (may be NULL) receives the Philox words and host
+ * normals[4 n] (may be NULL) the four float64 normals of each draw.  Uses a
+ * temporary device buffer; runs on hip_stream and synchronises it.  EK_EINVAL
+ * for n < 0, n > 2^24 or NULL counters. */
+ek_status ek_philox(const uint32_t* counters, int32_t n, uint64_t seed, uint32_t* words,
+                    double* normals, void* hip_stream);
 
 /* Bead-spring chain (Sec. II.B): bonds between chain neighbours, repulsive
  * WCA between bead pairs and between beads and boundary solid sites,

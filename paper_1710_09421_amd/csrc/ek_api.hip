@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "ek_context.h"
+#include "philox.h"
 
 using namespace ek;
 
@@ -58,7 +59,7 @@ ek_status check_params(const ek_params* p, std::string& why) {
     why = "the learned warm start needs nx, ny, nz divisible by 4 (two 2x2x2 poolings)";
     return EK_EINVAL;
   }
-  if (p->fluctuations != 0) { why = "thermal fluctuations are not available"; return EK_EINVAL; }
+  if (p->fluctuations != 0 && p->fluctuations != 1) { why = "fluctuations must be 0 or 1"; return EK_EINVAL; }
   return EK_OK;
 }
 
@@ -131,6 +132,28 @@ LBParams ek_ctx::lb_params() const {
 }
 
 double ek_ctx::inv_eps() const { return 4.0 * M_PI * p.bjerrum * p.kT; }
+
+// Stochastic term of the step that starts after `step` completed steps:
+// key from the seed, amplitude m omega (2 - omega) per species with the
+// thermal mass m = k_B T / v_T^2 (v_T^2 = 1/3 on D3Q19), and the norms of
+// the mode polynomials under the lattice weights.
+NoiseParams ek_ctx::noise_params(long long step) const {
+  NoiseParams np{};
+  np.key0 = uint32_t(p.seed & 0xFFFFFFFFull);
+  np.key1 = uint32_t(p.seed >> 32);
+  np.step = uint32_t(step);
+  const double m = p.kT * 3.0;
+  for (int s = 0; s < 3; ++s) {
+    const double om = 1.0 / p.tau[s];
+    np.amp2[s] = m * om * (2.0 - om);
+  }
+  for (int k = 4; k < Q; ++k) {
+    double n2 = 0.0;
+    for (int q = 0; q < Q; ++q) n2 += weight(q) * double(mode_poly(k, q)) * double(mode_poly(k, q));
+    np.inv_norm[k - 4] = 1.0 / std::sqrt(n2);
+  }
+  return np;
+}
 
 double ek_ctx::jacobi_radius() const {
   if (p.rho_jacobi > 0.0) return p.rho_jacobi;
@@ -283,6 +306,8 @@ ek_status ek_ctx::step_impl(int n_steps) {
   }
   for (int t = 0; t < n_steps; ++t) {
     const BeadTableView bt = bead_view();
+    const NoiseParams noise = noise_params(step_count);
+    const NoiseParams* npp = p.fluctuations ? &noise : nullptr;
     record(t, 0);
     // charge density of ions, walls and beads at time t
     if (n_beads > 0) {
@@ -325,12 +350,13 @@ ek_status ek_ctx::step_impl(int n_steps) {
     }
     launch_lb_step<T>((const T*)fcur(), (T*)fnext(), mask, psi, lp, bt, partials, nb_lb,
                       overlap ? MASK_DEFER : 0u, dims, g, ls,
-                      timing ? events[6 * t + 3] : nullptr, timing ? events[6 * t + 4] : nullptr);
+                      timing ? events[6 * t + 3] : nullptr, timing ? events[6 * t + 4] : nullptr,
+                      npp);
     if (overlap) {
       EK_HIP(hipEventRecord(side_join, side_stream));
       EK_HIP(hipStreamWaitEvent(stream, side_join, 0));
       launch_lb_tail<T>((const T*)fcur(), (T*)fnext(), mask, psi, lp, bt, bead_origin(), n_beads,
-                        partials, nb_bulk, nb_lb, dims, stream);
+                        partials, nb_bulk, nb_lb, dims, stream, npp);
     }
     launch_sum_partials(partials, nb_lb, stats_dev, timing ? 1 : 0, stream);
     cur_is_a = !cur_is_a;

@@ -97,6 +97,7 @@ struct ek_ctx {
   void* fcur();
   void* fnext();
   ek::LBParams lb_params() const;
+  ek::NoiseParams noise_params(long long step) const;
   double inv_eps() const;
   double jacobi_radius() const;
   ek_status read_scalars(ek::PoissonScalars* out);

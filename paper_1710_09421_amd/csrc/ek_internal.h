@@ -69,6 +69,7 @@ struct LBParams {
 };
 
 struct BeadTableView;      // md_table.h
+struct NoiseParams;        // philox.h
 
 // Sets the message ek_last_error(NULL) returns on the calling thread.
 void set_thread_error(const std::string& msg);
@@ -109,17 +110,21 @@ void launch_charge(const T* f, const uint32_t* mask, const double* wall_q, doubl
 // recorded at the kernel's own start and end.
 int lb_step_blocks(const SiteGrid& g, int nz);
 int lb_tail_blocks(int n_beads);
+// With `noise` (not null) the populations get the stochastic term of the
+// thermal fluctuations.
 template <typename T>
 int launch_lb_step(const T* fsrc, T* fdst, const uint32_t* mask, const double* psi,
                    const LBParams& lp, const BeadTableView& bt, double* partials, int nblocks,
                    uint32_t skip, Dims d, const SiteGrid& g, hipStream_t s,
-                   hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+                   hipEvent_t start = nullptr, hipEvent_t stop = nullptr,
+                   const NoiseParams* noise = nullptr);
 // The sites flagged MASK_DEFER in the boxes of n_beads beads (box origins of
 // the step); partials of blocks first_block .. of the same layout.
 template <typename T>
 void launch_lb_tail(const T* fsrc, T* fdst, uint32_t* mask, const double* psi, const LBParams& lp,
                     const BeadTableView& bt, const int* origin, int n_beads, double* partials,
-                    int first_block, int nblocks, Dims d, hipStream_t s);
+                    int first_block, int nblocks, Dims d, hipStream_t s,
+                    const NoiseParams* noise = nullptr);
 template <typename T>
 void launch_moments(const T* f, const uint32_t* mask, int species, double nref, double* n_out,
                     double* u_out, Dims d, hipStream_t s);

@@ -500,6 +500,7 @@ ek_status check(const ek_params* p, int n_rep, int max_beads, std::string& why) 
   // float64 populations are switched off in the persistent kernel: that path
   // has no oracle parity on record since its team rewrites
   if (p->precision != EK_FP32) { why = "the ensemble stores float32 populations only (EK_FP32)"; return EK_EINVAL; }
+  if (p->fluctuations != 0) { why = "the ensemble runs without thermal fluctuations"; return EK_EINVAL; }
   return EK_OK;
 }
 

@@ -82,21 +82,22 @@ __global__ __launch_bounds__(BLOCK) void k_charge(const T* __restrict__ f,
 // momentum of f(t) in float64, and the number of sites updated.  Sites with
 // a `skip` bit are left to k_lb_tail.  Partials: [c * nblocks + block], the
 // blocks of this launch first.
-template <typename T, typename I>
+template <typename T, typename I, bool FLUCT>
 __global__ __launch_bounds__(BLOCK) void k_lb_step(const T* __restrict__ fsrc,
                                                    T* __restrict__ fdst,
                                                    const uint32_t* __restrict__ mask,
                                                    const double* __restrict__ psi, LBParams lp,
                                                    BeadTableView bt,
                                                    double* __restrict__ partials, int nblocks,
-                                                   uint32_t skip, Dims d, int zb) {
+                                                   uint32_t skip, Dims d, int zb, NoiseParams np) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
   if (x < d.nx && y < d.ny)
     for (int k = 0; k < zb; ++k)
-      if (lb_site<T, I>(fsrc, fdst, mask, psi, lp, bt, x, y, blockIdx.z * zb + k, d, acc, skip))
+      if (lb_site<T, I, 7, FLUCT>(fsrc, fdst, mask, psi, lp, bt, x, y, blockIdx.z * zb + k, d, acc,
+                                  skip, &np))
         acc[6] += 1.0;
   block_partials<7>(acc, partials, bid, nblocks);
 }
@@ -107,14 +108,15 @@ __global__ __launch_bounds__(BLOCK) void k_lb_step(const T* __restrict__ fsrc,
 // node in several boxes is updated by the lowest bead whose box holds it
 // (the boxes' origins are fixed for the step), which also clears its flag.
 // Needs every side of the box >= BOX (no box overlaps itself).
-template <typename T, typename I>
+template <typename T, typename I, bool FLUCT>
 __global__ __launch_bounds__(BLOCK) void k_lb_tail(const T* __restrict__ fsrc,
                                                    T* __restrict__ fdst, uint32_t* mask,
                                                    const double* __restrict__ psi, LBParams lp,
                                                    BeadTableView bt,
                                                    const int* __restrict__ origin, int n_beads,
                                                    double* __restrict__ partials,
-                                                   int first_block, int nblocks, Dims d) {
+                                                   int first_block, int nblocks, Dims d,
+                                                   NoiseParams np) {
   // origins of the beads up to this block's last one, staged in LDS for the
   // test against every lower bead
   extern __shared__ int so[];
@@ -134,7 +136,8 @@ __global__ __launch_bounds__(BLOCK) void k_lb_tail(const T* __restrict__ fsrc,
         first = false;
     if (first) {
       const int x = wrap(gx, d.nx), y = wrap(gy, d.ny), z = wrap(gz, d.nz);
-      lb_site<T, I>(fsrc, fdst, mask, psi, lp, bt, x, y, z, d, acc);   // not counted in acc[6]
+      lb_site<T, I, 7, FLUCT>(fsrc, fdst, mask, psi, lp, bt, x, y, z, d, acc, 0u,
+                              &np);   // not counted in acc[6]
       atomicAnd(&mask[((long long)z * d.ny + y) * d.nx + x], ~MASK_DEFER);
     }
   }
@@ -274,31 +277,45 @@ template <typename T>
 int launch_lb_step(const T* fsrc, T* fdst, const uint32_t* mask, const double* psi,
                    const LBParams& lp, const BeadTableView& bt, double* partials, int nblocks,
                    uint32_t skip, Dims d, const SiteGrid& g, hipStream_t s, hipEvent_t start,
-                   hipEvent_t stop) {
+                   hipEvent_t stop, const NoiseParams* noise) {
   const int zb = lb_planes_per_block(g, d.nz);
   const dim3 grid(g.grid.x, g.grid.y, d.nz / zb);
+  const NoiseParams np = noise ? *noise : NoiseParams{};
   // the events (when given) are stamped at the kernel's own start and end
-  if (fits_idx32<T>(d.n))
-    hipExtLaunchKernelGGL((k_lb_step<T, uint32_t>), grid, g.block, 0, s, start, stop, 0, fsrc,
-                          fdst, mask, psi, lp, bt, partials, nblocks, skip, d, zb);
-  else
-    hipExtLaunchKernelGGL((k_lb_step<T, long long>), grid, g.block, 0, s, start, stop, 0, fsrc,
-                          fdst, mask, psi, lp, bt, partials, nblocks, skip, d, zb);
+  auto go = [&](auto kernel) {
+    hipExtLaunchKernelGGL(kernel, grid, g.block, 0, s, start, stop, 0, fsrc, fdst, mask, psi, lp,
+                          bt, partials, nblocks, skip, d, zb, np);
+  };
+  const bool i32 = fits_idx32<T>(d.n);
+  if (noise) {
+    if (i32) go(k_lb_step<T, uint32_t, true>);
+    else go(k_lb_step<T, long long, true>);
+  } else {
+    if (i32) go(k_lb_step<T, uint32_t, false>);
+    else go(k_lb_step<T, long long, false>);
+  }
   return int(grid.x * grid.y * grid.z);
 }
 
 template <typename T>
 void launch_lb_tail(const T* fsrc, T* fdst, uint32_t* mask, const double* psi, const LBParams& lp,
                     const BeadTableView& bt, const int* origin, int n_beads, double* partials,
-                    int first_block, int nblocks, Dims d, hipStream_t s) {
+                    int first_block, int nblocks, Dims d, hipStream_t s, const NoiseParams* noise) {
   const int blocks = lb_tail_blocks(n_beads);
   const size_t lds = (size_t)3 * n_beads * sizeof(int);   // at most 12 KiB (MAX_BEADS = 1024)
-  if (fits_idx32<T>(d.n))
-    hipLaunchKernelGGL((k_lb_tail<T, uint32_t>), dim3(blocks), dim3(BLOCK), lds, s, fsrc, fdst,
-                       mask, psi, lp, bt, origin, n_beads, partials, first_block, nblocks, d);
-  else
-    hipLaunchKernelGGL((k_lb_tail<T, long long>), dim3(blocks), dim3(BLOCK), lds, s, fsrc, fdst,
-                       mask, psi, lp, bt, origin, n_beads, partials, first_block, nblocks, d);
+  const NoiseParams np = noise ? *noise : NoiseParams{};
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(BLOCK), lds, s, fsrc, fdst, mask, psi, lp, bt,
+                       origin, n_beads, partials, first_block, nblocks, d, np);
+  };
+  const bool i32 = fits_idx32<T>(d.n);
+  if (noise) {
+    if (i32) go(k_lb_tail<T, uint32_t, true>);
+    else go(k_lb_tail<T, long long, true>);
+  } else {
+    if (i32) go(k_lb_tail<T, uint32_t, false>);
+    else go(k_lb_tail<T, long long, false>);
+  }
 }
 
 template <typename T>
@@ -329,10 +346,10 @@ void launch_mean_shift(const double* partials, int nblocks, double inv_n, double
   template int launch_lb_step<T>(const T*, T*, const uint32_t*, const double*,               \
                                  const LBParams&, const BeadTableView&, double*, int,        \
                                  uint32_t, Dims, const SiteGrid&, hipStream_t, hipEvent_t,   \
-                                 hipEvent_t);                                                \
+                                 hipEvent_t, const NoiseParams*);                            \
   template void launch_lb_tail<T>(const T*, T*, uint32_t*, const double*, const LBParams&,   \
                                   const BeadTableView&, const int*, int, double*, int, int,  \
-                                  Dims, hipStream_t);                                        \
+                                  Dims, hipStream_t, const NoiseParams*);                    \
   template void launch_moments<T>(const T*, const uint32_t*, int, double, double*, double*,  \
                                   Dims, hipStream_t);
 EK_INST(float)

@@ -188,6 +188,13 @@ ek_status ek_ctx::beads_advance(bool overlap, hipEvent_t chain_end) {
   mp.track = cross_on ? 1 : 0;
   mp.step = (int)(step_count + 1);
   mp.z_plane = cross_plane;
+  if (p.fluctuations) {
+    mp.thermal = 1;
+    mp.key0 = uint32_t(p.seed & 0xFFFFFFFFull);
+    mp.key1 = uint32_t(p.seed >> 32);
+    mp.tstep = uint32_t(step_count);
+    mp.xi_scale = std::sqrt(2.0 * poly.gamma * p.kT * poly.n_sub);   // h = 1 / n_sub
+  }
   // lanes per bead so that a chain fills at most 512 threads (register budget
   // of 256 per thread); chains beyond 512 beads take one lane each
   const int tpb = n_beads <= 64 ? 8 : (n_beads <= 128 ? 4 : (n_beads <= 256 ? 2 : 1));

@@ -14,6 +14,7 @@
 
 #include "ek_internal.h"
 #include "md_table.h"
+#include "philox.h"
 
 namespace ek {
 
@@ -122,14 +123,16 @@ __device__ inline double charge_site(const T* __restrict__ f, const uint32_t* __
 
 // Fused step at one fluid site: pull + bounce-back, moments, field from the
 // potential, closed-form implicit drag, BGK collision with the half-force
-// (Guo) forcing term, aligned store.  Adds the site's species masses and
-// momentum of f(t) to acc[0..5] (float64).  Sites whose link word has one of
-// the `skip` bits are left alone; returns whether the site was updated.
-template <typename T, typename I = long long, int NA>
+// (Guo) forcing term, with FLUCT the stochastic term of the populations
+// (philox.h), aligned store.  Adds the site's species masses and momentum of
+// f(t) to acc[0..5] (float64).  Sites whose link word has one of the `skip`
+// bits are left alone; returns whether the site was updated.
+template <typename T, typename I = long long, int NA, bool FLUCT = false>
 __device__ inline bool lb_site(const T* __restrict__ fsrc, T* __restrict__ fdst,
                                const uint32_t* __restrict__ mask, const double* __restrict__ psi,
                                const LBParams& lp, const BeadTableView& bt, int x, int y, int z,
-                               const Dims& d, double (&acc)[NA], uint32_t skip = 0u) {
+                               const Dims& d, double (&acc)[NA], uint32_t skip = 0u,
+                               const NoiseParams* noise = nullptr) {
   static_assert(NA >= 6, "masses and momentum take six sums");
   const I N = I(d.n);
   const I r = (I(z) * I(d.ny) + I(y)) * I(d.nx) + I(x);
@@ -217,6 +220,12 @@ __device__ inline bool lb_site(const T* __restrict__ fsrc, T* __restrict__ fdst,
       const T pu = ph[0] * u[0] + ph[1] * u[1] + ph[2] * u[2];
       const T ns = n[s];
       const T dn = dns[s];  // kept from the sum: n - nref would lose it in float32
+      T delta[FLUCT ? Q : 1];
+      if constexpr (FLUCT) {
+#pragma unroll
+        for (int p = 0; p < Q; ++p) delta[p] = T(0);
+        add_lattice_noise<T>(delta, *noise, s, uint32_t(r), ns);
+      }
 #pragma unroll
       for (int p = 0; p < Q; ++p) {
         const T cu = T(CX[p]) * u[0] + T(CY[p]) * u[1] + T(CZ[p]) * u[2];
@@ -225,7 +234,8 @@ __device__ inline bool lb_site(const T* __restrict__ fsrc, T* __restrict__ fdst,
         // deviation of the second-order equilibrium (vT2 = 1/3) and forcing
         const T geq = w * (dn + ns * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu));
         const T src = w * ns * (T(3) * cf + T(9) * cu * cf - T(3) * pu);
-        const T gs = g[s][p] - om * (g[s][p] - geq) + half * src;
+        T gs = g[s][p] - om * (g[s][p] - geq) + half * src;
+        if constexpr (FLUCT) gs += delta[FLUCT ? p : 0];
         out.store(p, r, gs);
       }
     }

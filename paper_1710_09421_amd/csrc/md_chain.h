@@ -9,6 +9,7 @@
 
 #include "ek_internal.h"
 #include "md_table.h"
+#include "philox.h"
 
 namespace ek {
 
@@ -96,6 +97,12 @@ struct MDParams {
   // (k_bond, l_bond, Eq. polymermodel) with the WCA only for |i - j| > 1
   int bond = 0;
   double k_bond = 0.0, l_bond = 0.0;
+  // thermal noise (philox.h): xi ~ N(0, xi_scale^2) per component and
+  // substep, xi_scale = sqrt(2 gamma k_B T / h), from the counter
+  // (bead, tstep, substep, 1); tstep = steps completed before this one
+  int thermal = 0;
+  uint32_t key0 = 0, key1 = 0, tstep = 0;
+  double xi_scale = 0.0;
 };
 
 __device__ inline double min_image(double v, double L) { return v - L * rint(v / L); }
@@ -684,13 +691,22 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
       for (int c = 0; c < 12; ++c) acc[c] = group_sum<TPB>(acc[c]);
 #pragma unroll
       for (int c = 0; c < 3; ++c) F[c] = group_sum<TPB>(F[c]);
-      // friction of each species and the substep update
+      // friction of each species (with the thermal noise shared by the
+      // species' number fractions) and the substep update
+      double xi[3] = {0.0, 0.0, 0.0};
+      if (mp.thermal) {
+        const Philox4 w = philox4x32_10(uint32_t(i), mp.tstep, uint32_t(sub), 1u, mp.key0, mp.key1);
+        double z[4];
+        box_muller4<double>(w, z);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xi[c] = mp.xi_scale * z[c];
+      }
       double ftot[3] = {F[0], F[1], F[2]};
 #pragma unroll
       for (int s = 0; s < 3; ++s)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          phi[s][c] = mp.gamma * acc[9 + s] * (acc[3 * s + c] - V[c]);
+          phi[s][c] = mp.gamma * acc[9 + s] * (acc[3 * s + c] - V[c]) + acc[9 + s] * xi[c];
           ftot[c] += phi[s][c];
         }
 #pragma unroll

@@ -95,6 +95,7 @@ def _load():
         "ek_set_crossing_plane": (c_int32, [c_void_p, ctypes.c_double]),
         "ek_get_crossings": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
         "ek_get_stats": (c_int32, [c_void_p, P(ek_stats)]),
+        "ek_philox": (c_int32, [c_void_p, c_int32, ctypes.c_uint64, c_void_p, c_void_p, c_void_p]),
         "ek_state_bytes": (c_int32, [c_void_p, P(c_size_t)]),
         "ek_save_state": (c_int32, [c_void_p, c_void_p, c_size_t]),
         "ek_load_state": (c_int32, [c_void_p, c_void_p, c_size_t]),
@@ -157,11 +158,28 @@ def _ptr(a):
     return a.ctypes.data_as(c_void_p)
 
 
+def philox(counters, seed, stream=None):
+    """ek_philox: the device generator's words and float64 normals for
+    counters [n, 4] (uint32) under the 64-bit seed."""
+    import torch
+    lib_ = lib()
+    c = np.ascontiguousarray(counters, dtype=np.uint32).reshape(-1, 4)
+    words = np.empty_like(c)
+    z = np.empty(c.shape, dtype=np.float64)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    st = lib_.ek_philox(_ptr(c), c.shape[0], int(seed), _ptr(words), _ptr(z),
+                        c_void_p(s.cuda_stream))
+    if st != EK_OK:
+        msg = lib_.ek_last_error(None)
+        raise EKError(st, msg.decode() if msg else "")
+    return words, z
+
+
 def make_params(shape, precision=EK_FP32, valence=(0.0, 1.0, -1.0), tau=(1.0, 1.0, 1.0),
                 omega_drag=(1.0, 1.0, 1.0), kT=1.0 / 3.0, bjerrum=0.7, E_ext=(0.0, 0.0, 0.0),
                 F_ext=None, poisson_method=EK_POISSON_SOR, poisson_tol=1e-8,
                 poisson_max_iter=100000, poisson_check_every=1, rho_jacobi=0.0,
-                warm_start=EK_WS_PREV):
+                warm_start=EK_WS_PREV, fluctuations=0, seed=0):
     nz, ny, nx = shape
     p = ek_params()
     p.nx, p.ny, p.nz = nx, ny, nz
@@ -177,7 +195,7 @@ def make_params(shape, precision=EK_FP32, valence=(0.0, 1.0, -1.0), tau=(1.0, 1.
     p.poisson_method, p.poisson_tol = poisson_method, poisson_tol
     p.poisson_max_iter, p.poisson_check_every = poisson_max_iter, poisson_check_every
     p.rho_jacobi, p.warm_start = rho_jacobi, warm_start
-    p.seed, p.fluctuations = 0, 0
+    p.seed, p.fluctuations = int(seed), int(fluctuations)
     return p
 
 

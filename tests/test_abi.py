@@ -54,8 +54,13 @@ def test_workspace_bytes_validates(ek):
     bad = ek.make_params((32, 32, 32), tau=(0.5, 1.0, 1.0))
     assert lib.ek_workspace_bytes(ctypes.byref(bad), 0, ctypes.byref(nbytes)) == ek.EK_EINVAL
     bad = ek.make_params((32, 32, 32))
-    bad.fluctuations = 1
+    bad.fluctuations = 2
     assert lib.ek_workspace_bytes(ctypes.byref(bad), 0, ctypes.byref(nbytes)) == ek.EK_EINVAL
+    ok = ek.make_params((32, 32, 32), fluctuations=1, seed=2 ** 40 + 7)
+    assert lib.ek_workspace_bytes(ctypes.byref(ok), 0, ctypes.byref(nbytes)) == ek.EK_OK
+    ens = ek.make_params((16, 16, 16), poisson_method=ek.EK_POISSON_MG, fluctuations=1)
+    assert lib.ek_ensemble_workspace_bytes(ctypes.byref(ens), 2, 8, ctypes.byref(nbytes)) == ek.EK_EINVAL
+    assert b"fluctuations" in lib.ek_ensemble_last_error(None)
 
 
 def test_learned_warm_start_needs_sizes_divisible_by_4(ek):
@@ -109,3 +114,10 @@ def test_ensemble_refuses_float64_populations(ek):
     h = ctypes.c_void_p()
     assert lib.ek_ensemble_create(ctypes.byref(p64), 2, 8, None, 0, None, ctypes.byref(h)) == ek.EK_EINVAL
     assert not h.value
+
+
+def test_philox_refuses_bad_arguments(ek):
+    lib = ek.lib()
+    assert lib.ek_philox(None, 4, 1, None, None, None) == ek.EK_EINVAL
+    assert lib.ek_philox(None, -1, 1, None, None, None) == ek.EK_EINVAL
+    assert lib.ek_philox(None, 0, 1, None, None, None) == ek.EK_OK

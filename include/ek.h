@@ -283,6 +283,33 @@ ek_status ek_load_state(struct ek_ctx* ctx, const void* host, size_t bytes);
 ek_status ek_poisson_solve(struct ek_ctx* ctx, const double* dev_rho, double* dev_psi,
                            int32_t warm_start, ek_poisson_report* rep);
 
+/* For callers that cannot allocate device or pinned memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * stand-alone solve of ek_poisson_solve without a context.  p gives the
+ * lattice size, bjerrum, kT and the solver settings (poisson_method must be
+ * EK_POISSON_SOR: red-black SOR with the Chebyshev schedule, Sec. II.C;
+ * poisson_tol, poisson_max_iter, poisson_check_every, rho_jacobi); dev_rho
+ * and dev_psi are float64 device buffers of nz*ny*nx values as in
+ * ek_poisson_solve (dev_psi: the start on entry unless warm_start is
+ * EK_WS_ZERO, the mean-free solution on return); warm_start EK_WS_ZERO,
+ * EK_WS_PREV or EK_WS_EXTRAP (the latter two start from dev_psi as given);
+ * work is enqueued on hip_stream (a hipStream_t, NULL = default stream),
+ * which is synchronised before the call returns; rep may be NULL.  For the
+ * same parameters and inputs the result equals ek_poisson_solve's on a
+ * context created with them, bit for bit.
+ * The solver's scratch (right-hand side, block partial sums, solver scalars)
+ * is one static device array of the library, about 18.5 MB on each device
+ * the call runs on, held until the process ends: lattices of at most 2^21
+ * sites (EK_EINVAL beyond, with a message in ek_last_error(NULL)).  The call
+ * allocates nothing (no hipMalloc, hipFree or hipHostMalloc).  Calls that
+ * overlap on one device (several host threads or streams) share that array
+ * and race.  Errors: EK_EINVAL for invalid parameters or NULL buffers (no
+ * work enqueued), EK_ENOCONV when poisson_max_iter iterations do not reach
+ * the tolerance (dev_psi then holds the last iterate), EK_EHIP for a failing
+ * HIP call; ek_last_error(NULL) gives the message. */
+ek_status ek_poisson_solve_noalloc(const ek_params* p, const double* dev_rho, double* dev_psi,
+                                   int32_t warm_start, void* hip_stream, ek_poisson_report* rep);
+
 /* Exactly `iterations` red-black SOR iterations (Chebyshev schedule restarted)
  * on A psi = b with no convergence test and no mean removal: dev_b and
  * dev_psi are float64 device buffers; used to compare iterates. */

@@ -101,6 +101,8 @@ def _load():
         "ek_load_state": (c_int32, [c_void_p, c_void_p, c_size_t]),
         "ek_poisson_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, P(ek_poisson_report)]),
         "ek_poisson_sor_iterations": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32]),
+        "ek_poisson_solve_noalloc": (c_int32, [P(ek_params), c_void_p, c_void_p, c_int32, c_void_p,
+                                               P(ek_poisson_report)]),
         "ek_set_timing": (c_int32, [c_void_p, c_int32]),
         "ek_set_launch_mode": (c_int32, [c_void_p, c_int32]),
         "ek_get_timing": (c_int32, [c_void_p, P(ek_timing)]),
@@ -156,6 +158,23 @@ def lib():
 
 def _ptr(a):
     return a.ctypes.data_as(c_void_p)
+
+
+def poisson_solve_noalloc(params, rho, psi, warm_start=EK_WS_PREV, stream=None):
+    """ek_poisson_solve_noalloc: rho, psi float64 CUDA tensors of the lattice
+    shape (psi updated in place); no context, nothing allocated."""
+    import torch
+    lib_ = lib()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rep = ek_poisson_report()
+    st = lib_.ek_poisson_solve_noalloc(byref(params), c_void_p(rho.data_ptr()),
+                                       c_void_p(psi.data_ptr()), warm_start,
+                                       c_void_p(s.cuda_stream), byref(rep))
+    if st != EK_OK:
+        msg = lib_.ek_last_error(None)
+        raise EKError(st, msg.decode() if msg else "")
+    return dict(iterations=rep.iterations, residual=rep.residual,
+                initial_residual=rep.initial_residual)
 
 
 def philox(counters, seed, stream=None):

@@ -12,6 +12,14 @@ Readings taken (listed with the others in the design notes):
     with x^a = n^a / n the local number fraction, so that the three species
     together exert gamma (ubar - V_i); the fluid receives the opposite impulse
     as a force density spread with the same weights;
+  * coupling kernel: the trilinear kernel above, or (poly["coupling"] ==
+    "theta") the occupation cube theta_i of Eq. totalforcefluid, the nodes
+    within the cube of side sigma around the bead, each with the same
+    weight, renormalised over the fluid nodes of the cube so that
+    sum_r theta_i(r) = 1 (the friction the fluid receives then equals the
+    bead's); it replaces the trilinear weights for the fluid velocity and
+    composition at the bead and for the spreading of the friction, while
+    the bead charge and the field keep the trilinear weights;
   * fluid fields seen by the beads over the MD substeps of one lattice step:
     densities from the populations at time t, and node velocities
     (j^a + K^a) / n^a, where j^a is the momentum of the populations at time t
@@ -75,6 +83,23 @@ def trilinear(R, shape):
         for a in range(3):
             wk = wk * (d[:, a] if o[a] else (1.0 - d[:, a]))
         w[:, k] = wk
+    return idx, w
+
+
+def theta_weights(R, shape, sigma):
+    """Occupation cube of Eq. totalforcefluid: theta_i(r) = 1 for the
+    lattice nodes r with R_i - sigma/2 < r <= R_i + sigma/2 in every axis
+    (the cube of side sigma around the bead), 0 elsewhere.  For
+    1 <= sigma <= 2 these nodes are among the 8 corners of the bead's cell:
+    returns the corner indices of `trilinear` and the indicator [N, 8]."""
+    idx, _ = trilinear(R, shape)
+    i0 = np.floor(R)
+    w = np.ones((R.shape[0], 8))
+    for k in range(8):
+        for a in range(3):
+            node = i0[:, a] + ((k >> a) & 1)
+            inside = (node - R[:, a] > -0.5 * sigma) & (node - R[:, a] <= 0.5 * sigma)
+            w[:, k] *= inside
     return idx, w
 
 
@@ -196,15 +221,20 @@ def wall_energy(R, walls, box, eps, sigma):
     return e
 
 
-def deposit_charge(R, q, shape):
-    """Bead charge on the lattice: sum_i q_i W(r - R_i), plain trilinear weights."""
+def deposit_charge(R, q, shape, fluid=None):
+    """Bead charge on the lattice: sum_i q_i W(r - R_i), plain trilinear
+    weights, or with `fluid` the weights renormalised over the fluid corners
+    (insulating walls: the solid holds no potential)."""
     rho = np.zeros(shape)
     idx, w = trilinear(R, shape)
+    if fluid is not None:
+        fl = gather(fluid, idx).astype(np.float64)
+        w = w * fl / (w * fl).sum(axis=1, keepdims=True)
     np.add.at(rho, (idx[..., 2], idx[..., 1], idx[..., 0]), q[:, None] * w)
     return rho
 
 
-def md_substeps(R, V, n, j, E, fluid, walls, poly, thermal=None):
+def md_substeps(R, V, n, j, E, fluid, walls, poly, thermal=None, field_on_fluid=False):
     """Advance the beads over one lattice step and spread the friction.
 
     R, V: [N, 3]; n: [S, Z, Y, X] and j: [S, 3, Z, Y, X] from the populations
@@ -214,7 +244,9 @@ def md_substeps(R, V, n, j, E, fluid, walls, poly, thermal=None):
     "harmonic" with k_bond, l_bond).
 
     thermal: optional (seed, step, kT) switching on the bead noise of this
-    lattice step.
+    lattice step.  field_on_fluid: interpolate the field with the weights
+    renormalised over the fluid corners (insulating walls, where the bead
+    charge is deposited with those weights too).
 
     Returns (R, V, K) with K [S, 3, Z, Y, X] the force density on each species
     accumulated over the substeps (the fluid's share of the friction).
@@ -233,9 +265,16 @@ def md_substeps(R, V, n, j, E, fluid, walls, poly, thermal=None):
     V = np.array(V, dtype=np.float64, copy=True)
     # electric force with the plain weights at the positions of the deposit
     idx0, w0 = trilinear(R, shape)
+    if field_on_fluid:
+        fl0 = gather(fluid, idx0).astype(np.float64)
+        w0 = w0 * fl0 / (w0 * fl0).sum(axis=1, keepdims=True)
     F_el = q[:, None] * (w0[None] * gather(E, idx0)).sum(axis=-1).T           # [N, 3]
+    theta = poly.get("coupling", "trilinear") == "theta"
     for sub in range(poly["n_sub"]):
-        idx, w = trilinear(R, shape)
+        if theta:
+            idx, w = theta_weights(R, shape, poly["sigma"])
+        else:
+            idx, w = trilinear(R, shape)
         fl = gather(fluid, idx).astype(np.float64)
         wsum = (w * fl).sum(axis=1)
         if np.any(wsum <= 0.0):

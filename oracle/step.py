@@ -35,6 +35,9 @@ class Params:
     poisson_max_iter: int = 100000
     rho_j: float = None                          # Jacobi radius for the Chebyshev schedule
     fluctuations: bool = False                   # thermal noise on populations and beads
+    walls: str = "periodic"                      # Poisson domain: "periodic" whole box with
+                                                 # wall charges on solid sites, or "neumann":
+                                                 # insulating walls (fluid sites only)
     seed: int = 0                                # key of the counter-based generator
 
     @property
@@ -43,11 +46,13 @@ class Params:
 
 
 def polymer_params(n_beads, q=-1.0, M=1.0, k_fene=30.0, R0=1.5, eps=1.0, sigma=1.0,
-                   gamma=20.0, n_sub=40, bond="fene", k_bond=0.0, l_bond=0.0):
-    """bond "fene" (k_fene, R0) or "harmonic" (k_bond, l_bond: Eq. polymermodel)."""
+                   gamma=20.0, n_sub=40, bond="fene", k_bond=0.0, l_bond=0.0,
+                   coupling="trilinear"):
+    """bond "fene" (k_fene, R0) or "harmonic" (k_bond, l_bond: Eq. polymermodel);
+    coupling "trilinear" or "theta" (the occupation cube of Eq. totalforcefluid)."""
     return dict(M=M, q=np.full(n_beads, q, dtype=np.float64), k_fene=k_fene, R0=R0,
                 eps=eps, sigma=sigma, gamma=gamma, n_sub=n_sub, bond=bond, k_bond=k_bond,
-                l_bond=l_bond)
+                l_bond=l_bond, coupling=coupling)
 
 
 class Simulation:
@@ -79,25 +84,46 @@ class Simulation:
             self.R = None
 
     # -- pieces of one step -------------------------------------------------
+    @property
+    def neumann(self):
+        return self.p.walls == "neumann"
+
     def charge_density(self, n):
+        """Charge of ions and beads, plus the wall charges on solid sites for
+        the periodic whole-box problem (insulating walls carry theirs as the
+        surface flux of their faces, poisson.neumann_rhs)."""
         z = np.asarray(self.p.valence, dtype=np.float64)
-        rho = np.einsum("s,szyx->zyx", z, n) + self.wall_q
+        rho = np.einsum("s,szyx->zyx", z, n)
+        if not self.neumann:
+            rho = rho + self.wall_q
         if self.R is not None:
-            rho = rho + md.deposit_charge(self.R, self.poly["q"], self.shape)
+            rho = rho + md.deposit_charge(self.R, self.poly["q"], self.shape,
+                                          fluid=self.fluid if self.neumann else None)
         return rho
 
     def solve_potential(self, rho_e):
-        b = poisson.rhs_from_charge(rho_e, self.p.eps)
-        psi, it, rr = poisson.sor_red_black_chebyshev(
-            b, self.psi, self.p.poisson_tol, self.p.poisson_max_iter, self.p.rho_j)
+        if self.neumann:
+            b = poisson.neumann_rhs(rho_e, self.wall_q, self.solid, self.p.eps)
+            psi, it, rr = poisson.sor_neumann(b, self.psi, self.fluid, self.p.poisson_tol,
+                                              self.p.poisson_max_iter, self.p.rho_j)
+        else:
+            b = poisson.rhs_from_charge(rho_e, self.p.eps)
+            psi, it, rr = poisson.sor_red_black_chebyshev(
+                b, self.psi, self.p.poisson_tol, self.p.poisson_max_iter, self.p.rho_j)
         self.last_iters, self.last_residual = it, rr
         return psi
+
+    def field(self):
+        if self.neumann:
+            return poisson.electric_field_neumann(self.psi, self.solid, self.wall_q, self.p.eps,
+                                                  self.p.E_ext)
+        return poisson.electric_field(self.psi, self.p.E_ext)
 
     def step(self):
         n, j = lb.moments(self.f)
         rho_e = self.charge_density(n)
         self.psi = self.solve_potential(rho_e)
-        E = poisson.electric_field(self.psi, self.p.E_ext)
+        E = self.field()
 
         S = n.shape[0]
         z = np.asarray(self.p.valence, dtype=np.float64)
@@ -106,7 +132,8 @@ class Simulation:
         thermal = (self.p.seed, self.t, self.p.kT) if self.p.fluctuations else None
         if self.R is not None:
             self.R, self.V, K = md.md_substeps(self.R, self.V, n, j, E, self.fluid,
-                                               self.walls, self.poly, thermal=thermal)
+                                               self.walls, self.poly, thermal=thermal,
+                                               field_on_fluid=self.neumann)
             nsafe = np.where(self.fluid[None], n, 1.0)
             G = G + K / nsafe[:, None]
         tau = np.asarray(self.p.tau, dtype=np.float64)

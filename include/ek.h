@@ -102,7 +102,29 @@ typedef struct {
                                   Langevin noise on the beads (Sec. II.B), at
                                   temperature kT, from the counter-based
                                   generator described below                   */
+  int32_t walls;               /* EK_WALLS_PERIODIC: Eq. poisson on the whole
+                                  periodic box, wall charges as point charges
+                                  on solid sites; EK_WALLS_INSULATING: the
+                                  Neumann condition -grad psi . n = Sigma/eps
+                                  of insulating walls (see below)             */
 } ek_params;
+
+/* Insulating walls (ek_params.walls = EK_WALLS_INSULATING; the boundary
+ * condition stated after Eq. poisson): the potential lives on the fluid sites
+ * only.  The charge wall_q of a solid site (ek_set_geometry) is its surface
+ * charge, divided equally over its faces shared with fluid sites (a charged
+ * solid site without such a face is EK_EINVAL); each face's flux Sigma_f/eps
+ * enters the balance of the fluid cell it bounds.  The fluid mean of the
+ * charge is removed and the fluid mean of psi fixed at 0 (psi is 0 on solid
+ * sites); the field at a fluid site is the central difference with
+ * psi + Sigma_f/eps in place of a solid face neighbour.  Bead charges are
+ * deposited, and the field interpolated at the beads, with the trilinear
+ * weights renormalised over the fluid corners.  Needs EK_POISSON_SOR (the
+ * paper's red-black SOR, over the fluid sites) and a start other than
+ * EK_WS_LEARNED; ek_poisson_solve, ek_poisson_sor_iterations and
+ * ek_get_poisson_system, which work on the periodic problem, return
+ * EK_ESTATE for such a context; the ensemble refuses it. */
+enum { EK_WALLS_PERIODIC = 0, EK_WALLS_INSULATING = 1 };
 
 /* Thermal fluctuations (ek_params.fluctuations = 1).
  * Populations (Sec. II.C): after the collision every fluid site gets, per
@@ -143,6 +165,14 @@ ek_status ek_philox(const uint32_t* counters, int32_t n, uint64_t seed, uint32_t
  * U = k_bond (r - l_bond)^2 / 2, with the WCA only between beads more than
  * one apart along the chain. */
 enum { EK_BOND_FENE = 0, EK_BOND_HARMONIC = 1 };
+/* Friction coupling of beads and fluid: the trilinear kernel of Sec. II.C
+ * (velocity and composition interpolated, friction spread, with the weights
+ * renormalised over the fluid corners), or the occupation cube theta_i of
+ * Eq. totalforcefluid: the lattice nodes r with R - sigma/2 < r <= R + sigma/2
+ * in every axis, equal weights renormalised over the fluid ones (needs
+ * 1 <= sigma <= 2, so that they are corners of the bead's cell).  The bead
+ * charge and the field at the bead keep the trilinear weights either way. */
+enum { EK_COUPLE_TRILINEAR = 0, EK_COUPLE_THETA = 1 };
 typedef struct {
   double M;                    /* bead mass                                    */
   double k_fene, R0;           /* FENE spring constant and maximum extension   */
@@ -152,6 +182,7 @@ typedef struct {
   int32_t bond;                /* EK_BOND_FENE or EK_BOND_HARMONIC             */
   double k_bond, l_bond;       /* harmonic spring constant (>= 0) and rest
                                   length (> 0)                                 */
+  int32_t coupling;            /* EK_COUPLE_TRILINEAR or EK_COUPLE_THETA       */
 } ek_polymer_params;
 
 typedef struct {
@@ -254,10 +285,12 @@ ek_status ek_get_stats(struct ek_ctx* ctx, ek_stats* out);
  * crossing plane and record, and the counters the next steps depend on (step
  * count, the previous solve's cycle count, which schedules the next solve's
  * residual tests); a network set with ek_set_model, the launch mode and the
- * timers are not part of it.  Loading it into a context created with the same
- * ek_params (lattice size, precision and warm start must match; max_beads at
- * least the state's chain) and stepping on gives bit for bit the results the
- * saved context would have given.
+ * timers are not part of it, nor are the ek_params: loading it into a
+ * context created with the same ek_params (lattice size, precision and warm
+ * start must match, which is checked; max_beads at least the state's chain)
+ * and stepping on gives bit for bit the results the saved context would have
+ * given, while a context with other physical parameters (field, relaxation
+ * times, ...) continues the state under its own.
  *
  * ek_state_bytes: size of the state of the context as it stands (it grows
  *   with the chain).

@@ -60,6 +60,12 @@ ek_status check_params(const ek_params* p, std::string& why) {
     return EK_EINVAL;
   }
   if (p->fluctuations != 0 && p->fluctuations != 1) { why = "fluctuations must be 0 or 1"; return EK_EINVAL; }
+  if (p->walls != EK_WALLS_PERIODIC && p->walls != EK_WALLS_INSULATING) { why = "unknown walls"; return EK_EINVAL; }
+  if (p->walls == EK_WALLS_INSULATING &&
+      (p->poisson_method != EK_POISSON_SOR || p->warm_start == EK_WS_LEARNED)) {
+    why = "insulating walls need EK_POISSON_SOR and a start other than EK_WS_LEARNED";
+    return EK_EINVAL;
+  }
   return EK_OK;
 }
 
@@ -174,10 +180,16 @@ ek_status ek_ctx::read_scalars(PoissonScalars* out) {
 // is already in ps).  The residual is tested after every `check_every`
 // iterations; iterations are enqueued in batches ahead of the test and turn
 // into no-ops once the device-side flag is set.
+int ek_ctx::residual_launch(const double* bb, const double* x) {
+  const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
+  if (insulating()) return launch_residual_neu(x, bb, mask, ps, partials, dims, g, stream);
+  return launch_residual(x, bb, ps, partials, dims, g, stream);
+}
+
 ek_status ek_ctx::sor_solve(const double* bb, double* x, PoissonScalars h, int& iters, double& res,
                            double& res0) {
-  const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
   const SiteGrid cg = colour_grid(p.nx, p.ny, p.nz, bx_colour);
+  const bool neu = insulating();
   const double rj = jacobi_radius();
   ek_status st = EK_OK;
   int it = 0;
@@ -189,13 +201,14 @@ ek_status ek_ctx::sor_solve(const double* bb, double* x, PoissonScalars h, int& 
     const int nrun = std::min(batch, p.poisson_max_iter - it);
     for (int k = 0; k < nrun; ++k) {
       for (int colour = 0; colour < 2; ++colour) {
-        launch_sor_half(x, bb, ps, colour, omega, dims, cg, stream);
+        if (neu) launch_sor_half_neu(x, bb, mask, ps, colour, omega, dims, cg, stream);
+        else launch_sor_half(x, bb, ps, colour, omega, dims, cg, stream);
         omega = first ? 1.0 / (1.0 - 0.5 * rj * rj) : 1.0 / (1.0 - 0.25 * rj * rj * omega);
         first = false;
       }
       ++it;
       if (it % ce == 0 || it == p.poisson_max_iter) {
-        const int nr = launch_residual(x, bb, ps, partials, dims, g, stream);
+        const int nr = residual_launch(bb, x);
         launch_residual_final(partials, nr, p.poisson_tol, it, 0, ps, stream);
       }
     }
@@ -213,13 +226,13 @@ ek_status ek_ctx::sor_solve(const double* bb, double* x, PoissonScalars h, int& 
     return fail(EK_ENOCONV, buf);
   }
   iters = h.iters;
-  launch_psi_shift(x, ps, 1.0 / double(dims.n), dims, stream);
+  if (neu) launch_psi_shift_neu(x, mask, ps, 1.0 / double(n_fluid), dims, stream);
+  else launch_psi_shift(x, ps, 1.0 / double(dims.n), dims, stream);
   return EK_OK;
 }
 
 ek_status ek_ctx::initial_residual(const double* bb, const double* x, PoissonScalars* h) {
-  const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
-  const int nr = launch_residual(x, bb, ps, partials, dims, g, stream);
+  const int nr = residual_launch(bb, x);
   launch_residual_final(partials, nr, p.poisson_tol, 0, 1, ps, stream);
   return read_scalars(h);
 }
@@ -304,6 +317,10 @@ ek_status ek_ctx::step_impl(int n_steps) {
     ek_status st = ensure_events(n_steps);
     if (st) return st;
   }
+  WallView wv;
+  wv.face_q = wall_q;
+  wv.inv_eps = inv_eps();
+  const WallView* wvp = insulating() ? &wv : nullptr;
   for (int t = 0; t < n_steps; ++t) {
     const BeadTableView bt = bead_view();
     const NoiseParams noise = noise_params(step_count);
@@ -318,9 +335,10 @@ ek_status ek_ctx::step_impl(int n_steps) {
     // psi = 2 psi(t-1) - psi(t-2) once two previous solutions exist
     const int extrap = p.warm_start == EK_WS_EXTRAP ? std::min(psi_hist, 2) : 0;
     launch_charge<T>((const T*)fcur(), mask, wall_q, b, partials, lp, inv_eps(), dims, g, stream, bt,
-                     psi, psi_old, extrap);
+                     psi, psi_old, extrap, insulating());
     if (p.warm_start == EK_WS_EXTRAP) psi_hist = std::min(psi_hist + 1, 2);
-    launch_mean_shift(partials, nb, 1.0 / double(dims.n), inv_eps(), ps, stream);
+    launch_mean_shift(partials, nb, 1.0 / double(insulating() ? n_fluid : dims.n), inv_eps(), ps,
+                      stream);
     record(t, 1);
     if (p.warm_start == EK_WS_ZERO) launch_fill(psi, 0.0, dims.n, stream);
     int iters = 0;
@@ -351,12 +369,12 @@ ek_status ek_ctx::step_impl(int n_steps) {
     launch_lb_step<T>((const T*)fcur(), (T*)fnext(), mask, psi, lp, bt, partials, nb_lb,
                       overlap ? MASK_DEFER : 0u, dims, g, ls,
                       timing ? events[6 * t + 3] : nullptr, timing ? events[6 * t + 4] : nullptr,
-                      npp);
+                      npp, wvp);
     if (overlap) {
       EK_HIP(hipEventRecord(side_join, side_stream));
       EK_HIP(hipStreamWaitEvent(stream, side_join, 0));
       launch_lb_tail<T>((const T*)fcur(), (T*)fnext(), mask, psi, lp, bt, bead_origin(), n_beads,
-                        partials, nb_bulk, nb_lb, dims, stream, npp);
+                        partials, nb_bulk, nb_lb, dims, stream, npp, wvp);
     }
     launch_sum_partials(partials, nb_lb, stats_dev, timing ? 1 : 0, stream);
     cur_is_a = !cur_is_a;
@@ -542,13 +560,41 @@ ek_status ek_set_geometry(ek_ctx* ctx, const uint8_t* solid, const double* wall_
   std::vector<uint32_t> m;
   const long long nfluid = build_link_words(solid, wall_q, d, m);
   if (nfluid == 0) return ctx->fail(EK_EINVAL, "geometry has no fluid site");
+  std::vector<double> face_q;
+  if (ctx->insulating()) {
+    // insulating walls: the charge of a solid site is shared by its faces
+    // with the fluid (Sigma_f = q / faces); every fluid site needs a fluid
+    // face neighbour (else its potential is undefined)
+    face_q.assign(d.n, 0.0);
+    for (long long r = 0; r < d.n; ++r) {
+      int faces = 0;
+      for (int q = 1; q <= 6; ++q) faces += (m[r] >> q) & 1u;    // solid face neighbours
+      const bool is_solid = (m[r] & MASK_SOLID) != 0;
+      if (!is_solid && faces == 6) return ctx->fail(EK_EINVAL, "a fluid site has no fluid face neighbour");
+      if (!is_solid || !wall_q || wall_q[r] == 0.0) continue;
+      const int z = int(r / ((long long)d.nx * d.ny)), y = int((r / d.nx) % d.ny), x = int(r % d.nx);
+      int open = 0;
+      for (int q = 1; q <= 6; ++q) {
+        const int sx = (x + CX[q] + d.nx) % d.nx, sy = (y + CY[q] + d.ny) % d.ny,
+                  sz = (z + CZ[q] + d.nz) % d.nz;
+        open += solid[((long long)sz * d.ny + sy) * d.nx + sx] ? 0 : 1;
+      }
+      if (open == 0)
+        return ctx->fail(EK_EINVAL, "insulating walls: a charged solid site has no face shared with the fluid");
+      face_q[r] = wall_q[r] / open;
+    }
+  }
   EK_HIP(hipMemcpy(ctx->mask, m.data(), d.n * 4, hipMemcpyHostToDevice));
-  if (wall_q) {
+  if (ctx->insulating()) {
+    EK_HIP(hipMemcpy(ctx->wall_q, face_q.data(), d.n * 8, hipMemcpyHostToDevice));
+  } else if (wall_q) {
     EK_HIP(hipMemcpy(ctx->wall_q, wall_q, d.n * 8, hipMemcpyHostToDevice));
   } else {
     launch_fill(ctx->wall_q, 0.0, d.n, ctx->stream);
   }
   ctx->host_solid.assign(solid, solid + d.n);
+  if (wall_q) ctx->host_wall_q.assign(wall_q, wall_q + d.n);
+  else ctx->host_wall_q.assign(d.n, 0.0);
   ctx->n_fluid = nfluid;
   const size_t tsz = ctx->p.precision == EK_FP64 ? 8 : 4;
   EK_HIP(hipMemsetAsync(ctx->fA, 0, 3 * Q * d.n * tsz, ctx->stream));
@@ -615,6 +661,7 @@ ek_status ek_set_model(ek_ctx* ctx, const float* params, int32_t n, float out_sc
 
 ek_status ek_get_poisson_system(ek_ctx* ctx, double* dev_rhs, double* dev_psi) {
   if (!ctx) return EK_EINVAL;
+  if (ctx->insulating()) return ctx->fail(EK_ESTATE, "the context has insulating walls");
   if (!ctx->have_solve) return ctx->fail(EK_ESTATE, "no Poisson solve has run yet");
   if (dev_rhs) launch_rhs_copy(ctx->b, ctx->ps, dev_rhs, ctx->dims.n, ctx->stream);
   if (dev_psi)
@@ -694,6 +741,7 @@ ek_status ek_get_timing(ek_ctx* ctx, ek_timing* out) {
 ek_status ek_poisson_solve(ek_ctx* ctx, const double* dev_rho, double* dev_psi,
                            int32_t warm_start, ek_poisson_report* rep) {
   if (!ctx) return EK_EINVAL;
+  if (ctx->insulating()) return ctx->fail(EK_ESTATE, "the context has insulating walls");
   if (!dev_rho || !dev_psi) return ctx->fail(EK_EINVAL, "NULL device buffer");
   if (warm_start < EK_WS_ZERO || warm_start > EK_WS_EXTRAP) return ctx->fail(EK_EINVAL, "unknown warm_start");
   if (warm_start == EK_WS_LEARNED && !(ctx->net && ctx->net->have_params))
@@ -723,6 +771,7 @@ ek_status ek_poisson_solve(ek_ctx* ctx, const double* dev_rho, double* dev_psi,
 ek_status ek_poisson_sor_iterations(ek_ctx* ctx, const double* dev_b, double* dev_psi,
                                     int32_t iterations) {
   if (!ctx) return EK_EINVAL;
+  if (ctx->insulating()) return ctx->fail(EK_ESTATE, "the context has insulating walls");
   if (!dev_b || !dev_psi || iterations < 0) return ctx->fail(EK_EINVAL, "bad arguments");
   const SiteGrid cg = colour_grid(ctx->p.nx, ctx->p.ny, ctx->p.nz, ctx->bx_colour);
   launch_ps_reset(ctx->ps, 0.0, ctx->stream);

@@ -47,6 +47,7 @@ struct ek_ctx {
 
   // host-side state
   std::vector<uint8_t> host_solid;
+  std::vector<double> host_wall_q;     // the wall charges as given (for the state)
   long long n_fluid = 0;
   double nref[3] = {0, 0, 0};
   bool have_geometry = false;
@@ -98,6 +99,7 @@ struct ek_ctx {
   void* fnext();
   ek::LBParams lb_params() const;
   ek::NoiseParams noise_params(long long step) const;
+  bool insulating() const { return p.walls == EK_WALLS_INSULATING; }
   double inv_eps() const;
   double jacobi_radius() const;
   ek_status read_scalars(ek::PoissonScalars* out);
@@ -108,6 +110,9 @@ struct ek_ctx {
   ek_status mg_solve(const double* b, double* x, ek::PoissonScalars h, int& iters, double& res,
                      double& res0);
   ek_status initial_residual(const double* b, const double* x, ek::PoissonScalars* h);
+  // residual kernel of the context's problem (periodic or insulating walls);
+  // returns the number of block partials
+  int residual_launch(const double* b, const double* x);
   ek_status learned_start(const double* b, double* x, ek::PoissonScalars* h);
   void mg_setup();
   void mg_release();

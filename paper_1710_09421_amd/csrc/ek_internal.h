@@ -70,6 +70,13 @@ struct LBParams {
 
 struct BeadTableView;      // md_table.h
 struct NoiseParams;        // philox.h
+// Insulating walls: the surface charge Sigma_f of the faces of each solid
+// site (face_q, in place of the point charges of the periodic problem) and
+// 1 / eps for the ghost values psi_r + Sigma_f / eps of the field.
+struct WallView {
+  const double* face_q = nullptr;
+  double inv_eps = 0.0;
+};
 
 // Sets the message ek_last_error(NULL) returns on the calling thread.
 void set_thread_error(const std::string& msg);
@@ -98,11 +105,14 @@ void launch_init_species(T* f, const uint32_t* mask, const double* n_dev, int sp
                          double nref, Dims d, hipStream_t s);
 // With psi_old (the extrapolated start) and extrap = 1 or 2 the pass also
 // copies psi to psi_old (1) or sets psi = 2 psi - psi_old, psi_old = old psi (2).
+// insulating: the charge of insulating walls (fluid sites only, the wall
+// faces' surface charge added to the fluid sites they bound).
 template <typename T>
 void launch_charge(const T* f, const uint32_t* mask, const double* wall_q, double* b,
                    double* partials, const LBParams& lp, double inv_eps, Dims d,
                    const SiteGrid& g, hipStream_t s, const BeadTableView& bt,
-                   double* psi = nullptr, double* psi_old = nullptr, int extrap = 0);
+                   double* psi = nullptr, double* psi_old = nullptr, int extrap = 0,
+                   bool insulating = false);
 // Fused step over the sites without a `skip` bit.  Writes its block partials
 // (seven components: masses, momentum, sites updated) first in a layout of
 // `nblocks` blocks (lb_step_blocks(g, nz), plus the tail's blocks when a tail
@@ -117,14 +127,14 @@ int launch_lb_step(const T* fsrc, T* fdst, const uint32_t* mask, const double* p
                    const LBParams& lp, const BeadTableView& bt, double* partials, int nblocks,
                    uint32_t skip, Dims d, const SiteGrid& g, hipStream_t s,
                    hipEvent_t start = nullptr, hipEvent_t stop = nullptr,
-                   const NoiseParams* noise = nullptr);
+                   const NoiseParams* noise = nullptr, const WallView* walls = nullptr);
 // The sites flagged MASK_DEFER in the boxes of n_beads beads (box origins of
 // the step); partials of blocks first_block .. of the same layout.
 template <typename T>
 void launch_lb_tail(const T* fsrc, T* fdst, uint32_t* mask, const double* psi, const LBParams& lp,
                     const BeadTableView& bt, const int* origin, int n_beads, double* partials,
                     int first_block, int nblocks, Dims d, hipStream_t s,
-                    const NoiseParams* noise = nullptr);
+                    const NoiseParams* noise = nullptr, const WallView* walls = nullptr);
 template <typename T>
 void launch_moments(const T* f, const uint32_t* mask, int species, double nref, double* n_out,
                     double* u_out, Dims d, hipStream_t s);
@@ -146,6 +156,16 @@ void launch_residual_final(const double* partials, int nblocks, double tol, int 
                            int initial, PoissonScalars* ps, hipStream_t s);
 void launch_psi_shift(double* psi, const PoissonScalars* ps, double inv_n, Dims d,
                       hipStream_t s);
+// Insulating walls: the same over the fluid sites only (the link words give
+// the solid face neighbours); inv_nf = 1 / number of fluid sites.
+void launch_sor_half_neu(double* psi, const double* b, const uint32_t* mask,
+                         const PoissonScalars* ps, int colour, double omega, Dims d,
+                         const SiteGrid& g, hipStream_t s);
+int launch_residual_neu(const double* psi, const double* b, const uint32_t* mask,
+                        PoissonScalars* ps, double* partials, Dims d, const SiteGrid& g,
+                        hipStream_t s);
+void launch_psi_shift_neu(double* psi, const uint32_t* mask, const PoissonScalars* ps,
+                          double inv_nf, Dims d, hipStream_t s);
 void launch_fill(double* x, double v, long long n, hipStream_t s);
 void launch_ps_reset(PoissonScalars* ps, double shift, hipStream_t s);
 void launch_ps_rearm(PoissonScalars* ps, hipStream_t s);

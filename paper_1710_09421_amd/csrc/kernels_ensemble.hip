@@ -501,6 +501,7 @@ ek_status check(const ek_params* p, int n_rep, int max_beads, std::string& why) 
   // has no oracle parity on record since its team rewrites
   if (p->precision != EK_FP32) { why = "the ensemble stores float32 populations only (EK_FP32)"; return EK_EINVAL; }
   if (p->fluctuations != 0) { why = "the ensemble runs without thermal fluctuations"; return EK_EINVAL; }
+  if (p->walls != EK_WALLS_PERIODIC) { why = "the ensemble solves the periodic Poisson problem only"; return EK_EINVAL; }
   return EK_OK;
 }
 
@@ -768,7 +769,9 @@ ek_status ek_ensemble_set_replica(ek_ensemble* e, int32_t r, const double* E_ext
                       1.122462048309373 * pp->sigma >= 2.0 ||
                       (pp->bond != EK_BOND_FENE && pp->bond != EK_BOND_HARMONIC) ||
                       (pp->bond == EK_BOND_FENE && !(pp->R0 > 0)) ||
-                      (pp->bond == EK_BOND_HARMONIC && (!(pp->k_bond >= 0) || !(pp->l_bond > 0)))))
+                      (pp->bond == EK_BOND_HARMONIC && (!(pp->k_bond >= 0) || !(pp->l_bond > 0))) ||
+                      (pp->coupling != EK_COUPLE_TRILINEAR && pp->coupling != EK_COUPLE_THETA) ||
+                      (pp->coupling == EK_COUPLE_THETA && !(pp->sigma >= 1.0 && pp->sigma <= 2.0))))
     return e->fail(EK_EINVAL, "bad chain arguments");
   const Dims d = e->d;
   const size_t n = d.n;
@@ -830,6 +833,8 @@ ek_status ek_ensemble_set_replica(ek_ensemble* e, int32_t r, const double* E_ext
     mp.bond = pp->bond;
     mp.k_bond = pp->k_bond;
     mp.l_bond = pp->l_bond;
+    mp.theta = pp->coupling == EK_COUPLE_THETA ? 1 : 0;
+    mp.half_sigma = 0.5 * pp->sigma;
   }
   e->have_replica[r] = true;
   return EK_OK;

@@ -48,7 +48,7 @@ struct StartExtrap {
   int mode;
 };
 
-template <typename T, typename I>
+template <typename T, typename I, bool NEU>
 __global__ __launch_bounds__(BLOCK) void k_charge(const T* __restrict__ f,
                                                   const uint32_t* __restrict__ mask,
                                                   const double* __restrict__ wall_q,
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(BLOCK) void k_charge(const T* __restrict__ f,
   const int nblocks = gridDim.x * gridDim.y * gridDim.z;
   double acc[1] = {0.0};
   if (x < d.nx && y < d.ny) {
-    const double rho = charge_site<T, I>(f, mask, wall_q, lp, bt, x, y, z, d);
+    const double rho = charge_site<T, I, NEU>(f, mask, wall_q, lp, bt, x, y, z, d);
     const long long r = ((long long)z * d.ny + y) * d.nx + x;
     b[r] = -rho * inv_eps;
     acc[0] = rho;
@@ -82,22 +82,26 @@ __global__ __launch_bounds__(BLOCK) void k_charge(const T* __restrict__ f,
 // momentum of f(t) in float64, and the number of sites updated.  Sites with
 // a `skip` bit are left to k_lb_tail.  Partials: [c * nblocks + block], the
 // blocks of this launch first.
-template <typename T, typename I, bool FLUCT>
+// Variants V of the fused step: bit 0 the thermal fluctuations, bit 1 the
+// field of insulating walls.
+template <typename T, typename I, int V>
 __global__ __launch_bounds__(BLOCK) void k_lb_step(const T* __restrict__ fsrc,
                                                    T* __restrict__ fdst,
                                                    const uint32_t* __restrict__ mask,
                                                    const double* __restrict__ psi, LBParams lp,
                                                    BeadTableView bt,
                                                    double* __restrict__ partials, int nblocks,
-                                                   uint32_t skip, Dims d, int zb, NoiseParams np) {
+                                                   uint32_t skip, Dims d, int zb, NoiseParams np,
+                                                   WallView wv) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
   if (x < d.nx && y < d.ny)
     for (int k = 0; k < zb; ++k)
-      if (lb_site<T, I, 7, FLUCT>(fsrc, fdst, mask, psi, lp, bt, x, y, blockIdx.z * zb + k, d, acc,
-                                  skip, &np))
+      if (lb_site<T, I, 7, (V & 1) != 0, (V & 2) != 0>(fsrc, fdst, mask, psi, lp, bt, x, y,
+                                                        blockIdx.z * zb + k, d, acc, skip, &np,
+                                                        &wv))
         acc[6] += 1.0;
   block_partials<7>(acc, partials, bid, nblocks);
 }
@@ -108,7 +112,7 @@ __global__ __launch_bounds__(BLOCK) void k_lb_step(const T* __restrict__ fsrc,
 // node in several boxes is updated by the lowest bead whose box holds it
 // (the boxes' origins are fixed for the step), which also clears its flag.
 // Needs every side of the box >= BOX (no box overlaps itself).
-template <typename T, typename I, bool FLUCT>
+template <typename T, typename I, int V>
 __global__ __launch_bounds__(BLOCK) void k_lb_tail(const T* __restrict__ fsrc,
                                                    T* __restrict__ fdst, uint32_t* mask,
                                                    const double* __restrict__ psi, LBParams lp,
@@ -116,7 +120,7 @@ __global__ __launch_bounds__(BLOCK) void k_lb_tail(const T* __restrict__ fsrc,
                                                    const int* __restrict__ origin, int n_beads,
                                                    double* __restrict__ partials,
                                                    int first_block, int nblocks, Dims d,
-                                                   NoiseParams np) {
+                                                   NoiseParams np, WallView wv) {
   // origins of the beads up to this block's last one, staged in LDS for the
   // test against every lower bead
   extern __shared__ int so[];
@@ -136,8 +140,8 @@ __global__ __launch_bounds__(BLOCK) void k_lb_tail(const T* __restrict__ fsrc,
         first = false;
     if (first) {
       const int x = wrap(gx, d.nx), y = wrap(gy, d.ny), z = wrap(gz, d.nz);
-      lb_site<T, I, 7, FLUCT>(fsrc, fdst, mask, psi, lp, bt, x, y, z, d, acc, 0u,
-                              &np);   // not counted in acc[6]
+      lb_site<T, I, 7, (V & 1) != 0, (V & 2) != 0>(fsrc, fdst, mask, psi, lp, bt, x, y, z, d,
+                                                    acc, 0u, &np, &wv);   // not counted in acc[6]
       atomicAnd(&mask[((long long)z * d.ny + y) * d.nx + x], ~MASK_DEFER);
     }
   }
@@ -246,14 +250,20 @@ template <typename T>
 void launch_charge(const T* f, const uint32_t* mask, const double* wall_q, double* b,
                    double* partials, const LBParams& lp, double inv_eps, Dims d,
                    const SiteGrid& g, hipStream_t s, const BeadTableView& bt, double* psi,
-                   double* psi_old, int extrap) {
+                   double* psi_old, int extrap, bool insulating) {
   const StartExtrap start{psi, psi_old, psi_old ? extrap : 0};
-  if (fits_idx32<T>(d.n))
-    hipLaunchKernelGGL((k_charge<T, uint32_t>), g.grid, g.block, 0, s, f, mask, wall_q, b,
-                       partials, lp, inv_eps, bt, d, start);
-  else
-    hipLaunchKernelGGL((k_charge<T, long long>), g.grid, g.block, 0, s, f, mask, wall_q, b,
-                       partials, lp, inv_eps, bt, d, start);
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, g.grid, g.block, 0, s, f, mask, wall_q, b, partials, lp, inv_eps,
+                       bt, d, start);
+  };
+  const bool i32 = fits_idx32<T>(d.n);
+  if (insulating) {
+    if (i32) go(k_charge<T, uint32_t, true>);
+    else go(k_charge<T, long long, true>);
+  } else {
+    if (i32) go(k_charge<T, uint32_t, false>);
+    else go(k_charge<T, long long, false>);
+  }
 }
 
 // z-planes per block of the fused step: each block sums its sites' masses
@@ -277,22 +287,27 @@ template <typename T>
 int launch_lb_step(const T* fsrc, T* fdst, const uint32_t* mask, const double* psi,
                    const LBParams& lp, const BeadTableView& bt, double* partials, int nblocks,
                    uint32_t skip, Dims d, const SiteGrid& g, hipStream_t s, hipEvent_t start,
-                   hipEvent_t stop, const NoiseParams* noise) {
+                   hipEvent_t stop, const NoiseParams* noise, const WallView* walls) {
   const int zb = lb_planes_per_block(g, d.nz);
   const dim3 grid(g.grid.x, g.grid.y, d.nz / zb);
   const NoiseParams np = noise ? *noise : NoiseParams{};
+  const WallView wv = walls ? *walls : WallView{};
   // the events (when given) are stamped at the kernel's own start and end
   auto go = [&](auto kernel) {
     hipExtLaunchKernelGGL(kernel, grid, g.block, 0, s, start, stop, 0, fsrc, fdst, mask, psi, lp,
-                          bt, partials, nblocks, skip, d, zb, np);
+                          bt, partials, nblocks, skip, d, zb, np, wv);
   };
-  const bool i32 = fits_idx32<T>(d.n);
-  if (noise) {
-    if (i32) go(k_lb_step<T, uint32_t, true>);
-    else go(k_lb_step<T, long long, true>);
+  const int v = (noise ? 1 : 0) | (walls ? 2 : 0);
+  if (fits_idx32<T>(d.n)) {
+    if (v == 0) go(k_lb_step<T, uint32_t, 0>);
+    else if (v == 1) go(k_lb_step<T, uint32_t, 1>);
+    else if (v == 2) go(k_lb_step<T, uint32_t, 2>);
+    else go(k_lb_step<T, uint32_t, 3>);
   } else {
-    if (i32) go(k_lb_step<T, uint32_t, false>);
-    else go(k_lb_step<T, long long, false>);
+    if (v == 0) go(k_lb_step<T, long long, 0>);
+    else if (v == 1) go(k_lb_step<T, long long, 1>);
+    else if (v == 2) go(k_lb_step<T, long long, 2>);
+    else go(k_lb_step<T, long long, 3>);
   }
   return int(grid.x * grid.y * grid.z);
 }
@@ -300,21 +315,27 @@ int launch_lb_step(const T* fsrc, T* fdst, const uint32_t* mask, const double* p
 template <typename T>
 void launch_lb_tail(const T* fsrc, T* fdst, uint32_t* mask, const double* psi, const LBParams& lp,
                     const BeadTableView& bt, const int* origin, int n_beads, double* partials,
-                    int first_block, int nblocks, Dims d, hipStream_t s, const NoiseParams* noise) {
+                    int first_block, int nblocks, Dims d, hipStream_t s, const NoiseParams* noise,
+                    const WallView* walls) {
   const int blocks = lb_tail_blocks(n_beads);
   const size_t lds = (size_t)3 * n_beads * sizeof(int);   // at most 12 KiB (MAX_BEADS = 1024)
   const NoiseParams np = noise ? *noise : NoiseParams{};
+  const WallView wv = walls ? *walls : WallView{};
   auto go = [&](auto kernel) {
     hipLaunchKernelGGL(kernel, dim3(blocks), dim3(BLOCK), lds, s, fsrc, fdst, mask, psi, lp, bt,
-                       origin, n_beads, partials, first_block, nblocks, d, np);
+                       origin, n_beads, partials, first_block, nblocks, d, np, wv);
   };
-  const bool i32 = fits_idx32<T>(d.n);
-  if (noise) {
-    if (i32) go(k_lb_tail<T, uint32_t, true>);
-    else go(k_lb_tail<T, long long, true>);
+  const int v = (noise ? 1 : 0) | (walls ? 2 : 0);
+  if (fits_idx32<T>(d.n)) {
+    if (v == 0) go(k_lb_tail<T, uint32_t, 0>);
+    else if (v == 1) go(k_lb_tail<T, uint32_t, 1>);
+    else if (v == 2) go(k_lb_tail<T, uint32_t, 2>);
+    else go(k_lb_tail<T, uint32_t, 3>);
   } else {
-    if (i32) go(k_lb_tail<T, uint32_t, false>);
-    else go(k_lb_tail<T, long long, false>);
+    if (v == 0) go(k_lb_tail<T, long long, 0>);
+    else if (v == 1) go(k_lb_tail<T, long long, 1>);
+    else if (v == 2) go(k_lb_tail<T, long long, 2>);
+    else go(k_lb_tail<T, long long, 3>);
   }
 }
 
@@ -342,14 +363,14 @@ void launch_mean_shift(const double* partials, int nblocks, double inv_n, double
                                        hipStream_t);                                         \
   template void launch_charge<T>(const T*, const uint32_t*, const double*, double*, double*, \
                                  const LBParams&, double, Dims, const SiteGrid&, hipStream_t,\
-                                 const BeadTableView&, double*, double*, int);               \
+                                 const BeadTableView&, double*, double*, int, bool);         \
   template int launch_lb_step<T>(const T*, T*, const uint32_t*, const double*,               \
                                  const LBParams&, const BeadTableView&, double*, int,        \
                                  uint32_t, Dims, const SiteGrid&, hipStream_t, hipEvent_t,   \
-                                 hipEvent_t, const NoiseParams*);                            \
+                                 hipEvent_t, const NoiseParams*, const WallView*);           \
   template void launch_lb_tail<T>(const T*, T*, uint32_t*, const double*, const LBParams&,   \
                                   const BeadTableView&, const int*, int, double*, int, int,  \
-                                  Dims, hipStream_t, const NoiseParams*);                    \
+                                  Dims, hipStream_t, const NoiseParams*, const WallView*);   \
   template void launch_moments<T>(const T*, const uint32_t*, int, double, double*, double*,  \
                                   Dims, hipStream_t);
 EK_INST(float)

@@ -22,6 +22,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "ek_context.h"
@@ -44,11 +45,15 @@ BeadState carve(char* mem, int maxb) {
   s.origin = (int*)take(maxb * 3 * 4 + 4);
   s.mom = (double*)take((size_t)maxb * BOX3 * MOM * 8 + 8);
   s.efield = (double*)take((size_t)maxb * BOX3 * 3 * 8 + 8);
-  s.flags = (unsigned char*)take((size_t)maxb * WIN3 + 8);
+  s.flags = (unsigned char*)take((size_t)maxb * WIN3_MAX + 8);
   s.err = (int*)take(64);
   s.cross = (int*)take((size_t)maxb * 3 * 4 + 4);
   return s;
 }
+
+// Wall reach of a chain (WallGeom): 1 for a WCA cut-off below two lattice
+// spacings, 2 below three.
+int wall_reach(double sigma) { return 1.122462048309373 * sigma < 2.0 ? 1 : 2; }
 
 // Empty table (once, when the context is created: the workspace arrives
 // uninitialised).
@@ -67,25 +72,29 @@ __global__ __launch_bounds__(256) void k_table_clear(int* keys, long long* vals,
 }
 
 __global__ __launch_bounds__(256) void k_deposit(BeadState bs, int n, int* keys, long long* vals,
-                                                 uint32_t* mask, Dims d, int bits) {
+                                                 uint32_t* mask, Dims d, int bits, int fluid_only) {
   deposit_items(bs, n, keys, vals, mask, d, bits, blockIdx.x * blockDim.x + threadIdx.x,
-                gridDim.x * blockDim.x);
+                gridDim.x * blockDim.x, fluid_only != 0);
 }
 
 // One block per bead: moments and field on the 4^3 box, flags on the 6^3 window.
-template <typename T>
+template <typename T, int WR>
 __global__ __launch_bounds__(256) void k_bead_box(BeadState bs, const T* __restrict__ f,
                                                   uint32_t* mask, const double* __restrict__ psi,
-                                                  LBParams lp, Dims d, int defer) {
-  bead_box_item(bs, blockIdx.x, threadIdx.x, f, mask, psi, lp, d, defer ? mask : nullptr);
+                                                  LBParams lp, Dims d, int defer,
+                                                  const double* face_q, double inv_eps) {
+  constexpr int items = WallGeom<WR>::W3 > BOX3 ? WallGeom<WR>::W3 : BOX3;
+  for (int t = threadIdx.x; t < items; t += blockDim.x)
+    bead_box_item<T, WR>(bs, blockIdx.x, t, f, mask, psi, lp, d, defer ? mask : nullptr, face_q,
+                         inv_eps);
 }
 
-template <bool LDS, int TPB, int MAXT>
+template <bool LDS, int TPB, int MAXT, int WR>
 __global__ __launch_bounds__(MAXT) void k_md(BeadState bs, MDParams mp, int* gkeys,
                                              long long* gvals, uint32_t* mask, Dims d,
                                              int gbits, int lds_bits) {
   extern __shared__ __align__(16) unsigned char smem[];
-  md_chain<LDS, TPB>(bs, mp, gkeys, gvals, mask, d, gbits, lds_bits, smem);
+  md_chain<LDS, TPB, true, WR>(bs, mp, gkeys, gvals, mask, d, gbits, lds_bits, smem);
 }
 
 __global__ void k_err_reset(int* err) {
@@ -114,7 +123,7 @@ size_t ek::bead_state_bytes(int maxb) {
   size_t t = 0;
   t += align256(maxb * 3 * 8 + 8) * 2 + align256(maxb * 8 + 8) + align256(maxb * 3 * 4 + 4);
   t += align256((size_t)maxb * BOX3 * MOM * 8 + 8) + align256((size_t)maxb * BOX3 * 3 * 8 + 8);
-  t += align256((size_t)maxb * WIN3 + 8) + align256(64);
+  t += align256((size_t)maxb * WIN3_MAX + 8) + align256(64);
   t += align256((size_t)maxb * 3 * 4 + 4);   // plane crossing record
   return t;
 }
@@ -147,7 +156,7 @@ ek_status ek_ctx::beads_deposit() {
   BeadState bs = carve(bead_mem, max_beads < 1 ? 1 : max_beads);
   launch_table_clear(keys, vals, mask, dims.n, stream);
   hipLaunchKernelGGL(k_deposit, dim3((8 * n_beads + 255) / 256), dim3(256), 0, stream, bs, n_beads,
-                     keys, vals, mask, dims, HASH_BITS);
+                     keys, vals, mask, dims, HASH_BITS, insulating() ? 1 : 0);
   return EK_OK;
 }
 
@@ -155,8 +164,13 @@ template <typename T>
 ek_status ek_ctx::beads_advance(bool overlap, hipEvent_t chain_end) {
   BeadState bs = carve(bead_mem, max_beads < 1 ? 1 : max_beads);
   const LBParams lp = lb_params();
-  hipLaunchKernelGGL(k_bead_box<T>, dim3(n_beads), dim3(256), 0, stream, bs, (const T*)fcur(),
-                     mask, psi, lp, dims, overlap ? 1 : 0);
+  const int wr = wall_reach(poly.sigma);
+  auto box = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3(n_beads), dim3(256), 0, stream, bs, (const T*)fcur(), mask, psi,
+                       lp, dims, overlap ? 1 : 0, insulating() ? wall_q : nullptr, inv_eps());
+  };
+  if (wr == 1) box(k_bead_box<T, 1>);
+  else box(k_bead_box<T, 2>);
   const hipStream_t cs = stream;   // the chain follows the box gather on the context stream
   if (overlap) {
     // the lattice update outside the boxes (launched by the caller on the
@@ -188,6 +202,9 @@ ek_status ek_ctx::beads_advance(bool overlap, hipEvent_t chain_end) {
   mp.track = cross_on ? 1 : 0;
   mp.step = (int)(step_count + 1);
   mp.z_plane = cross_plane;
+  mp.theta = poly.coupling == EK_COUPLE_THETA ? 1 : 0;
+  mp.half_sigma = 0.5 * poly.sigma;
+  mp.field_fluid = insulating() ? 1 : 0;
   if (p.fluctuations) {
     mp.thermal = 1;
     mp.key0 = uint32_t(p.seed & 0xFFFFFFFFull);
@@ -204,32 +221,40 @@ ek_status ek_ctx::beads_advance(bool overlap, hipEvent_t chain_end) {
     hipLaunchKernelGGL(kernel, dim3(1), dim3(threads), lds, cs, bs, mp, keys, vals, mask, dims,
                        HASH_BITS, bits);
   };
-  if (n_beads <= LDS_MAX_BEADS) {
-    int bits = 6;
-    while ((1 << bits) < 16 * n_beads) ++bits;          // load factor <= 1/2 for 8 corners/bead
-    const size_t lds = sr_bytes + ((size_t)1 << bits) * (9 * 8 + 4) + md_list_bytes(true, threads, 8);
-    if (lds > 64 * 1024 &&
-        hipFuncSetAttribute((const void*)k_md<true, 8, 512>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds) != hipSuccess)
-      return fail(EK_EHIP, "cannot raise the LDS limit of the chain kernel");
-    md(k_md<true, 8, 512>, lds, bits);
-  } else {
+  // the kernel instance for the chain's size and wall reach
+  auto launch = [&](auto wr_tag) -> ek_status {
+    constexpr int WR = decltype(wr_tag)::value;
+    if (n_beads <= LDS_MAX_BEADS) {
+      int bits = 6;
+      while ((1 << bits) < 16 * n_beads) ++bits;          // load factor <= 1/2 for 8 corners/bead
+      const size_t lds = sr_bytes + ((size_t)1 << bits) * (9 * 8 + 4) + md_list_bytes(true, threads, 8);
+      if (lds > 64 * 1024 &&
+          hipFuncSetAttribute((const void*)k_md<true, 8, 512, WR>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return fail(EK_EHIP, "cannot raise the LDS limit of the chain kernel");
+      md(k_md<true, 8, 512, WR>, lds, bits);
+      return EK_OK;
+    }
     // positions and the per-lane pair lists
     const size_t lds = sr_bytes + md_list_bytes(false, threads, tpb);
     if (tpb == 4) {
-      md(k_md<false, 4, 512>, lds, 0);
+      md(k_md<false, 4, 512, WR>, lds, 0);
     } else if (tpb == 2) {
-      md(k_md<false, 2, 512>, lds, 0);
+      md(k_md<false, 2, 512, WR>, lds, 0);
     } else if (threads <= 512) {
-      md(k_md<false, 1, 512>, lds, 0);
+      md(k_md<false, 1, 512, WR>, lds, 0);
     } else {
       if (lds > 64 * 1024 &&
-          hipFuncSetAttribute((const void*)k_md<false, 1, 1024>,
+          hipFuncSetAttribute((const void*)k_md<false, 1, 1024, WR>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return fail(EK_EHIP, "cannot raise the LDS limit of the chain kernel");
-      md(k_md<false, 1, 1024>, lds, 0);
+      md(k_md<false, 1, 1024, WR>, lds, 0);
     }
-  }
+    return EK_OK;
+  };
+  const ek_status lst = wr == 1 ? launch(std::integral_constant<int, 1>{})
+                                : launch(std::integral_constant<int, 2>{});
+  if (lst) return lst;
   if (chain_end && hipEventRecord(chain_end, cs) != hipSuccess)
     return fail(EK_EHIP, "recording the chain timer failed");
   return EK_OK;
@@ -266,8 +291,12 @@ extern "C" ek_status ek_set_polymer(ek_ctx* ctx, int32_t n, const double* pos, c
         (fene && (!(pp->R0 > 0) || !(pp->k_fene >= 0))) ||
         (!fene && (!(pp->k_bond >= 0) || !(pp->l_bond > 0))))
       return ctx->fail(EK_EINVAL, "invalid polymer parameters");
-    if (1.122462048309373 * pp->sigma >= 2.0)
-      return ctx->fail(EK_EINVAL, "WCA cut-off must stay below two lattice spacings");
+    if (1.122462048309373 * pp->sigma >= 3.0)
+      return ctx->fail(EK_EINVAL, "WCA cut-off must stay below three lattice spacings");
+    if (pp->coupling != EK_COUPLE_TRILINEAR && pp->coupling != EK_COUPLE_THETA)
+      return ctx->fail(EK_EINVAL, "unknown coupling");
+    if (pp->coupling == EK_COUPLE_THETA && !(pp->sigma >= 1.0 && pp->sigma <= 2.0))
+      return ctx->fail(EK_EINVAL, "the occupation cube needs 1 <= sigma <= 2");
     const Dims d = ctx->dims;
     for (int i = 0; i < n; ++i) {
       for (int c = 0; c < 3; ++c)

@@ -142,7 +142,128 @@ __global__ __launch_bounds__(BLOCK) void k_rho_to_b(const double* __restrict__ r
   block_partials<1>(acc, partials, bid, nblocks);
 }
 
+// ---------------------------------------------------------------------------
+// Insulating walls: the operator over the fluid sites only.  Bits 1..6 of the
+// link word mark the solid face neighbours (bit p: the site r - c_p is
+// solid): bit 1 the -x neighbour, 2 +x, 3 -y, 4 +y, 5 -z, 6 +z.  The walls'
+// surface charge is in b already (charge pass), so a solid face simply
+// drops out of the sum; b + shift is the right-hand side at fluid sites.
+// ---------------------------------------------------------------------------
+struct FaceNbrs {
+  long long xm, xp, ym, yp, zm, zp;
+};
+
+__device__ inline FaceNbrs face_nbrs(int x, int y, int z, const Dims& d) {
+  const int xm = x == 0 ? d.nx - 1 : x - 1, xp = x == d.nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
+  const long long nxy = (long long)d.nx * d.ny;
+  const long long row = z * nxy + (long long)y * d.nx;
+  return FaceNbrs{row + xm, row + xp, z * nxy + (long long)ym * d.nx + x,
+                  z * nxy + (long long)yp * d.nx + x, zm * nxy + (long long)y * d.nx + x,
+                  zp * nxy + (long long)y * d.nx + x};
+}
+
+// Sum of psi over the fluid face neighbours and their number.
+__device__ inline double open_sum(const double* __restrict__ psi, uint32_t m, const FaceNbrs& n,
+                                  int& k) {
+  double s = 0.0;
+  k = 0;
+  if (!(m & (1u << 1))) { s += psi[n.xm]; ++k; }
+  if (!(m & (1u << 2))) { s += psi[n.xp]; ++k; }
+  if (!(m & (1u << 3))) { s += psi[n.ym]; ++k; }
+  if (!(m & (1u << 4))) { s += psi[n.yp]; ++k; }
+  if (!(m & (1u << 5))) { s += psi[n.zm]; ++k; }
+  if (!(m & (1u << 6))) { s += psi[n.zp]; ++k; }
+  return s;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_sor_half_neu(double* __restrict__ psi,
+                                                        const double* __restrict__ b,
+                                                        const uint32_t* __restrict__ mask,
+                                                        const PoissonScalars* __restrict__ ps,
+                                                        int colour, double omega, Dims d) {
+  if (ps->done) return;
+  const int tx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (tx >= d.nx / 2 || y >= d.ny) return;
+  const int x = 2 * tx + ((colour + y + z) & 1);
+  const long long r = ((long long)z * d.ny + y) * d.nx + x;
+  const uint32_t m = mask[r];
+  if (m & MASK_SOLID) return;
+  int k;
+  const double nbsum = open_sum(psi, m, face_nbrs(x, y, z, d), k);
+  const double rhs = b[r] + ps->shift;
+  const double old = psi[r];
+  psi[r] = old + omega * ((nbsum - rhs) / double(k) - old);
+}
+
+// Partial sums of r^2, b^2 and psi over the fluid sites, r = b - A_N psi.
+__global__ __launch_bounds__(BLOCK) void k_residual_neu(const double* __restrict__ psi,
+                                                        const double* __restrict__ b,
+                                                        const uint32_t* __restrict__ mask,
+                                                        const PoissonScalars* __restrict__ ps,
+                                                        double* __restrict__ partials, Dims d) {
+  if (ps->done) return;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const int nblocks = gridDim.x * gridDim.y * gridDim.z;
+  double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kz = 0; kz < RESIDUAL_PLANES; ++kz) {
+    const int z = blockIdx.z * RESIDUAL_PLANES + kz;
+    if (x < d.nx && y < d.ny && z < d.nz) {
+      const long long r = ((long long)z * d.ny + y) * d.nx + x;
+      const uint32_t m = mask[r];
+      if (!(m & MASK_SOLID)) {
+        int k;
+        const double c = psi[r];
+        const double lap = open_sum(psi, m, face_nbrs(x, y, z, d), k) - double(k) * c;
+        const double rhs = b[r] + ps->shift;
+        const double res = rhs - lap;
+        acc[0] += res * res;
+        acc[1] += rhs * rhs;
+        acc[2] += c;
+      }
+    }
+  }
+  block_partials<3>(acc, partials, bid, nblocks);
+}
+
+// psi - (fluid mean of psi) at fluid sites, 0 at solid sites.
+__global__ __launch_bounds__(BLOCK) void k_psi_shift_neu(double* __restrict__ psi,
+                                                         const uint32_t* __restrict__ mask,
+                                                         const PoissonScalars* __restrict__ ps,
+                                                         double inv_nf, long long n) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  psi[r] = (ps->zero_rhs || (mask[r] & MASK_SOLID)) ? 0.0 : psi[r] - ps->psum * inv_nf;
+}
+
 }  // namespace
+
+void launch_sor_half_neu(double* psi, const double* b, const uint32_t* mask,
+                         const PoissonScalars* ps, int colour, double omega, Dims d,
+                         const SiteGrid& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_sor_half_neu, g.grid, g.block, 0, s, psi, b, mask, ps, colour, omega, d);
+}
+
+int launch_residual_neu(const double* psi, const double* b, const uint32_t* mask,
+                        PoissonScalars* ps, double* partials, Dims d, const SiteGrid& g,
+                        hipStream_t s) {
+  dim3 grid = g.grid;
+  grid.z = (d.nz + RESIDUAL_PLANES - 1) / RESIDUAL_PLANES;
+  hipLaunchKernelGGL(k_residual_neu, grid, g.block, 0, s, psi, b, mask, ps, partials, d);
+  return int(grid.x * grid.y * grid.z);
+}
+
+void launch_psi_shift_neu(double* psi, const uint32_t* mask, const PoissonScalars* ps,
+                          double inv_nf, Dims d, hipStream_t s) {
+  const int blocks = int((d.n + BLOCK - 1) / BLOCK);
+  hipLaunchKernelGGL(k_psi_shift_neu, dim3(blocks), dim3(BLOCK), 0, s, psi, mask, ps, inv_nf, d.n);
+}
 
 void launch_sor_half(double* psi, const double* b, const PoissonScalars* ps, int colour,
                      double omega, Dims d, const SiteGrid& g, hipStream_t s) {

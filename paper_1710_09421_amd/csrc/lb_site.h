@@ -95,7 +95,10 @@ __device__ inline T recip(T x) {
 
 // Charge density at site (x, y, z): sum of z^a n^a over the charged species
 // (fluid sites), the fixed wall charge and the beads' deposited charge.
-template <typename T, typename I = long long>
+// With NEU (insulating walls) solid sites carry nothing and a fluid site adds
+// the surface charge of its wall faces (stored at the solid face neighbours,
+// `wall_q` then holding Sigma_f).
+template <typename T, typename I = long long, bool NEU = false>
 __device__ inline double charge_site(const T* __restrict__ f, const uint32_t* __restrict__ mask,
                                      const double* __restrict__ wall_q, const LBParams& lp,
                                      const BeadTableView& bt, int x, int y, int z, const Dims& d) {
@@ -103,7 +106,8 @@ __device__ inline double charge_site(const T* __restrict__ f, const uint32_t* __
   const I r = (I(z) * I(d.ny) + I(y)) * I(d.nx) + I(x);
   const uint32_t m = mask[r];
   double rho = 0.0;
-  if (m & MASK_CHARGED) rho += wall_q[r];
+  if (NEU && (m & MASK_SOLID)) return 0.0;
+  if (!NEU && (m & MASK_CHARGED)) rho += wall_q[r];
   if (!(m & MASK_SOLID)) {
     const NbrT<I> nb = neighbours_t<I>(x, y, z, d);
 #pragma unroll
@@ -116,6 +120,11 @@ __device__ inline double charge_site(const T* __restrict__ f, const uint32_t* __
       for (int p = 0; p < Q; ++p) dn += g[p];
       rho += lp.valence[s] * (lp.nref[s] + double(dn));
     }
+    if constexpr (NEU) {
+#pragma unroll
+      for (int p = 1; p <= 6; ++p)
+        if ((m >> p) & 1u) rho += wall_q[nb.zo[1 - CZ[p]] + nb.yo[1 - CY[p]] + nb.xo[1 - CX[p]]];
+    }
   }
   if (m & MASK_BEAD) rho += bt.charge_at(r);
   return rho;
@@ -127,12 +136,13 @@ __device__ inline double charge_site(const T* __restrict__ f, const uint32_t* __
 // (philox.h), aligned store.  Adds the site's species masses and momentum of
 // f(t) to acc[0..5] (float64).  Sites whose link word has one of the `skip`
 // bits are left alone; returns whether the site was updated.
-template <typename T, typename I = long long, int NA, bool FLUCT = false>
+template <typename T, typename I = long long, int NA, bool FLUCT = false, bool NEU = false>
 __device__ inline bool lb_site(const T* __restrict__ fsrc, T* __restrict__ fdst,
                                const uint32_t* __restrict__ mask, const double* __restrict__ psi,
                                const LBParams& lp, const BeadTableView& bt, int x, int y, int z,
                                const Dims& d, double (&acc)[NA], uint32_t skip = 0u,
-                               const NoiseParams* noise = nullptr) {
+                               const NoiseParams* noise = nullptr,
+                               const WallView* walls = nullptr) {
   static_assert(NA >= 6, "masses and momentum take six sums");
   const I N = I(d.n);
   const I r = (I(z) * I(d.ny) + I(y)) * I(d.nx) + I(x);
@@ -145,10 +155,24 @@ __device__ inline bool lb_site(const T* __restrict__ fsrc, T* __restrict__ fdst,
     for (int s = 0; s < 3; ++s)
       pull<T, I>(Planes<T, I>(fsrc + (size_t)s * Q * d.n, N), r, m, nb, N, g[s]);
 
-    // electric field E = -grad psi (central differences) + applied field
-    const T ex = T(-0.5 * (psi[nb.zo[1] + nb.yo[1] + nb.xo[2]] - psi[nb.zo[1] + nb.yo[1] + nb.xo[0]]) + lp.eext[0]);
-    const T ey = T(-0.5 * (psi[nb.zo[1] + nb.yo[2] + nb.xo[1]] - psi[nb.zo[1] + nb.yo[0] + nb.xo[1]]) + lp.eext[1]);
-    const T ez = T(-0.5 * (psi[nb.zo[2] + nb.yo[1] + nb.xo[1]] - psi[nb.zo[0] + nb.yo[1] + nb.xo[1]]) + lp.eext[2]);
+    // electric field E = -grad psi (central differences) + applied field;
+    // with insulating walls a solid face neighbour is replaced by the ghost
+    // value psi_r + Sigma_f / eps of its face (bit p of the link word: the
+    // neighbour r - c_p is solid; bits 1/2 are -x/+x, 3/4 -y/+y, 5/6 -z/+z)
+    T ex, ey, ez;
+    if constexpr (NEU) {
+      const double pc = psi[r];
+      auto side = [&](int bit, I idx) -> double {
+        return ((m >> bit) & 1u) ? pc + walls->face_q[idx] * walls->inv_eps : psi[idx];
+      };
+      ex = T(-0.5 * (side(2, nb.zo[1] + nb.yo[1] + nb.xo[2]) - side(1, nb.zo[1] + nb.yo[1] + nb.xo[0])) + lp.eext[0]);
+      ey = T(-0.5 * (side(4, nb.zo[1] + nb.yo[2] + nb.xo[1]) - side(3, nb.zo[1] + nb.yo[0] + nb.xo[1])) + lp.eext[1]);
+      ez = T(-0.5 * (side(6, nb.zo[2] + nb.yo[1] + nb.xo[1]) - side(5, nb.zo[0] + nb.yo[1] + nb.xo[1])) + lp.eext[2]);
+    } else {
+      ex = T(-0.5 * (psi[nb.zo[1] + nb.yo[1] + nb.xo[2]] - psi[nb.zo[1] + nb.yo[1] + nb.xo[0]]) + lp.eext[0]);
+      ey = T(-0.5 * (psi[nb.zo[1] + nb.yo[2] + nb.xo[1]] - psi[nb.zo[1] + nb.yo[0] + nb.xo[1]]) + lp.eext[1]);
+      ez = T(-0.5 * (psi[nb.zo[2] + nb.yo[1] + nb.xo[1]] - psi[nb.zo[0] + nb.yo[1] + nb.xo[1]]) + lp.eext[2]);
+    }
 
     double kb[3][3];
     const bool has_bead = (m & MASK_BEAD) != 0;

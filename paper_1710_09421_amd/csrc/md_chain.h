@@ -17,6 +17,21 @@ constexpr int BOX = 4;          // moment box edge (nodes floor(R0) - 1 .. floor
 constexpr int BOX3 = BOX * BOX * BOX;
 constexpr int WIN = 6;          // flag window edge (nodes floor(R0) - 2 .. floor(R0) + 3)
 constexpr int WIN3 = WIN * WIN * WIN;
+
+// Wall reach WR: the bead-wall WCA looks at the wall sites floor(R) - WR ..
+// floor(R) + 1 + WR in each axis (an S^3 cube around the bead's cell), which
+// holds every site closer than WR + 1 to the bead: WR = 1 for a cut-off
+// 2^(1/6) sigma below 2, WR = 2 below 3.  Since the bead stays within one
+// cell of its start over a step, the flag window of the step spans
+// floor(R0) - 1 - WR .. floor(R0) + 2 + WR, W = 2 WR + 4 sites per axis.
+template <int WR>
+struct WallGeom {
+  static constexpr int S = 2 * WR + 2;
+  static constexpr int S3 = S * S * S;
+  static constexpr int W = 2 * WR + 4;
+  static constexpr int W3 = W * W * W;
+};
+constexpr int WIN3_MAX = WallGeom<2>::W3;   // per-bead flag storage of a single context
 constexpr int MOM = 15;         // x[3] (n^a / n), 1/n^a [3], j[3][3]
 
 enum : int { ERR_BOX = 1, ERR_FLUID = 2, ERR_BOND = 4, ERR_TABLE = 8 };
@@ -28,7 +43,7 @@ struct BeadState {
   int* origin;        // [maxb][3] floor(R0) - 1 of the current step
   double* mom;        // [maxb][BOX3][MOM]
   double* efield;     // [maxb][BOX3][3]
-  unsigned char* flags;  // [maxb][WIN3]: bit0 fluid, bit1 wall
+  unsigned char* flags;  // [maxb][W3 of the wall reach]: bit0 fluid, bit1 wall
   int* err;           // error bits
   int* cross = nullptr;  // [maxb][3] plane crossings: first step, last step, net count
 };
@@ -103,6 +118,13 @@ struct MDParams {
   int thermal = 0;
   uint32_t key0 = 0, key1 = 0, tstep = 0;
   double xi_scale = 0.0;
+  // coupling kernel: 0 trilinear, 1 the occupation cube of side 2 half_sigma
+  // (Eq. totalforcefluid) for the velocity at the bead and the friction
+  int theta = 0;
+  double half_sigma = 0.5;
+  // insulating walls: the field at the bead with the trilinear weights
+  // renormalised over the fluid corners (where its charge was deposited)
+  int field_fluid = 0;
 };
 
 __device__ inline double min_image(double v, double L) { return v - L * rint(v / L); }
@@ -217,18 +239,30 @@ __device__ inline void table_clear_items(int* keys, long long* vals, uint32_t* m
   }
 }
 
-// Bead charges on the 8 corner nodes with the plain trilinear weights.
+// Bead charges on the 8 corner nodes with the plain trilinear weights, or
+// (fluid_only, insulating walls) with the weights renormalised over the
+// fluid corners.
 __device__ inline void deposit_items(const BeadState& bs, int n, int* keys, long long* vals,
                                      uint32_t* mask, const Dims& d, int bits, int tid,
-                                     int nthreads) {
+                                     int nthreads, bool fluid_only = false) {
   for (int t = tid; t < 8 * n; t += nthreads) {
     const int i = t >> 3, k = t & 7;
     const double* R = bs.R + 3 * i;
     const double fx = floor(R[0]), fy = floor(R[1]), fz = floor(R[2]);
     const double dx = R[0] - fx, dy = R[1] - fy, dz = R[2] - fz;
     const int ox = k & 1, oy = (k >> 1) & 1, oz = (k >> 2) & 1;
-    const double w = (ox ? dx : 1.0 - dx) * (oy ? dy : 1.0 - dy) * (oz ? dz : 1.0 - dz);
+    double w = (ox ? dx : 1.0 - dx) * (oy ? dy : 1.0 - dy) * (oz ? dz : 1.0 - dz);
     const long long site = site_of(int(fx) + ox, int(fy) + oy, int(fz) + oz, d);
+    if (fluid_only) {
+      if (mask[site] & MASK_SOLID) continue;
+      double wsum = 0.0;
+      for (int k2 = 0; k2 < 8; ++k2) {
+        const int px = k2 & 1, py = (k2 >> 1) & 1, pz = (k2 >> 2) & 1;
+        if (mask[site_of(int(fx) + px, int(fy) + py, int(fz) + pz, d)] & MASK_SOLID) continue;
+        wsum += (px ? dx : 1.0 - dx) * (py ? dy : 1.0 - dy) * (pz ? dz : 1.0 - dz);
+      }
+      w /= wsum;
+    }
     const int h = table_insert(keys, mask, site, bs.err, bits);
     if (h < 0) continue;
     atomicAdd((unsigned long long*)&vals[(size_t)h * SLOT_VALUES],
@@ -236,16 +270,21 @@ __device__ inline void deposit_items(const BeadState& bs, int n, int* keys, long
   }
 }
 
-// Fields of time t around bead i: item t < WIN3 sets the fluid / wall flags of
-// the 6^3 window, item t < BOX3 the moments and field of one node of the 4^3
-// box.  The box origin is written by item 0.  With `defer` set, every box
-// node is also flagged MASK_DEFER: the chain's friction can only reach nodes
-// of the boxes, so the lattice update of all other sites need not wait for it.
-template <typename T>
+// Fields of time t around bead i: item t < W3 sets the fluid / wall flags of
+// the flag window (W^3 for the wall reach WR), item t < BOX3 the moments and
+// field of one node of the 4^3 box.  The box origin is written by item 0.
+// With `defer` set, every box node is also flagged MASK_DEFER: the chain's
+// friction can only reach nodes of the boxes, so the lattice update of all
+// other sites need not wait for it.
+// With `walls` (insulating walls) the field at a fluid node takes the ghost
+// value psi + Sigma_f / eps for a solid face neighbour, and is 0 at a solid
+// node (the beads then interpolate it over fluid corners only).
+template <typename T, int WR = 1>
 __device__ inline void bead_box_item(const BeadState& bs, int i, int t, const T* __restrict__ f,
                                      const uint32_t* mask,
                                      const double* __restrict__ psi, const LBParams& lp,
-                                     const Dims& d, uint32_t* defer = nullptr) {
+                                     const Dims& d, uint32_t* defer = nullptr,
+                                     const double* face_q = nullptr, double inv_eps = 0.0) {
   const double* R = bs.R + 3 * i;
   const int bx = int(floor(R[0])) - 1, by = int(floor(R[1])) - 1, bz = int(floor(R[2])) - 1;
   if (t == 0) {
@@ -253,10 +292,11 @@ __device__ inline void bead_box_item(const BeadState& bs, int i, int t, const T*
     bs.origin[3 * i + 1] = by;
     bs.origin[3 * i + 2] = bz;
   }
-  if (t < WIN3) {
-    const int wx = t % WIN, wy = (t / WIN) % WIN, wz = t / (WIN * WIN);
-    const uint32_t m = mask[site_of(bx - 1 + wx, by - 1 + wy, bz - 1 + wz, d)];
-    bs.flags[(size_t)i * WIN3 + t] =
+  using G = WallGeom<WR>;
+  if (t < G::W3) {
+    const int wx = t % G::W, wy = (t / G::W) % G::W, wz = t / (G::W * G::W);
+    const uint32_t m = mask[site_of(bx - WR + wx, by - WR + wy, bz - WR + wz, d)];
+    bs.flags[(size_t)i * G::W3 + t] =
         (unsigned char)(((m & MASK_SOLID) ? 0 : 1) | ((m & MASK_WALL) ? 2 : 0));
   }
   if (t >= BOX3) return;
@@ -307,6 +347,22 @@ __device__ inline void bead_box_item(const BeadState& bs, int i, int t, const T*
 #pragma unroll
   for (int c = 0; c < MOM; ++c) mo[c] = v[c];
   double* e = bs.efield + ((size_t)i * BOX3 + t) * 3;
+  if (face_q) {
+    if (m & MASK_SOLID) {
+      e[0] = e[1] = e[2] = 0.0;
+      return;
+    }
+    const double pc = psi[r];
+    // bit p of the link word: the neighbour r - c_p is solid (1/2: -x/+x,
+    // 3/4: -y/+y, 5/6: -z/+z)
+    auto side = [&](int bit, long long idx) {
+      return ((m >> bit) & 1u) ? pc + face_q[idx] * inv_eps : psi[idx];
+    };
+    e[0] = -0.5 * (side(2, site_of(cx + 1, cy, cz, d)) - side(1, site_of(cx - 1, cy, cz, d))) + lp.eext[0];
+    e[1] = -0.5 * (side(4, site_of(cx, cy + 1, cz, d)) - side(3, site_of(cx, cy - 1, cz, d))) + lp.eext[1];
+    e[2] = -0.5 * (side(6, site_of(cx, cy, cz + 1, d)) - side(5, site_of(cx, cy, cz - 1, d))) + lp.eext[2];
+    return;
+  }
   e[0] = -0.5 * (psi[site_of(cx + 1, cy, cz, d)] - psi[site_of(cx - 1, cy, cz, d)]) + lp.eext[0];
   e[1] = -0.5 * (psi[site_of(cx, cy + 1, cz, d)] - psi[site_of(cx, cy - 1, cz, d)]) + lp.eext[1];
   e[2] = -0.5 * (psi[site_of(cx, cy, cz + 1, d)] - psi[site_of(cx, cy, cz - 1, d)]) + lp.eext[2];
@@ -339,10 +395,12 @@ __host__ __device__ inline size_t md_list_bytes(bool lds_table, int threads, int
 // with LISTS the pair lists (md_list_bytes; without them every lane walks all
 // its candidate partners each substep: the persistent ensemble kernel, whose
 // registers the lists would spill).
-template <bool LDS, int TPB, bool LISTS = true>
+template <bool LDS, int TPB, bool LISTS = true, int WR = 1>
 __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gkeys,
                                 long long* gvals, uint32_t* mask, const Dims& d, int gbits,
                                 int lds_bits, unsigned char* smem) {
+  using G = WallGeom<WR>;
+  constexpr int WIN = G::W;                                    // flag window edge
   constexpr int CPL = 8 / TPB;                                 // corners per lane
   double* sR = (double*)smem;                                  // [3 * n]
   long long* lvals = (long long*)(smem + (((size_t)mp.n * 24 + 15) & ~size_t(15)));
@@ -396,7 +454,7 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
   const double iR02 = 1.0 / (mp.R0 * mp.R0);
   const double* mom = bs.mom + (size_t)(live ? i : 0) * BOX3 * MOM;
   const double* ef = bs.efield + (size_t)(live ? i : 0) * BOX3 * 3;
-  const unsigned char* fl = bs.flags + (size_t)(live ? i : 0) * WIN3;
+  const unsigned char* fl = bs.flags + (size_t)(live ? i : 0) * G::W3;
   int cell[3] = {INT_MIN, INT_MIN, INT_MIN};
   int slot[CPL], bidx[CPL];
   double wfl[CPL];
@@ -407,10 +465,14 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
   // its cell on; with more corners per lane they are read each substep.
   constexpr bool CACHE = CPL <= 2;   // node momenta too
   constexpr bool CACHE_E = CPL <= 4; // field and wall flags
-  constexpr int NWS = 64 / TPB;     // wall sites per lane
+  constexpr int NWS = G::S3 / TPB;  // wall sites per lane
+  static_assert(G::S3 % TPB == 0, "wall sites split evenly over a bead's lanes");
+  constexpr int NWB = (NWS + 63) / 64;
   double mo_c[CACHE ? CPL : 1][MOM];
   double e_c[CACHE_E ? CPL : 1][3];
-  unsigned long long wall_bits = 0;
+  unsigned long long wall_bits[NWB];
+#pragma unroll
+  for (int b = 0; b < NWB; ++b) wall_bits[b] = 0;
   // this lane's share of q E(R(t)): the field is interpolated once, with the
   // plain weights at the position where the bead's charge was deposited for
   // this step's solve (the electrostatic forces on ions, walls and beads then
@@ -464,7 +526,7 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
 #pragma unroll
         for (int k8 = 0; k8 < 8; ++k8) {
           const int ox = k8 & 1, oy = (k8 >> 1) & 1, oz = (k8 >> 2) & 1;
-          const int wi = (lx + ox + 1) + WIN * ((ly + oy + 1) + WIN * (lz + oz + 1));
+          const int wi = (lx + ox + WR) + WIN * ((ly + oy + WR) + WIN * (lz + oz + WR));
           fl_all[k8] = (fl[wi] & 1) ? 1.0 : 0.0;
         }
 #pragma unroll
@@ -474,7 +536,7 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
           bidx[a] = (lx + ox) + BOX * ((ly + oy) + BOX * (lz + oz));
           // from the flag window, not fl_all[k8]: k8 depends on the lane, and
           // a register array indexed at run time would live in scratch memory
-          wfl[a] = (fl[(lx + ox + 1) + WIN * ((ly + oy + 1) + WIN * (lz + oz + 1))] & 1) ? 1.0 : 0.0;
+          wfl[a] = (fl[(lx + ox + WR) + WIN * ((ly + oy + WR) + WIN * (lz + oz + WR))] & 1) ? 1.0 : 0.0;
           slot[a] = -1;
           if (wfl[a] != 0.0) {
             const long long site = site_of(fx + ox, fy + oy, fz + oz, d);
@@ -495,15 +557,16 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
           }
         }
         if constexpr (CACHE_E) {
-          wall_bits = 0;
+#pragma unroll
+          for (int b = 0; b < NWB; ++b) wall_bits[b] = 0;
 #pragma unroll
           for (int k = 0; k < NWS; ++k) {
             const int wsite = lane + k * TPB;
-            const int wx = wsite & 3, wy = (wsite >> 2) & 3, wz = wsite >> 4;
-            const int ix = fx - 1 + wx - org[0] + 1, iy = fy - 1 + wy - org[1] + 1,
-                      iz = fz - 1 + wz - org[2] + 1;
+            const int wx = wsite % G::S, wy = (wsite / G::S) % G::S, wz = wsite / (G::S * G::S);
+            // site floor(R) - WR + w sits at window index (floor(R) - org) + w
+            const int ix = lx + wx, iy = ly + wy, iz = lz + wz;
             if (ix < 0 || ix >= WIN || iy < 0 || iy >= WIN || iz < 0 || iz >= WIN) continue;
-            if (fl[ix + WIN * (iy + WIN * iz)] & 2) wall_bits |= 1ull << k;
+            if (fl[ix + WIN * (iy + WIN * iz)] & 2) wall_bits[k >> 6] |= 1ull << (k & 63);
           }
         }
       }
@@ -519,18 +582,28 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
           for (int k = 0; k < 9; ++k)
             kpre[a][k] = slot[a] < 0 ? 0.0 : (LDS ? ln.get(slot[a], k) : gn.get(slot[a], k));
       }
-      // plain and fluid-renormalised trilinear weights
-      double wsum = 0.0;
+      // plain and fluid-renormalised trilinear weights; with the occupation
+      // cube, its node indicator per axis (offset 0: d < sigma/2, offset 1:
+      // d >= 1 - sigma/2) renormalised over the fluid nodes
+      auto cube = [&](int ox, int oy, int oz) {
+        const double hs = mp.half_sigma;
+        return ((ox ? dx >= 1.0 - hs : dx < hs) && (oy ? dy >= 1.0 - hs : dy < hs) &&
+                (oz ? dz >= 1.0 - hs : dz < hs)) ? 1.0 : 0.0;
+      };
+      double wsum = 0.0, wsum_c = 0.0;
 #pragma unroll
       for (int k8 = 0; k8 < 8; ++k8) {
         const int ox = k8 & 1, oy = (k8 >> 1) & 1, oz = (k8 >> 2) & 1;
         wsum += fl_all[k8] * (ox ? dx : 1.0 - dx) * (oy ? dy : 1.0 - dy) * (oz ? dz : 1.0 - dz);
+        if (mp.theta) wsum_c += fl_all[k8] * cube(ox, oy, oz);
       }
-      if (!(wsum > 0.0)) {
+      if (!mp.theta) wsum_c = wsum;
+      if (!(wsum_c > 0.0) || !(wsum > 0.0)) {
         if (lane == 0) atomicOr(bs.err, ERR_FLUID);
-        wsum = 1.0;
+        wsum = wsum > 0.0 ? wsum : 1.0;
+        wsum_c = wsum_c > 0.0 ? wsum_c : 1.0;
       }
-      const double iws = 1.0 / wsum;
+      const double iws = 1.0 / wsum_c;
       // this lane's corners: velocities from the node momentum (populations of
       // time t plus the friction impulse of earlier substeps), composition,
       // and on the first substep the electric field with the plain weights
@@ -542,11 +615,12 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
         const int k8 = lane * CPL + a;
         const int ox = k8 & 1, oy = (k8 >> 1) & 1, oz = (k8 >> 2) & 1;
         const double w = (ox ? dx : 1.0 - dx) * (oy ? dy : 1.0 - dy) * (oz ? dz : 1.0 - dz);
-        wt[a] = w * wfl[a] * iws;
+        wt[a] = (mp.theta ? cube(ox, oy, oz) : w) * wfl[a] * iws;
         if (sub == 0) {
           const double* e = CACHE_E ? e_c[CACHE_E ? a : 0] : ef + (size_t)bidx[a] * 3;
+          const double we = mp.field_fluid ? w * wfl[a] / wsum : w;
 #pragma unroll
-          for (int c = 0; c < 3; ++c) qe[c] += q * w * e[c];
+          for (int c = 0; c < 3; ++c) qe[c] += q * we * e[c];
         }
         if (wt[a] != 0.0) {
           const double* mo = CACHE ? mo_c[CACHE ? a : 0] : mom + (size_t)bidx[a] * MOM;
@@ -627,7 +701,7 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
           }
       }
       // WCA against wall-site centres: site k of this lane is lane + k TPB of
-      // the 4^3 sites around the bead's cell
+      // the S^3 sites around the bead's cell
       auto wall_at = [&](int ax, int ay, int az) {
         const double dv[3] = {R[0] - ax, R[1] - ay, R[2] - az};
         const double r2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
@@ -641,18 +715,21 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
       };
       if constexpr (CACHE_E) {
         // only the wall sites among them, in increasing k
-        for (unsigned long long mb = wall_bits; mb; mb &= mb - 1) {
-          const int wsite = lane + __builtin_ctzll(mb) * TPB;
-          wall_at(fx - 1 + (wsite & 3), fy - 1 + ((wsite >> 2) & 3), fz - 1 + (wsite >> 4));
-        }
+#pragma unroll
+        for (int b = 0; b < NWB; ++b)
+          for (unsigned long long mb = wall_bits[b]; mb; mb &= mb - 1) {
+            const int wsite = lane + (64 * b + __builtin_ctzll(mb)) * TPB;
+            wall_at(fx - WR + wsite % G::S, fy - WR + (wsite / G::S) % G::S,
+                    fz - WR + wsite / (G::S * G::S));
+          }
       } else {
         for (int k = 0; k < NWS; ++k) {
           const int wsite = lane + k * TPB;
-          const int ax = fx - 1 + (wsite & 3), ay = fy - 1 + ((wsite >> 2) & 3), az = fz - 1 + (wsite >> 4);
-          const int ix = ax - org[0] + 1, iy = ay - org[1] + 1, iz = az - org[2] + 1;
+          const int wx = wsite % G::S, wy = (wsite / G::S) % G::S, wz = wsite / (G::S * G::S);
+          const int ix = lx + wx, iy = ly + wy, iz = lz + wz;
           if (ix < 0 || ix >= WIN || iy < 0 || iy >= WIN || iz < 0 || iz >= WIN) continue;
           if (!(fl[ix + WIN * (iy + WIN * iz)] & 2)) continue;
-          wall_at(ax, ay, az);
+          wall_at(fx - WR + wx, fy - WR + wy, fz - WR + wz);
         }
       }
       if (bond_lane) {

@@ -77,6 +77,8 @@ extern "C" ek_status ek_poisson_solve_noalloc(const ek_params* p, const double* 
   if (ek_workspace_bytes(p, 0, &ws) != EK_OK) return EK_EINVAL;   // message already set
   if (p->poisson_method != EK_POISSON_SOR)
     return fail(EK_EINVAL, "the no-allocation solve runs red-black SOR (EK_POISSON_SOR) only");
+  if (p->walls != EK_WALLS_PERIODIC)
+    return fail(EK_EINVAL, "the no-allocation solve is the periodic problem (EK_WALLS_PERIODIC)");
   if (warm_start != EK_WS_ZERO && warm_start != EK_WS_PREV && warm_start != EK_WS_EXTRAP)
     return fail(EK_EINVAL, "warm_start must be EK_WS_ZERO, EK_WS_PREV or EK_WS_EXTRAP");
   if (!dev_rho || !dev_psi) return fail(EK_EINVAL, "NULL device buffer");

@@ -116,8 +116,8 @@ ek_status ek_save_state(ek_ctx* ctx, void* host, size_t bytes) {
   };
   const BeadState bs = bead_state_view(ctx->bead_mem, ctx->max_beads);
   const size_t nb = (size_t)ctx->n_beads;
-  bool ok = d2h(s.wall_q, ctx->wall_q, d.n * 8) && d2h(s.f, ctx->fcur(), 3 * Q * d.n * tsz) &&
-            d2h(s.psi, ctx->psi, d.n * 8);
+  std::memcpy(pay + s.wall_q, ctx->host_wall_q.data(), d.n * 8);
+  bool ok = d2h(s.f, ctx->fcur(), 3 * Q * d.n * tsz) && d2h(s.psi, ctx->psi, d.n * 8);
   if (ok && ctx->p.warm_start == EK_WS_EXTRAP) ok = d2h(s.psi_old, ctx->psi_old, d.n * 8);
   if (ok && nb) ok = d2h(s.R, bs.R, nb * 24) && d2h(s.V, bs.V, nb * 24) && d2h(s.cross, bs.cross, nb * 12);
   if (!ok) return ctx->fail(EK_EHIP, "copying the state to the host failed");

@@ -31,16 +31,23 @@ class ek_params(ctypes.Structure):
                 ("F_ext", (c_double * 3) * 3), ("poisson_method", c_int32),
                 ("poisson_tol", c_double), ("poisson_max_iter", c_int32),
                 ("poisson_check_every", c_int32), ("rho_jacobi", c_double),
-                ("warm_start", c_int32), ("seed", c_uint64), ("fluctuations", c_int32)]
+                ("warm_start", c_int32), ("seed", c_uint64), ("fluctuations", c_int32),
+                ("walls", c_int32)]
 
 
 class ek_polymer_params(ctypes.Structure):
     _fields_ = [("M", c_double), ("k_fene", c_double), ("R0", c_double), ("eps", c_double),
                 ("sigma", c_double), ("gamma", c_double), ("n_sub", c_int32), ("bond", c_int32),
-                ("k_bond", c_double), ("l_bond", c_double)]
+                ("k_bond", c_double), ("l_bond", c_double), ("coupling", c_int32)]
 
 
 EK_BOND_FENE, EK_BOND_HARMONIC = 0, 1
+EK_COUPLE_TRILINEAR, EK_COUPLE_THETA = 0, 1
+EK_WALLS_PERIODIC, EK_WALLS_INSULATING = 0, 1
+
+
+def _coupling_code(coupling):
+    return {"trilinear": EK_COUPLE_TRILINEAR, "theta": EK_COUPLE_THETA}.get(coupling, coupling)
 
 
 def _bond_code(bond):
@@ -198,7 +205,7 @@ def make_params(shape, precision=EK_FP32, valence=(0.0, 1.0, -1.0), tau=(1.0, 1.
                 omega_drag=(1.0, 1.0, 1.0), kT=1.0 / 3.0, bjerrum=0.7, E_ext=(0.0, 0.0, 0.0),
                 F_ext=None, poisson_method=EK_POISSON_SOR, poisson_tol=1e-8,
                 poisson_max_iter=100000, poisson_check_every=1, rho_jacobi=0.0,
-                warm_start=EK_WS_PREV, fluctuations=0, seed=0):
+                warm_start=EK_WS_PREV, fluctuations=0, seed=0, walls=EK_WALLS_PERIODIC):
     nz, ny, nx = shape
     p = ek_params()
     p.nx, p.ny, p.nz = nx, ny, nz
@@ -215,6 +222,7 @@ def make_params(shape, precision=EK_FP32, valence=(0.0, 1.0, -1.0), tau=(1.0, 1.
     p.poisson_max_iter, p.poisson_check_every = poisson_max_iter, poisson_check_every
     p.rho_jacobi, p.warm_start = rho_jacobi, warm_start
     p.seed, p.fluctuations = int(seed), int(fluctuations)
+    p.walls = {"periodic": EK_WALLS_PERIODIC, "insulating": EK_WALLS_INSULATING}.get(walls, walls)
     return p
 
 
@@ -266,12 +274,13 @@ class Context:
         self._check(self._lib.ek_set_species_density(self._h, species, _ptr(a)), self._h)
 
     def set_polymer(self, pos, vel, charge, M=1.0, k_fene=30.0, R0=1.5, eps=1.0, sigma=1.0,
-                    gamma=20.0, n_sub=40, bond="fene", k_bond=0.0, l_bond=0.0):
+                    gamma=20.0, n_sub=40, bond="fene", k_bond=0.0, l_bond=0.0,
+                    coupling="trilinear"):
         pos = np.ascontiguousarray(pos, dtype=np.float64)
         vel = np.ascontiguousarray(vel, dtype=np.float64)
         q = np.ascontiguousarray(charge, dtype=np.float64)
         pp = ek_polymer_params(M, k_fene, R0, eps, sigma, gamma, n_sub, _bond_code(bond), k_bond,
-                               l_bond)
+                               l_bond, _coupling_code(coupling))
         self._check(self._lib.ek_set_polymer(self._h, pos.shape[0], _ptr(pos), _ptr(vel), _ptr(q),
                                              byref(pp)), self._h)
 
@@ -395,6 +404,7 @@ def from_workload(wl, precision=EK_FP32, poisson_method=EK_POISSON_SOR, poisson_
         ctx.set_polymer(wl.beads_R, wl.beads_V, pp["q"], M=pp["M"], k_fene=pp["k_fene"],
                         R0=pp["R0"], eps=pp["eps"], sigma=pp["sigma"], gamma=pp["gamma"],
                         n_sub=pp["n_sub"], bond=pp.get("bond", "fene"), k_bond=pp.get("k_bond", 0.0),
+                        coupling=pp.get("coupling", "trilinear"),
                         l_bond=pp.get("l_bond", 0.0))
     return ctx
 
@@ -445,7 +455,8 @@ class Ensemble:
                     self._h)
 
     def set_replica(self, r, E_ext, n0, pos=None, vel=None, charge=None, M=1.0, k_fene=30.0, R0=1.5,
-                    eps=1.0, sigma=1.0, gamma=20.0, n_sub=40, bond="fene", k_bond=0.0, l_bond=0.0):
+                    eps=1.0, sigma=1.0, gamma=20.0, n_sub=40, bond="fene", k_bond=0.0, l_bond=0.0,
+                    coupling="trilinear"):
         E = np.ascontiguousarray(E_ext, dtype=np.float64)
         n = np.ascontiguousarray(n0, dtype=np.float64).reshape((3,) + self.shape)
         nb = 0 if pos is None else int(np.asarray(pos).shape[0])
@@ -455,7 +466,7 @@ class Ensemble:
             vel = np.ascontiguousarray(vel, dtype=np.float64)
             q = np.ascontiguousarray(charge, dtype=np.float64)
             pp = ek_polymer_params(M, k_fene, R0, eps, sigma, gamma, n_sub, _bond_code(bond),
-                                   k_bond, l_bond)
+                                   k_bond, l_bond, _coupling_code(coupling))
             args = [_ptr(pos), _ptr(vel), _ptr(q), byref(pp)]
         self._check(self._lib.ek_ensemble_set_replica(self._h, r, _ptr(E), _ptr(n), nb, *args),
                     self._h)
@@ -521,7 +532,8 @@ def ensemble_from_workloads(wls, precision=EK_FP32, poisson_tol=1e-8, poisson_ma
             ens.set_replica(r, w.E_ext, w.n0, w.beads_R, w.beads_V, pp["q"], M=pp["M"],
                             k_fene=pp["k_fene"], R0=pp["R0"], eps=pp["eps"], sigma=pp["sigma"],
                             gamma=pp["gamma"], n_sub=pp["n_sub"], bond=pp.get("bond", "fene"),
-                            k_bond=pp.get("k_bond", 0.0), l_bond=pp.get("l_bond", 0.0))
+                            k_bond=pp.get("k_bond", 0.0), l_bond=pp.get("l_bond", 0.0),
+                            coupling=pp.get("coupling", "trilinear"))
         else:
             ens.set_replica(r, w.E_ext, w.n0)
     return ens

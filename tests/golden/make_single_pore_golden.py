@@ -1,10 +1,11 @@
-"""Writes the float64 oracle's state after 100 steps of a pore system,
+"""Writes the float64 oracle's state after a number of steps of a pore system,
 sampled at a fixed set of fluid sites, for the GPU parity tests at the
 shapes the benchmark runs.  Inputs come from the seeded workload generator;
 every stored value comes from oracle/ alone.
 
-    python tests/golden/make_single_pore_golden.py single-pore   (about 5 min)
+    python tests/golden/make_single_pore_golden.py single-pore   (about 25 min)
     python tests/golden/make_single_pore_golden.py whole-row     (about 3 min)
+    python tests/golden/make_single_pore_golden.py translocation (about 5 min)
 
 single-pore: single_pore_64x64x128_100steps.npz, the 64 x 64 x 128 single
   pore with its 32-bead chain (slab 10, pore radius 5, wall charge -0.01,
@@ -12,6 +13,10 @@ single-pore: single_pore_64x64x128_100steps.npz, the 64 x 64 x 128 single
 whole-row: whole_row_256x8x24_100steps.npz, a 256 x 8 x 24 pore box (slab 4,
   pore radius 3, wall charge -0.01, salt 0.01, E_z = 0.01) with an 8-bead
   chain (seed 77): rows of 256 sites, as in the 256 x 256 x 512 pore.
+translocation: translocation_96x96x160_5steps.npz, the translocation set-up
+  of Sec. IV.A (workloads.paper_translocation: 40-site membrane, pore of
+  diameter 12, 100 beads with harmonic bonds of length 2 and sigma = 2, one
+  MD step per lattice step), 5 steps (the oracle needs about 45 s a step).
 
 Stored: the sampled site indices (8,000: 6,000 uniform over the fluid, 2,000
 from the slab layers and the layer on each side of it), the densities
@@ -33,11 +38,11 @@ sys.path.insert(0, ROOT)
 from oracle import step as ostep  # noqa: E402
 from paper_1710_09421_amd import workloads  # noqa: E402
 
-STEPS = 100
 CASES = {
-    "single-pore": ("single_pore_64x64x128_100steps.npz", lambda: workloads.single_pore()),
+    "single-pore": ("single_pore_64x64x128_100steps.npz", lambda: workloads.single_pore(), 100),
     "whole-row": ("whole_row_256x8x24_100steps.npz",
-                  lambda: workloads.pore_system((24, 8, 256), 4, 3, 0.01, 0.01, -0.01, 8, 77)),
+                  lambda: workloads.pore_system((24, 8, 256), 4, 3, 0.01, 0.01, -0.01, 8, 77), 100),
+    "translocation": ("translocation_96x96x160_5steps.npz", workloads.paper_translocation, 5),
 }
 
 
@@ -56,7 +61,7 @@ def sample_sites(wl, seed=2024):
 
 
 def main(case):
-    name, make = CASES[case]
+    name, make, steps = CASES[case]
     out = os.path.join(HERE, name)
     wl = make()
     p = ostep.Params(valence=wl.valence, tau=wl.tau, omega_drag=wl.omega_drag,
@@ -64,9 +69,9 @@ def main(case):
     sim = ostep.Simulation(p, wl.solid.astype(bool), wl.wall_q, wl.n0,
                            beads=(wl.beads_R, wl.beads_V, wl.polymer))
     t0 = time.time()
-    for k in range(STEPS):
+    for k in range(steps):
         sim.step()
-        if (k + 1) % 10 == 0:
+        if (k + 1) % 10 == 0 or steps < 10:
             print(f"step {k + 1}: {time.time() - t0:.0f} s, Poisson {sim.last_iters} iterations",
                   flush=True)
     idx = sample_sites(wl)
@@ -74,7 +79,7 @@ def main(case):
     u = sim.velocities()
     fluid = wl.solid == 0
     np.savez_compressed(
-        out, sites=idx, shape=np.array(wl.shape), steps=np.array([STEPS]),
+        out, sites=idx, shape=np.array(wl.shape), steps=np.array([steps]),
         n=n.reshape(3, -1)[:, idx], u=u.reshape(3, 3, -1)[:, :, idx],
         psi=sim.psi.ravel()[idx],
         u_scale=np.array([np.abs(u[s][:, fluid]).max() for s in range(3)]),

@@ -328,3 +328,23 @@ def test_lone_charged_bead_accelerates_along_qE():
                           beads=(R, np.zeros_like(R), poly))
     sim.step()
     assert np.allclose(sim.V[0], q * np.asarray(E_ext) / M, rtol=1e-9, atol=1e-15)
+
+
+def test_sigma_two_pair_and_wall_forces_are_minus_energy_gradients():
+    """The translocation set-up's beads (sigma = 2, cut-off 2.245 beyond two
+    lattice spacings, epsilon = k_B T): WCA pair and bead-wall forces are
+    minus the gradients of their energies, including wall sites two cells
+    away, and vanish beyond the cut-off."""
+    sigma, eps = 2.0, 1.0 / 3.0
+    R = np.array([[3.0, 3.0, 5.0], [5.1, 3.2, 5.0], [4.0, 4.9, 6.1], [7.0, 3.0, 5.1]])
+    F = md.wca_pair_forces(R, BOX, eps, sigma, skip_bonded=True)
+    g = numerical_gradient(lambda X: md.wca_energy(X, BOX, eps, sigma, skip_bonded=True), R)
+    assert np.allclose(F, -g, rtol=1e-5, atol=1e-6) and np.abs(F).max() > 0.1
+    solid = np.zeros((14, 10, 12), dtype=bool)
+    solid[:3] = True
+    walls = md.wall_sites(solid)
+    Rw = np.array([[4.3, 3.2, 4.1], [6.1, 7.7, 5.3], [1.0, 1.0, 8.0]])    # 2.1 and 3.3 above z = 2
+    Fw = md.wall_forces(Rw, walls, BOX, eps, sigma)
+    gw = numerical_gradient(lambda X: md.wall_energy(X, walls, BOX, eps, sigma), Rw)
+    assert np.allclose(Fw, -gw, rtol=1e-5, atol=1e-6)
+    assert Fw[0, 2] > 0 and not Fw[1].any() and not Fw[2].any()

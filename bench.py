@@ -154,6 +154,10 @@ def learned_comparison():
     held = learned.generate(2, 4, 1, seed=90210, first=20, log=lambda s: None)
     summary, _ = learned.evaluate(params, scale, held, repeats=3, log=lambda s: None)
     progress(f"learned start on held-out fields: {json.dumps(summary)}")
+    from paper_1710_09421_amd import ek
+    sor, _ = learned.evaluate(params, scale, held, repeats=1, log=lambda s: None,
+                              method=ek.EK_POISSON_SOR)
+    progress(f"learned start with the red-black SOR finisher: {json.dumps(sor)}")
     sim = learned.simulate(params, scale, steps=100, warmup=10, log=lambda s: None)
     progress(f"learned start in the time loop: {json.dumps(sim)}")
     r = lambda x: round(x, 4)
@@ -163,6 +167,11 @@ def learned_comparison():
         out[k] = {"solves": v["n"], "cycles": r(v["cycles"]), "ms": r(v["ms"]),
                   "initial_residual": float(f"{v['initial_residual']:.3e}"),
                   "network_consulted": v["consulted"], "network_rejected": v["fallbacks"]}
+    out["sor_finisher"] = {k: {"solves": v["n"], "iterations": r(v["cycles"]), "ms": r(v["ms"]),
+                               "initial_residual": float(f"{v['initial_residual']:.3e}"),
+                               "network_consulted": v["consulted"],
+                               "network_rejected": v["fallbacks"]}
+                           for k, v in sor.items()}
     out["time_loop"] = {k: {"poisson_ms_per_step": r(v["ms_poisson_per_step"]),
                             "cycles_per_step": r(v["cycles_per_step"]),
                             "network_consulted_steps": v["consulted_steps"]}
@@ -178,7 +187,8 @@ def measure_context(wl, args, steps, warmup):
     progress(f"workload {wl.name}: {wl.sites} sites")
     prec = ek.EK_FP32 if args.precision == "fp32" else ek.EK_FP64
     method = ek.EK_POISSON_SOR if args.poisson == "sor" else ek.EK_POISSON_MG
-    start = ek.EK_WS_EXTRAP if args.start == "extrapolated" else ek.EK_WS_PREV
+    start = {"extrapolated": ek.EK_WS_EXTRAP, "quadratic": ek.EK_WS_EXTRAP2}.get(args.start,
+                                                                               ek.EK_WS_PREV)
     ctx = ek.from_workload(wl, precision=prec, poisson_method=method,
                            poisson_check_every=args.check_every,
                            poisson_max_iter=200 if method == ek.EK_POISSON_MG else 100000,
@@ -255,7 +265,9 @@ def measure_ensemble(args, steps):
     wls = [workloads.ensemble_replica(r) for r in range(n_rep)]
     progress(f"{n_rep} replicas of {wls[0].shape[::-1]}, chains "
              f"{sorted(set(int(w.beads_R.shape[0]) for w in wls))}")
-    start = ek.EK_WS_EXTRAP if args.start == "extrapolated" else ek.EK_WS_PREV
+    # the persistent kernel extrapolates linearly (it has no quadratic start)
+    start = ek.EK_WS_PREV if args.start == "previous" else ek.EK_WS_EXTRAP
+    start_name = "previous" if args.start == "previous" else "extrapolated"
     ens = ek.ensemble_from_workloads(wls, precision=ek.EK_FP32, poisson_tol=1e-8,
                                      warm_start=start)
     progress("ensemble ready")
@@ -287,7 +299,7 @@ def measure_ensemble(args, steps):
             "sites": sites,
             "threads_per_workgroup": tune["threads"],
             "workgroups_per_replica": tune["group"],
-            "poisson": f"mg to 1e-8 per replica from the {args.start} start, "
+            "poisson": f"mg to 1e-8 per replica from the {start_name} start, "
                        f"last solve {min(cycles)}-{max(cycles)} cycles",
             "lb_bytes_per_step_gb": round(lb_bytes / 1e9, 3),
         },
@@ -304,9 +316,11 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--poisson", default="mg", choices=["sor", "mg"])
     ap.add_argument("--check-every", type=int, default=4)
-    ap.add_argument("--start", default="extrapolated", choices=["previous", "extrapolated"],
-                    help="start of each step's Poisson solve: the previous solution or the "
-                         "linear extrapolation of the two previous ones")
+    ap.add_argument("--start", default="quadratic",
+                    choices=["previous", "extrapolated", "quadratic"],
+                    help="start of each step's Poisson solve: the previous solution, the "
+                         "linear extrapolation of the two previous ones or the quadratic one "
+                         "of the three previous ones")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="measure only the named workload (no single-pore and ensemble keys)")

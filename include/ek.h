@@ -64,11 +64,13 @@ typedef enum {
 enum { EK_FP32 = 0, EK_FP64 = 1 };                 /* population storage type */
 enum { EK_POISSON_SOR = 0, EK_POISSON_MG = 1 };    /* Poisson method          */
 /* Start of each step's Poisson solve: zero; the previous step's solution
- * (Sec. II.C); the learned guess (see ek_set_model); or the linear
+ * (Sec. II.C); the learned guess (see ek_set_model); the linear
  * extrapolation in time 2 psi(t-1) - psi(t-2) of the two previous steps'
  * solutions (the previous solution on the first two steps after
- * ek_set_geometry).  The solver finishes every start to the same tolerance. */
-enum { EK_WS_ZERO = 0, EK_WS_PREV = 1, EK_WS_LEARNED = 2, EK_WS_EXTRAP = 3 };
+ * ek_set_geometry); or the quadratic one 3 psi(t-1) - 3 psi(t-2) + psi(t-3)
+ * (linear on the third step, the previous solution before).  The solver
+ * finishes every start to the same tolerance. */
+enum { EK_WS_ZERO = 0, EK_WS_PREV = 1, EK_WS_LEARNED = 2, EK_WS_EXTRAP = 3, EK_WS_EXTRAP2 = 4 };
 
 /* Problem statement (Sec. II.A-C).  Copied at ek_create. */
 typedef struct {
@@ -94,7 +96,7 @@ typedef struct {
   int32_t warm_start;          /* EK_WS_ZERO, EK_WS_PREV, EK_WS_LEARNED
                                   (ek_set_model; sizes multiples of 4) or
                                   EK_WS_EXTRAP (one more float64 field in
-                                  the workspace)                               */
+                                  the workspace) or EK_WS_EXTRAP2 (two more) */
   uint64_t seed;               /* key of the thermal noise (64 bits)           */
   int32_t fluctuations;        /* 0: none; 1: thermal fluctuations (Sec. II.A
                                   and II.C): the stochastic term Delta of
@@ -308,9 +310,9 @@ ek_status ek_load_state(struct ek_ctx* ctx, const void* host, size_t bytes);
 /* Standalone Poisson solve on device buffers: dev_rho[nz*ny*nx] charge
  * density, dev_psi[nz*ny*nx] warm start on entry and solution (mean zero) on
  * return, both float64.  Uses the context's method, tolerance and iteration
- * limit; warm_start EK_WS_ZERO clears dev_psi first, EK_WS_PREV and
- * EK_WS_EXTRAP start from dev_psi as given (a stand-alone solve has no
- * history to extrapolate), EK_WS_LEARNED consults the network (EK_ESTATE
+ * limit; warm_start EK_WS_ZERO clears dev_psi first, EK_WS_PREV,
+ * EK_WS_EXTRAP and EK_WS_EXTRAP2 start from dev_psi as given (a stand-alone
+ * solve has no history to extrapolate), EK_WS_LEARNED consults the network (EK_ESTATE
  * without a model); other values give EK_EINVAL.  The context's own fields
  * (populations, potential) are not touched. */
 ek_status ek_poisson_solve(struct ek_ctx* ctx, const double* dev_rho, double* dev_psi,

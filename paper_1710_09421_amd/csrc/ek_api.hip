@@ -54,7 +54,7 @@ ek_status check_params(const ek_params* p, std::string& why) {
     return EK_EINVAL;
   }
   if (p->rho_jacobi < 0.0 || p->rho_jacobi >= 1.0) { why = "rho_jacobi must be in [0, 1)"; return EK_EINVAL; }
-  if (p->warm_start < EK_WS_ZERO || p->warm_start > EK_WS_EXTRAP) { why = "unknown warm_start"; return EK_EINVAL; }
+  if (p->warm_start < EK_WS_ZERO || p->warm_start > EK_WS_EXTRAP2) { why = "unknown warm_start"; return EK_EINVAL; }
   if (p->warm_start == EK_WS_LEARNED && !UNet::shape_ok(p->nx, p->ny, p->nz)) {
     why = "the learned warm start needs nx, ny, nz divisible by 4 (two 2x2x2 poolings)";
     return EK_EINVAL;
@@ -72,7 +72,7 @@ ek_status check_params(const ek_params* p, std::string& why) {
 // Workspace layout (every block 256-byte aligned).
 struct Layout {
   size_t fA, fB, mask, wall_q, psi, b, partials, ps, stats, keys, vals, beads, mg, net, guess,
-      psi_old, total;
+      psi_old, psi_old2, total;
 };
 
 Layout make_layout(const ek_params* p, int max_beads) {
@@ -102,7 +102,8 @@ Layout make_layout(const ek_params* p, int max_beads) {
   const bool learned = p->warm_start == EK_WS_LEARNED;
   L.net = take(learned ? UNet::bytes(p->nx, p->ny, p->nz, false) : 0);
   L.guess = take(learned ? n * 8 : 0);
-  L.psi_old = take(p->warm_start == EK_WS_EXTRAP ? n * 8 : 0);
+  L.psi_old = take(p->warm_start == EK_WS_EXTRAP || p->warm_start == EK_WS_EXTRAP2 ? n * 8 : 0);
+  L.psi_old2 = take(p->warm_start == EK_WS_EXTRAP2 ? n * 8 : 0);
   L.total = off;
   return L;
 }
@@ -333,10 +334,15 @@ ek_status ek_ctx::step_impl(int n_steps) {
     }
     // the charge pass also prepares the extrapolated start (EK_WS_EXTRAP):
     // psi = 2 psi(t-1) - psi(t-2) once two previous solutions exist
-    const int extrap = p.warm_start == EK_WS_EXTRAP ? std::min(psi_hist, 2) : 0;
+    // (and the quadratic one of EK_WS_EXTRAP2 once three exist: mode 4;
+    // the linear one with the history shifted on the third step: mode 3)
+    int extrap = 0;
+    if (p.warm_start == EK_WS_EXTRAP) extrap = std::min(psi_hist, 2);
+    if (p.warm_start == EK_WS_EXTRAP2) extrap = psi_hist >= 3 ? 4 : (psi_hist == 2 ? 3 : psi_hist);
     launch_charge<T>((const T*)fcur(), mask, wall_q, b, partials, lp, inv_eps(), dims, g, stream, bt,
-                     psi, psi_old, extrap, insulating());
+                     psi, psi_old, extrap, insulating(), psi_old2);
     if (p.warm_start == EK_WS_EXTRAP) psi_hist = std::min(psi_hist + 1, 2);
+    if (p.warm_start == EK_WS_EXTRAP2) psi_hist = std::min(psi_hist + 1, 3);
     launch_mean_shift(partials, nb, 1.0 / double(insulating() ? n_fluid : dims.n), inv_eps(), ps,
                       stream);
     record(t, 1);
@@ -527,7 +533,9 @@ ek_status ek_create(const ek_params* p, int32_t max_beads, void* dev_ws, size_t 
       return EK_EHIP;
     }
   }
-  if (p->warm_start == EK_WS_EXTRAP) c->psi_old = (double*)(ws + L.psi_old);
+  if (p->warm_start == EK_WS_EXTRAP || p->warm_start == EK_WS_EXTRAP2)
+    c->psi_old = (double*)(ws + L.psi_old);
+  if (p->warm_start == EK_WS_EXTRAP2) c->psi_old2 = (double*)(ws + L.psi_old2);
   *out = c;
   return EK_OK;
 }
@@ -743,7 +751,7 @@ ek_status ek_poisson_solve(ek_ctx* ctx, const double* dev_rho, double* dev_psi,
   if (!ctx) return EK_EINVAL;
   if (ctx->insulating()) return ctx->fail(EK_ESTATE, "the context has insulating walls");
   if (!dev_rho || !dev_psi) return ctx->fail(EK_EINVAL, "NULL device buffer");
-  if (warm_start < EK_WS_ZERO || warm_start > EK_WS_EXTRAP) return ctx->fail(EK_EINVAL, "unknown warm_start");
+  if (warm_start < EK_WS_ZERO || warm_start > EK_WS_EXTRAP2) return ctx->fail(EK_EINVAL, "unknown warm_start");
   if (warm_start == EK_WS_LEARNED && !(ctx->net && ctx->net->have_params))
     return ctx->fail(EK_ESTATE, "learned warm start without a model (ek_set_model)");
   const SiteGrid g = site_grid(ctx->p.nx, ctx->p.ny, ctx->p.nz, ctx->bx_sites);

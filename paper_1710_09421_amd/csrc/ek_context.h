@@ -127,6 +127,7 @@ struct ek_ctx {
   // extrapolated start (p.warm_start == EK_WS_EXTRAP): psi(t-2), and how many
   // previous step solutions the history holds (0, 1 or 2)
   double* psi_old = nullptr;
+  double* psi_old2 = nullptr;          // psi(t-3) of the quadratic start (EK_WS_EXTRAP2)
   int psi_hist = 0;
   template <typename T>
   ek_status step_impl(int n_steps);

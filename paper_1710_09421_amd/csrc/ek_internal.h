@@ -112,7 +112,7 @@ void launch_charge(const T* f, const uint32_t* mask, const double* wall_q, doubl
                    double* partials, const LBParams& lp, double inv_eps, Dims d,
                    const SiteGrid& g, hipStream_t s, const BeadTableView& bt,
                    double* psi = nullptr, double* psi_old = nullptr, int extrap = 0,
-                   bool insulating = false);
+                   bool insulating = false, double* psi_old2 = nullptr);
 // Fused step over the sites without a `skip` bit.  Writes its block partials
 // (seven components: masses, momentum, sites updated) first in a layout of
 // `nblocks` blocks (lb_step_blocks(g, nz), plus the tail's blocks when a tail

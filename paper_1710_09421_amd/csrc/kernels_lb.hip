@@ -41,11 +41,14 @@ __global__ __launch_bounds__(BLOCK) void k_init_species(T* __restrict__ f,
 // + fixed wall charge + bead charge; stores -rho_e / eps and partial sums of
 // rho_e (for the mean that the periodic problem removes).  With `start` set
 // it also prepares the extrapolated start of the solve at the site:
-// start.mode 1 keeps psi and copies it to old, 2 sets psi = 2 psi - old.
+// start.mode 1 keeps psi and copies it to old, 2 sets psi = 2 psi - old,
+// 3 does the same and copies old to old2, 4 sets psi = 3 psi - 3 old + old2
+// and shifts the history (old2 = old, old = psi before).
 struct StartExtrap {
   double* psi;
   double* old;
   int mode;
+  double* old2;
 };
 
 template <typename T, typename I, bool NEU>
@@ -69,7 +72,15 @@ __global__ __launch_bounds__(BLOCK) void k_charge(const T* __restrict__ f,
     acc[0] = rho;
     if (start.mode) {
       const double p = start.psi[r];
-      if (start.mode == 2) start.psi[r] = 2.0 * p - start.old[r];
+      if (start.mode == 2 || start.mode == 3) {
+        const double o = start.old[r];
+        start.psi[r] = 2.0 * p - o;
+        if (start.mode == 3) start.old2[r] = o;
+      } else if (start.mode == 4) {
+        const double o = start.old[r];
+        start.psi[r] = 3.0 * (p - o) + start.old2[r];
+        start.old2[r] = o;
+      }
       start.old[r] = p;
     }
   }
@@ -250,8 +261,8 @@ template <typename T>
 void launch_charge(const T* f, const uint32_t* mask, const double* wall_q, double* b,
                    double* partials, const LBParams& lp, double inv_eps, Dims d,
                    const SiteGrid& g, hipStream_t s, const BeadTableView& bt, double* psi,
-                   double* psi_old, int extrap, bool insulating) {
-  const StartExtrap start{psi, psi_old, psi_old ? extrap : 0};
+                   double* psi_old, int extrap, bool insulating, double* psi_old2) {
+  const StartExtrap start{psi, psi_old, psi_old ? extrap : 0, psi_old2};
   auto go = [&](auto kernel) {
     hipLaunchKernelGGL(kernel, g.grid, g.block, 0, s, f, mask, wall_q, b, partials, lp, inv_eps,
                        bt, d, start);
@@ -363,7 +374,7 @@ void launch_mean_shift(const double* partials, int nblocks, double inv_n, double
                                        hipStream_t);                                         \
   template void launch_charge<T>(const T*, const uint32_t*, const double*, double*, double*, \
                                  const LBParams&, double, Dims, const SiteGrid&, hipStream_t,\
-                                 const BeadTableView&, double*, double*, int, bool);         \
+                                 const BeadTableView&, double*, double*, int, bool, double*);\
   template int launch_lb_step<T>(const T*, T*, const uint32_t*, const double*,               \
                                  const LBParams&, const BeadTableView&, double*, int,        \
                                  uint32_t, Dims, const SiteGrid&, hipStream_t, hipEvent_t,   \

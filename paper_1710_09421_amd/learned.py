@@ -172,19 +172,30 @@ def _timed(fn, sync):
     return r, (time.perf_counter() - t) * 1e3
 
 
-def evaluate(params, out_scale, data, tol=1e-8, repeats=3, log=print):
-    """Poisson solves of every held-out pair by multigrid to `tol` from a zero
-    start, from the network's guess, and (for consecutive pairs of one
-    trajectory) from the previous pair's solution with and without the
-    network.  Wall time per solve is the median over `repeats` (host clock
-    around the call, which ends synchronised), network included."""
+def evaluate(params, out_scale, data, tol=1e-8, repeats=3, log=print, method=None):
+    """Poisson solves of every held-out pair to `tol` from a zero start, from
+    the network's guess, and (for consecutive pairs of one trajectory) from
+    the previous pair's solution with and without the network; the finisher
+    is multigrid (method None or EK_POISSON_MG) or the paper's red-black SOR
+    with the Chebyshev schedule (EK_POISSON_SOR, residual tested every 4
+    iterations).  Wall time per solve is the median over `repeats` (host
+    clock around the call, which ends synchronised), network included."""
     import torch
     n = data["rhs"].shape[0]
     shape = tuple(data["rhs"].shape[1:])
-    p = ek.make_params((shape[0], shape[1], shape[2]), poisson_method=ek.EK_POISSON_MG,
-                       poisson_tol=tol, poisson_max_iter=400, warm_start=ek.EK_WS_LEARNED)
+    method = ek.EK_POISSON_MG if method is None else method
+    sor = method == ek.EK_POISSON_SOR
+    p = ek.make_params((shape[0], shape[1], shape[2]), poisson_method=method,
+                       poisson_tol=tol, poisson_max_iter=100000 if sor else 400,
+                       poisson_check_every=4 if sor else 1, warm_start=ek.EK_WS_LEARNED)
     ctx = ek.Context(p)
     ctx.set_model(params, out_scale)
+    # the network on its own, for starts that take its guess whatever its
+    # residual ("learned, kept"): the gate compares residuals, which suits
+    # multigrid; SOR's slow modes are the smooth ones a guess can supply even
+    # when its residual is large
+    net = ek.UNet(shape, training=False)
+    net.set_params(params, out_scale)
     sync = torch.cuda.synchronize
     psi = torch.zeros(shape, dtype=torch.float64, device="cuda")
     rows = []
@@ -211,6 +222,17 @@ def evaluate(params, out_scale, data, tol=1e-8, repeats=3, log=print):
                 err_ref = psi.clone()
         row["learned"]["max_diff_vs_zero_start"] = float((psi - err_ref).abs().max() /
                                                          err_ref.abs().max())
+        solid_u8 = sol.to(torch.uint8)
+        ts = []
+        for _ in range(repeats):
+            def kept():
+                net.forward(data["rhs"][i], solid_u8, psi)
+                return ctx.poisson_solve(rho, psi, ek.EK_WS_PREV)
+            rep, ms = _timed(kept, sync)
+            ts.append(ms)
+        row["learned, kept"] = dict(cycles=rep["iterations"], residual=rep["residual"],
+                                    initial=rep["initial_residual"], ms=float(np.median(ts)),
+                                    fallback=0, consulted=1)
         if i % per > 0:
             for name, ws in (("previous", ek.EK_WS_PREV), ("previous+learned", ek.EK_WS_LEARNED)):
                 ts = []
@@ -224,8 +246,9 @@ def evaluate(params, out_scale, data, tol=1e-8, repeats=3, log=print):
                                  consulted=ctx.stats()["consulted"] if ws == ek.EK_WS_LEARNED else 0)
         rows.append(row)
     ctx.close()
+    net.close()
     summary = {}
-    for name in ("zero", "learned", "previous", "previous+learned"):
+    for name in ("zero", "learned", "learned, kept", "previous", "previous+learned"):
         rs = [r[name] for r in rows if name in r]
         if not rs:
             continue

@@ -78,16 +78,19 @@ def test_learned_warm_start_needs_sizes_divisible_by_4(ek):
 
 
 def test_extrapolated_start_workspace(ek):
-    """EK_WS_EXTRAP keeps psi(t-2): one more float64 field; unknown starts are
-    rejected."""
+    """EK_WS_EXTRAP keeps psi(t-2): one more float64 field; EK_WS_EXTRAP2
+    keeps psi(t-3) as well: two more; unknown starts are rejected."""
     lib = ek.lib()
-    plain, extrap = ctypes.c_size_t(), ctypes.c_size_t()
+    plain, extrap, quad = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
     p0 = ek.make_params((32, 32, 32), warm_start=ek.EK_WS_PREV)
     p1 = ek.make_params((32, 32, 32), warm_start=ek.EK_WS_EXTRAP)
+    p2 = ek.make_params((32, 32, 32), warm_start=ek.EK_WS_EXTRAP2)
     assert lib.ek_workspace_bytes(ctypes.byref(p0), 0, ctypes.byref(plain)) == ek.EK_OK
     assert lib.ek_workspace_bytes(ctypes.byref(p1), 0, ctypes.byref(extrap)) == ek.EK_OK
+    assert lib.ek_workspace_bytes(ctypes.byref(p2), 0, ctypes.byref(quad)) == ek.EK_OK
     assert extrap.value - plain.value >= 32 ** 3 * 8
-    bad = ek.make_params((32, 32, 32), warm_start=4)
+    assert quad.value - extrap.value >= 32 ** 3 * 8
+    bad = ek.make_params((32, 32, 32), warm_start=ek.EK_WS_EXTRAP2 + 1)
     assert lib.ek_workspace_bytes(ctypes.byref(bad), 0, ctypes.byref(plain)) == ek.EK_EINVAL
 
 

@@ -134,6 +134,24 @@ def test_pore_fp32_matches_oracle_after_100_steps(ek):
     assert opoisson.relative_residual(ctx.potential(), b) < 1e-3
 
 
+@pytest.mark.parametrize("start", ["extrapolated", "quadratic"])
+def test_pore_fp32_multigrid_extrapolated_starts_match_oracle(ek, start):
+    """The extrapolated starts of the solve (2 psi(t-1) - psi(t-2) and
+    3 psi(t-1) - 3 psi(t-2) + psi(t-3)) change where the multigrid begins,
+    not where it ends: 100 steps agree with the oracle's previous-solution
+    SOR at the same tolerance."""
+    wl = pore()
+    ws = ek.EK_WS_EXTRAP if start == "extrapolated" else ek.EK_WS_EXTRAP2
+    ctx = ek.from_workload(wl, precision=ek.EK_FP32, poisson_method=ek.EK_POISSON_MG,
+                           poisson_tol=1e-9, poisson_max_iter=200, warm_start=ws)
+    sim = oracle_sim(wl, 1e-10)
+    ctx.step(100)
+    sim.run(100)
+    err = compare(ctx, sim, wl.solid == 0)
+    print(start, err, ctx.stats()["poisson_residual0"])
+    assert max(err.values()) < 1e-5, err
+
+
 def test_pore_fp64_matches_oracle(ek):
     wl = pore()
     ctx = ek.from_workload(wl, precision=ek.EK_FP64, poisson_tol=1e-10, poisson_check_every=1)

@@ -538,9 +538,10 @@ ek_status ek_ensemble_set_threads(ek_ensemble* ens, int32_t threads);
 ek_status ek_ensemble_set_group(ek_ensemble* ens, int32_t group);
 
 /* Autotuner: times `steps` ensemble steps with every candidate workgroup size
- * and team size (the replicas advance by those steps, like a warm-up; team
- * sizes the device refuses are skipped) and keeps the fastest; *out (may be
- * NULL) receives the choice and its time. */
+ * and team size, in two interleaved passes over the candidates, each keeping
+ * its faster pass (the replicas advance by 1 + 2 `steps` steps per candidate,
+ * like a warm-up; team sizes the device refuses are skipped), and keeps the
+ * fastest; *out (may be NULL) receives the choice and its time. */
 ek_status ek_ensemble_autotune(ek_ensemble* ens, int32_t steps, ek_tune_result* out);
 
 #ifdef __cplusplus

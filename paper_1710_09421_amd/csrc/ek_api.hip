@@ -71,7 +71,7 @@ ek_status check_params(const ek_params* p, std::string& why) {
 
 // Workspace layout (every block 256-byte aligned).
 struct Layout {
-  size_t fA, fB, mask, wall_q, psi, b, partials, ps, stats, keys, vals, beads, mg, net, guess,
+  size_t fA, fB, mask, wall_q, psi, b, partials, ps, stats, keys, vals, beads, mg, mgt, net, guess,
       psi_old, psi_old2, total;
 };
 
@@ -99,6 +99,7 @@ Layout make_layout(const ek_params* p, int max_beads) {
   L.vals = take((size_t)HASH_SLOTS * 10 * 8);
   L.beads = take(bead_state_bytes(max_beads));
   L.mg = take(mg_workspace_bytes(p->nx, p->ny, p->nz));
+  L.mgt = take(p->poisson_method == EK_POISSON_MG ? mg_sweep_bytes(p->nx, p->ny, p->nz) : 0);
   const bool learned = p->warm_start == EK_WS_LEARNED;
   L.net = take(learned ? UNet::bytes(p->nx, p->ny, p->nz, false) : 0);
   L.guess = take(learned ? n * 8 : 0);
@@ -501,6 +502,7 @@ ek_status ek_create(const ek_params* p, int32_t max_beads, void* dev_ws, size_t 
   c->vals = (long long*)(ws + L.vals);
   c->bead_mem = ws + L.beads;
   c->mg_mem = ws + L.mg;
+  c->mg_tmp = p->poisson_method == EK_POISSON_MG ? ws + L.mgt : nullptr;
   if (hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
     if (own) (void)hipFree(ws);
     delete c;

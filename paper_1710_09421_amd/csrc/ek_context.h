@@ -14,6 +14,7 @@ size_t bead_state_bytes(int max_beads);
 void launch_table_init(int* keys, long long* vals, hipStream_t s);
 void launch_table_init_bits(int* keys, long long* vals, int bits, hipStream_t s);
 size_t mg_workspace_bytes(int nx, int ny, int nz);
+size_t mg_sweep_bytes(int nx, int ny, int nz);
 }  // namespace ek
 
 // The learned warm start consults the network only when the relative
@@ -44,6 +45,7 @@ struct ek_ctx {
   long long* vals = nullptr;
   char* bead_mem = nullptr;
   char* mg_mem = nullptr;
+  char* mg_tmp = nullptr;              // sweep buffers of the multigrid (or null)
 
   // host-side state
   std::vector<uint8_t> host_solid;

@@ -864,36 +864,56 @@ ek_status ek_ensemble_autotune(ek_ensemble* e, int32_t steps, ek_tune_result* ou
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
     return e->fail(EK_EHIP, "hipEventCreate failed");
-  int best = e->threads, best_group = e->group;
-  double best_ms = INFINITY;
-  ek_status st = EK_OK;
-  const int threads_c[] = {256, 512, 1024};
-  const int groups_c[] = {1, 2, 4};
-  for (int cand : threads_c)
-    for (int grp : groups_c) {
-      st = run_steps(e, 1, cand, grp);        // first launch of a variant: not timed
-      if (st == EK_EHIP && grp > 1 && e->err.find("cooperative") != std::string::npos) {
-        st = EK_OK;                            // this team size does not fit the device
-        continue;
-      }
-      if (st) break;
-      (void)hipEventRecord(a, e->stream);
-      st = run_steps(e, steps, cand, grp);
-      (void)hipEventRecord(b, e->stream);
-      if (st) break;
-      (void)hipEventSynchronize(b);
-      float ms = 0.0f;
-      (void)hipEventElapsedTime(&ms, a, b);
-      const double per = ms / steps;
-      if (per < best_ms) {
-        best_ms = per;
-        best = cand;
-        best_group = grp;
-      }
+  // Every candidate is timed in two interleaved passes and keeps its faster
+  // time: the replicas are still relaxing while the tuner runs (the Poisson
+  // solves get cheaper from step to step), and a single pass in a fixed order
+  // would favour whichever candidate comes last.
+  constexpr int NT = 3, NG = 3, PASSES = 2;
+  const int threads_c[NT] = {256, 512, 1024};
+  const int groups_c[NG] = {1, 2, 4};
+  double per_c[NT][NG];
+  bool fits[NT][NG];
+  for (int i = 0; i < NT; ++i)
+    for (int j = 0; j < NG; ++j) {
+      per_c[i][j] = INFINITY;
+      fits[i][j] = true;
     }
+  ek_status st = EK_OK;
+  for (int pass = 0; pass < PASSES && !st; ++pass)
+    for (int i = 0; i < NT && !st; ++i)
+      for (int j = 0; j < NG && !st; ++j) {
+        if (!fits[i][j]) continue;
+        const int cand = threads_c[i], grp = groups_c[j];
+        if (pass == 0) {
+          st = run_steps(e, 1, cand, grp);    // first launch of a variant: not timed
+          if (st == EK_EHIP && grp > 1 && e->err.find("cooperative") != std::string::npos) {
+            st = EK_OK;                        // this team size does not fit the device
+            fits[i][j] = false;
+            continue;
+          }
+          if (st) break;
+        }
+        (void)hipEventRecord(a, e->stream);
+        st = run_steps(e, steps, cand, grp);
+        (void)hipEventRecord(b, e->stream);
+        if (st) break;
+        (void)hipEventSynchronize(b);
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        per_c[i][j] = std::min(per_c[i][j], double(ms) / steps);
+      }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (st) return st;
+  int best = e->threads, best_group = e->group;
+  double best_ms = INFINITY;
+  for (int i = 0; i < NT; ++i)
+    for (int j = 0; j < NG; ++j)
+      if (fits[i][j] && per_c[i][j] < best_ms) {
+        best_ms = per_c[i][j];
+        best = threads_c[i];
+        best_group = groups_c[j];
+      }
   e->threads = best;
   e->group = best_group;
   if (out) {

@@ -101,6 +101,208 @@ __global__ __launch_bounds__(256) void k_prolong(Lvl F, Lvl C, const PoissonScal
   prolong_cell(F, C, X, Y, blockIdx.z);
 }
 
+// Out-of-place prolongation: dst = src + P e over the 8 children of a coarse
+// cell (the finest level, whose pre-smoothed iterate is in the sweep buffer).
+__global__ __launch_bounds__(256) void k_prolong_to(Lvl F, Lvl C, const double* src, double* dst,
+                                                    const PoissonScalars* ps) {
+  if (ps->done) return;
+  const int X = blockIdx.x * blockDim.x + threadIdx.x;
+  const int Y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (X >= C.nx || Y >= C.ny) return;
+  prolong_cell(F, C, X, Y, blockIdx.z, src, dst);
+}
+
+// --- one full red-black sweep per launch, marching up z -----------------------
+// xout = (colour-0 half sweep, then colour-1 half sweep)(xin), out of place.
+// A workgroup owns the TX x TY tile at (x0, y0) of the planes z0 .. z0+zc-1
+// and keeps five planes of the tile plus a two-site ring in LDS.  At step k it
+// relaxes the colour-0 sites of plane k on the tile and a one-site ring (from
+// the old colour-1 values of planes k-1, k, k+1), then the colour-1 sites of
+// plane k-1 on the tile (whose neighbours are all colour-0 sites, now new),
+// and writes plane k-1.  The ring's colour-0 values are recomputed by every
+// tile that borders them, from the same old values in the same order, so no
+// workgroup waits for another and every site gets the update of the two
+// in-place half sweeps (the same formula and summation order; the compiler
+// may contract its multiply-adds differently, so the two agree to rounding:
+// 4e-11 relative on psi after four steps of the 256x256x512 pore, with the
+// same cycle counts).  Each site of xin and f is read once from memory
+// (plus the rings and the two planes either side of a chunk, which the
+// neighbouring workgroups read too) and xout is written once: 24 bytes per
+// site for the sweep, against 48 for two half sweeps over the interleaved
+// colours.  The loads run ahead of their use: the right-hand side of a step
+// is read during the step before, the iterate planes two steps before.
+// zc >= 1 divides nz; TX divides nx, TY divides ny; all sides even.
+constexpr int SWEEP_THREADS = 256;
+constexpr int SWEEP_SLOTS = 5;
+
+template <int TX, int TY>
+struct SweepRegs {
+  static constexpr int REGION = (TX + 4) * (TY + 4);
+  static constexpr int XPT = (REGION + SWEEP_THREADS - 1) / SWEEP_THREADS;
+  static constexpr int RED_ROW = TX / 2 + 1;             // colour-0 sites per ring-1 row
+  static constexpr int RED_ITEMS = RED_ROW * (TY + 2);
+  static constexpr int RPT = (RED_ITEMS + SWEEP_THREADS - 1) / SWEEP_THREADS;
+  static constexpr int PAIR_ITEMS = (TX / 2) * TY;
+  static constexpr int BPT = (PAIR_ITEMS + SWEEP_THREADS - 1) / SWEEP_THREADS;
+  double x[XPT];    // an iterate plane (tile and two-site ring), to be stored in LDS
+  double fr[RPT];   // f at this thread's colour-0 ring sites of a plane
+  double fb[BPT];   // f at this thread's colour-1 tile sites of a plane
+};
+
+template <int TX, int TY>
+__global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_z(Lvl L, const double* __restrict__ xin,
+                                                           double* __restrict__ xout, int zc,
+                                                           const PoissonScalars* ps, int level0,
+                                                           double omega) {
+  static_assert(TX % 2 == 0 && TY % 2 == 0, "even tiles");
+  using R = SweepRegs<TX, TY>;
+  constexpr int RX = TX + 4, RY = TY + 4;
+  __shared__ double P[SWEEP_SLOTS][RY][RX];
+  if (ps->done) return;
+  const double shift = level0 ? ps->shift : 0.0;
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
+  const double h2 = L.h2;
+  const double* __restrict__ f = L.f;
+  const int tid = threadIdx.x;
+  // workgroup -> (tile, chunk): consecutive groups of the launch go to
+  // different XCDs, so group b is renumbered to put neighbouring tiles of a
+  // chunk on one XCD (whose L2 then serves their shared rings)
+  const int ntx = nx / TX, nty = ny / TY;
+  const int nblk = gridDim.x;
+  int b = blockIdx.x;
+  if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
+  const int tx_i = b % ntx;
+  const int rest = b / ntx;
+  const int ty_i = rest % nty;
+  const int chunk = rest / nty;
+  const int x0 = tx_i * TX, y0 = ty_i * TY, z0 = chunk * zc, z1 = z0 + zc;
+  const int zb = z0 - 2;                                   // plane of relative index 0
+
+  auto wrapi = [](int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); };
+  auto plane_base = [&](int q) {                           // any plane index, wrapped here
+    int zq = q % nz;
+    if (zq < 0) zq += nz;
+    return (long long)zq * ny * nx;
+  };
+  auto slot = [&](int q) { return (q - zb) % SWEEP_SLOTS; };
+  // The loads are issued unconditionally (indexes past the end are clamped,
+  // their values never used): loads inside branches would leave the compiler
+  // unable to count the ones in flight, and it would then wait for all of
+  // them, the loads meant for later steps included, before the first use.
+  auto gather_x = [&](int q, double (&r)[R::XPT]) {
+    const long long base = plane_base(q);
+#pragma unroll
+    for (int u = 0; u < R::XPT; ++u) {
+      const int t = min(tid + u * SWEEP_THREADS, R::REGION - 1);
+      const int j = t / RX, i = t - j * RX;
+      r[u] = xin[base + (long long)wrapi(y0 - 2 + j, ny) * nx + wrapi(x0 - 2 + i, nx)];
+    }
+  };
+  auto store_x = [&](int s, const double (&r)[R::XPT]) {
+#pragma unroll
+    for (int u = 0; u < R::XPT; ++u) {
+      const int t = tid + u * SWEEP_THREADS;
+      if (t < R::REGION) {
+        const int j = t / RX, i = t - j * RX;
+        P[s][j][i] = r[u];
+      }
+    }
+  };
+  // colour-0 item t of plane k: ring-1 row j, column i (colour 0 means
+  // (x0 - 2 + i) + (y0 - 2 + j) + k even)
+  auto red_site = [&](int t, int k, int& j, int& i) {
+    const int jj = t / R::RED_ROW, m = t - jj * R::RED_ROW;
+    j = 1 + jj;
+    i = (((x0 + y0 + k + j) & 1) ? 1 : 2) + 2 * m;
+  };
+  // colour-1 item t of plane k: tile row jj, pair m; the colour-1 site is the
+  // first of the pair when x0 + 2 m + y0 + jj + k is odd
+  auto black_first = [&](int jj, int m, int k) { return ((x0 + 2 * m + y0 + jj + k) & 1) != 0; };
+  auto gather_fr = [&](int k, double (&r)[R::RPT]) {
+    const long long base = plane_base(k);
+#pragma unroll
+    for (int u = 0; u < R::RPT; ++u) {
+      const int t = min(tid + u * SWEEP_THREADS, R::RED_ITEMS - 1);
+      int j, i;
+      red_site(t, k, j, i);
+      r[u] = f[base + (long long)wrapi(y0 - 2 + j, ny) * nx + wrapi(x0 - 2 + i, nx)];
+    }
+  };
+  auto gather_fb = [&](int k, double (&r)[R::BPT]) {
+    const long long base = plane_base(k);
+#pragma unroll
+    for (int u = 0; u < R::BPT; ++u) {
+      const int t = min(tid + u * SWEEP_THREADS, R::PAIR_ITEMS - 1);
+      const int jj = t / (TX / 2), m = t - jj * (TX / 2);
+      r[u] = f[base + (long long)(y0 + jj) * nx + x0 + 2 * m + (black_first(jj, m, k) ? 0 : 1)];
+    }
+  };
+  // Step k.  cur holds the iterate plane k+2 (stored at the end), f of the
+  // colour-0 sites of plane k and of the colour-1 sites of plane k-1; nxt
+  // receives plane k+3 and f of planes k+1 (colour 0) and k (colour 1).
+  auto step = [&](int k, R& cur, R& nxt) {
+    // (near the chunk's end the planes are clamped: loaded, never used)
+    gather_x(min(k + 3, z1 + 1), nxt.x);
+    gather_fr(min(k + 1, z1), nxt.fr);
+    gather_fb(max(min(k, z1 - 1), z0), nxt.fb);
+    const int sk = slot(k), skm = slot(k + SWEEP_SLOTS - 1), skp = slot(k + 1),
+              skm2 = slot(k + SWEEP_SLOTS - 2);
+#pragma unroll
+    for (int u = 0; u < R::RPT; ++u) {
+      const int t = tid + u * SWEEP_THREADS;
+      if (t < R::RED_ITEMS) {
+        int j, i;
+        red_site(t, k, j, i);
+        const double xo = P[sk][j][i];
+        const double nb = P[sk][j][i - 1] + P[sk][j][i + 1] + P[sk][j - 1][i] + P[sk][j + 1][i] +
+                          P[skm][j][i] + P[skp][j][i];
+        const double gs = (nb - h2 * (cur.fr[u] + shift)) * (1.0 / 6.0);
+        P[sk][j][i] = omega == 1.0 ? gs : xo + omega * (gs - xo);
+      }
+    }
+    __syncthreads();
+    if (k - 1 >= z0) {
+      const long long base = plane_base(k - 1);
+#pragma unroll
+      for (int u = 0; u < R::BPT; ++u) {
+        const int t = tid + u * SWEEP_THREADS;
+        if (t < R::PAIR_ITEMS) {
+          const int jj = t / (TX / 2), m = t - jj * (TX / 2);
+          const int j = 2 + jj, i0 = 2 + 2 * m;
+          const bool first = black_first(jj, m, k - 1);
+          const int ib = first ? i0 : i0 + 1, ir = first ? i0 + 1 : i0;
+          const double xo = P[skm][j][ib];
+          const double nb = P[skm][j][ib - 1] + P[skm][j][ib + 1] + P[skm][j - 1][ib] +
+                            P[skm][j + 1][ib] + P[skm2][j][ib] + P[sk][j][ib];
+          const double gs = (nb - h2 * (cur.fb[u] + shift)) * (1.0 / 6.0);
+          const double vb = omega == 1.0 ? gs : xo + omega * (gs - xo);
+          const double vr = P[skm][j][ir];
+          double2 out;
+          out.x = first ? vb : vr;
+          out.y = first ? vr : vb;
+          *reinterpret_cast<double2*>(xout + base + (long long)(y0 + jj) * nx + x0 + 2 * m) = out;
+        }
+      }
+    }
+    if (k + 2 <= z1 + 1) store_x(slot(k + 2), cur.x);
+    __syncthreads();
+  };
+  R A, B;
+  for (int q = zb; q <= z0; ++q) {                         // planes z0-2, z0-1, z0
+    gather_x(q, A.x);
+    store_x(slot(q), A.x);
+  }
+  gather_x(z0 + 1, A.x);
+  gather_fr(z0 - 1, A.fr);
+  __syncthreads();
+  int k = z0 - 1;
+  for (; k + 1 <= z1; k += 2) {
+    step(k, A, B);
+    step(k + 1, B, A);
+  }
+  if (k <= z1) step(k, A, B);
+}
+
 // The coarse part of the cycle runs on copies of the coarse levels in LDS:
 // level `first` arrives with its right-hand side and a zero iterate in global
 // memory, its iterate goes back to global memory at the end.  As on the
@@ -206,6 +408,12 @@ struct ek_ctx::MG {
   int coarsest_sweeps = COARSEST_SWEEPS;
   const double* pinv = nullptr;   // inverse for the direct coarsest solve, or null
   bool coarse_kernel = true;      // false: the coarsest level does not fit LDS
+  // Full sweeps by k_sweep_z (out of place) on the launched levels whose tiles
+  // fit: tile (sweep_tx, sweep_ty), zc planes per workgroup; 0 = half sweeps.
+  // The finest level sweeps into tmp0 and back, the others into tmp1.
+  std::vector<int> sweep_tx, sweep_ty, sweep_zc;
+  double* tmp0 = nullptr;
+  double* tmp1 = nullptr;
   // One V-cycle, and one V-cycle followed by the residual test, recorded as
   // graphs for the level-0 pair (b, x) they were recorded with: a replay
   // dispatches the cycle's ~30 dependent launches faster than the launches
@@ -249,6 +457,13 @@ size_t ek::mg_workspace_bytes(int nx, int ny, int nz) {
   // the coarsest level's inverse (direct solve)
   bytes += (size_t)COARSEST_DIRECT_MAX * COARSEST_DIRECT_MAX * 8;
   return bytes;
+}
+
+// The sweep buffers of the out-of-place full sweeps: the finest level and the
+// next (every coarser level fits in the latter).
+size_t ek::mg_sweep_bytes(int nx, int ny, int nz) {
+  const size_t n0 = (size_t)nx * ny * nz;
+  return 2 * 256 + ((n0 * 8 + 255) & ~size_t(255)) + ((n0 + 7) / 8 * 8 + 255) / 256 * 256;
 }
 
 // Inverse of M = A + c 11^T / n for the periodic 7-point operator A of level
@@ -361,6 +576,41 @@ void ek_ctx::mg_setup() {
     else
       (void)hipGetLastError();
   }
+  // full-sweep tiles of the launched levels: the first of 64x8, 64x16 and
+  // 32x8 that divides the level and gives 1024 or more workgroups at 8 or
+  // more planes per workgroup, else the one with the most workgroups if
+  // that is 512 or more (a smaller level keeps the half sweeps, whose
+  // launches fill the chip); levels whose post-smoothing is fused with the
+  // correction keep the half sweeps too
+  mg->sweep_tx.assign(nl, 0);
+  mg->sweep_ty.assign(nl, 0);
+  mg->sweep_zc.assign(nl, 0);
+  if (mg_tmp) {
+    char* t = mg_tmp + 256;
+    mg->tmp0 = (double*)t;
+    mg->tmp1 = (double*)(t + ((((size_t)p.nx * p.ny * p.nz) * 8 + 255) & ~size_t(255)) + 256);
+    for (int l = 0; l < fc; ++l) {
+      const Lvl& L = mg->levels[l];
+      if (L.n <= FUSED_CORRECTION_MAX_SITES) continue;
+      const int cand[3][2] = {{64, 8}, {64, 16}, {32, 8}};
+      long long best_wg = 0;
+      for (const auto& tc : cand) {
+        if (L.nx % tc[0] || L.ny % tc[1] || L.nz % 2) continue;
+        const long long tiles = (long long)(L.nx / tc[0]) * (L.ny / tc[1]);
+        int zc = L.nz;
+        while (zc % 2 == 0 && zc / 2 >= 8 && tiles * (L.nz / zc) < 1024) zc /= 2;
+        const long long wg = tiles * (L.nz / zc);
+        if (wg > best_wg) {
+          best_wg = wg;
+          mg->sweep_tx[l] = tc[0];
+          mg->sweep_ty[l] = tc[1];
+          mg->sweep_zc[l] = zc;
+        }
+        if (wg >= 1024) break;
+      }
+      if (best_wg < 512) mg->sweep_tx[l] = mg->sweep_ty[l] = mg->sweep_zc[l] = 0;
+    }
+  }
   mg->omega_coarsest = omega_opt(c.nx, c.ny, c.nz);
   const double rate = std::max(mg->omega_coarsest - 1.0, 1e-3);
   const double reduction = nl > 1 ? COARSEST_REDUCTION : 1e-10;
@@ -436,6 +686,21 @@ bool ek_ctx::mg_graphs(const double* bb, double* x) {
   return true;
 }
 
+// One full sweep of level L from xin into xout with the tile of the plan.
+static void launch_sweep_z(const Lvl& L, int tx, int ty, int zc, const double* xin, double* xout,
+                           const PoissonScalars* ps, int level0, hipStream_t s) {
+  const dim3 grid((unsigned)((L.nx / tx) * (L.ny / ty) * (L.nz / zc)));
+  if (tx == 64 && ty == 16)
+    hipLaunchKernelGGL((k_sweep_z<64, 16>), grid, dim3(SWEEP_THREADS), 0, s, L, xin, xout, zc, ps,
+                       level0, MG_OMEGA);
+  else if (tx == 64)
+    hipLaunchKernelGGL((k_sweep_z<64, 8>), grid, dim3(SWEEP_THREADS), 0, s, L, xin, xout, zc, ps,
+                       level0, MG_OMEGA);
+  else
+    hipLaunchKernelGGL((k_sweep_z<32, 8>), grid, dim3(SWEEP_THREADS), 0, s, L, xin, xout, zc, ps,
+                       level0, MG_OMEGA);
+}
+
 ek_status ek_ctx::mg_vcycle(const double* bb, double* x) {
   std::vector<Lvl>& L = mg->levels;
   L[0].x = x;
@@ -451,16 +716,28 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x) {
   }
   // Levels 1 .. fc-1 arrive from the restriction with their first colour-0
   // half sweep done; the level handed to the coarse kernel arrives at zero.
+  // The finest level with a full-sweep plan is pre-smoothed by one full
+  // sweep into tmp0 (NU1 = 1), restricted from there, and corrected back
+  // into x by the prolongation.
+  static_assert(NU1 == 1 && NU2 % 2 == 0, "the out-of-place sweeps end in x");
+  const bool pre0 = mg->sweep_tx[0] != 0;
   for (int l = 0; l < fc; ++l) {
-    for (int s = 0; s < NU1; ++s)
-      for (int c = 0; c < 2; ++c) {
-        if (l > 0 && s == 0 && c == 0) continue;
-        hipLaunchKernelGGL(k_smooth, colour_launch(L[l]).grid, colour_launch(L[l]).block, 0, stream,
-                           L[l], c, ps, l == 0 ? 1 : 0, MG_OMEGA);
-      }
+    Lvl F = L[l];
+    if (l == 0 && pre0) {
+      launch_sweep_z(L[0], mg->sweep_tx[0], mg->sweep_ty[0], mg->sweep_zc[0], x, mg->tmp0, ps, 1,
+                     stream);
+      F.x = mg->tmp0;
+    } else {
+      for (int s = 0; s < NU1; ++s)
+        for (int c = 0; c < 2; ++c) {
+          if (l > 0 && s == 0 && c == 0) continue;
+          hipLaunchKernelGGL(k_smooth, colour_launch(L[l]).grid, colour_launch(L[l]).block, 0,
+                             stream, L[l], c, ps, l == 0 ? 1 : 0, MG_OMEGA);
+        }
+    }
     const double omega_red = (l + 1 < fc && NU1 > 0) ? MG_OMEGA : 0.0;
     hipLaunchKernelGGL(k_restrict, level_launch(L[l + 1]).grid, level_launch(L[l + 1]).block, 0,
-                       stream, L[l], L[l + 1], ps, l == 0 ? 1 : 0, omega_red);
+                       stream, F, L[l + 1], ps, l == 0 ? 1 : 0, omega_red);
   }
   if (mg->coarse_kernel) {
     LvlSet set{};
@@ -482,6 +759,23 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x) {
   // coarse-grid correction: fused into the first post-smoothing sweep on
   // levels up to FUSED_CORRECTION_MAX_SITES, a pass of its own above
   for (int l = fc - 1; l >= 0; --l) {
+    if (mg->sweep_tx[l]) {
+      // correction (out of place from tmp0 on the finest level), then NU2
+      // full sweeps x -> tmp -> x
+      double* tmp = l == 0 ? mg->tmp0 : mg->tmp1;
+      if (l == 0 && pre0)
+        hipLaunchKernelGGL(k_prolong_to, level_launch(L[1]).grid, level_launch(L[1]).block, 0,
+                           stream, L[0], L[1], mg->tmp0, x, ps);
+      else
+        hipLaunchKernelGGL(k_prolong, level_launch(L[l + 1]).grid, level_launch(L[l + 1]).block, 0,
+                           stream, L[l], L[l + 1], ps);
+      for (int s = 0; s < NU2; ++s) {
+        const bool to_tmp = (s & 1) == 0;
+        launch_sweep_z(L[l], mg->sweep_tx[l], mg->sweep_ty[l], mg->sweep_zc[l],
+                       to_tmp ? L[l].x : tmp, to_tmp ? tmp : L[l].x, ps, l == 0 ? 1 : 0, stream);
+      }
+      continue;
+    }
     const bool fused = NU2 > 0 && L[l].n <= FUSED_CORRECTION_MAX_SITES;
     if (!fused)
       hipLaunchKernelGGL(k_prolong, level_launch(L[l + 1]).grid, level_launch(L[l + 1]).block, 0,

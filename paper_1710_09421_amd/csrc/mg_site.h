@@ -117,7 +117,10 @@ __device__ inline void prolong_site(const Lvl& F, const Lvl& C, int x, int y, in
 // The corrections of the 8 fine children of coarse cell (X, Y, Z), each the
 // sum of prolong_value term by term, from the cell's 3x3x3 coarse
 // neighbourhood read once; the two children in a fine row are adjacent.
-__device__ inline void prolong_cell(const Lvl& F, const Lvl& C, int X, int Y, int Z) {
+// src and dst are fine-level iterates (the same array for the in-place
+// correction).
+__device__ inline void prolong_cell(const Lvl& F, const Lvl& C, int X, int Y, int Z,
+                                    const double* src, double* dst) {
   const int xs[3] = {X == 0 ? C.nx - 1 : X - 1, X, X + 1 == C.nx ? 0 : X + 1};
   const int ys[3] = {Y == 0 ? C.ny - 1 : Y - 1, Y, Y + 1 == C.ny ? 0 : Y + 1};
   const int zs[3] = {Z == 0 ? C.nz - 1 : Z - 1, Z, Z + 1 == C.nz ? 0 : Z + 1};
@@ -134,8 +137,8 @@ __device__ inline void prolong_cell(const Lvl& F, const Lvl& C, int X, int Y, in
 #pragma unroll
     for (int oy = 0; oy < 2; ++oy) {
       const int zn = oz ? 2 : 0, yn = oy ? 2 : 0;
-      double* px = F.x + idx3(2 * X, 2 * Y + oy, 2 * Z + oz, F);
-      const double v0 = px[0], v1 = px[1];
+      const int r0 = idx3(2 * X, 2 * Y + oy, 2 * Z + oz, F);
+      const double v0 = src[r0], v1 = src[r0 + 1];
       double e[2];
 #pragma unroll
       for (int ox = 0; ox < 2; ++ox) {
@@ -144,9 +147,13 @@ __device__ inline void prolong_cell(const Lvl& F, const Lvl& C, int X, int Y, in
                 a * a * b * c[zn][1][1] + b * b * a * c[1][yn][xn] + b * a * b * c[zn][1][xn] +
                 a * b * b * c[zn][yn][1] + b * b * b * c[zn][yn][xn];
       }
-      px[0] = v0 + e[0];
-      px[1] = v1 + e[1];
+      dst[r0] = v0 + e[0];
+      dst[r0 + 1] = v1 + e[1];
     }
+}
+
+__device__ inline void prolong_cell(const Lvl& F, const Lvl& C, int X, int Y, int Z) {
+  prolong_cell(F, C, X, Y, Z, F.x, F.x);
 }
 
 // First post-smoothing sweep with the coarse-grid correction applied on the

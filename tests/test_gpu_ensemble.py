@@ -198,8 +198,8 @@ def test_autotune_picks_a_candidate(ek):
     assert res["threads"] in (256, 512, 1024) and res["group"] in (1, 2, 4)
     assert res["ms_per_step"] > 0
     ens.step(2)
-    for r in range(4):   # 3 workgroup sizes x 3 team sizes x (1 + 2) steps, then 2
-        assert ens.stats(r)["step"] == 9 * (1 + 2) + 2
+    for r in range(4):   # 3 workgroup sizes x 3 team sizes x (1 + 2 + 2) steps, then 2
+        assert ens.stats(r)["step"] == 9 * (1 + 2 + 2) + 2
 
 
 def test_no_convergence_names_the_replica(ek):

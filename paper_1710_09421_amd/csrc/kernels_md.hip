@@ -89,13 +89,18 @@ __global__ __launch_bounds__(256) void k_bead_box(BeadState bs, const T* __restr
                          inv_eps);
 }
 
-template <bool LDS, int TPB, int MAXT, int WR>
+template <bool LDS, int TPB, int NBL, int MAXT, int WR>
 __global__ __launch_bounds__(MAXT) void k_md(BeadState bs, MDParams mp, int* gkeys,
                                              long long* gvals, uint32_t* mask, Dims d,
-                                             int gbits, int lds_bits) {
+                                             int gbits, int lds_slots) {
   extern __shared__ __align__(16) unsigned char smem[];
-  md_chain<LDS, TPB, true, WR>(bs, mp, gkeys, gvals, mask, d, gbits, lds_bits, smem);
+  md_chain<LDS, TPB, NBL, WR>(bs, mp, gkeys, gvals, mask, d, gbits, lds_slots, smem);
 }
+
+// LDS of one workgroup the chain kernel may use: the device's limit for a
+// kernel that asks for it (160 KiB on gfx950), else the default 64 KiB.
+constexpr size_t CHAIN_LDS_MAX = 159 * 1024;   // 160 KiB less the static LDS of the kernel
+constexpr size_t CHAIN_LDS_DEFAULT = 64 * 1024;
 
 __global__ void k_err_reset(int* err) {
   if (threadIdx.x == 0) *err = 0;
@@ -217,40 +222,38 @@ ek_status ek_ctx::beads_advance(bool overlap, hipEvent_t chain_end) {
   const int tpb = n_beads <= 64 ? 8 : (n_beads <= 128 ? 4 : (n_beads <= 256 ? 2 : 1));
   const int threads = ((n_beads * tpb + 63) / 64) * 64;
   const size_t sr_bytes = ((size_t)n_beads * 24 + 15) & ~size_t(15);
-  auto md = [&](auto kernel, size_t lds, int bits) {
+  // The node table lives in LDS: 16 slots per bead (a load factor of at most
+  // 1/2 for eight corners per bead) where they fit beside the positions and
+  // the pair lists, else as many as fit (sites past them go to the global
+  // table).  Chains of at most SMALL_CHAIN beads list every candidate partner.
+  auto md = [&](auto kernel, int nbl) -> ek_status {
+    const size_t fixed = sr_bytes + md_list_bytes(threads, nbl);
+    auto slots_for = [&](size_t budget) {
+      const long long room = budget > fixed ? (long long)((budget - fixed) / (9 * 8 + 4)) : 0;
+      return (int)std::min<long long>(16LL * n_beads, room);
+    };
+    int slots = slots_for(CHAIN_LDS_MAX);
+    size_t lds = fixed + (size_t)slots * (9 * 8 + 4);
+    if (lds > CHAIN_LDS_DEFAULT &&
+        hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds) != hipSuccess) {
+      (void)hipGetLastError();
+      slots = slots_for(CHAIN_LDS_DEFAULT);
+      lds = fixed + (size_t)slots * (9 * 8 + 4);
+    }
+    if (slots < 1) return fail(EK_EHIP, "the chain's positions and pair lists do not fit LDS");
     hipLaunchKernelGGL(kernel, dim3(1), dim3(threads), lds, cs, bs, mp, keys, vals, mask, dims,
-                       HASH_BITS, bits);
+                       HASH_BITS, slots);
+    return EK_OK;
   };
   // the kernel instance for the chain's size and wall reach
   auto launch = [&](auto wr_tag) -> ek_status {
     constexpr int WR = decltype(wr_tag)::value;
-    if (n_beads <= LDS_MAX_BEADS) {
-      int bits = 6;
-      while ((1 << bits) < 16 * n_beads) ++bits;          // load factor <= 1/2 for 8 corners/bead
-      const size_t lds = sr_bytes + ((size_t)1 << bits) * (9 * 8 + 4) + md_list_bytes(true, threads, 8);
-      if (lds > 64 * 1024 &&
-          hipFuncSetAttribute((const void*)k_md<true, 8, 512, WR>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return fail(EK_EHIP, "cannot raise the LDS limit of the chain kernel");
-      md(k_md<true, 8, 512, WR>, lds, bits);
-      return EK_OK;
-    }
-    // positions and the per-lane pair lists
-    const size_t lds = sr_bytes + md_list_bytes(false, threads, tpb);
-    if (tpb == 4) {
-      md(k_md<false, 4, 512, WR>, lds, 0);
-    } else if (tpb == 2) {
-      md(k_md<false, 2, 512, WR>, lds, 0);
-    } else if (threads <= 512) {
-      md(k_md<false, 1, 512, WR>, lds, 0);
-    } else {
-      if (lds > 64 * 1024 &&
-          hipFuncSetAttribute((const void*)k_md<false, 1, 1024, WR>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return fail(EK_EHIP, "cannot raise the LDS limit of the chain kernel");
-      md(k_md<false, 1, 1024, WR>, lds, 0);
-    }
-    return EK_OK;
+    if (tpb == 8) return md(k_md<true, 8, SMALL_CHAIN / 8, 512, WR>, SMALL_CHAIN / 8);
+    if (tpb == 4) return md(k_md<true, 4, NB_PER_LANE, 512, WR>, NB_PER_LANE);
+    if (tpb == 2) return md(k_md<true, 2, NB_PER_LANE, 512, WR>, NB_PER_LANE);
+    if (threads <= 512) return md(k_md<true, 1, NB_PER_LANE, 512, WR>, NB_PER_LANE);
+    return md(k_md<true, 1, NB_PER_LANE, 1024, WR>, NB_PER_LANE);
   };
   const ek_status lst = wr == 1 ? launch(std::integral_constant<int, 1>{})
                                 : launch(std::integral_constant<int, 2>{});

@@ -151,9 +151,9 @@ __device__ inline long long round_fixed(double x) {
 }
 
 // Node accumulators for the friction impulse: the context's global table, or
-// (for chains of at most LDS_MAX_BEADS beads) a table in LDS that is flushed to
-// the global one once after the substeps.  Values are int64 fixed point, so
-// the sums are exact whatever the order of the additions.
+// a table in LDS (sites it has no room for stay in the global table) that is
+// flushed to the global one once after the substeps.  Values are int64 fixed
+// point, so the sums are exact whatever the order of the additions.
 struct GlobalNodes {
   int* keys;
   long long* vals;
@@ -169,27 +169,40 @@ struct GlobalNodes {
   }
 };
 
+// LDS probes of an insertion before the site goes to the global table.
+constexpr int LDS_PROBES = 32;
+
+// The LDS table has any number of slots (positions h = mulhi(mix(site), slots)
+// and linear probing); a site whose probe path holds no free slot within
+// LDS_PROBES probes is kept in the global table instead.  Every lane that
+// looks up a site walks the same path over slots that, once taken, stay
+// taken, so all of them reach the same decision.  Slot codes: h >= 0 the LDS
+// slot, h <= -2 the global slot -2 - h, -1 none (the global table is full).
 struct LdsNodes {
   int* keys;          // LDS [slots]
   long long* vals;    // LDS [slots][9]
-  int bits;
+  int slots;
   int* err;
+  GlobalNodes global;
   __device__ int slot(long long site) {
-    const int n = 1 << bits;
-    int h = int(((unsigned long long)site * 0x9E3779B97F4A7C15ull) >> (64 - bits));
-    for (int k = 0; k < n; ++k) {
+    const unsigned long long mix = (unsigned long long)site * 0x9E3779B97F4A7C15ull;
+    int h = int(((mix >> 32) * (unsigned long long)slots) >> 32);
+    const int probes = slots < LDS_PROBES ? slots : LDS_PROBES;
+    for (int k = 0; k < probes; ++k) {
       const int prev = atomicCAS(&keys[h], -1, int(site));
       if (prev == -1 || prev == int(site)) return h;
-      h = (h + 1) & (n - 1);
+      h = h + 1 == slots ? 0 : h + 1;
     }
-    atomicOr(err, ERR_TABLE);
-    return -1;
+    const int g = global.slot(site);
+    return g < 0 ? -1 : -2 - g;
   }
   __device__ double get(int h, int c) const {
-    return double(vals[h * 9 + c]) * (1.0 / FIX_FORCE);
+    if (h >= 0) return double(vals[h * 9 + c]) * (1.0 / FIX_FORCE);
+    return global.get(-2 - h, c);
   }
   __device__ void add(int h, int c, long long v) {
-    atomicAdd((unsigned long long*)&vals[h * 9 + c], (unsigned long long)v);
+    if (h >= 0) atomicAdd((unsigned long long*)&vals[h * 9 + c], (unsigned long long)v);
+    else global.add(-2 - h, c, v);
   }
 };
 
@@ -370,46 +383,43 @@ __device__ inline void bead_box_item(const BeadState& bs, int i, int t, const T*
 
 // Pair partners kept per lane: lane l of bead i lists the beads j = l,
 // l + TPB, ... within the WCA cut-off plus NB_SKIN at the last build, in
-// increasing j.  The list is rebuilt when any bead has moved more than
-// NB_SKIN / 2 since the build, so every pair inside the cut-off stays listed.
-// Chains with the node table in LDS (at most LDS_MAX_BEADS beads) have room
-// for every candidate; longer chains keep up to NB_PER_LANE partners per lane
-// and a lane that would list more switches the chain back to all pairs.  A
-// lane sums the same nonzero pair terms in the same order either way.
+// increasing j, up to NBL of them (a template parameter).  The list is rebuilt
+// when any bead has moved more than NB_SKIN / 2 since the build, so every
+// pair inside the cut-off stays listed.  Chains of at most SMALL_CHAIN beads
+// with eight lanes per bead have room for every candidate
+// (NBL = SMALL_CHAIN / 8); longer chains keep up to NB_PER_LANE partners per
+// lane and a lane that would list more switches the chain back to all pairs.
+// A lane sums the same nonzero pair terms in the same order either way.
 constexpr int NB_PER_LANE = 32;
 constexpr double NB_SKIN = 0.6;
-constexpr int LDS_MAX_BEADS = 64;
+constexpr int SMALL_CHAIN = 64;
 
-__host__ __device__ constexpr int md_list_len(bool lds_table, int tpb) {
-  return lds_table ? (LDS_MAX_BEADS + tpb - 1) / tpb : NB_PER_LANE;
-}
-
-// LDS bytes of md_chain beyond the positions and the LDS node table.
-__host__ __device__ inline size_t md_list_bytes(bool lds_table, int threads, int tpb) {
-  return (size_t)threads * md_list_len(lds_table, tpb) * sizeof(unsigned short);
+// LDS bytes of the pair lists.
+__host__ __device__ inline size_t md_list_bytes(int threads, int nbl) {
+  return (size_t)threads * nbl * sizeof(unsigned short);
 }
 
 // n_sub substeps of one chain by one workgroup (TPB lanes per bead; the
 // threads beyond n * TPB only take part in the barriers).  smem: LDS for the
-// bead positions, when LDS is set the node table of 2^lds_bits slots, and
-// with LISTS the pair lists (md_list_bytes; without them every lane walks all
-// its candidate partners each substep: the persistent ensemble kernel, whose
-// registers the lists would spill).
-template <bool LDS, int TPB, bool LISTS = true, int WR = 1>
+// bead positions, when LDS is set the node table of lds_slots slots (sites
+// that find no room there go to the global table), and with NBL > 0 the pair
+// lists (md_list_bytes; with NBL = 0 every lane walks all its candidate
+// partners each substep: the persistent ensemble kernel, whose registers the
+// lists would spill).
+template <bool LDS, int TPB, int NBL, int WR = 1>
 __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gkeys,
                                 long long* gvals, uint32_t* mask, const Dims& d, int gbits,
-                                int lds_bits, unsigned char* smem) {
+                                int lds_slots, unsigned char* smem) {
   using G = WallGeom<WR>;
   constexpr int WIN = G::W;                                    // flag window edge
   constexpr int CPL = 8 / TPB;                                 // corners per lane
   double* sR = (double*)smem;                                  // [3 * n]
   long long* lvals = (long long*)(smem + (((size_t)mp.n * 24 + 15) & ~size_t(15)));
-  const int lslots = LDS ? (1 << lds_bits) : 0;
+  const int lslots = LDS ? lds_slots : 0;
   int* lkeys = (int*)(lvals + (size_t)lslots * 9);
   // pair lists: entry k of thread t at nbl[k * blockDim.x + t], after the
   // LDS node table
-  constexpr bool NLIST = LISTS;
-  constexpr int NBL = md_list_len(LDS, TPB);
+  constexpr bool NLIST = NBL > 0;
   unsigned short* nbl = (unsigned short*)(lkeys + lslots);
   __shared__ int s_rebuild, s_overflow;
   if (NLIST && threadIdx.x == 0) {
@@ -443,7 +453,7 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
   const double z_start = R[2];   // for the plane crossing record
   __syncthreads();
   GlobalNodes gn{gkeys, gvals, mask, bs.err, gbits};
-  LdsNodes ln{lkeys, lvals, lds_bits, bs.err};
+  LdsNodes ln{lkeys, lvals, lslots, bs.err, gn};
 
   const double h = 1.0 / mp.n_sub;
   const double hM = h / mp.M;
@@ -580,7 +590,7 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
         for (int a = 0; a < CPL; ++a)
 #pragma unroll
           for (int k = 0; k < 9; ++k)
-            kpre[a][k] = slot[a] < 0 ? 0.0 : (LDS ? ln.get(slot[a], k) : gn.get(slot[a], k));
+            kpre[a][k] = slot[a] == -1 ? 0.0 : (LDS ? ln.get(slot[a], k) : gn.get(slot[a], k));
       }
       // plain and fluid-renormalised trilinear weights; with the occupation
       // cube, its node indicator per axis (offset 0: d < sigma/2, offset 1:
@@ -631,7 +641,7 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
             for (int c = 0; c < 3; ++c) {
               const double kacc =
                   PRE_K ? kpre[PRE_K ? a : 0][3 * s + c]
-                        : (slot[a] < 0 ? 0.0 : (LDS ? ln.get(slot[a], 3 * s + c)
+                        : (slot[a] == -1 ? 0.0 : (LDS ? ln.get(slot[a], 3 * s + c)
                                                     : gn.get(slot[a], 3 * s + c)));
               acc[3 * s + c] += wt[a] * (mo[6 + 3 * s + c] + kacc) * mo[3 + s];
             }
@@ -647,7 +657,7 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
       constexpr int NBOND = TPB >= 2 ? 1 : 2;        // bonds per bond lane
       const int bond0 = TPB >= 2 ? lane : 0;         // 0: bond to i - 1, 1: to i + 1
       const bool bond_lane = TPB >= 2 ? lane < 2 : true;
-      constexpr bool PRE_B = LDS && LISTS;
+      constexpr bool PRE_B = LDS && NLIST;
       double PB[PRE_B ? NBOND : 1][3];
       if constexpr (PRE_B) {
 #pragma unroll
@@ -678,7 +688,7 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
         // read together (one LDS round trip each), the terms are added in
         // list order
         constexpr int CH = 4;
-        static_assert(md_list_len(true, TPB) % CH == 0 && NB_PER_LANE % CH == 0, "list chunks");
+        static_assert(NBL % CH == 0, "list chunks");
         for (int k0 = 0; k0 < nb_count; k0 += CH) {
           int jj[CH];
 #pragma unroll
@@ -796,7 +806,7 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
     if (live) {
 #pragma unroll
       for (int a = 0; a < CPL; ++a) {
-        if (wt[a] == 0.0 || slot[a] < 0) continue;
+        if (wt[a] == 0.0 || slot[a] == -1) continue;
         const double g = -h * wt[a] * FIX_FORCE;   // impulse scale of this corner
 #pragma unroll
         for (int s = 0; s < 3; ++s)

@@ -150,6 +150,8 @@ void launch_mean_shift(const double* partials, int nblocks, double inv_n, double
 void launch_sor_half(double* psi, const double* b, const PoissonScalars* ps, int colour,
                      double omega, Dims d, const SiteGrid& g, hipStream_t s);
 // Returns the number of block partials it writes (for launch_residual_final).
+// Blocks (partial sums) of launch_residual for a lattice and its site grid.
+int residual_blocks(const Dims& d, const SiteGrid& g);
 int launch_residual(const double* psi, const double* b, PoissonScalars* ps, double* partials,
                     Dims d, const SiteGrid& g, hipStream_t s);
 void launch_residual_final(const double* partials, int nblocks, double tol, int iter,

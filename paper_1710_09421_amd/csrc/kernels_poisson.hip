@@ -81,6 +81,127 @@ __global__ __launch_bounds__(BLOCK) void k_residual(const double* __restrict__ p
   block_partials<3>(acc, partials, bid, nblocks);
 }
 
+// The same sums marching up z: a workgroup owns a RZ_TX x RZ_TY tile of zc
+// planes and keeps three planes of the tile and a one-site ring in LDS (a
+// fourth receives the plane after them), so psi and b are read once from
+// memory (the rings and the planes either side of a chunk again by the
+// neighbouring workgroups, mostly from the cache).  Each thread adds its
+// sites' terms in plane order; block_partials combines the threads.  The
+// loads are issued a step ahead and without branches (indexes past the end
+// are clamped, their values never used), so the compiler waits only for the
+// load in use.
+constexpr int RZ_TX = 64, RZ_TY = 8, RZ_THREADS = 256;
+
+template <int TX, int TY>
+__global__ __launch_bounds__(RZ_THREADS) void k_residual_z(const double* __restrict__ psi,
+                                                           const double* __restrict__ b,
+                                                           const PoissonScalars* __restrict__ ps,
+                                                           double* __restrict__ partials, Dims d,
+                                                           int zc) {
+  constexpr int RX = TX + 2, RY = TY + 2, REGION = RX * RY;
+  constexpr int XPT = (REGION + RZ_THREADS - 1) / RZ_THREADS;
+  constexpr int SPT = TX * TY / RZ_THREADS;
+  static_assert((TX * TY) % RZ_THREADS == 0, "whole tiles per thread");
+  struct Regs {
+    double x[XPT];   // a psi plane (tile and ring), to be stored in LDS
+    double b[SPT];   // b at this thread's tile sites of a plane
+  };
+  __shared__ double P[4][RY][RX];
+  if (ps->done) return;
+  const double shift = ps->shift;
+  const int nx = d.nx, ny = d.ny, nz = d.nz, tid = threadIdx.x;
+  // workgroup -> (tile, chunk), neighbouring tiles of a chunk on one XCD
+  const int ntx = nx / TX, nty = ny / TY, nblk = gridDim.x;
+  int bb = blockIdx.x;
+  if ((nblk & 7) == 0) bb = (bb & 7) * (nblk >> 3) + (bb >> 3);
+  const int tx_i = bb % ntx, rest = bb / ntx, ty_i = rest % nty, chunk = rest / nty;
+  const int x0 = tx_i * TX, y0 = ty_i * TY, z0 = chunk * zc, z1 = z0 + zc;
+  auto wrapi = [](int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); };
+  auto plane_base = [&](int q) {
+    int zq = q % nz;
+    if (zq < 0) zq += nz;
+    return (long long)zq * ny * nx;
+  };
+  auto slot = [&](int q) { return (q - z0 + 1) & 3; };
+  auto gather_x = [&](int q, double (&r)[XPT]) {
+    const long long base = plane_base(q);
+#pragma unroll
+    for (int u = 0; u < XPT; ++u) {
+      const int t = min(tid + u * RZ_THREADS, REGION - 1);
+      const int j = t / RX, i = t - j * RX;
+      r[u] = psi[base + (long long)wrapi(y0 - 1 + j, ny) * nx + wrapi(x0 - 1 + i, nx)];
+    }
+  };
+  auto store_x = [&](int sl, const double (&r)[XPT]) {
+#pragma unroll
+    for (int u = 0; u < XPT; ++u) {
+      const int t = tid + u * RZ_THREADS;
+      if (t < REGION) {
+        const int j = t / RX, i = t - j * RX;
+        P[sl][j][i] = r[u];
+      }
+    }
+  };
+  auto gather_b = [&](int k, double (&r)[SPT]) {
+    const long long base = plane_base(k);
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) {
+      const int t = tid + u * RZ_THREADS;
+      const int jj = t / TX, ii = t - jj * TX;
+      r[u] = b[base + (long long)(y0 + jj) * nx + x0 + ii];
+    }
+  };
+  double acc[3] = {0.0, 0.0, 0.0};
+  // step k: the residual of plane k (planes k-1, k, k+1 in LDS, b of plane k
+  // in cur); nxt receives plane k+3 (stored at the end of step k+1) and b of
+  // plane k+1
+  auto step = [&](int k, Regs& cur, Regs& nxt) {
+    gather_x(min(k + 3, z1), nxt.x);
+    gather_b(min(k + 1, z1 - 1), nxt.b);
+    const int s0 = slot(k), sm = slot(k - 1), sp = slot(k + 1);
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) {
+      const int t = tid + u * RZ_THREADS;
+      const int j = 1 + t / TX, i = 1 + t % TX;
+      const double c = P[s0][j][i];
+      const double lap = P[s0][j][i - 1] + P[s0][j][i + 1] + P[s0][j - 1][i] + P[s0][j + 1][i] +
+                         P[sm][j][i] + P[sp][j][i] - 6.0 * c;
+      const double rhs = cur.b[u] + shift;
+      const double res = rhs - lap;
+      acc[0] += res * res;
+      acc[1] += rhs * rhs;
+      acc[2] += c;
+    }
+    if (k + 2 <= z1) store_x(slot(k + 2), cur.x);
+    __syncthreads();
+  };
+  Regs A, B;
+  for (int q = z0 - 1; q <= z0 + 1; ++q) {
+    gather_x(q, A.x);
+    store_x(slot(q), A.x);
+  }
+  gather_x(min(z0 + 2, z1), A.x);
+  gather_b(z0, A.b);
+  __syncthreads();
+  int k = z0;
+  for (; k + 1 < z1; k += 2) {
+    step(k, A, B);
+    step(k + 1, B, A);
+  }
+  if (k < z1) step(k, A, B);
+  block_partials<3>(acc, partials, blockIdx.x, gridDim.x);
+}
+
+// Chunk height of the z-marching residual, or 0 where its tile does not
+// divide the lattice or it would give fewer than 512 workgroups.
+int residual_zc(const Dims& d) {
+  if (d.nx % RZ_TX || d.ny % RZ_TY) return 0;
+  const long long tiles = (long long)(d.nx / RZ_TX) * (d.ny / RZ_TY);
+  int zc = d.nz;
+  while (zc % 2 == 0 && zc / 2 >= 8 && tiles * (d.nz / zc) < 1024) zc /= 2;
+  return tiles * (d.nz / zc) >= 512 ? zc : 0;
+}
+
 __global__ __launch_bounds__(1024) void k_residual_final(const double* __restrict__ partials,
                                                          int nblocks, double tol, int iter,
                                                          int initial, PoissonScalars* ps) {
@@ -270,12 +391,23 @@ void launch_sor_half(double* psi, const double* b, const PoissonScalars* ps, int
   hipLaunchKernelGGL(k_sor_half, g.grid, g.block, 0, s, psi, b, ps, colour, omega, d);
 }
 
+int residual_blocks(const Dims& d, const SiteGrid& g) {
+  if (const int zc = residual_zc(d)) return (d.nx / RZ_TX) * (d.ny / RZ_TY) * (d.nz / zc);
+  return int(g.grid.x * g.grid.y * ((d.nz + RESIDUAL_PLANES - 1) / RESIDUAL_PLANES));
+}
+
 int launch_residual(const double* psi, const double* b, PoissonScalars* ps, double* partials,
                     Dims d, const SiteGrid& g, hipStream_t s) {
+  const int nblocks = residual_blocks(d, g);
+  if (const int zc = residual_zc(d)) {
+    hipLaunchKernelGGL((k_residual_z<RZ_TX, RZ_TY>), dim3(nblocks), dim3(RZ_THREADS), 0, s, psi, b,
+                       ps, partials, d, zc);
+    return nblocks;
+  }
   dim3 grid = g.grid;
   grid.z = (d.nz + RESIDUAL_PLANES - 1) / RESIDUAL_PLANES;
   hipLaunchKernelGGL(k_residual, grid, g.block, 0, s, psi, b, ps, partials, d);
-  return int(grid.x * grid.y * grid.z);
+  return nblocks;
 }
 
 void launch_residual_final(const double* partials, int nblocks, double tol, int iter,

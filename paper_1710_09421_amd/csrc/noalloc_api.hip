@@ -91,9 +91,9 @@ extern "C" ek_status ek_poisson_solve_noalloc(const ek_params* p, const double* 
   }
   const SiteGrid g = site_grid(p->nx, p->ny, p->nz);
   const SiteGrid cg = colour_grid(p->nx, p->ny, p->nz);
-  // the residual reduction writes 3 components over its blocks (z planes in
-  // groups of 4), the charge reduction 1 over the site grid's blocks
-  const long long res_blocks = (long long)g.grid.x * g.grid.y * ((p->nz + 3) / 4);
+  // the residual reduction writes 3 components over its blocks, the charge
+  // reduction 1 over the site grid's blocks
+  const long long res_blocks = residual_blocks(d, g);
   if ((long long)g.nblocks() > NOALLOC_PARTIALS || 3 * res_blocks > NOALLOC_PARTIALS)
     return fail(EK_EINVAL, "lattice shape needs more block partials than the scratch holds");
 

@@ -370,7 +370,7 @@ __global__ __launch_bounds__(MAXT) void k_ensemble(RepDev* reps, EnsConst ec) {
       for (int it = tid; it < R.n_beads * WIN3; it += MAXT)
         bead_box_item(R.bs, it / WIN3, it % WIN3, fsrc, R.mask, R.psi, lp, d);
       __syncthreads();
-      md_chain<true, TPB, 0>(R.bs, R.mp, R.keys, R.vals, R.mask, d, ENS_TABLE_BITS,
+      md_chain<true, TPB, 0, 1, false>(R.bs, R.mp, R.keys, R.vals, R.mask, d, ENS_TABLE_BITS,
                              1 << ec.lds_bits, smem);
     }
     TEAM_SYNC();

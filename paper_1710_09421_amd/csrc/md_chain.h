@@ -405,8 +405,9 @@ __host__ __device__ inline size_t md_list_bytes(int threads, int nbl) {
 // that find no room there go to the global table), and with NBL > 0 the pair
 // lists (md_list_bytes; with NBL = 0 every lane walks all its candidate
 // partners each substep: the persistent ensemble kernel, whose registers the
-// lists would spill).
-template <bool LDS, int TPB, int NBL, int WR = 1>
+// lists would spill).  THERMAL = false compiles the bead noise out (the
+// ensemble, which runs without thermal fluctuations).
+template <bool LDS, int TPB, int NBL, int WR = 1, bool THERMAL = true>
 __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gkeys,
                                 long long* gvals, uint32_t* mask, const Dims& d, int gbits,
                                 int lds_slots, unsigned char* smem) {
@@ -781,7 +782,7 @@ __device__ inline void md_chain(const BeadState& bs, const MDParams& mp, int* gk
       // friction of each species (with the thermal noise shared by the
       // species' number fractions) and the substep update
       double xi[3] = {0.0, 0.0, 0.0};
-      if (mp.thermal) {
+      if (THERMAL && mp.thermal) {
         const Philox4 w = philox4x32_10(uint32_t(i), mp.tstep, uint32_t(sub), 1u, mp.key0, mp.key1);
         double z[4];
         box_muller4<double>(w, z);

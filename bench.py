@@ -259,6 +259,7 @@ def measure_ensemble(args, steps):
     """64 uneven replicas of the 48 x 48 x 96 pore system in one persistent
     launch per call; the autotuner picks the workgroup size and the number of
     workgroups per replica during warm-up."""
+    import numpy as np
     import torch
     from paper_1710_09421_amd import ek, workloads
     n_rep = 64
@@ -275,11 +276,16 @@ def measure_ensemble(args, steps):
     progress(f"autotuned: {tune}")
     ens.step(1)
     torch.cuda.synchronize()
+    ph0 = [ens.phase_times(r) for r in range(n_rep)]
     t0 = time.perf_counter()
     ens.step(steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     progress(f"timed {steps} steps in {dt:.3f} s")
+    ph1 = [ens.phase_times(r) for r in range(n_rep)]
+    # per-step phase times of each replica's team (the kernel's own clock)
+    phase = {k: [(ph1[r][k] - ph0[r][k]) / steps for r in range(n_rep)]
+             for k in ("charge", "poisson", "chain", "lb")}
     sites = n_rep * wls[0].sites
     cycles = [ens.stats(r)["poisson_iters"] for r in range(n_rep)]
     # release the ensemble while the runtime is fully up, not from a finaliser
@@ -289,6 +295,10 @@ def measure_ensemble(args, steps):
     torch.cuda.synchronize()
     fluid = sum(w.fluid_sites for w in wls)
     lb_bytes = fluid * (2 * 57 * 4 + 8) + sites * 4
+    # the teams run their collide-and-stream phases side by side: the
+    # ensemble's lattice bytes of a step over the slowest team's phase time
+    lb_max = max(phase["lb"])
+    lb_gbs = lb_bytes / (lb_max * 1e-3) / 1e9
     return {
         "value": round(3 * sites * steps / dt / 1e6, 1),
         "ms_per_step": round(dt / steps * 1e3, 4),
@@ -302,6 +312,14 @@ def measure_ensemble(args, steps):
             "poisson": f"mg to 1e-8 per replica from the {start_name} start, "
                        f"last solve {min(cycles)}-{max(cycles)} cycles",
             "lb_bytes_per_step_gb": round(lb_bytes / 1e9, 3),
+            "phase_ms_per_step": {k: round(float(np.mean(v)), 4) for k, v in phase.items()},
+            "phase_ms_per_step_max": {k: round(float(np.max(v)), 4) for k, v in phase.items()},
+        },
+        "lb_phase_roofline": {
+            "phase": "fused collide-and-stream of all replicas (per-team clock in the kernel)",
+            "bound": "hbm", "achieved": round(lb_gbs, 1), "peak": 8000.0, "unit": "GB/s",
+            "frac": round(lb_gbs / 8000.0, 4), "bytes_per_step": int(lb_bytes),
+            "ms_per_step": round(lb_max, 4),
         },
     }
 

@@ -524,6 +524,17 @@ ek_status ek_ensemble_get_potential(ek_ensemble* ens, int32_t r, double* psi);
 ek_status ek_ensemble_get_beads(ek_ensemble* ens, int32_t r, double* pos, double* vel);
 ek_status ek_ensemble_get_stats(ek_ensemble* ens, int32_t r, ek_stats* out);
 
+/* Time spent by replica r's team in the phases of every step it has taken
+ * since the ensemble was created (the persistent kernel's own clock:
+ * thread 0 of the team's first workgroup reads the device wall clock at the
+ * team barriers that end the phases), in milliseconds: ms[0] the bead deposit
+ * and charge pass (Eq. poisson's right-hand side), ms[1] the Poisson solve
+ * and gauge, ms[2] the chain (Sec. II.B), ms[3] the fused collide-and-stream
+ * (Eq. kernelf2) with its sums.  Host array of 4; reads the values as of the
+ * last ek_ensemble_step / ek_ensemble_autotune.  EK_EINVAL for a bad r or a
+ * NULL ms; EK_EHIP when the device reports no wall-clock rate. */
+ek_status ek_ensemble_phase_times(ek_ensemble* ens, int32_t r, double* ms);
+
 /* Workgroup size of the persistent kernel (256, 512 or 1024). */
 ek_status ek_ensemble_set_threads(ek_ensemble* ens, int32_t threads);
 

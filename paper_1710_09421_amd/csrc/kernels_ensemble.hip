@@ -78,6 +78,10 @@ struct RepDev {
   double last_res;
   double last_res0;
   double stats[6];            // species masses and fluid momentum of f(t)
+  // wall-clock ticks spent by the team's first workgroup in the phases of
+  // all steps so far: charge pass, Poisson solve, chain, collide-and-stream
+  unsigned long long phase_ticks[4];
+  unsigned long long phase_mark;   // clock at the start of the current phase
 };
 
 struct EnsConst {
@@ -244,8 +248,22 @@ __global__ __launch_bounds__(MAXT) void k_ensemble(RepDev* reps, EnsConst ec) {
     __syncthreads();                                  \
     break;                                            \
   }
+  // phase clock (thread 0 of member 0): each phase ends at a team barrier,
+  // so its span is the team's.  The counters are the replica's own words in
+  // global memory, not registers of every thread (the 512-thread instance
+  // has none to spare) nor static LDS (40 more bytes there moved the
+  // kernel's LDS layout and made that instance 50 % slower).
+  const bool timer = tid == 0 && g == 0;
+  auto lap = [&](int ph) {
+    if (timer) {
+      const unsigned long long now = wall_clock64();
+      R.phase_ticks[ph] += now - R.phase_mark;
+      R.phase_mark = now;
+    }
+  };
   for (int step = 0; step < ec.n_steps; ++step) {
     if (s_status != ST_OK) break;
+    if (timer) R.phase_mark = wall_clock64();
     const T* fsrc = (const T*)R.f[cur];
     T* fdst = (T*)R.f[cur ^ 1];
     BeadTableView bt;
@@ -283,6 +301,7 @@ __global__ __launch_bounds__(MAXT) void k_ensemble(RepDev* reps, EnsConst ec) {
       break;
     }
     const double shift = rs[0] / double(N) * ec.inv_eps;
+    lap(0);
 
     // Poisson: multigrid cycles until ||b - A psi|| / ||b|| <= tol
     auto residual = [&](double& rel, double& psum, double& b2) -> bool {
@@ -364,6 +383,7 @@ __global__ __launch_bounds__(MAXT) void k_ensemble(RepDev* reps, EnsConst ec) {
     const double mean = zero_rhs ? 0.0 : psum / double(N);
     for (int t = first; t < N; t += stride) R.psi[t] = zero_rhs ? 0.0 : R.psi[t] - mean;
     TEAM_SYNC();
+    lap(1);
 
     // chain (member 0): fields around the beads, then n_sub substeps
     if (R.n_beads > 0 && g == 0) {
@@ -374,6 +394,7 @@ __global__ __launch_bounds__(MAXT) void k_ensemble(RepDev* reps, EnsConst ec) {
                              1 << ec.lds_bits, smem);
     }
     TEAM_SYNC();
+    lap(2);
 
     // fused collide-and-stream
     double acc[6] = {0, 0, 0, 0, 0, 0};
@@ -403,6 +424,7 @@ __global__ __launch_bounds__(MAXT) void k_ensemble(RepDev* reps, EnsConst ec) {
     // every member reads the chain's error word before any member clears it
     // in the next step's deposit
     TEAM_SYNC();
+    lap(3);
   }
 #undef TEAM_SYNC
   if (tid == 0 && g == 0) {
@@ -438,6 +460,7 @@ struct ek_ensemble {
   EnsConst ec{};
   int threads = 512;
   int group = 1;              // workgroups per replica
+  double wall_khz = 0.0;      // rate of the device's wall clock
   std::string err;
 
   ek_status fail(ek_status st, const std::string& m) {
@@ -645,6 +668,14 @@ ek_status ek_ensemble_create(const ek_params* base, int32_t n_rep, int32_t max_b
   e->stream = (hipStream_t)hip_stream;
   e->ws = ws;
   e->own = own;
+  {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess)
+      e->wall_khz = khz;
+    else
+      (void)hipGetLastError();
+  }
   e->reps_dev = (RepDev*)ws;
   e->wall_q = (double*)(ws + shared_bytes(n_rep));
   const RepLayout RL = rep_layout(base, max_beads);
@@ -968,6 +999,14 @@ ek_status ek_ensemble_get_beads(ek_ensemble* e, int32_t r, double* pos, double* 
       (vel && hipMemcpyAsync(vel, R.bs.V, R.n_beads * 24, hipMemcpyDeviceToHost, e->stream) != hipSuccess) ||
       hipStreamSynchronize(e->stream) != hipSuccess)
     return e->fail(EK_EHIP, "reading beads failed");
+  return EK_OK;
+}
+
+ek_status ek_ensemble_phase_times(ek_ensemble* e, int32_t r, double* ms) {
+  if (!e || !ms) return EK_EINVAL;
+  if (r < 0 || r >= e->n_rep) return e->fail(EK_EINVAL, "bad replica");
+  if (!(e->wall_khz > 0)) return e->fail(EK_EHIP, "the device's wall-clock rate is unknown");
+  for (int ph = 0; ph < 4; ++ph) ms[ph] = double(e->reps[r].phase_ticks[ph]) / e->wall_khz;
   return EK_OK;
 }
 

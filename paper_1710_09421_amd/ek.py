@@ -144,6 +144,7 @@ def _load():
         "ek_ensemble_get_stats": (c_int32, [c_void_p, c_int32, P(ek_stats)]),
         "ek_ensemble_set_threads": (c_int32, [c_void_p, c_int32]),
         "ek_ensemble_autotune": (c_int32, [c_void_p, c_int32, P(ek_tune_result)]),
+        "ek_ensemble_phase_times": (c_int32, [c_void_p, c_int32, c_void_p]),
         "ek_ensemble_set_group": (c_int32, [c_void_p, c_int32]),
     }
     for name, (res, args) in sig.items():
@@ -505,6 +506,14 @@ class Ensemble:
         if nb:
             self._check(self._lib.ek_ensemble_get_beads(self._h, r, _ptr(pos), _ptr(vel)), self._h)
         return pos, vel
+
+    def phase_times(self, r):
+        """ek_ensemble_phase_times: ms spent by replica r's team in the charge
+        pass, the Poisson solve, the chain and the collide-and-stream of all
+        its steps so far."""
+        ms = np.empty(4)
+        self._check(self._lib.ek_ensemble_phase_times(self._h, r, _ptr(ms)), self._h)
+        return dict(charge=ms[0], poisson=ms[1], chain=ms[2], lb=ms[3])
 
     def stats(self, r):
         s = ek_stats()

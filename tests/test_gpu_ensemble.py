@@ -230,3 +230,28 @@ def test_harmonic_replicas_match_single_contexts(ek):
         R_e, _ = ens.beads(r)
         R_c, _ = ctx.beads(wl.beads_R.shape[0])
         assert np.abs(R_e - R_c).max() < 1e-6, r
+
+
+def test_phase_times(ek):
+    """ek_ensemble_phase_times: the persistent kernel's own clock of the four
+    phases grows with the steps taken and its sum stays below the host's
+    wall time around the call; a bad replica index is rejected."""
+    import time
+    import torch
+    ens = ek.ensemble_from_workloads(replicas(), precision=ek.EK_FP32)
+    ens.step(1)
+    before = [ens.phase_times(r) for r in range(4)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.step(3)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    for r in range(4):
+        after = ens.phase_times(r)
+        grew = {k: after[k] - before[r][k] for k in after}
+        assert all(v > 0.0 for v in grew.values()), grew
+        assert sum(grew.values()) <= wall_ms * 1.01 + 0.05, (grew, wall_ms)
+    with pytest.raises(ek.EKError) as e:
+        ens.phase_times(4)
+    assert e.value.status == ek.EK_EINVAL
+    ens.close()

@@ -134,10 +134,10 @@ def test_polymer_argument_checks(ek):
 
 @pytest.mark.parametrize("n_beads,steps", [(48, 8), (80, 8), (130, 8), (300, 3)])
 def test_long_chain_fp64_matches_oracle(ek, n_beads, steps):
-    """Chains of up to 64 beads keep the node table in LDS (8 lanes per bead:
-    48 beads fill six waves); beyond 64 beads it moves to global memory (4
-    lanes per bead up to 128 beads, then 2, then 1) and the WCA partners come
-    from per-lane pair lists."""
+    """Chains of up to 64 beads run 8 lanes per bead (48 beads fill six
+    waves) and list every candidate partner; longer chains run 4 lanes per
+    bead up to 128 beads, then 2, then 1, with per-lane pair lists of bounded
+    length.  Every chain keeps its node table in LDS."""
     wl = workloads.pore_system((64, 40, 40), 8, 5, 0.01, 0.01, -0.01, n_beads, 41,
                                bead_q=workloads.STABLE_BEAD_CHARGE, steps=10)
     ctx = ek.from_workload(wl, precision=ek.EK_FP64, poisson_tol=1e-10, poisson_check_every=1)
@@ -173,8 +173,9 @@ def test_pair_lists_rebuilt_within_a_step(ek):
 @pytest.mark.parametrize("n_beads,steps", [(8, 20), (80, 8)])
 def test_harmonic_chain_fp64_matches_oracle(ek, n_beads, steps):
     """The bonded term of Eq. polymermodel (harmonic bonds of rest length 1)
-    with the WCA only between beads more than one apart, on the LDS node
-    table with pair lists (8 beads) and on the global one (80 beads)."""
+    with the WCA only between beads more than one apart: 8 lanes per bead
+    with every candidate listed (8 beads) and 4 lanes per bead with bounded
+    pair lists (80 beads)."""
     if n_beads == 8:
         wl = pore_with_chain(seed=34)
     else:
@@ -189,6 +190,41 @@ def test_harmonic_chain_fp64_matches_oracle(ek, n_beads, steps):
     print(n_beads, err)
     assert max(err.values()) < 1e-8, err
     assert np.abs(sim.V).max() > 1e-4
+
+
+def test_node_table_overflow_into_global_memory_matches_oracle(ek):
+    """A 300-bead chain on a grid of spacing 2 (harmonic bonds of rest
+    length 2 along a snake path, each bead at a cell centre): no two beads
+    share a corner, so the chain touches 2,400 nodes, more than the 1,778
+    slots of LDS node table the launcher gives a 300-bead chain (160 KiB
+    less its positions and pair lists; 498 if only 64 KiB were granted).
+    At least 622 sites therefore live in the global table, and the chain
+    still matches the oracle."""
+    wl = workloads.pore_system((64, 40, 40), 8, 5, 0.01, 0.01, -0.01, 300, 41,
+                               bead_q=workloads.STABLE_BEAD_CHARGE, steps=10)
+    pts = []
+    for k in range(3):
+        for j in range(10):
+            row = [(10.5 + 2 * i, 10.5 + 2 * (j if k % 2 == 0 else 9 - j), 45.5 + 2 * k)
+                   for i in range(10)]
+            pts.extend(row if j % 2 == 0 else row[::-1])
+    R = np.array(pts, dtype=np.float64)
+    assert R.shape == (300, 3)
+    assert np.allclose(np.linalg.norm(np.diff(R, axis=0), axis=1), 2.0)
+    corners = {tuple(np.floor(r).astype(int) + np.array(o)) for r in R
+               for o in np.ndindex(2, 2, 2)}
+    assert len(corners) == 8 * 300
+    wl.beads_R = R
+    wl.beads_V = np.zeros_like(R)
+    wl.polymer.update(bond="harmonic", k_bond=10.0, l_bond=2.0)
+    ctx = ek.from_workload(wl, precision=ek.EK_FP64, poisson_tol=1e-10, poisson_check_every=1)
+    sim = oracle_sim(wl, 1e-10)
+    ctx.step(3)
+    sim.run(3)
+    err = errors(ctx, sim, wl)
+    print(err)
+    assert max(err.values()) < 1e-8, err
+    assert np.abs(sim.V).max() > 1e-6
 
 
 def test_harmonic_bond_parameters_are_checked(ek):

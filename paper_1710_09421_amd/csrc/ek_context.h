@@ -118,7 +118,10 @@ struct ek_ctx {
   ek_status learned_start(const double* b, double* x, ek::PoissonScalars* h);
   void mg_setup();
   void mg_release();
-  ek_status mg_vcycle(const double* b, double* x);
+  // One V-cycle; with norm_blocks given, its last finest-level sweep also
+  // leaves the residual norms' block partials where the finest level allows
+  // it (*norm_blocks = their count, else 0: the caller takes the residual).
+  ek_status mg_vcycle(const double* b, double* x, int* norm_blocks = nullptr);
   bool mg_graphs(const double* b, double* x);
   ek_status poisson(const double* b, double* x, bool learned, int& iters, double& res,
                     double& res0);

@@ -35,6 +35,7 @@
 
 #include "ek_context.h"
 #include "mg_site.h"
+#include "reduce.h"
 
 using namespace ek;
 
@@ -303,6 +304,257 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_z(Lvl L, const double* 
   if (k <= z1) step(k, A, B);
 }
 
+// --- a full sweep that also takes the residual of its result ---------------
+// As k_sweep_z, with a three-site ring: the colour-0 sites are relaxed on the
+// tile and two rings, the colour-1 sites on the tile and one ring, so the
+// swept values of the tile and its one-site ring are final and the residual
+// r = (f + shift) - A x of the result is taken on the tile as the march goes:
+// at step k, after the colour-1 sites of plane k-1, the residual of plane k-2
+// (from planes k-3, k-2 and k-1).  MODE = SWEEP_RESTRICT adds the residuals
+// of each 2 x 2 x 2 block in the order of restrict_site and writes the coarse
+// level's right-hand side (and its first colour-0 half sweep, omega_red), so
+// the pre-smoothing of the finest level and its restriction are one pass;
+// MODE = SWEEP_NORMS adds r^2, (f + shift)^2 and x for the convergence test
+// (block partials as k_residual), so the last post-smoothing sweep of a tested
+// cycle is its residual pass too.  A chunk computes the colour-1 sites of the
+// planes either side of it as well (its neighbours do too), and keeps six
+// planes in LDS.  zc even, z0 even; TX, TY multiples of 4.
+enum : int { SWEEP_RESTRICT = 1, SWEEP_NORMS = 2 };
+
+template <int TX, int TY>
+struct SweepRRegs {
+  static constexpr int RX = TX + 6, RY = TY + 6;
+  static constexpr int REGION = RX * RY;
+  static constexpr int XPT = (REGION + SWEEP_THREADS - 1) / SWEEP_THREADS;
+  static constexpr int RED_ROW = TX / 2 + 2;              // colour-0 sites per ring-2 row
+  static constexpr int RED_ITEMS = RED_ROW * (TY + 4);
+  static constexpr int RPT = (RED_ITEMS + SWEEP_THREADS - 1) / SWEEP_THREADS;
+  static constexpr int BLK_ROW = TX / 2 + 1;              // colour-1 sites per ring-1 row
+  static constexpr int BLK_ITEMS = BLK_ROW * (TY + 2);
+  static constexpr int BPT = (BLK_ITEMS + SWEEP_THREADS - 1) / SWEEP_THREADS;
+  static constexpr int CELLS = (TX / 2) * (TY / 2);       // 2 x 2 blocks of the tile
+  double x[XPT];     // an iterate plane (tile and three-site ring), to be stored in LDS
+  double fr[RPT];    // f at this thread's colour-0 ring-2 sites of a plane
+  double fb[BPT];    // f at this thread's colour-1 ring-1 sites of a plane
+  double ft[2];      // f at this thread's two tile sites of a plane (a row of its 2 x 2 block)
+};
+
+template <int TX, int TY, int MODE>
+__global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_zr(Lvl L, const double* __restrict__ xin,
+                                                            double* __restrict__ xout, int zc,
+                                                            const PoissonScalars* ps, int level0,
+                                                            double omega, Lvl C, double omega_red,
+                                                            double* __restrict__ partials) {
+  static_assert(TX % 4 == 0 && TY % 4 == 0, "tiles of whole 2 x 2 blocks");
+  static_assert(2 * SweepRRegs<TX, TY>::CELLS <= SWEEP_THREADS, "a 2 x 2 block per thread pair");
+  using R = SweepRRegs<TX, TY>;
+  constexpr int RX = R::RX, RY = R::RY, NS = 6;
+  __shared__ double P[NS][RY][RX];
+  if (ps->done) return;
+  const double shift = level0 ? ps->shift : 0.0;
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
+  const double h2 = L.h2, ih2 = 1.0 / L.h2;
+  const double* __restrict__ f = L.f;
+  const int tid = threadIdx.x;
+  const int ntx = nx / TX, nty = ny / TY, nblk = gridDim.x;
+  int b = blockIdx.x;
+  if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
+  const int tx_i = b % ntx, rest = b / ntx, ty_i = rest % nty, chunk = rest / nty;
+  const int x0 = tx_i * TX, y0 = ty_i * TY, z0 = chunk * zc, z1 = z0 + zc;
+  const int zb = z0 - 3;                                    // plane in slot-relative index 0
+  auto wrapi = [](int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); };
+  auto plane_base = [&](int q) {
+    int zq = q % nz;
+    if (zq < 0) zq += nz;
+    return (long long)zq * ny * nx;
+  };
+  auto slot = [&](int q) { return (q - zb) % NS; };
+  auto gather_x = [&](int q, double (&r)[R::XPT]) {
+    const long long base = plane_base(q);
+#pragma unroll
+    for (int u = 0; u < R::XPT; ++u) {
+      const int t = min(tid + u * SWEEP_THREADS, R::REGION - 1);
+      const int j = t / RX, i = t - j * RX;
+      r[u] = xin[base + (long long)wrapi(y0 - 3 + j, ny) * nx + wrapi(x0 - 3 + i, nx)];
+    }
+  };
+  auto store_x = [&](int sl, const double (&r)[R::XPT]) {
+#pragma unroll
+    for (int u = 0; u < R::XPT; ++u) {
+      const int t = tid + u * SWEEP_THREADS;
+      if (t < R::REGION) {
+        const int j = t / RX, i = t - j * RX;
+        P[sl][j][i] = r[u];
+      }
+    }
+  };
+  // colour-0 item t of plane k: ring-2 row j in [1, TY + 5), column i
+  auto red_site = [&](int t, int k, int& j, int& i) {
+    const int jj = t / R::RED_ROW, m = t - jj * R::RED_ROW;
+    j = 1 + jj;
+    i = (((x0 + y0 + k + j) & 1) ? 1 : 2) + 2 * m;
+  };
+  // colour-1 item t of plane k: ring-1 row j in [2, TY + 4), column i
+  auto black_site = [&](int t, int k, int& j, int& i) {
+    const int jj = t / R::BLK_ROW, m = t - jj * R::BLK_ROW;
+    j = 2 + jj;
+    i = (((x0 + y0 + k + 1 + j) & 1) ? 3 : 2) + 2 * m;
+  };
+  // tile 2 x 2 block of this thread pair: threads 2c and 2c + 1 take row
+  // 3 + 2 cy + (tid & 1) of block c, sites at columns 3 + 2 cx and 4 + 2 cx
+  const int cell = min(tid >> 1, R::CELLS - 1);
+  const int cx = cell % (TX / 2), cy = cell / (TX / 2), crow = tid & 1;
+  const bool has_cell = (tid >> 1) < R::CELLS;
+  auto gather_fr = [&](int k, double (&r)[R::RPT]) {
+    const long long base = plane_base(k);
+#pragma unroll
+    for (int u = 0; u < R::RPT; ++u) {
+      const int t = min(tid + u * SWEEP_THREADS, R::RED_ITEMS - 1);
+      int j, i;
+      red_site(t, k, j, i);
+      r[u] = f[base + (long long)wrapi(y0 - 3 + j, ny) * nx + wrapi(x0 - 3 + i, nx)];
+    }
+  };
+  auto gather_fb = [&](int k, double (&r)[R::BPT]) {
+    const long long base = plane_base(k);
+#pragma unroll
+    for (int u = 0; u < R::BPT; ++u) {
+      const int t = min(tid + u * SWEEP_THREADS, R::BLK_ITEMS - 1);
+      int j, i;
+      black_site(t, k, j, i);
+      r[u] = f[base + (long long)wrapi(y0 - 3 + j, ny) * nx + wrapi(x0 - 3 + i, nx)];
+    }
+  };
+  auto gather_ft = [&](int k, double (&r)[2]) {
+    const long long base = plane_base(k) + (long long)(y0 + 2 * cy + crow) * nx + x0 + 2 * cx;
+    r[0] = f[base];
+    r[1] = f[base + 1];
+  };
+  double acc[3] = {0.0, 0.0, 0.0};   // SWEEP_NORMS
+  double rsum = 0.0;                 // SWEEP_RESTRICT: this thread's row of the block so far
+  // Step k, in two phases between barriers:
+  //   1. colour 0 of plane k (tile and two rings); the tile of plane k-2,
+  //      final since step k-1, is written, and the residual of plane k-3
+  //      taken (from planes k-4, k-3, k-2);
+  //   2. colour 1 of plane k-1 (tile and one ring); plane k+2 is stored, in
+  //      the slot of plane k-4, which phase 1 used last.
+  // The two parts of phase 1 touch disjoint planes (k-1 .. k+1 and k-4 ..
+  // k-2), so one barrier separates the phases.  cur holds plane k+2, f of the
+  // colour-0 sites of plane k, of the colour-1 sites of plane k-1 and of this
+  // thread's tile row of plane k-3; nxt receives plane k+3 and f of planes
+  // k+1, k and k-2 (clamped near the chunk's ends: loaded, never used).
+  auto step = [&](int k, R& cur, R& nxt) {
+    gather_x(min(k + 3, z1 + 2), nxt.x);
+    gather_fr(min(k + 1, z1 + 1), nxt.fr);
+    gather_fb(max(min(k, z1), z0 - 1), nxt.fb);
+    gather_ft(max(min(k - 2, z1 - 1), z0), nxt.ft);
+    const int sk = slot(k), skm = slot(k + NS - 1), skp = slot(k + 1), skm2 = slot(k + NS - 2),
+              skm3 = slot(k + NS - 3), skm4 = slot(k + NS - 4);
+    // 1a. colour 0 of plane k on the tile and two rings
+    if (k <= z1 + 1) {
+#pragma unroll
+      for (int u = 0; u < R::RPT; ++u) {
+        const int t = tid + u * SWEEP_THREADS;
+        if (t < R::RED_ITEMS) {
+          int j, i;
+          red_site(t, k, j, i);
+          const double xo = P[sk][j][i];
+          const double nb = P[sk][j][i - 1] + P[sk][j][i + 1] + P[sk][j - 1][i] + P[sk][j + 1][i] +
+                            P[skm][j][i] + P[skp][j][i];
+          const double gs = (nb - h2 * (cur.fr[u] + shift)) * (1.0 / 6.0);
+          P[sk][j][i] = omega == 1.0 ? gs : xo + omega * (gs - xo);
+        }
+      }
+    }
+    // 1b. write the tile of plane k-2; the residual of plane k-3
+    if (k - 2 >= z0 && k - 2 < z1) {
+      const long long base = plane_base(k - 2);
+      for (int t = tid; t < (TX / 2) * TY; t += SWEEP_THREADS) {
+        const int jj = t / (TX / 2), m = t - jj * (TX / 2);
+        double2 out;
+        out.x = P[skm2][3 + jj][3 + 2 * m];
+        out.y = P[skm2][3 + jj][4 + 2 * m];
+        *reinterpret_cast<double2*>(xout + base + (long long)(y0 + jj) * nx + x0 + 2 * m) = out;
+      }
+    }
+    if (k - 3 >= z0 && k - 3 < z1) {
+      if (has_cell) {
+        const int j = 3 + 2 * cy + crow;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int i = 3 + 2 * cx + q;
+          const double c = P[skm3][j][i];
+          const double nb = P[skm3][j][i - 1] + P[skm3][j][i + 1] + P[skm3][j - 1][i] +
+                            P[skm3][j + 1][i] + P[skm4][j][i] + P[skm2][j][i];
+          const double rhs = cur.ft[q] + shift;
+          if (MODE == SWEEP_RESTRICT) {
+            rsum += rhs - (nb - 6.0 * c) * ih2;
+          } else {
+            const double res = rhs - (nb - 6.0 * c);
+            acc[0] += res * res;
+            acc[1] += rhs * rhs;
+            acc[2] += c;
+          }
+        }
+      }
+      if (MODE == SWEEP_RESTRICT && ((k - 3) & 1)) {
+        // the block's second plane: the coarse cell's right-hand side (the
+        // two rows' sums met in the even thread) and its first colour-0 half
+        // sweep from the zero start
+        const double other = __shfl_xor(rsum, 1, 64);
+        if (has_cell && crow == 0) {
+          const int X = x0 / 2 + cx, Y = y0 / 2 + cy, Z = (k - 3) >> 1;
+          const long long t = ((long long)Z * C.ny + Y) * C.nx + X;
+          const double fc = 0.125 * (rsum + other);
+          C.f[t] = fc;
+          double xc = 0.0;
+          if (omega_red != 0.0 && ((X + Y + Z) & 1) == 0) {
+            const double gs = (0.0 - C.h2 * (fc + 0.0)) * (1.0 / 6.0);
+            xc = omega_red == 1.0 ? gs : 0.0 + omega_red * (gs - 0.0);
+          }
+          C.x[t] = xc;
+        }
+        rsum = 0.0;
+      }
+    }
+    __syncthreads();
+    // 2. colour 1 of plane k-1 on the tile and one ring (the planes either
+    // side of the chunk as well); store plane k+2
+    if (k >= z0 && k <= z1 + 1) {
+#pragma unroll
+      for (int u = 0; u < R::BPT; ++u) {
+        const int t = tid + u * SWEEP_THREADS;
+        if (t < R::BLK_ITEMS) {
+          int j, i;
+          black_site(t, k - 1, j, i);
+          const double xo = P[skm][j][i];
+          const double nb = P[skm][j][i - 1] + P[skm][j][i + 1] + P[skm][j - 1][i] +
+                            P[skm][j + 1][i] + P[skm2][j][i] + P[sk][j][i];
+          const double gs = (nb - h2 * (cur.fb[u] + shift)) * (1.0 / 6.0);
+          P[skm][j][i] = omega == 1.0 ? gs : xo + omega * (gs - xo);
+        }
+      }
+    }
+    if (k + 2 <= z1 + 2) store_x(slot(k + 2), cur.x);
+    __syncthreads();
+  };
+  R A, B;
+  for (int q = zb; q <= z0 - 1; ++q) {                      // planes z0-3, z0-2, z0-1
+    gather_x(q, A.x);
+    store_x(slot(q), A.x);
+  }
+  gather_x(z0, A.x);
+  gather_fr(z0 - 2, A.fr);
+  __syncthreads();
+  int k = z0 - 2;
+  for (; k + 1 <= z1 + 2; k += 2) {
+    step(k, A, B);
+    step(k + 1, B, A);
+  }
+  if (k <= z1 + 2) step(k, A, B);
+  if (MODE == SWEEP_NORMS) block_partials<3>(acc, partials, blockIdx.x, gridDim.x);
+}
+
 // The coarse part of the cycle runs on copies of the coarse levels in LDS:
 // level `first` arrives with its right-hand side and a zero iterate in global
 // memory, its iterate goes back to global memory at the end.  As on the
@@ -414,6 +666,10 @@ struct ek_ctx::MG {
   std::vector<int> sweep_tx, sweep_ty, sweep_zc;
   double* tmp0 = nullptr;
   double* tmp1 = nullptr;
+  // the finest level's pre-smoothing sweep also restricts, and a tested
+  // cycle's last sweep also takes the residual norms (k_sweep_zr: a 64 x 8
+  // tile and chunks of an even number of planes)
+  bool fused0 = false;
   // One V-cycle, and one V-cycle followed by the residual test, recorded as
   // graphs for the level-0 pair (b, x) they were recorded with: a replay
   // dispatches the cycle's ~30 dependent launches faster than the launches
@@ -610,6 +866,8 @@ void ek_ctx::mg_setup() {
       }
       if (best_wg < 512) mg->sweep_tx[l] = mg->sweep_ty[l] = mg->sweep_zc[l] = 0;
     }
+    mg->fused0 = fc > 1 && mg->sweep_tx[0] == 64 && mg->sweep_ty[0] == 8 &&
+                 mg->sweep_zc[0] % 2 == 0;
   }
   mg->omega_coarsest = omega_opt(c.nx, c.ny, c.nz);
   const double rate = std::max(mg->omega_coarsest - 1.0, 1e-3);
@@ -670,8 +928,9 @@ bool ek_ctx::mg_graphs(const double* bb, double* x) {
   const bool ok =
       record_graph(stream, &m.cycle, [&] { mg_vcycle(bb, x); }) &&
       record_graph(stream, &m.cycle_test, [&] {
-        mg_vcycle(bb, x);
-        const int nr = launch_residual(x, bb, ps, partials, dims, g, stream);
+        int nb = 0;
+        mg_vcycle(bb, x, &nb);
+        const int nr = nb ? nb : launch_residual(x, bb, ps, partials, dims, g, stream);
         // iteration -1: the test reads the cycle count the coarse kernel keeps
         launch_residual_final(partials, nr, p.poisson_tol, -1, 0, ps, stream);
       });
@@ -701,7 +960,23 @@ static void launch_sweep_z(const Lvl& L, int tx, int ty, int zc, const double* x
                        level0, MG_OMEGA);
 }
 
-ek_status ek_ctx::mg_vcycle(const double* bb, double* x) {
+// The finest level's full sweep with the residual of its result (restriction
+// into level C, or the norms' block partials); returns the block count.
+static int launch_sweep_zr(const Lvl& L, int zc, const double* xin, double* xout,
+                           const PoissonScalars* ps, int mode, const Lvl& C, double omega_red,
+                           double* partials, hipStream_t s) {
+  const int nblocks = (L.nx / 64) * (L.ny / 8) * (L.nz / zc);
+  if (mode == SWEEP_RESTRICT)
+    hipLaunchKernelGGL((k_sweep_zr<64, 8, SWEEP_RESTRICT>), dim3(nblocks), dim3(SWEEP_THREADS), 0,
+                       s, L, xin, xout, zc, ps, 1, MG_OMEGA, C, omega_red, partials);
+  else
+    hipLaunchKernelGGL((k_sweep_zr<64, 8, SWEEP_NORMS>), dim3(nblocks), dim3(SWEEP_THREADS), 0, s,
+                       L, xin, xout, zc, ps, 1, MG_OMEGA, C, 0.0, partials);
+  return nblocks;
+}
+
+ek_status ek_ctx::mg_vcycle(const double* bb, double* x, int* norm_blocks) {
+  if (norm_blocks) *norm_blocks = 0;
   std::vector<Lvl>& L = mg->levels;
   L[0].x = x;
   L[0].f = const_cast<double*>(bb);
@@ -723,6 +998,12 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x) {
   const bool pre0 = mg->sweep_tx[0] != 0;
   for (int l = 0; l < fc; ++l) {
     Lvl F = L[l];
+    const double omega_red = (l + 1 < fc && NU1 > 0) ? MG_OMEGA : 0.0;
+    if (l == 0 && mg->fused0) {   // sweep and restriction in one pass
+      launch_sweep_zr(L[0], mg->sweep_zc[0], x, mg->tmp0, ps, SWEEP_RESTRICT, L[1], omega_red,
+                      nullptr, stream);
+      continue;
+    }
     if (l == 0 && pre0) {
       launch_sweep_z(L[0], mg->sweep_tx[0], mg->sweep_ty[0], mg->sweep_zc[0], x, mg->tmp0, ps, 1,
                      stream);
@@ -735,7 +1016,6 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x) {
                              stream, L[l], c, ps, l == 0 ? 1 : 0, MG_OMEGA);
         }
     }
-    const double omega_red = (l + 1 < fc && NU1 > 0) ? MG_OMEGA : 0.0;
     hipLaunchKernelGGL(k_restrict, level_launch(L[l + 1]).grid, level_launch(L[l + 1]).block, 0,
                        stream, F, L[l + 1], ps, l == 0 ? 1 : 0, omega_red);
   }
@@ -771,6 +1051,11 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x) {
                            stream, L[l], L[l + 1], ps);
       for (int s = 0; s < NU2; ++s) {
         const bool to_tmp = (s & 1) == 0;
+        if (l == 0 && s == NU2 - 1 && norm_blocks && mg->fused0) {   // the test's residual too
+          *norm_blocks = launch_sweep_zr(L[0], mg->sweep_zc[0], tmp, L[0].x, ps, SWEEP_NORMS,
+                                         L[1], 0.0, partials, stream);
+          continue;
+        }
         launch_sweep_z(L[l], mg->sweep_tx[l], mg->sweep_ty[l], mg->sweep_zc[l],
                        to_tmp ? L[l].x : tmp, to_tmp ? tmp : L[l].x, ps, l == 0 ? 1 : 0, stream);
       }
@@ -817,10 +1102,11 @@ ek_status ek_ctx::mg_solve(const double* bb, double* x, PoissonScalars h, int& i
         if (e != hipSuccess) return fail(EK_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
         continue;
       }
-      st = mg_vcycle(bb, x);
+      int nb = 0;
+      st = mg_vcycle(bb, x, test ? &nb : nullptr);
       if (st) return st;
       if (!test) continue;
-      const int nr = launch_residual(x, bb, ps, partials, dims, g, stream);
+      const int nr = nb ? nb : launch_residual(x, bb, ps, partials, dims, g, stream);
       launch_residual_final(partials, nr, p.poisson_tol, it, 0, ps, stream);
     }
     untested = 0;

@@ -187,8 +187,8 @@ def measure_context(wl, args, steps, warmup):
     progress(f"workload {wl.name}: {wl.sites} sites")
     prec = ek.EK_FP32 if args.precision == "fp32" else ek.EK_FP64
     method = ek.EK_POISSON_SOR if args.poisson == "sor" else ek.EK_POISSON_MG
-    start = {"extrapolated": ek.EK_WS_EXTRAP, "quadratic": ek.EK_WS_EXTRAP2}.get(args.start,
-                                                                               ek.EK_WS_PREV)
+    start = {"extrapolated": ek.EK_WS_EXTRAP, "quadratic": ek.EK_WS_EXTRAP2,
+             "cubic": ek.EK_WS_EXTRAP3}.get(args.start, ek.EK_WS_PREV)
     ctx = ek.from_workload(wl, precision=prec, poisson_method=method,
                            poisson_check_every=args.check_every,
                            poisson_max_iter=200 if method == ek.EK_POISSON_MG else 100000,
@@ -335,10 +335,11 @@ def main():
     ap.add_argument("--poisson", default="mg", choices=["sor", "mg"])
     ap.add_argument("--check-every", type=int, default=4)
     ap.add_argument("--start", default="quadratic",
-                    choices=["previous", "extrapolated", "quadratic"],
+                    choices=["previous", "extrapolated", "quadratic", "cubic"],
                     help="start of each step's Poisson solve: the previous solution, the "
-                         "linear extrapolation of the two previous ones or the quadratic one "
-                         "of the three previous ones")
+                         "linear extrapolation of the two previous ones, the quadratic one "
+                         "of the three previous ones or the cubic one of the four previous "
+                         "ones")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="measure only the named workload (no single-pore and ensemble keys)")

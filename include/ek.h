@@ -68,9 +68,18 @@ enum { EK_POISSON_SOR = 0, EK_POISSON_MG = 1 };    /* Poisson method          */
  * extrapolation in time 2 psi(t-1) - psi(t-2) of the two previous steps'
  * solutions (the previous solution on the first two steps after
  * ek_set_geometry); or the quadratic one 3 psi(t-1) - 3 psi(t-2) + psi(t-3)
- * (linear on the third step, the previous solution before).  The solver
+ * (linear on the third step, the previous solution before); or the cubic one
+ * 4 psi(t-1) - 6 psi(t-2) + 4 psi(t-3) - psi(t-4) (quadratic on the fourth
+ * step, linear on the third, the previous solution before).  The solver
  * finishes every start to the same tolerance. */
-enum { EK_WS_ZERO = 0, EK_WS_PREV = 1, EK_WS_LEARNED = 2, EK_WS_EXTRAP = 3, EK_WS_EXTRAP2 = 4 };
+enum {
+  EK_WS_ZERO = 0,
+  EK_WS_PREV = 1,
+  EK_WS_LEARNED = 2,
+  EK_WS_EXTRAP = 3,
+  EK_WS_EXTRAP2 = 4,
+  EK_WS_EXTRAP3 = 5
+};
 
 /* Problem statement (Sec. II.A-C).  Copied at ek_create. */
 typedef struct {
@@ -96,7 +105,8 @@ typedef struct {
   int32_t warm_start;          /* EK_WS_ZERO, EK_WS_PREV, EK_WS_LEARNED
                                   (ek_set_model; sizes multiples of 4) or
                                   EK_WS_EXTRAP (one more float64 field in
-                                  the workspace) or EK_WS_EXTRAP2 (two more) */
+                                  the workspace), EK_WS_EXTRAP2 (two more)
+                                  or EK_WS_EXTRAP3 (three more)           */
   uint64_t seed;               /* key of the thermal noise (64 bits)           */
   int32_t fluctuations;        /* 0: none; 1: thermal fluctuations (Sec. II.A
                                   and II.C): the stochastic term Delta of
@@ -311,7 +321,7 @@ ek_status ek_load_state(struct ek_ctx* ctx, const void* host, size_t bytes);
  * density, dev_psi[nz*ny*nx] warm start on entry and solution (mean zero) on
  * return, both float64.  Uses the context's method, tolerance and iteration
  * limit; warm_start EK_WS_ZERO clears dev_psi first, EK_WS_PREV,
- * EK_WS_EXTRAP and EK_WS_EXTRAP2 start from dev_psi as given (a stand-alone
+ * EK_WS_EXTRAP, EK_WS_EXTRAP2 and EK_WS_EXTRAP3 start from dev_psi as given (a stand-alone
  * solve has no history to extrapolate), EK_WS_LEARNED consults the network (EK_ESTATE
  * without a model); other values give EK_EINVAL.  The context's own fields
  * (populations, potential) are not touched. */

@@ -54,7 +54,7 @@ ek_status check_params(const ek_params* p, std::string& why) {
     return EK_EINVAL;
   }
   if (p->rho_jacobi < 0.0 || p->rho_jacobi >= 1.0) { why = "rho_jacobi must be in [0, 1)"; return EK_EINVAL; }
-  if (p->warm_start < EK_WS_ZERO || p->warm_start > EK_WS_EXTRAP2) { why = "unknown warm_start"; return EK_EINVAL; }
+  if (p->warm_start < EK_WS_ZERO || p->warm_start > EK_WS_EXTRAP3) { why = "unknown warm_start"; return EK_EINVAL; }
   if (p->warm_start == EK_WS_LEARNED && !UNet::shape_ok(p->nx, p->ny, p->nz)) {
     why = "the learned warm start needs nx, ny, nz divisible by 4 (two 2x2x2 poolings)";
     return EK_EINVAL;
@@ -72,7 +72,7 @@ ek_status check_params(const ek_params* p, std::string& why) {
 // Workspace layout (every block 256-byte aligned).
 struct Layout {
   size_t fA, fB, mask, wall_q, psi, b, partials, ps, stats, keys, vals, beads, mg, mgt, net, guess,
-      psi_old, psi_old2, total;
+      psi_old, psi_old2, psi_old3, total;
 };
 
 Layout make_layout(const ek_params* p, int max_beads) {
@@ -103,8 +103,10 @@ Layout make_layout(const ek_params* p, int max_beads) {
   const bool learned = p->warm_start == EK_WS_LEARNED;
   L.net = take(learned ? UNet::bytes(p->nx, p->ny, p->nz, false) : 0);
   L.guess = take(learned ? n * 8 : 0);
-  L.psi_old = take(p->warm_start == EK_WS_EXTRAP || p->warm_start == EK_WS_EXTRAP2 ? n * 8 : 0);
-  L.psi_old2 = take(p->warm_start == EK_WS_EXTRAP2 ? n * 8 : 0);
+  const int held = extrap_history(p->warm_start);
+  L.psi_old = take(held >= 1 ? n * 8 : 0);
+  L.psi_old2 = take(held >= 2 ? n * 8 : 0);
+  L.psi_old3 = take(held >= 3 ? n * 8 : 0);
   L.total = off;
   return L;
 }
@@ -333,17 +335,21 @@ ek_status ek_ctx::step_impl(int n_steps) {
       ek_status st = beads_deposit();
       if (st) return st;
     }
-    // the charge pass also prepares the extrapolated start (EK_WS_EXTRAP):
-    // psi = 2 psi(t-1) - psi(t-2) once two previous solutions exist
-    // (and the quadratic one of EK_WS_EXTRAP2 once three exist: mode 4;
-    // the linear one with the history shifted on the third step: mode 3)
+    // the charge pass also prepares the extrapolated start: with psi_hist
+    // previous solutions held (psi, then the history buffers) it extrapolates
+    // with the highest order they allow, up to the order of the warm start,
+    // and shifts the history by one (the mode numbers of StartExtrap)
+    const int held = extrap_history(p.warm_start);
     int extrap = 0;
-    if (p.warm_start == EK_WS_EXTRAP) extrap = std::min(psi_hist, 2);
-    if (p.warm_start == EK_WS_EXTRAP2) extrap = psi_hist >= 3 ? 4 : (psi_hist == 2 ? 3 : psi_hist);
+    if (held > 0) {
+      const int order = std::min(psi_hist - 1, held);  // -1: no solution yet
+      static const int keep[3] = {1, 3, 5};            // order < held: history deepens
+      static const int top[4] = {0, 2, 4, 6};          // order == held
+      if (order >= 0) extrap = order == held ? top[order] : keep[order];
+    }
     launch_charge<T>((const T*)fcur(), mask, wall_q, b, partials, lp, inv_eps(), dims, g, stream, bt,
-                     psi, psi_old, extrap, insulating(), psi_old2);
-    if (p.warm_start == EK_WS_EXTRAP) psi_hist = std::min(psi_hist + 1, 2);
-    if (p.warm_start == EK_WS_EXTRAP2) psi_hist = std::min(psi_hist + 1, 3);
+                     psi, psi_old, extrap, insulating(), psi_old2, psi_old3);
+    if (held > 0) psi_hist = std::min(psi_hist + 1, held + 1);
     launch_mean_shift(partials, nb, 1.0 / double(insulating() ? n_fluid : dims.n), inv_eps(), ps,
                       stream);
     record(t, 1);
@@ -535,9 +541,10 @@ ek_status ek_create(const ek_params* p, int32_t max_beads, void* dev_ws, size_t 
       return EK_EHIP;
     }
   }
-  if (p->warm_start == EK_WS_EXTRAP || p->warm_start == EK_WS_EXTRAP2)
-    c->psi_old = (double*)(ws + L.psi_old);
-  if (p->warm_start == EK_WS_EXTRAP2) c->psi_old2 = (double*)(ws + L.psi_old2);
+  const int held = extrap_history(p->warm_start);
+  if (held >= 1) c->psi_old = (double*)(ws + L.psi_old);
+  if (held >= 2) c->psi_old2 = (double*)(ws + L.psi_old2);
+  if (held >= 3) c->psi_old3 = (double*)(ws + L.psi_old3);
   *out = c;
   return EK_OK;
 }
@@ -753,7 +760,7 @@ ek_status ek_poisson_solve(ek_ctx* ctx, const double* dev_rho, double* dev_psi,
   if (!ctx) return EK_EINVAL;
   if (ctx->insulating()) return ctx->fail(EK_ESTATE, "the context has insulating walls");
   if (!dev_rho || !dev_psi) return ctx->fail(EK_EINVAL, "NULL device buffer");
-  if (warm_start < EK_WS_ZERO || warm_start > EK_WS_EXTRAP2) return ctx->fail(EK_EINVAL, "unknown warm_start");
+  if (warm_start < EK_WS_ZERO || warm_start > EK_WS_EXTRAP3) return ctx->fail(EK_EINVAL, "unknown warm_start");
   if (warm_start == EK_WS_LEARNED && !(ctx->net && ctx->net->have_params))
     return ctx->fail(EK_ESTATE, "learned warm start without a model (ek_set_model)");
   const SiteGrid g = site_grid(ctx->p.nx, ctx->p.ny, ctx->p.nz, ctx->bx_sites);

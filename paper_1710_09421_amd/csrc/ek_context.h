@@ -129,10 +129,12 @@ struct ek_ctx {
   // learned warm start (present when p.warm_start == EK_WS_LEARNED)
   ek::UNet* net = nullptr;
   double* guess = nullptr;
-  // extrapolated start (p.warm_start == EK_WS_EXTRAP): psi(t-2), and how many
-  // previous step solutions the history holds (0, 1 or 2)
+  // extrapolated starts (EK_WS_EXTRAP, EK_WS_EXTRAP2, EK_WS_EXTRAP3): psi(t-2),
+  // psi(t-3), psi(t-4) as the order needs them, and how many previous step
+  // solutions psi and the history hold (0 up to the order + 1)
   double* psi_old = nullptr;
-  double* psi_old2 = nullptr;          // psi(t-3) of the quadratic start (EK_WS_EXTRAP2)
+  double* psi_old2 = nullptr;
+  double* psi_old3 = nullptr;
   int psi_hist = 0;
   template <typename T>
   ek_status step_impl(int n_steps);

@@ -103,8 +103,16 @@ struct PoissonScalars {
 template <typename T>
 void launch_init_species(T* f, const uint32_t* mask, const double* n_dev, int species,
                          double nref, Dims d, hipStream_t s);
-// With psi_old (the extrapolated start) and extrap = 1 or 2 the pass also
-// copies psi to psi_old (1) or sets psi = 2 psi - psi_old, psi_old = old psi (2).
+// Previous solutions besides psi that an extrapolated start of the solve
+// keeps: 1 for the linear, 2 for the quadratic, 3 for the cubic one.
+inline int extrap_history(int warm_start) {
+  return warm_start == EK_WS_EXTRAP ? 1
+         : warm_start == EK_WS_EXTRAP2 ? 2
+         : warm_start == EK_WS_EXTRAP3 ? 3
+                                       : 0;
+}
+// With psi_old (an extrapolated start) and extrap != 0 the pass also prepares
+// the start and shifts the history buffers (the modes of StartExtrap).
 // insulating: the charge of insulating walls (fluid sites only, the wall
 // faces' surface charge added to the fluid sites they bound).
 template <typename T>
@@ -112,7 +120,8 @@ void launch_charge(const T* f, const uint32_t* mask, const double* wall_q, doubl
                    double* partials, const LBParams& lp, double inv_eps, Dims d,
                    const SiteGrid& g, hipStream_t s, const BeadTableView& bt,
                    double* psi = nullptr, double* psi_old = nullptr, int extrap = 0,
-                   bool insulating = false, double* psi_old2 = nullptr);
+                   bool insulating = false, double* psi_old2 = nullptr,
+                   double* psi_old3 = nullptr);
 // Fused step over the sites without a `skip` bit.  Writes its block partials
 // (seven components: masses, momentum, sites updated) first in a layout of
 // `nblocks` blocks (lb_step_blocks(g, nz), plus the tail's blocks when a tail

@@ -40,15 +40,24 @@ __global__ __launch_bounds__(BLOCK) void k_init_species(T* __restrict__ f,
 // Charge pass: n^a at time t for every charged species, rho_e = sum z^a n^a
 // + fixed wall charge + bead charge; stores -rho_e / eps and partial sums of
 // rho_e (for the mean that the periodic problem removes).  With `start` set
-// it also prepares the extrapolated start of the solve at the site:
-// start.mode 1 keeps psi and copies it to old, 2 sets psi = 2 psi - old,
-// 3 does the same and copies old to old2, 4 sets psi = 3 psi - 3 old + old2
-// and shifts the history (old2 = old, old = psi before).
+// it also prepares the extrapolated start of the solve at the site, from the
+// last solution p = psi and the earlier ones o = old, o2 = old2, o3 = old3
+// (time t-1 down to t-4), and shifts the history by one step (old = p, and
+// old2 = o, old3 = o2 where the mode keeps them):
+//   mode 1  psi = p                                      old = p
+//   mode 2  psi = 2p - o  (linear)                        old = p
+//   mode 3  linear, the history deepened                  old = p, old2 = o
+//   mode 4  psi = 3p - 3o + o2  (quadratic)               old = p, old2 = o
+//   mode 5  quadratic, the history deepened               ... and old3 = o2
+//   mode 6  psi = 4p - 6o + 4o2 - o3  (cubic)             ... and old3 = o2
+// (the Newton backward-difference forms of the polynomial through the last
+// two, three or four solutions, evaluated one step ahead).
 struct StartExtrap {
   double* psi;
   double* old;
   int mode;
   double* old2;
+  double* old3;
 };
 
 template <typename T, typename I, bool NEU>
@@ -76,10 +85,18 @@ __global__ __launch_bounds__(BLOCK) void k_charge(const T* __restrict__ f,
         const double o = start.old[r];
         start.psi[r] = 2.0 * p - o;
         if (start.mode == 3) start.old2[r] = o;
-      } else if (start.mode == 4) {
+      } else if (start.mode == 4 || start.mode == 5) {
         const double o = start.old[r];
-        start.psi[r] = 3.0 * (p - o) + start.old2[r];
+        const double o2 = start.old2[r];
+        start.psi[r] = 3.0 * (p - o) + o2;
         start.old2[r] = o;
+        if (start.mode == 5) start.old3[r] = o2;
+      } else if (start.mode == 6) {
+        const double o = start.old[r];
+        const double o2 = start.old2[r];
+        start.psi[r] = 4.0 * (p + o2) - 6.0 * o - start.old3[r];
+        start.old2[r] = o;
+        start.old3[r] = o2;
       }
       start.old[r] = p;
     }
@@ -261,8 +278,9 @@ template <typename T>
 void launch_charge(const T* f, const uint32_t* mask, const double* wall_q, double* b,
                    double* partials, const LBParams& lp, double inv_eps, Dims d,
                    const SiteGrid& g, hipStream_t s, const BeadTableView& bt, double* psi,
-                   double* psi_old, int extrap, bool insulating, double* psi_old2) {
-  const StartExtrap start{psi, psi_old, psi_old ? extrap : 0, psi_old2};
+                   double* psi_old, int extrap, bool insulating, double* psi_old2,
+                   double* psi_old3) {
+  const StartExtrap start{psi, psi_old, psi_old ? extrap : 0, psi_old2, psi_old3};
   auto go = [&](auto kernel) {
     hipLaunchKernelGGL(kernel, g.grid, g.block, 0, s, f, mask, wall_q, b, partials, lp, inv_eps,
                        bt, d, start);
@@ -374,7 +392,8 @@ void launch_mean_shift(const double* partials, int nblocks, double inv_n, double
                                        hipStream_t);                                         \
   template void launch_charge<T>(const T*, const uint32_t*, const double*, double*, double*, \
                                  const LBParams&, double, Dims, const SiteGrid&, hipStream_t,\
-                                 const BeadTableView&, double*, double*, int, bool, double*);\
+                                 const BeadTableView&, double*, double*, int, bool, double*,  \
+                                 double*);                                                   \
   template int launch_lb_step<T>(const T*, T*, const uint32_t*, const double*,               \
                                  const LBParams&, const BeadTableView&, double*, int,        \
                                  uint32_t, Dims, const SiteGrid&, hipStream_t, hipEvent_t,   \

@@ -10,7 +10,8 @@
 //               post-collision values stored as deviations from w_p nref
 //     psi       nz*ny*nx doubles: the last solution
 //     psi_old   nz*ny*nx doubles: the solution before it (extrapolated starts)
-//     psi_old2  nz*ny*nx doubles: the one before that (quadratic start)
+//     psi_old2  nz*ny*nx doubles: the one before that (quadratic, cubic start)
+//     psi_old3  nz*ny*nx doubles: the one before that (cubic start)
 //     q, R, V   n_beads, 3*n_beads, 3*n_beads doubles
 //     cross     3*n_beads int32: first step, last step, net count
 // The header carries the counters the next steps depend on (step count,
@@ -50,7 +51,7 @@ struct StateHeader {
 size_t up8(size_t x) { return (x + 7) & ~size_t(7); }
 
 struct Sections {
-  size_t solid, wall_q, f, psi, psi_old, psi_old2, q, R, V, cross, total;
+  size_t solid, wall_q, f, psi, psi_old, psi_old2, psi_old3, q, R, V, cross, total;
 };
 
 Sections sections(const ek_params& p, int n_beads) {
@@ -63,8 +64,10 @@ Sections sections(const ek_params& p, int n_beads) {
   s.wall_q = take(n * 8);
   s.f = take(3 * Q * n * tsz);
   s.psi = take(n * 8);
-  s.psi_old = take(p.warm_start == EK_WS_EXTRAP || p.warm_start == EK_WS_EXTRAP2 ? n * 8 : 0);
-  s.psi_old2 = take(p.warm_start == EK_WS_EXTRAP2 ? n * 8 : 0);
+  const int held = extrap_history(p.warm_start);
+  s.psi_old = take(held >= 1 ? n * 8 : 0);
+  s.psi_old2 = take(held >= 2 ? n * 8 : 0);
+  s.psi_old3 = take(held >= 3 ? n * 8 : 0);
   s.q = take((size_t)n_beads * 8);
   s.R = take((size_t)n_beads * 24);
   s.V = take((size_t)n_beads * 24);
@@ -122,6 +125,7 @@ ek_status ek_save_state(ek_ctx* ctx, void* host, size_t bytes) {
   bool ok = d2h(s.f, ctx->fcur(), 3 * Q * d.n * tsz) && d2h(s.psi, ctx->psi, d.n * 8);
   if (ok && ctx->psi_old) ok = d2h(s.psi_old, ctx->psi_old, d.n * 8);
   if (ok && ctx->psi_old2) ok = d2h(s.psi_old2, ctx->psi_old2, d.n * 8);
+  if (ok && ctx->psi_old3) ok = d2h(s.psi_old3, ctx->psi_old3, d.n * 8);
   if (ok && nb) ok = d2h(s.R, bs.R, nb * 24) && d2h(s.V, bs.V, nb * 24) && d2h(s.cross, bs.cross, nb * 12);
   if (!ok) return ctx->fail(EK_EHIP, "copying the state to the host failed");
   ek_status st = ctx->sync();
@@ -177,7 +181,8 @@ ek_status ek_load_state(ek_ctx* ctx, const void* host, size_t bytes) {
     return ctx->fail(EK_EINVAL, "state buffer truncated");
   const unsigned char* pay = (const unsigned char*)host + sizeof(StateHeader);
   if (checksum(pay, s.total) != h.checksum) return ctx->fail(EK_EINVAL, "state checksum mismatch");
-  if (h.psi_hist < 0 || h.psi_hist > 3 || h.last_iters < 0 || h.solo_iters < 0 || h.step_count < 0)
+  const int held = extrap_history(ctx->p.warm_start);
+  if (h.psi_hist < 0 || h.psi_hist > (held ? held + 1 : 0) || h.last_iters < 0 || h.solo_iters < 0 || h.step_count < 0)
     return ctx->fail(EK_EINVAL, "state counters out of range");
 
   // geometry (link words, wall charges; clears populations and counters)
@@ -191,6 +196,7 @@ ek_status ek_load_state(ek_ctx* ctx, const void* host, size_t bytes) {
   bool ok = h2d(ctx->fA, s.f, 3 * Q * d.n * tsz) && h2d(ctx->psi, s.psi, d.n * 8);
   if (ok && ctx->psi_old) ok = h2d(ctx->psi_old, s.psi_old, d.n * 8);
   if (ok && ctx->psi_old2) ok = h2d(ctx->psi_old2, s.psi_old2, d.n * 8);
+  if (ok && ctx->psi_old3) ok = h2d(ctx->psi_old3, s.psi_old3, d.n * 8);
   if (!ok) return ctx->fail(EK_EHIP, "copying the state to the device failed");
   ctx->cur_is_a = true;
   for (int k = 0; k < 3; ++k) {

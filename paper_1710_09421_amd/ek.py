@@ -18,7 +18,7 @@ EK_OK, EK_EINVAL, EK_EHIP, EK_ENOCONV, EK_EUNSTABLE, EK_ESTATE, EK_ENOMEM = 0, -
 EK_FP32, EK_FP64 = 0, 1
 EK_POISSON_SOR, EK_POISSON_MG = 0, 1
 EK_LAUNCH_GRAPHS, EK_LAUNCH_OVERLAP = 1, 2
-EK_WS_ZERO, EK_WS_PREV, EK_WS_LEARNED, EK_WS_EXTRAP, EK_WS_EXTRAP2 = 0, 1, 2, 3, 4
+EK_WS_ZERO, EK_WS_PREV, EK_WS_LEARNED, EK_WS_EXTRAP, EK_WS_EXTRAP2, EK_WS_EXTRAP3 = 0, 1, 2, 3, 4, 5
 
 _STATUS = {0: "EK_OK", -1: "EK_EINVAL", -2: "EK_EHIP", -3: "EK_ENOCONV", -4: "EK_EUNSTABLE",
            -5: "EK_ESTATE", -6: "EK_ENOMEM"}

@@ -79,18 +79,19 @@ def test_learned_warm_start_needs_sizes_divisible_by_4(ek):
 
 def test_extrapolated_start_workspace(ek):
     """EK_WS_EXTRAP keeps psi(t-2): one more float64 field; EK_WS_EXTRAP2
-    keeps psi(t-3) as well: two more; unknown starts are rejected."""
+    keeps psi(t-3) as well: two more; EK_WS_EXTRAP3 keeps psi(t-4) too:
+    three more; unknown starts are rejected."""
     lib = ek.lib()
-    plain, extrap, quad = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
-    p0 = ek.make_params((32, 32, 32), warm_start=ek.EK_WS_PREV)
-    p1 = ek.make_params((32, 32, 32), warm_start=ek.EK_WS_EXTRAP)
-    p2 = ek.make_params((32, 32, 32), warm_start=ek.EK_WS_EXTRAP2)
-    assert lib.ek_workspace_bytes(ctypes.byref(p0), 0, ctypes.byref(plain)) == ek.EK_OK
-    assert lib.ek_workspace_bytes(ctypes.byref(p1), 0, ctypes.byref(extrap)) == ek.EK_OK
-    assert lib.ek_workspace_bytes(ctypes.byref(p2), 0, ctypes.byref(quad)) == ek.EK_OK
-    assert extrap.value - plain.value >= 32 ** 3 * 8
-    assert quad.value - extrap.value >= 32 ** 3 * 8
-    bad = ek.make_params((32, 32, 32), warm_start=ek.EK_WS_EXTRAP2 + 1)
+    sizes = []
+    for ws in (ek.EK_WS_PREV, ek.EK_WS_EXTRAP, ek.EK_WS_EXTRAP2, ek.EK_WS_EXTRAP3):
+        p = ek.make_params((32, 32, 32), warm_start=ws)
+        out = ctypes.c_size_t()
+        assert lib.ek_workspace_bytes(ctypes.byref(p), 0, ctypes.byref(out)) == ek.EK_OK
+        sizes.append(out.value)
+    for more, fewer in zip(sizes[1:], sizes[:-1]):
+        assert more - fewer == 32 ** 3 * 8
+    plain = ctypes.c_size_t()
+    bad = ek.make_params((32, 32, 32), warm_start=ek.EK_WS_EXTRAP3 + 1)
     assert lib.ek_workspace_bytes(ctypes.byref(bad), 0, ctypes.byref(plain)) == ek.EK_EINVAL
 
 

@@ -134,14 +134,15 @@ def test_pore_fp32_matches_oracle_after_100_steps(ek):
     assert opoisson.relative_residual(ctx.potential(), b) < 1e-3
 
 
-@pytest.mark.parametrize("start", ["extrapolated", "quadratic"])
+@pytest.mark.parametrize("start", ["extrapolated", "quadratic", "cubic"])
 def test_pore_fp32_multigrid_extrapolated_starts_match_oracle(ek, start):
-    """The extrapolated starts of the solve (2 psi(t-1) - psi(t-2) and
-    3 psi(t-1) - 3 psi(t-2) + psi(t-3)) change where the multigrid begins,
-    not where it ends: 100 steps agree with the oracle's previous-solution
-    SOR at the same tolerance."""
+    """The extrapolated starts of the solve (the linear, quadratic and cubic
+    polynomials in time through the last two, three, four solutions) change
+    where the multigrid begins, not where it ends: 100 steps agree with the
+    oracle's previous-solution SOR at the same tolerance."""
     wl = pore()
-    ws = ek.EK_WS_EXTRAP if start == "extrapolated" else ek.EK_WS_EXTRAP2
+    ws = {"extrapolated": ek.EK_WS_EXTRAP, "quadratic": ek.EK_WS_EXTRAP2,
+          "cubic": ek.EK_WS_EXTRAP3}[start]
     ctx = ek.from_workload(wl, precision=ek.EK_FP32, poisson_method=ek.EK_POISSON_MG,
                            poisson_tol=1e-9, poisson_max_iter=200, warm_start=ws)
     sim = oracle_sim(wl, 1e-10)

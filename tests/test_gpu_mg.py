@@ -176,3 +176,46 @@ def test_extrapolated_start_needs_fewer_cycles(ek):
     print(cycles, res0)
     assert res0["extrapolated"] < 0.5 * res0["previous"]
     assert cycles["extrapolated"] <= cycles["previous"]
+
+
+def _ahead_weights(m):
+    """Weights of the values at times -1, -2, .., -m in the value at time 0 of
+    the polynomial of degree m - 1 through them (Lagrange's form)."""
+    t = -np.arange(1, m + 1, dtype=float)
+    w = np.ones(m)
+    for j in range(m):
+        for i in range(m):
+            if i != j:
+                w[j] *= (0.0 - t[i]) / (t[j] - t[i])
+    return w
+
+
+@pytest.mark.parametrize("start,points", [("extrapolated", 2), ("quadratic", 3), ("cubic", 4)])
+def test_extrapolated_start_is_the_polynomial_through_the_last_solutions(ek, start, points):
+    """Step k's solve starts from the polynomial in time through the last
+    min(k - 1, points) solutions, evaluated one step ahead (zero on the first
+    step after the geometry): the residual of that field against step k's
+    right-hand side, formed here on the host from the solutions read back,
+    is the initial residual the solver reports."""
+    wl = workloads.pore_system((32, 24, 24), 6, 4, 0.01, 0.01, -0.01, 8, 32, steps=12)
+    ws = {"extrapolated": ek.EK_WS_EXTRAP, "quadratic": ek.EK_WS_EXTRAP2,
+          "cubic": ek.EK_WS_EXTRAP3}[start]
+    ctx = ek.from_workload(wl, precision=ek.EK_FP32, poisson_method=ek.EK_POISSON_MG,
+                           poisson_tol=1e-12, poisson_max_iter=200, warm_start=ws)
+    rhs = torch.empty(wl.shape, dtype=torch.float64, device="cuda")
+    psi = torch.empty_like(rhs)
+    hist = []
+    for k in range(1, 10):
+        ctx.step(1)
+        ctx.poisson_system(rhs, psi)
+        b = rhs.cpu().numpy()
+        m = min(k - 1, points)
+        guess = np.zeros(wl.shape)
+        for w, old in zip(_ahead_weights(m), hist[::-1]):
+            guess += w * old
+        want = opoisson.relative_residual(guess, b)
+        got = ctx.stats()["poisson_residual0"]
+        print(k, m, got, want)
+        assert got == pytest.approx(want, rel=1e-7), (k, got, want)
+        hist.append(ctx.potential())
+    ctx.close()

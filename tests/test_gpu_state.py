@@ -54,10 +54,11 @@ def _snapshot(ctx, n_beads, cross=True):
     return out
 
 
-@pytest.mark.parametrize("start", ["extrapolated", "quadratic", "previous"])
+@pytest.mark.parametrize("start", ["extrapolated", "quadratic", "cubic", "previous"])
 def test_resume_is_bitwise_equal_to_the_uninterrupted_run(ek, start):
     wl = _workload()
-    ws = {"extrapolated": ek.EK_WS_EXTRAP, "quadratic": ek.EK_WS_EXTRAP2}.get(start, ek.EK_WS_PREV)
+    ws = {"extrapolated": ek.EK_WS_EXTRAP, "quadratic": ek.EK_WS_EXTRAP2,
+          "cubic": ek.EK_WS_EXTRAP3}.get(start, ek.EK_WS_PREV)
     zp = float(wl.beads_R[:, 2].mean())
     full = _context(ek, wl, ws)
     full.set_crossing_plane(zp)

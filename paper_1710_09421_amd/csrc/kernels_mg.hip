@@ -318,7 +318,11 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_z(Lvl L, const double* 
 // (block partials as k_residual), so the last post-smoothing sweep of a tested
 // cycle is its residual pass too.  A chunk computes the colour-1 sites of the
 // planes either side of it as well (its neighbours do too), and keeps six
-// planes in LDS.  zc even, z0 even; TX, TY multiples of 4.
+// planes in LDS.  The nz planes are cut into nch chunks of an even number of
+// planes (their heights differ by at most two), so that the launch can be
+// sized to the workgroups the chip holds at once whatever nz is: the kernel
+// needs more LDS than k_sweep_z and fewer of its workgroups fit a compute
+// unit.  nz even, 1 <= nch <= nz / 2; TX, TY multiples of 4.
 enum : int { SWEEP_RESTRICT = 1, SWEEP_NORMS = 2 };
 
 template <int TX, int TY>
@@ -341,7 +345,7 @@ struct SweepRRegs {
 
 template <int TX, int TY, int MODE>
 __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_zr(Lvl L, const double* __restrict__ xin,
-                                                            double* __restrict__ xout, int zc,
+                                                            double* __restrict__ xout, int nch,
                                                             const PoissonScalars* ps, int level0,
                                                             double omega, Lvl C, double omega_red,
                                                             double* __restrict__ partials) {
@@ -360,7 +364,8 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_zr(Lvl L, const double*
   int b = blockIdx.x;
   if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
   const int tx_i = b % ntx, rest = b / ntx, ty_i = rest % nty, chunk = rest / nty;
-  const int x0 = tx_i * TX, y0 = ty_i * TY, z0 = chunk * zc, z1 = z0 + zc;
+  const int x0 = tx_i * TX, y0 = ty_i * TY, half = nz >> 1;
+  const int z0 = 2 * (chunk * half / nch), z1 = 2 * ((chunk + 1) * half / nch);
   const int zb = z0 - 3;                                    // plane in slot-relative index 0
   auto wrapi = [](int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); };
   auto plane_base = [&](int q) {
@@ -668,8 +673,9 @@ struct ek_ctx::MG {
   double* tmp1 = nullptr;
   // the finest level's pre-smoothing sweep also restricts, and a tested
   // cycle's last sweep also takes the residual norms (k_sweep_zr: a 64 x 8
-  // tile and chunks of an even number of planes)
+  // tile, zr_chunks chunks of an even number of planes)
   bool fused0 = false;
+  int zr_chunks = 0;
   // One V-cycle, and one V-cycle followed by the residual test, recorded as
   // graphs for the level-0 pair (b, x) they were recorded with: a replay
   // dispatches the cycle's ~30 dependent launches faster than the launches
@@ -728,6 +734,36 @@ size_t ek::mg_sweep_bytes(int nx, int ny, int nz) {
 // vector, which M lifts; for a mean-free f, M^-1 f is the mean-free solution
 // of A x = f.  Gauss-Jordan elimination with partial pivoting in double;
 // false if a pivot vanishes.
+// Chunks along z of the finest level's k_sweep_zr launch: the count whose
+// launch ends after the fewest plane steps when its workgroups run in rounds
+// of as many as the chip holds at once (a chunk of h planes takes h + 5
+// steps); `fallback` when the device cannot be asked.
+static int zr_chunk_count(const Lvl& L, int fallback) {
+  int dev = 0, ncu = 0, occ_r = 0, occ_n = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_r, k_sweep_zr<64, 8, SWEEP_RESTRICT>,
+                                                   SWEEP_THREADS, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_n, k_sweep_zr<64, 8, SWEEP_NORMS>,
+                                                   SWEEP_THREADS, 0) != hipSuccess ||
+      ncu < 1 || std::min(occ_r, occ_n) < 1)
+    return fallback;
+  const long long tiles = (long long)(L.nx / 64) * (L.ny / 8);
+  const long long slots = (long long)std::min(occ_r, occ_n) * ncu;
+  const int half = L.nz / 2;
+  int best = fallback;
+  long long best_steps = -1;
+  for (int nch = 1; nch <= half; ++nch) {
+    const long long rounds = (tiles * nch + slots - 1) / slots;
+    const long long steps = rounds * (2 * ((half + nch - 1) / nch) + 5);
+    if (best_steps < 0 || steps < best_steps) {
+      best_steps = steps;
+      best = nch;
+    }
+  }
+  return best;
+}
+
 static bool coarsest_inverse(const Lvl& C, std::vector<double>& inv) {
   const int n = int(C.n);
   std::vector<double> a((size_t)n * n, 0.0);
@@ -868,6 +904,7 @@ void ek_ctx::mg_setup() {
     }
     mg->fused0 = fc > 1 && mg->sweep_tx[0] == 64 && mg->sweep_ty[0] == 8 &&
                  mg->sweep_zc[0] % 2 == 0;
+    if (mg->fused0) mg->zr_chunks = zr_chunk_count(mg->levels[0], p.nz / mg->sweep_zc[0]);
   }
   mg->omega_coarsest = omega_opt(c.nx, c.ny, c.nz);
   const double rate = std::max(mg->omega_coarsest - 1.0, 1e-3);
@@ -961,17 +998,18 @@ static void launch_sweep_z(const Lvl& L, int tx, int ty, int zc, const double* x
 }
 
 // The finest level's full sweep with the residual of its result (restriction
-// into level C, or the norms' block partials); returns the block count.
-static int launch_sweep_zr(const Lvl& L, int zc, const double* xin, double* xout,
+// into level C, or the norms' block partials) in nch chunks along z; returns
+// the block count.
+static int launch_sweep_zr(const Lvl& L, int nch, const double* xin, double* xout,
                            const PoissonScalars* ps, int mode, const Lvl& C, double omega_red,
                            double* partials, hipStream_t s) {
-  const int nblocks = (L.nx / 64) * (L.ny / 8) * (L.nz / zc);
+  const int nblocks = (L.nx / 64) * (L.ny / 8) * nch;
   if (mode == SWEEP_RESTRICT)
     hipLaunchKernelGGL((k_sweep_zr<64, 8, SWEEP_RESTRICT>), dim3(nblocks), dim3(SWEEP_THREADS), 0,
-                       s, L, xin, xout, zc, ps, 1, MG_OMEGA, C, omega_red, partials);
+                       s, L, xin, xout, nch, ps, 1, MG_OMEGA, C, omega_red, partials);
   else
     hipLaunchKernelGGL((k_sweep_zr<64, 8, SWEEP_NORMS>), dim3(nblocks), dim3(SWEEP_THREADS), 0, s,
-                       L, xin, xout, zc, ps, 1, MG_OMEGA, C, 0.0, partials);
+                       L, xin, xout, nch, ps, 1, MG_OMEGA, C, 0.0, partials);
   return nblocks;
 }
 
@@ -1000,7 +1038,7 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x, int* norm_blocks) {
     Lvl F = L[l];
     const double omega_red = (l + 1 < fc && NU1 > 0) ? MG_OMEGA : 0.0;
     if (l == 0 && mg->fused0) {   // sweep and restriction in one pass
-      launch_sweep_zr(L[0], mg->sweep_zc[0], x, mg->tmp0, ps, SWEEP_RESTRICT, L[1], omega_red,
+      launch_sweep_zr(L[0], mg->zr_chunks, x, mg->tmp0, ps, SWEEP_RESTRICT, L[1], omega_red,
                       nullptr, stream);
       continue;
     }
@@ -1052,7 +1090,7 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x, int* norm_blocks) {
       for (int s = 0; s < NU2; ++s) {
         const bool to_tmp = (s & 1) == 0;
         if (l == 0 && s == NU2 - 1 && norm_blocks && mg->fused0) {   // the test's residual too
-          *norm_blocks = launch_sweep_zr(L[0], mg->sweep_zc[0], tmp, L[0].x, ps, SWEEP_NORMS,
+          *norm_blocks = launch_sweep_zr(L[0], mg->zr_chunks, tmp, L[0].x, ps, SWEEP_NORMS,
                                          L[1], 0.0, partials, stream);
           continue;
         }

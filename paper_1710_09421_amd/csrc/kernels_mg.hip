@@ -6,8 +6,10 @@
 // the previous in every direction while all sides stay even:
 //   level l, spacing h = 2^l:  (sum of 6 neighbours - 6 x) / h^2 = f_l
 //   smoother   red-black Gauss-Seidel (x = (sum nb - h^2 f) / 6) over-relaxed
-//              by MG_OMEGA, nu1 = NU1 = 1 and nu2 = NU2 = 2 (NU2_COARSE = 1
-//              on the levels of the one-workgroup coarse kernel)
+//              by MG_OMEGA, nu1 = NU1 = 1 and nu2 = NU2 = 2 (NU1_FUSED
+//              on a finest level whose last pre-smoothing sweep restricts,
+//              NU2_COARSE = 1 on the levels of the one-workgroup coarse
+//              kernel)
 //   restriction  f_{l+1} = average of the 8 fine residuals (fused with the
 //                residual, also zeroes the coarse iterate)
 //   prolongation trilinear cell-centred interpolation (weights 3/4, 1/4 per
@@ -61,6 +63,18 @@ constexpr long long FUSED_CORRECTION_MAX_SITES = 1ll << 18;
 // the single pore's step; from the previous solution it needed about 3 %
 // more cycles, which cancels the gain.
 constexpr int NU2_COARSE = 1;
+// Pre-smoothing sweeps on a finest level whose last pre-smoothing sweep also
+// restricts (k_sweep_zr): with the over-relaxed sweeps a V(1,2) cycle there
+// reduces the residual about 45-fold, so the 1e-8 of the pore systems from
+// the quadratic start (1e-5 to 1e-4) takes three cycles; two more
+// pre-smoothing sweeps make it two (256x256x512: 2.94 -> 2.00 cycles per
+// step, 3.16 -> 3.00 ms of Poisson; one more sweep gave 2.31 cycles and the
+// same time).
+constexpr int NU1_FUSED = 3;
+// A solve tests its residual from one cycle before the previous solve's count
+// on, unless the previous solve was this far above the tolerance one cycle
+// before its end.
+constexpr double EARLY_MARGIN = 4.0;
 
 // --- grid-wide kernels for the fine levels (3-D launch: x, y from the block,
 // z = blockIdx.z, so no index division) ------------------------------------
@@ -115,7 +129,7 @@ __global__ __launch_bounds__(256) void k_prolong_to(Lvl F, Lvl C, const double* 
 
 // --- one full red-black sweep per launch, marching up z -----------------------
 // xout = (colour-0 half sweep, then colour-1 half sweep)(xin), out of place.
-// A workgroup owns the TX x TY tile at (x0, y0) of the planes z0 .. z0+zc-1
+// A workgroup owns the TX x TY tile at (x0, y0) of the planes z0 .. z1-1
 // and keeps five planes of the tile plus a two-site ring in LDS.  At step k it
 // relaxes the colour-0 sites of plane k on the tile and a one-site ring (from
 // the old colour-1 values of planes k-1, k, k+1), then the colour-1 sites of
@@ -131,8 +145,11 @@ __global__ __launch_bounds__(256) void k_prolong_to(Lvl F, Lvl C, const double* 
 // neighbouring workgroups read too) and xout is written once: 24 bytes per
 // site for the sweep, against 48 for two half sweeps over the interleaved
 // colours.  The loads run ahead of their use: the right-hand side of a step
-// is read during the step before, the iterate planes two steps before.
-// zc >= 1 divides nz; TX divides nx, TY divides ny; all sides even.
+// is read during the step before, the iterate planes two steps before.  The
+// nz planes are cut into nch chunks (heights differ by at most one plane),
+// their number chosen so that the launch runs in as few rounds of the
+// workgroups the device holds at once as the chunks' extra steps allow:
+// 1 <= nch <= nz; TX divides nx, TY divides ny; all sides even.
 constexpr int SWEEP_THREADS = 256;
 constexpr int SWEEP_SLOTS = 5;
 
@@ -152,7 +169,7 @@ struct SweepRegs {
 
 template <int TX, int TY>
 __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_z(Lvl L, const double* __restrict__ xin,
-                                                           double* __restrict__ xout, int zc,
+                                                           double* __restrict__ xout, int nch,
                                                            const PoissonScalars* ps, int level0,
                                                            double omega) {
   static_assert(TX % 2 == 0 && TY % 2 == 0, "even tiles");
@@ -176,7 +193,8 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_z(Lvl L, const double* 
   const int rest = b / ntx;
   const int ty_i = rest % nty;
   const int chunk = rest / nty;
-  const int x0 = tx_i * TX, y0 = ty_i * TY, z0 = chunk * zc, z1 = z0 + zc;
+  const int x0 = tx_i * TX, y0 = ty_i * TY;
+  const int z0 = chunk * nz / nch, z1 = (chunk + 1) * nz / nch;
   const int zb = z0 - 2;                                   // plane of relative index 0
 
   auto wrapi = [](int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); };
@@ -319,10 +337,8 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_z(Lvl L, const double* 
 // cycle is its residual pass too.  A chunk computes the colour-1 sites of the
 // planes either side of it as well (its neighbours do too), and keeps six
 // planes in LDS.  The nz planes are cut into nch chunks of an even number of
-// planes (their heights differ by at most two), so that the launch can be
-// sized to the workgroups the chip holds at once whatever nz is: the kernel
-// needs more LDS than k_sweep_z and fewer of its workgroups fit a compute
-// unit.  nz even, 1 <= nch <= nz / 2; TX, TY multiples of 4.
+// planes (their heights differ by at most two).  nz even, 1 <= nch <= nz / 2;
+// TX, TY multiples of 4.
 enum : int { SWEEP_RESTRICT = 1, SWEEP_NORMS = 2 };
 
 template <int TX, int TY>
@@ -666,9 +682,9 @@ struct ek_ctx::MG {
   const double* pinv = nullptr;   // inverse for the direct coarsest solve, or null
   bool coarse_kernel = true;      // false: the coarsest level does not fit LDS
   // Full sweeps by k_sweep_z (out of place) on the launched levels whose tiles
-  // fit: tile (sweep_tx, sweep_ty), zc planes per workgroup; 0 = half sweeps.
-  // The finest level sweeps into tmp0 and back, the others into tmp1.
-  std::vector<int> sweep_tx, sweep_ty, sweep_zc;
+  // fit: tile (sweep_tx, sweep_ty), sweep_nch chunks along z; 0 = half
+  // sweeps.  The finest level sweeps into tmp0 and back, the others into tmp1.
+  std::vector<int> sweep_tx, sweep_ty, sweep_nch;
   double* tmp0 = nullptr;
   double* tmp1 = nullptr;
   // the finest level's pre-smoothing sweep also restricts, and a tested
@@ -728,34 +744,33 @@ size_t ek::mg_sweep_bytes(int nx, int ny, int nz) {
   return 2 * 256 + ((n0 * 8 + 255) & ~size_t(255)) + ((n0 + 7) / 8 * 8 + 255) / 256 * 256;
 }
 
-// Inverse of M = A + c 11^T / n for the periodic 7-point operator A of level
-// C ((sum of the 6 neighbours - 6 x) / h^2, a neighbour counted twice where a
-// side is 2 long), c = -6 / h^2.  A is singular only along the constant
-// vector, which M lifts; for a mean-free f, M^-1 f is the mean-free solution
-// of A x = f.  Gauss-Jordan elimination with partial pivoting in double;
-// false if a pivot vanishes.
-// Chunks along z of the finest level's k_sweep_zr launch: the count whose
-// launch ends after the fewest plane steps when its workgroups run in rounds
-// of as many as the chip holds at once (a chunk of h planes takes h + 5
-// steps); `fallback` when the device cannot be asked.
-static int zr_chunk_count(const Lvl& L, int fallback) {
-  int dev = 0, ncu = 0, occ_r = 0, occ_n = 0;
+// Workgroups of `kernel` (SWEEP_THREADS threads) that the device holds at
+// once, or 0 when it cannot be asked.
+template <typename F>
+static long long resident_workgroups(F kernel) {
+  int dev = 0, ncu = 0, occ = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_r, k_sweep_zr<64, 8, SWEEP_RESTRICT>,
-                                                   SWEEP_THREADS, 0) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_n, k_sweep_zr<64, 8, SWEEP_NORMS>,
-                                                   SWEEP_THREADS, 0) != hipSuccess ||
-      ncu < 1 || std::min(occ_r, occ_n) < 1)
-    return fallback;
-  const long long tiles = (long long)(L.nx / 64) * (L.ny / 8);
-  const long long slots = (long long)std::min(occ_r, occ_n) * ncu;
-  const int half = L.nz / 2;
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, SWEEP_THREADS, 0) != hipSuccess)
+    return 0;
+  return (long long)std::max(ncu, 0) * std::max(occ, 0);
+}
+
+// Chunks along z of a z-marching sweep over `tiles` tiles of a level of nz
+// planes, chunks of `unit` planes at a time (1, or 2 for whole 2 x 2 x 2
+// blocks): the count whose launch ends after the fewest plane steps when its
+// workgroups run in rounds of `slots` (the workgroups the device holds at
+// once), a chunk of h planes taking h + `extra` steps; `fallback` when the
+// device could not be asked (slots 0).
+static int sweep_chunks(long long tiles, int nz, int unit, int extra, long long slots,
+                        int fallback) {
+  if (slots < 1) return fallback;
+  const int units = nz / unit;
   int best = fallback;
   long long best_steps = -1;
-  for (int nch = 1; nch <= half; ++nch) {
+  for (int nch = 1; nch <= units; ++nch) {
     const long long rounds = (tiles * nch + slots - 1) / slots;
-    const long long steps = rounds * (2 * ((half + nch - 1) / nch) + 5);
+    const long long steps = rounds * (unit * ((units + nch - 1) / nch) + extra);
     if (best_steps < 0 || steps < best_steps) {
       best_steps = steps;
       best = nch;
@@ -764,6 +779,12 @@ static int zr_chunk_count(const Lvl& L, int fallback) {
   return best;
 }
 
+// Inverse of M = A + c 11^T / n for the periodic 7-point operator A of level
+// C ((sum of the 6 neighbours - 6 x) / h^2, a neighbour counted twice where a
+// side is 2 long), c = -6 / h^2.  A is singular only along the constant
+// vector, which M lifts; for a mean-free f, M^-1 f is the mean-free solution
+// of A x = f.  Gauss-Jordan elimination with partial pivoting in double;
+// false if a pivot vanishes.
 static bool coarsest_inverse(const Lvl& C, std::vector<double>& inv) {
   const int n = int(C.n);
   std::vector<double> a((size_t)n * n, 0.0);
@@ -876,7 +897,7 @@ void ek_ctx::mg_setup() {
   // correction keep the half sweeps too
   mg->sweep_tx.assign(nl, 0);
   mg->sweep_ty.assign(nl, 0);
-  mg->sweep_zc.assign(nl, 0);
+  mg->sweep_nch.assign(nl, 0);
   if (mg_tmp) {
     char* t = mg_tmp + 256;
     mg->tmp0 = (double*)t;
@@ -896,15 +917,33 @@ void ek_ctx::mg_setup() {
           best_wg = wg;
           mg->sweep_tx[l] = tc[0];
           mg->sweep_ty[l] = tc[1];
-          mg->sweep_zc[l] = zc;
+          mg->sweep_nch[l] = L.nz / zc;
         }
         if (wg >= 1024) break;
       }
-      if (best_wg < 512) mg->sweep_tx[l] = mg->sweep_ty[l] = mg->sweep_zc[l] = 0;
+      if (best_wg < 512) {
+        mg->sweep_tx[l] = mg->sweep_ty[l] = mg->sweep_nch[l] = 0;
+        continue;
+      }
+      // then as many chunks as end the launch soonest (a chunk of h planes
+      // takes h + 2 steps)
+      const int tx = mg->sweep_tx[l], ty = mg->sweep_ty[l];
+      const long long slots = tx == 32 ? resident_workgroups(k_sweep_z<32, 8>)
+                              : ty == 16 ? resident_workgroups(k_sweep_z<64, 16>)
+                                         : resident_workgroups(k_sweep_z<64, 8>);
+      mg->sweep_nch[l] = sweep_chunks((long long)(L.nx / tx) * (L.ny / ty), L.nz, 1, 2, slots,
+                                      mg->sweep_nch[l]);
     }
-    mg->fused0 = fc > 1 && mg->sweep_tx[0] == 64 && mg->sweep_ty[0] == 8 &&
-                 mg->sweep_zc[0] % 2 == 0;
-    if (mg->fused0) mg->zr_chunks = zr_chunk_count(mg->levels[0], p.nz / mg->sweep_zc[0]);
+    mg->fused0 = fc > 1 && mg->sweep_tx[0] == 64 && mg->sweep_ty[0] == 8;
+    if (mg->fused0) {
+      // chunks of whole 2 x 2 x 2 blocks, h + 5 steps each, as many
+      // workgroups at once as both variants hold
+      const Lvl& L = mg->levels[0];
+      const long long slots = std::min(resident_workgroups(k_sweep_zr<64, 8, SWEEP_RESTRICT>),
+                                       resident_workgroups(k_sweep_zr<64, 8, SWEEP_NORMS>));
+      mg->zr_chunks = sweep_chunks((long long)(L.nx / 64) * (L.ny / 8), L.nz, 2, 5, slots,
+                                   std::max(1, mg->sweep_nch[0] / 2));
+    }
   }
   mg->omega_coarsest = omega_opt(c.nx, c.ny, c.nz);
   const double rate = std::max(mg->omega_coarsest - 1.0, 1e-3);
@@ -983,17 +1022,17 @@ bool ek_ctx::mg_graphs(const double* bb, double* x) {
 }
 
 // One full sweep of level L from xin into xout with the tile of the plan.
-static void launch_sweep_z(const Lvl& L, int tx, int ty, int zc, const double* xin, double* xout,
+static void launch_sweep_z(const Lvl& L, int tx, int ty, int nch, const double* xin, double* xout,
                            const PoissonScalars* ps, int level0, hipStream_t s) {
-  const dim3 grid((unsigned)((L.nx / tx) * (L.ny / ty) * (L.nz / zc)));
+  const dim3 grid((unsigned)((L.nx / tx) * (L.ny / ty) * nch));
   if (tx == 64 && ty == 16)
-    hipLaunchKernelGGL((k_sweep_z<64, 16>), grid, dim3(SWEEP_THREADS), 0, s, L, xin, xout, zc, ps,
+    hipLaunchKernelGGL((k_sweep_z<64, 16>), grid, dim3(SWEEP_THREADS), 0, s, L, xin, xout, nch, ps,
                        level0, MG_OMEGA);
   else if (tx == 64)
-    hipLaunchKernelGGL((k_sweep_z<64, 8>), grid, dim3(SWEEP_THREADS), 0, s, L, xin, xout, zc, ps,
+    hipLaunchKernelGGL((k_sweep_z<64, 8>), grid, dim3(SWEEP_THREADS), 0, s, L, xin, xout, nch, ps,
                        level0, MG_OMEGA);
   else
-    hipLaunchKernelGGL((k_sweep_z<32, 8>), grid, dim3(SWEEP_THREADS), 0, s, L, xin, xout, zc, ps,
+    hipLaunchKernelGGL((k_sweep_z<32, 8>), grid, dim3(SWEEP_THREADS), 0, s, L, xin, xout, nch, ps,
                        level0, MG_OMEGA);
 }
 
@@ -1031,19 +1070,30 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x, int* norm_blocks) {
   // half sweep done; the level handed to the coarse kernel arrives at zero.
   // The finest level with a full-sweep plan is pre-smoothed by one full
   // sweep into tmp0 (NU1 = 1), restricted from there, and corrected back
-  // into x by the prolongation.
-  static_assert(NU1 == 1 && NU2 % 2 == 0, "the out-of-place sweeps end in x");
+  // into x by the prolongation; with the fused restriction by NU1_FUSED
+  // sweeps, which end in tmp0 (corrected into x as before) or in x
+  // (corrected in place).
+  static_assert(NU1 == 1 && NU2 % 2 == 0 && NU1_FUSED >= 1, "the out-of-place sweeps end in x");
+  const bool pre_in_x = mg->fused0 && NU1_FUSED % 2 == 0;
   const bool pre0 = mg->sweep_tx[0] != 0;
   for (int l = 0; l < fc; ++l) {
     Lvl F = L[l];
     const double omega_red = (l + 1 < fc && NU1 > 0) ? MG_OMEGA : 0.0;
-    if (l == 0 && mg->fused0) {   // sweep and restriction in one pass
-      launch_sweep_zr(L[0], mg->zr_chunks, x, mg->tmp0, ps, SWEEP_RESTRICT, L[1], omega_red,
-                      nullptr, stream);
+    if (l == 0 && mg->fused0) {
+      // NU1_FUSED sweeps back and forth between x and tmp0, the last one
+      // with the restriction in the same pass
+      double* a = x;
+      double* b = mg->tmp0;
+      for (int s = 0; s + 1 < NU1_FUSED; ++s) {
+        launch_sweep_z(L[0], 64, 8, mg->sweep_nch[0], a, b, ps, 1, stream);
+        std::swap(a, b);
+      }
+      launch_sweep_zr(L[0], mg->zr_chunks, a, b, ps, SWEEP_RESTRICT, L[1], omega_red, nullptr,
+                      stream);
       continue;
     }
     if (l == 0 && pre0) {
-      launch_sweep_z(L[0], mg->sweep_tx[0], mg->sweep_ty[0], mg->sweep_zc[0], x, mg->tmp0, ps, 1,
+      launch_sweep_z(L[0], mg->sweep_tx[0], mg->sweep_ty[0], mg->sweep_nch[0], x, mg->tmp0, ps, 1,
                      stream);
       F.x = mg->tmp0;
     } else {
@@ -1081,7 +1131,7 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x, int* norm_blocks) {
       // correction (out of place from tmp0 on the finest level), then NU2
       // full sweeps x -> tmp -> x
       double* tmp = l == 0 ? mg->tmp0 : mg->tmp1;
-      if (l == 0 && pre0)
+      if (l == 0 && pre0 && !pre_in_x)
         hipLaunchKernelGGL(k_prolong_to, level_launch(L[1]).grid, level_launch(L[1]).block, 0,
                            stream, L[0], L[1], mg->tmp0, x, ps);
       else
@@ -1094,7 +1144,7 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x, int* norm_blocks) {
                                          L[1], 0.0, partials, stream);
           continue;
         }
-        launch_sweep_z(L[l], mg->sweep_tx[l], mg->sweep_ty[l], mg->sweep_zc[l],
+        launch_sweep_z(L[l], mg->sweep_tx[l], mg->sweep_ty[l], mg->sweep_nch[l],
                        to_tmp ? L[l].x : tmp, to_tmp ? tmp : L[l].x, ps, l == 0 ? 1 : 0, stream);
       }
       continue;
@@ -1127,8 +1177,15 @@ ek_status ek_ctx::mg_solve(const double* bb, double* x, PoissonScalars h, int& i
   int batch = std::max(1, last_iters);
   // the previous solve needed `batch` cycles: the residual is first tested
   // after batch - 1 of them (a solve that converges earlier than that costs
-  // one extra cycle, the usual one saves the tests of the early cycles)
+  // one extra cycle, the usual one saves the tests of the early cycles), or
+  // only after the batch when the previous solve's residual one cycle before
+  // its end (its last residual over its mean rate per cycle) lay more than
+  // EARLY_MARGIN times above the tolerance
   int untested = std::max(0, batch - 2);
+  if (batch >= 2 && last_res > 0.0 && last_res0 > last_res) {
+    const double rate = std::pow(last_res / last_res0, 1.0 / batch);
+    if (last_res / rate > EARLY_MARGIN * p.poisson_tol) untested = batch - 1;
+  }
   const bool graphs = mg_graphs(bb, x);
   while (!h.done && it < p.poisson_max_iter) {
     const int nrun = std::min(batch, p.poisson_max_iter - it);

@@ -772,7 +772,9 @@ ek_status ek_poisson_solve(ek_ctx* ctx, const double* dev_rho, double* dev_psi,
   double res = 0, res0 = 0;
   const int saved = ctx->last_iters;
   ctx->last_iters = ctx->solo_iters;
+  ctx->solo = true;
   ek_status st = ctx->poisson(ctx->b, dev_psi, warm_start == EK_WS_LEARNED, iters, res, res0);
+  ctx->solo = false;
   ctx->solo_iters = iters;
   if (st == EK_OK) ctx->have_solve = true;
   ctx->last_iters = saved;

@@ -57,6 +57,7 @@ struct ek_ctx {
   long long step_count = 0;
   int last_iters = 0;
   int solo_iters = 0;
+  bool solo = false;   // a stand-alone solve (ek_poisson_solve) is running
   double last_res = 0.0;
   double last_res0 = 0.0;
   int last_fallback = 0;

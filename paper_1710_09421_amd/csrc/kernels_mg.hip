@@ -1178,11 +1178,12 @@ ek_status ek_ctx::mg_solve(const double* bb, double* x, PoissonScalars h, int& i
   // the previous solve needed `batch` cycles: the residual is first tested
   // after batch - 1 of them (a solve that converges earlier than that costs
   // one extra cycle, the usual one saves the tests of the early cycles), or
-  // only after the batch when the previous solve's residual one cycle before
-  // its end (its last residual over its mean rate per cycle) lay more than
-  // EARLY_MARGIN times above the tolerance
+  // in the time loop, whose consecutive solves start alike, only after the
+  // batch when the previous step's residual one cycle before its end (its
+  // last residual over its mean rate per cycle) lay more than EARLY_MARGIN
+  // times above the tolerance
   int untested = std::max(0, batch - 2);
-  if (batch >= 2 && last_res > 0.0 && last_res0 > last_res) {
+  if (!solo && batch >= 2 && last_res > 0.0 && last_res0 > last_res) {
     const double rate = std::pow(last_res / last_res0, 1.0 / batch);
     if (last_res / rate > EARLY_MARGIN * p.poisson_tol) untested = batch - 1;
   }

@@ -51,16 +51,33 @@ __device__ inline double block_sum_256(const double* part, int nblocks) {
 }
 
 // Sums of NC components of nblocks partials (layout [c * nblocks + block]) by
-// one block of 1024 threads: strided loads of every component first, then a
-// fixed tree per component.  Results valid in thread 0.
+// one block of 1024 threads: strided sums of every component first, then a
+// fixed tree per component.  Results valid in thread 0.  A thread adds its
+// partials in the order of i; the loads of U consecutive ones are issued
+// before the first of them is added, so that they are in flight together
+// (one load at a time would leave the sum of 65536 partials waiting on 64
+// memory latencies in a row).
 template <int NC>
 __device__ inline void block_sums_1024(const double* part, int nblocks, double (&out)[NC]) {
   __shared__ double sh[NC][1024];
+  constexpr int U = NC >= 32 ? 1 : 32 / NC;
   const int tid = threadIdx.x;
   double s[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) s[c] = 0.0;
-  for (int i = tid; i < nblocks; i += 1024) {
+  int i = tid;
+  for (; i + (U - 1) * 1024 < nblocks; i += U * 1024) {
+    double v[U][NC];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[u][c] = part[(size_t)c * nblocks + i + u * 1024];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) s[c] += v[u][c];
+  }
+  for (; i < nblocks; i += 1024) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) s[c] += part[(size_t)c * nblocks + i];
   }

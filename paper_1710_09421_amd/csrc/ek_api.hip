@@ -231,8 +231,15 @@ ek_status ek_ctx::sor_solve(const double* bb, double* x, PoissonScalars h, int& 
   }
   iters = h.iters;
   if (neu) launch_psi_shift_neu(x, mask, ps, 1.0 / double(n_fluid), dims, stream);
+  else if (defer_shift) shift_pending = true;
   else launch_psi_shift(x, ps, 1.0 / double(dims.n), dims, stream);
   return EK_OK;
+}
+
+void ek_ctx::settle_psi() {
+  if (!shift_pending) return;
+  launch_psi_shift(psi, ps, 1.0 / double(dims.n), dims, stream);
+  shift_pending = false;
 }
 
 ek_status ek_ctx::initial_residual(const double* bb, const double* x, PoissonScalars* h) {
@@ -347,8 +354,12 @@ ek_status ek_ctx::step_impl(int n_steps) {
       static const int top[4] = {0, 2, 4, 6};          // order == held
       if (order >= 0) extrap = order == held ? top[order] : keep[order];
     }
+    // (a mean left in psi by the previous solve is removed by the same pass)
+    if (extrap == 0) settle_psi();
     launch_charge<T>((const T*)fcur(), mask, wall_q, b, partials, lp, inv_eps(), dims, g, stream, bt,
-                     psi, psi_old, extrap, insulating(), psi_old2, psi_old3);
+                     psi, psi_old, extrap, insulating(), psi_old2, psi_old3,
+                     shift_pending ? ps : nullptr);
+    shift_pending = false;
     if (held > 0) psi_hist = std::min(psi_hist + 1, held + 1);
     launch_mean_shift(partials, nb, 1.0 / double(insulating() ? n_fluid : dims.n), inv_eps(), ps,
                       stream);
@@ -356,7 +367,9 @@ ek_status ek_ctx::step_impl(int n_steps) {
     if (p.warm_start == EK_WS_ZERO) launch_fill(psi, 0.0, dims.n, stream);
     int iters = 0;
     double res = 0, res0 = 0;
+    defer_shift = held > 0 && !insulating();
     ek_status st = poisson(b, psi, p.warm_start == EK_WS_LEARNED, iters, res, res0);
+    defer_shift = false;
     if (st) return st;
     last_iters = iters;
     last_res = res;
@@ -617,6 +630,7 @@ ek_status ek_set_geometry(ek_ctx* ctx, const uint8_t* solid, const double* wall_
   EK_HIP(hipMemsetAsync(ctx->fA, 0, 3 * Q * d.n * tsz, ctx->stream));
   EK_HIP(hipMemsetAsync(ctx->fB, 0, 3 * Q * d.n * tsz, ctx->stream));
   launch_fill(ctx->psi, 0.0, d.n, ctx->stream);
+  ctx->shift_pending = false;
   ctx->cur_is_a = true;
   ctx->have_geometry = true;
   for (int s = 0; s < 3; ++s) ctx->have_species[s] = false;
@@ -680,6 +694,7 @@ ek_status ek_get_poisson_system(ek_ctx* ctx, double* dev_rhs, double* dev_psi) {
   if (!ctx) return EK_EINVAL;
   if (ctx->insulating()) return ctx->fail(EK_ESTATE, "the context has insulating walls");
   if (!ctx->have_solve) return ctx->fail(EK_ESTATE, "no Poisson solve has run yet");
+  ctx->settle_psi();
   if (dev_rhs) launch_rhs_copy(ctx->b, ctx->ps, dev_rhs, ctx->dims.n, ctx->stream);
   if (dev_psi)
     EK_HIP(hipMemcpyAsync(dev_psi, ctx->psi, ctx->dims.n * 8, hipMemcpyDeviceToDevice, ctx->stream));
@@ -706,6 +721,7 @@ ek_status ek_get_moments(ek_ctx* ctx, int32_t species, double* n, double* u) {
 ek_status ek_get_potential(ek_ctx* ctx, double* psi) {
   if (!ctx) return EK_EINVAL;
   if (!psi) return ctx->fail(EK_EINVAL, "psi is NULL");
+  ctx->settle_psi();
   EK_HIP(hipMemcpyAsync(psi, ctx->psi, ctx->dims.n * 8, hipMemcpyDeviceToHost, ctx->stream));
   return ctx->sync();
 }
@@ -763,6 +779,7 @@ ek_status ek_poisson_solve(ek_ctx* ctx, const double* dev_rho, double* dev_psi,
   if (warm_start < EK_WS_ZERO || warm_start > EK_WS_EXTRAP3) return ctx->fail(EK_EINVAL, "unknown warm_start");
   if (warm_start == EK_WS_LEARNED && !(ctx->net && ctx->net->have_params))
     return ctx->fail(EK_ESTATE, "learned warm start without a model (ek_set_model)");
+  ctx->settle_psi();   // before ps is reused
   const SiteGrid g = site_grid(ctx->p.nx, ctx->p.ny, ctx->p.nz, ctx->bx_sites);
   launch_rho_to_b(dev_rho, ctx->b, ctx->partials, ctx->inv_eps(), ctx->dims, g, ctx->stream);
   launch_mean_shift(ctx->partials, g.nblocks(), 1.0 / double(ctx->dims.n), ctx->inv_eps(), ctx->ps,
@@ -793,6 +810,7 @@ ek_status ek_poisson_sor_iterations(ek_ctx* ctx, const double* dev_b, double* de
   if (ctx->insulating()) return ctx->fail(EK_ESTATE, "the context has insulating walls");
   if (!dev_b || !dev_psi || iterations < 0) return ctx->fail(EK_EINVAL, "bad arguments");
   const SiteGrid cg = colour_grid(ctx->p.nx, ctx->p.ny, ctx->p.nz, ctx->bx_colour);
+  ctx->settle_psi();   // before ps is reused
   launch_ps_reset(ctx->ps, 0.0, ctx->stream);
   const double rj = ctx->jacobi_radius();
   double omega = 1.0;

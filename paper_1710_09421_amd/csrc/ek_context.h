@@ -63,6 +63,12 @@ struct ek_ctx {
   int last_fallback = 0;
   int last_consulted = 0;
   bool have_solve = false;             // b, ps and psi hold a finished solve
+  // The time loop with an extrapolated start leaves the removal of the
+  // solution's mean to the next charge pass, which reads and writes psi
+  // anyway (defer_shift set around such a solve; shift_pending: psi still
+  // holds the solution before the shift, whose amount ps keeps).
+  bool defer_shift = false;
+  bool shift_pending = false;
   double mass[3] = {0, 0, 0};
   double mom[3] = {0, 0, 0};
   int bx_sites = 0, bx_colour = 0;     // launch shapes (0 = default)
@@ -117,6 +123,8 @@ struct ek_ctx {
   // returns the number of block partials
   int residual_launch(const double* b, const double* x);
   ek_status learned_start(const double* b, double* x, ek::PoissonScalars* h);
+  // Removes a pending mean from psi (before psi is read or ps reused).
+  void settle_psi();
   void mg_setup();
   void mg_release();
   // One V-cycle; with norm_blocks given, its last finest-level sweep also

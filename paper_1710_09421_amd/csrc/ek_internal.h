@@ -97,6 +97,13 @@ struct PoissonScalars {
   int cycles;             // multigrid cycles run since the flags were cleared
 };
 
+// A potential value with the solution's mean removed (zero for a vanishing
+// right-hand side): one fused multiply-add, so that the removal after the
+// solve and the one the next charge pass does round alike.
+__device__ inline double mean_removed(double v, const PoissonScalars* ps, double inv_n) {
+  return ps->zero_rhs ? 0.0 : __builtin_fma(-ps->psum, inv_n, v);
+}
+
 // ---------------------------------------------------------------------------
 // Launchers (kernel files).  All take the stream as last argument.
 // ---------------------------------------------------------------------------
@@ -112,7 +119,9 @@ inline int extrap_history(int warm_start) {
                                        : 0;
 }
 // With psi_old (an extrapolated start) and extrap != 0 the pass also prepares
-// the start and shifts the history buffers (the modes of StartExtrap).
+// the start and shifts the history buffers (the modes of StartExtrap); with
+// `pending` (not null) psi still holds the last solution before the removal
+// of its mean, which the pass then does first (as launch_psi_shift).
 // insulating: the charge of insulating walls (fluid sites only, the wall
 // faces' surface charge added to the fluid sites they bound).
 template <typename T>
@@ -121,7 +130,7 @@ void launch_charge(const T* f, const uint32_t* mask, const double* wall_q, doubl
                    const SiteGrid& g, hipStream_t s, const BeadTableView& bt,
                    double* psi = nullptr, double* psi_old = nullptr, int extrap = 0,
                    bool insulating = false, double* psi_old2 = nullptr,
-                   double* psi_old3 = nullptr);
+                   double* psi_old3 = nullptr, const PoissonScalars* pending = nullptr);
 // Fused step over the sites without a `skip` bit.  Writes its block partials
 // (seven components: masses, momentum, sites updated) first in a layout of
 // `nblocks` blocks (lb_step_blocks(g, nz), plus the tail's blocks when a tail

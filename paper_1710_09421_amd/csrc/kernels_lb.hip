@@ -51,13 +51,18 @@ __global__ __launch_bounds__(BLOCK) void k_init_species(T* __restrict__ f,
 //   mode 5  quadratic, the history deepened               ... and old3 = o2
 //   mode 6  psi = 4p - 6o + 4o2 - o3  (cubic)             ... and old3 = o2
 // (the Newton backward-difference forms of the polynomial through the last
-// two, three or four solutions, evaluated one step ahead).
+// two, three or four solutions, evaluated one step ahead).  With `pending`
+// the last solution still carries its mean: p = psi - psum / n (zero for a
+// vanishing right-hand side), as k_psi_shift would have left it, and mode 1
+// stores that p in psi too.
 struct StartExtrap {
   double* psi;
   double* old;
   int mode;
   double* old2;
   double* old3;
+  const PoissonScalars* pending;
+  double inv_n;
 };
 
 template <typename T, typename I, bool NEU>
@@ -80,7 +85,11 @@ __global__ __launch_bounds__(BLOCK) void k_charge(const T* __restrict__ f,
     b[r] = -rho * inv_eps;
     acc[0] = rho;
     if (start.mode) {
-      const double p = start.psi[r];
+      double p = start.psi[r];
+      if (start.pending) {
+        p = mean_removed(p, start.pending, start.inv_n);
+        if (start.mode == 1) start.psi[r] = p;
+      }
       if (start.mode == 2 || start.mode == 3) {
         const double o = start.old[r];
         start.psi[r] = 2.0 * p - o;
@@ -279,8 +288,9 @@ void launch_charge(const T* f, const uint32_t* mask, const double* wall_q, doubl
                    double* partials, const LBParams& lp, double inv_eps, Dims d,
                    const SiteGrid& g, hipStream_t s, const BeadTableView& bt, double* psi,
                    double* psi_old, int extrap, bool insulating, double* psi_old2,
-                   double* psi_old3) {
-  const StartExtrap start{psi, psi_old, psi_old ? extrap : 0, psi_old2, psi_old3};
+                   double* psi_old3, const PoissonScalars* pending) {
+  const StartExtrap start{psi,      psi_old,  psi_old ? extrap : 0, psi_old2,
+                          psi_old3, pending,  1.0 / double(d.n)};
   auto go = [&](auto kernel) {
     hipLaunchKernelGGL(kernel, g.grid, g.block, 0, s, f, mask, wall_q, b, partials, lp, inv_eps,
                        bt, d, start);
@@ -393,7 +403,7 @@ void launch_mean_shift(const double* partials, int nblocks, double inv_n, double
   template void launch_charge<T>(const T*, const uint32_t*, const double*, double*, double*, \
                                  const LBParams&, double, Dims, const SiteGrid&, hipStream_t,\
                                  const BeadTableView&, double*, double*, int, bool, double*,  \
-                                 double*);                                                   \
+                                 double*, const PoissonScalars*);                            \
   template int launch_lb_step<T>(const T*, T*, const uint32_t*, const double*,               \
                                  const LBParams&, const BeadTableView&, double*, int,        \
                                  uint32_t, Dims, const SiteGrid&, hipStream_t, hipEvent_t,   \

@@ -1220,6 +1220,7 @@ ek_status ek_ctx::mg_solve(const double* bb, double* x, PoissonScalars h, int& i
     return fail(EK_ENOCONV, buf);
   }
   iters = h.iters;
-  launch_psi_shift(x, ps, 1.0 / double(dims.n), dims, stream);
+  if (defer_shift) shift_pending = true;
+  else launch_psi_shift(x, ps, 1.0 / double(dims.n), dims, stream);
   return EK_OK;
 }

@@ -235,7 +235,7 @@ __global__ __launch_bounds__(BLOCK) void k_psi_shift(double* __restrict__ psi,
                                                      double inv_n, long long n) {
   const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
-  psi[r] = ps->zero_rhs ? 0.0 : psi[r] - ps->psum * inv_n;
+  psi[r] = mean_removed(psi[r], ps, inv_n);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_fill(double* __restrict__ x, double v, long long n) {

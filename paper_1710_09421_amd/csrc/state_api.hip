@@ -122,6 +122,7 @@ ek_status ek_save_state(ek_ctx* ctx, void* host, size_t bytes) {
   const BeadState bs = bead_state_view(ctx->bead_mem, ctx->max_beads);
   const size_t nb = (size_t)ctx->n_beads;
   std::memcpy(pay + s.wall_q, ctx->host_wall_q.data(), d.n * 8);
+  ctx->settle_psi();
   bool ok = d2h(s.f, ctx->fcur(), 3 * Q * d.n * tsz) && d2h(s.psi, ctx->psi, d.n * 8);
   if (ok && ctx->psi_old) ok = d2h(s.psi_old, ctx->psi_old, d.n * 8);
   if (ok && ctx->psi_old2) ok = d2h(s.psi_old2, ctx->psi_old2, d.n * 8);

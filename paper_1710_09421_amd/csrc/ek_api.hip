@@ -359,6 +359,7 @@ ek_status ek_ctx::step_impl(int n_steps) {
     launch_charge<T>((const T*)fcur(), mask, wall_q, b, partials, lp, inv_eps(), dims, g, stream, bt,
                      psi, psi_old, extrap, insulating(), psi_old2, psi_old3,
                      shift_pending ? ps : nullptr);
+    rotate_history(extrap, psi_old, psi_old2, psi_old3);
     shift_pending = false;
     if (held > 0) psi_hist = std::min(psi_hist + 1, held + 1);
     launch_mean_shift(partials, nb, 1.0 / double(insulating() ? n_fluid : dims.n), inv_eps(), ps,

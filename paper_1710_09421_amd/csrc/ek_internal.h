@@ -110,6 +110,21 @@ __device__ inline double mean_removed(double v, const PoissonScalars* ps, double
 template <typename T>
 void launch_init_species(T* f, const uint32_t* mask, const double* n_dev, int species,
                          double nref, Dims d, hipStream_t s);
+// The renaming of the history buffers after a charge pass in `mode`: p was
+// stored in old2 (modes 3, 4) or old3 (5, 6), which becomes old, the others
+// move one step deeper.
+inline void rotate_history(int mode, double*& old, double*& old2, double*& old3) {
+  if (mode == 3 || mode == 4) {
+    double* t = old2;
+    old2 = old;
+    old = t;
+  } else if (mode == 5 || mode == 6) {
+    double* t = old3;
+    old3 = old2;
+    old2 = old;
+    old = t;
+  }
+}
 // Previous solutions besides psi that an extrapolated start of the solve
 // keeps: 1 for the linear, 2 for the quadratic, 3 for the cubic one.
 inline int extrap_history(int warm_start) {
@@ -119,7 +134,8 @@ inline int extrap_history(int warm_start) {
                                        : 0;
 }
 // With psi_old (an extrapolated start) and extrap != 0 the pass also prepares
-// the start and shifts the history buffers (the modes of StartExtrap); with
+// the start and the history of the next step (the modes of StartExtrap; for
+// modes 3 to 6 the caller renames the buffers with rotate_history); with
 // `pending` (not null) psi still holds the last solution before the removal
 // of its mean, which the pass then does first (as launch_psi_shift).
 // insulating: the charge of insulating walls (fluid sites only, the wall

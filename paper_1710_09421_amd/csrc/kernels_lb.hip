@@ -42,7 +42,7 @@ __global__ __launch_bounds__(BLOCK) void k_init_species(T* __restrict__ f,
 // rho_e (for the mean that the periodic problem removes).  With `start` set
 // it also prepares the extrapolated start of the solve at the site, from the
 // last solution p = psi and the earlier ones o = old, o2 = old2, o3 = old3
-// (time t-1 down to t-4), and shifts the history by one step (old = p, and
+// (time t-1 down to t-4), and the history of the next step (old = p, and
 // old2 = o, old3 = o2 where the mode keeps them):
 //   mode 1  psi = p                                      old = p
 //   mode 2  psi = 2p - o  (linear)                        old = p
@@ -50,6 +50,8 @@ __global__ __launch_bounds__(BLOCK) void k_init_species(T* __restrict__ f,
 //   mode 4  psi = 3p - 3o + o2  (quadratic)               old = p, old2 = o
 //   mode 5  quadratic, the history deepened               ... and old3 = o2
 //   mode 6  psi = 4p - 6o + 4o2 - o3  (cubic)             ... and old3 = o2
+// Modes 3 to 6 store only p, in the buffer of the value that drops out (or
+// the unused deepest one), and the buffers are renamed afterwards.
 // (the Newton backward-difference forms of the polynomial through the last
 // two, three or four solutions, evaluated one step ahead).  With `pending`
 // the last solution still carries its mean: p = psi - psum / n (zero for a
@@ -90,24 +92,18 @@ __global__ __launch_bounds__(BLOCK) void k_charge(const T* __restrict__ f,
         p = mean_removed(p, start.pending, start.inv_n);
         if (start.mode == 1) start.psi[r] = p;
       }
+      // the history deepens by rotation: p goes to the buffer that becomes
+      // old, which is old for modes 1 and 2, old2 for 3 and 4 and old3 for
+      // 5 and 6 (the host then renames the buffers: rotate_history)
       if (start.mode == 2 || start.mode == 3) {
-        const double o = start.old[r];
-        start.psi[r] = 2.0 * p - o;
-        if (start.mode == 3) start.old2[r] = o;
+        start.psi[r] = 2.0 * p - start.old[r];
       } else if (start.mode == 4 || start.mode == 5) {
-        const double o = start.old[r];
-        const double o2 = start.old2[r];
-        start.psi[r] = 3.0 * (p - o) + o2;
-        start.old2[r] = o;
-        if (start.mode == 5) start.old3[r] = o2;
+        start.psi[r] = 3.0 * (p - start.old[r]) + start.old2[r];
       } else if (start.mode == 6) {
-        const double o = start.old[r];
-        const double o2 = start.old2[r];
-        start.psi[r] = 4.0 * (p + o2) - 6.0 * o - start.old3[r];
-        start.old2[r] = o;
-        start.old3[r] = o2;
+        start.psi[r] = 4.0 * (p + start.old2[r]) - 6.0 * start.old[r] - start.old3[r];
       }
-      start.old[r] = p;
+      double* dst = start.mode <= 2 ? start.old : (start.mode <= 4 ? start.old2 : start.old3);
+      dst[r] = p;
     }
   }
   block_partials<1>(acc, partials, bid, nblocks);

@@ -150,10 +150,19 @@ __global__ __launch_bounds__(256) void k_prolong_to(Lvl F, Lvl C, const double* 
 // their number chosen so that the launch runs in as few rounds of the
 // workgroups the device holds at once as the chunks' extra steps allow:
 // 1 <= nch <= nz; TX divides nx, TY divides ny; all sides even.
+// With CORR the sweep is the first post-smoothing sweep of a cycle and takes
+// the coarse-grid correction on the way in: each iterate plane gets the
+// trilinear interpolation of the coarse iterate C.x (cell-centred, weights
+// 3/4 and 1/4 per axis, as prolong_value) added as it is stored in LDS, in
+// two stages: the two coarse planes it lies between, over a window of the
+// coarse plane around the tile, are combined along z into Ez (one barrier
+// phase ahead), and each site then takes its four values of Ez along y and
+// x.  The separate prolongation pass (read xin, write xin + P e: 16 bytes
+// per site) is saved; xin stays unchanged.
 constexpr int SWEEP_THREADS = 256;
 constexpr int SWEEP_SLOTS = 5;
 
-template <int TX, int TY>
+template <int TX, int TY, bool CORR = false>
 struct SweepRegs {
   static constexpr int REGION = (TX + 4) * (TY + 4);
   static constexpr int XPT = (REGION + SWEEP_THREADS - 1) / SWEEP_THREADS;
@@ -162,20 +171,27 @@ struct SweepRegs {
   static constexpr int RPT = (RED_ITEMS + SWEEP_THREADS - 1) / SWEEP_THREADS;
   static constexpr int PAIR_ITEMS = (TX / 2) * TY;
   static constexpr int BPT = (PAIR_ITEMS + SWEEP_THREADS - 1) / SWEEP_THREADS;
+  // coarse window: the coarse cells of the region's sites and their
+  // neighbours, columns x0/2 - 2 .. x0/2 + TX/2 + 1, rows likewise
+  static constexpr int CWX = TX / 2 + 4, CWY = TY / 2 + 4, CW = CWX * CWY;
+  static constexpr int CPT = CORR ? (CW + SWEEP_THREADS - 1) / SWEEP_THREADS : 1;
   double x[XPT];    // an iterate plane (tile and two-site ring), to be stored in LDS
   double fr[RPT];   // f at this thread's colour-0 ring sites of a plane
   double fb[BPT];   // f at this thread's colour-1 tile sites of a plane
+  double c0[CPT];   // CORR: the coarse window of the plane's own coarse plane
+  double c1[CPT];   //       and of the one above or below it
 };
 
-template <int TX, int TY>
+template <int TX, int TY, bool CORR = false>
 __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_z(Lvl L, const double* __restrict__ xin,
                                                            double* __restrict__ xout, int nch,
                                                            const PoissonScalars* ps, int level0,
-                                                           double omega) {
+                                                           double omega, Lvl C) {
   static_assert(TX % 2 == 0 && TY % 2 == 0, "even tiles");
-  using R = SweepRegs<TX, TY>;
+  using R = SweepRegs<TX, TY, CORR>;
   constexpr int RX = TX + 4, RY = TY + 4;
   __shared__ double P[SWEEP_SLOTS][RY][RX];
+  __shared__ double Ez[CORR ? R::CW : 1];
   if (ps->done) return;
   const double shift = level0 ? ps->shift : 0.0;
   const int nx = L.nx, ny = L.ny, nz = L.nz;
@@ -217,13 +233,53 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_z(Lvl L, const double* 
       r[u] = xin[base + (long long)wrapi(y0 - 2 + j, ny) * nx + wrapi(x0 - 2 + i, nx)];
     }
   };
+  // (CORR) site (j, i) of the region lies in the coarse cell of window
+  // column (i >> 1) + 1, row (j >> 1) + 1 (x0, y0 even); its neighbour cell
+  // along an axis is the next one for an odd and the previous one for an even
+  // fine coordinate
   auto store_x = [&](int s, const double (&r)[R::XPT]) {
 #pragma unroll
     for (int u = 0; u < R::XPT; ++u) {
       const int t = tid + u * SWEEP_THREADS;
       if (t < R::REGION) {
         const int j = t / RX, i = t - j * RX;
-        P[s][j][i] = r[u];
+        double v = r[u];
+        if constexpr (CORR) {
+          const int wx = (i >> 1) + 1, wy = (j >> 1) + 1;
+          const int wxn = (i & 1) ? wx + 1 : wx - 1, wyn = (j & 1) ? wy + 1 : wy - 1;
+          const double* e0 = Ez + wy * R::CWX;
+          const double* e1 = Ez + wyn * R::CWX;
+          v += 0.75 * (0.75 * e0[wx] + 0.25 * e0[wxn]) + 0.25 * (0.75 * e1[wx] + 0.25 * e1[wxn]);
+        }
+        P[s][j][i] = v;
+      }
+    }
+  };
+  // (CORR) the coarse window of the two coarse planes fine plane q lies
+  // between: its own, q >> 1, and the next one for odd q, the previous one for
+  // even q (periodic)
+  auto cmod = [](int v, int n) { return ((v % n) + n) % n; };
+  auto gather_c = [&](int q, R& r) {
+    if constexpr (CORR) {
+      const int Z = q >> 1, Zn = (q & 1) ? Z + 1 : Z - 1;
+      const long long b0 = (long long)cmod(Z, C.nz) * C.ny * C.nx;
+      const long long b1 = (long long)cmod(Zn, C.nz) * C.ny * C.nx;
+#pragma unroll
+      for (int u = 0; u < R::CPT; ++u) {
+        const int t = min(tid + u * SWEEP_THREADS, R::CW - 1);
+        const int wy = t / R::CWX, wx = t - wy * R::CWX;
+        const long long off = (long long)cmod(y0 / 2 - 2 + wy, C.ny) * C.nx + cmod(x0 / 2 - 2 + wx, C.nx);
+        r.c0[u] = C.x[b0 + off];
+        r.c1[u] = C.x[b1 + off];
+      }
+    }
+  };
+  auto write_ez = [&](const R& r) {
+    if constexpr (CORR) {
+#pragma unroll
+      for (int u = 0; u < R::CPT; ++u) {
+        const int t = tid + u * SWEEP_THREADS;
+        if (t < R::CW) Ez[t] = 0.75 * r.c0[u] + 0.25 * r.c1[u];
       }
     }
   };
@@ -256,14 +312,18 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_z(Lvl L, const double* 
       r[u] = f[base + (long long)(y0 + jj) * nx + x0 + 2 * m + (black_first(jj, m, k) ? 0 : 1)];
     }
   };
-  // Step k.  cur holds the iterate plane k+2 (stored at the end), f of the
-  // colour-0 sites of plane k and of the colour-1 sites of plane k-1; nxt
-  // receives plane k+3 and f of planes k+1 (colour 0) and k (colour 1).
+  // Step k.  cur holds the iterate plane k+2 (stored at the end; with CORR its
+  // coarse window, combined into Ez in the first phase), f of the colour-0
+  // sites of plane k and of the colour-1 sites of plane k-1; nxt receives
+  // plane k+3 (and its coarse window) and f of planes k+1 (colour 0) and k
+  // (colour 1).
   auto step = [&](int k, R& cur, R& nxt) {
     // (near the chunk's end the planes are clamped: loaded, never used)
     gather_x(min(k + 3, z1 + 1), nxt.x);
+    gather_c(min(k + 3, z1 + 1), nxt);
     gather_fr(min(k + 1, z1), nxt.fr);
     gather_fb(max(min(k, z1 - 1), z0), nxt.fb);
+    if (k + 2 <= z1 + 1) write_ez(cur);
     const int sk = slot(k), skm = slot(k + SWEEP_SLOTS - 1), skp = slot(k + 1),
               skm2 = slot(k + SWEEP_SLOTS - 2);
 #pragma unroll
@@ -309,9 +369,16 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_z(Lvl L, const double* 
   R A, B;
   for (int q = zb; q <= z0; ++q) {                         // planes z0-2, z0-1, z0
     gather_x(q, A.x);
+    gather_c(q, A);
+    if constexpr (CORR) {
+      write_ez(A);
+      __syncthreads();
+    }
     store_x(slot(q), A.x);
+    if constexpr (CORR) __syncthreads();
   }
   gather_x(z0 + 1, A.x);
+  gather_c(z0 + 1, A);
   gather_fr(z0 - 1, A.fr);
   __syncthreads();
   int k = z0 - 1;
@@ -340,18 +407,19 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_z(Lvl L, const double* 
 // planes (their heights differ by at most two).  nz even, 1 <= nch <= nz / 2;
 // TX, TY multiples of 4.
 enum : int { SWEEP_RESTRICT = 1, SWEEP_NORMS = 2 };
+constexpr int ZR_THREADS = 256;
 
 template <int TX, int TY>
 struct SweepRRegs {
   static constexpr int RX = TX + 6, RY = TY + 6;
   static constexpr int REGION = RX * RY;
-  static constexpr int XPT = (REGION + SWEEP_THREADS - 1) / SWEEP_THREADS;
+  static constexpr int XPT = (REGION + ZR_THREADS - 1) / ZR_THREADS;
   static constexpr int RED_ROW = TX / 2 + 2;              // colour-0 sites per ring-2 row
   static constexpr int RED_ITEMS = RED_ROW * (TY + 4);
-  static constexpr int RPT = (RED_ITEMS + SWEEP_THREADS - 1) / SWEEP_THREADS;
+  static constexpr int RPT = (RED_ITEMS + ZR_THREADS - 1) / ZR_THREADS;
   static constexpr int BLK_ROW = TX / 2 + 1;              // colour-1 sites per ring-1 row
   static constexpr int BLK_ITEMS = BLK_ROW * (TY + 2);
-  static constexpr int BPT = (BLK_ITEMS + SWEEP_THREADS - 1) / SWEEP_THREADS;
+  static constexpr int BPT = (BLK_ITEMS + ZR_THREADS - 1) / ZR_THREADS;
   static constexpr int CELLS = (TX / 2) * (TY / 2);       // 2 x 2 blocks of the tile
   double x[XPT];     // an iterate plane (tile and three-site ring), to be stored in LDS
   double fr[RPT];    // f at this thread's colour-0 ring-2 sites of a plane
@@ -360,13 +428,13 @@ struct SweepRRegs {
 };
 
 template <int TX, int TY, int MODE>
-__global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_zr(Lvl L, const double* __restrict__ xin,
+__global__ __launch_bounds__(ZR_THREADS) void k_sweep_zr(Lvl L, const double* __restrict__ xin,
                                                             double* __restrict__ xout, int nch,
                                                             const PoissonScalars* ps, int level0,
                                                             double omega, Lvl C, double omega_red,
                                                             double* __restrict__ partials) {
   static_assert(TX % 4 == 0 && TY % 4 == 0, "tiles of whole 2 x 2 blocks");
-  static_assert(2 * SweepRRegs<TX, TY>::CELLS <= SWEEP_THREADS, "a 2 x 2 block per thread pair");
+  static_assert(2 * SweepRRegs<TX, TY>::CELLS <= ZR_THREADS, "a 2 x 2 block per thread pair");
   using R = SweepRRegs<TX, TY>;
   constexpr int RX = R::RX, RY = R::RY, NS = 6;
   __shared__ double P[NS][RY][RX];
@@ -394,7 +462,7 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_zr(Lvl L, const double*
     const long long base = plane_base(q);
 #pragma unroll
     for (int u = 0; u < R::XPT; ++u) {
-      const int t = min(tid + u * SWEEP_THREADS, R::REGION - 1);
+      const int t = min(tid + u * ZR_THREADS, R::REGION - 1);
       const int j = t / RX, i = t - j * RX;
       r[u] = xin[base + (long long)wrapi(y0 - 3 + j, ny) * nx + wrapi(x0 - 3 + i, nx)];
     }
@@ -402,7 +470,7 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_zr(Lvl L, const double*
   auto store_x = [&](int sl, const double (&r)[R::XPT]) {
 #pragma unroll
     for (int u = 0; u < R::XPT; ++u) {
-      const int t = tid + u * SWEEP_THREADS;
+      const int t = tid + u * ZR_THREADS;
       if (t < R::REGION) {
         const int j = t / RX, i = t - j * RX;
         P[sl][j][i] = r[u];
@@ -430,7 +498,7 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_zr(Lvl L, const double*
     const long long base = plane_base(k);
 #pragma unroll
     for (int u = 0; u < R::RPT; ++u) {
-      const int t = min(tid + u * SWEEP_THREADS, R::RED_ITEMS - 1);
+      const int t = min(tid + u * ZR_THREADS, R::RED_ITEMS - 1);
       int j, i;
       red_site(t, k, j, i);
       r[u] = f[base + (long long)wrapi(y0 - 3 + j, ny) * nx + wrapi(x0 - 3 + i, nx)];
@@ -440,7 +508,7 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_zr(Lvl L, const double*
     const long long base = plane_base(k);
 #pragma unroll
     for (int u = 0; u < R::BPT; ++u) {
-      const int t = min(tid + u * SWEEP_THREADS, R::BLK_ITEMS - 1);
+      const int t = min(tid + u * ZR_THREADS, R::BLK_ITEMS - 1);
       int j, i;
       black_site(t, k, j, i);
       r[u] = f[base + (long long)wrapi(y0 - 3 + j, ny) * nx + wrapi(x0 - 3 + i, nx)];
@@ -475,7 +543,7 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_zr(Lvl L, const double*
     if (k <= z1 + 1) {
 #pragma unroll
       for (int u = 0; u < R::RPT; ++u) {
-        const int t = tid + u * SWEEP_THREADS;
+        const int t = tid + u * ZR_THREADS;
         if (t < R::RED_ITEMS) {
           int j, i;
           red_site(t, k, j, i);
@@ -490,7 +558,7 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_zr(Lvl L, const double*
     // 1b. write the tile of plane k-2; the residual of plane k-3
     if (k - 2 >= z0 && k - 2 < z1) {
       const long long base = plane_base(k - 2);
-      for (int t = tid; t < (TX / 2) * TY; t += SWEEP_THREADS) {
+      for (int t = tid; t < (TX / 2) * TY; t += ZR_THREADS) {
         const int jj = t / (TX / 2), m = t - jj * (TX / 2);
         double2 out;
         out.x = P[skm2][3 + jj][3 + 2 * m];
@@ -544,7 +612,7 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_zr(Lvl L, const double*
     if (k >= z0 && k <= z1 + 1) {
 #pragma unroll
       for (int u = 0; u < R::BPT; ++u) {
-        const int t = tid + u * SWEEP_THREADS;
+        const int t = tid + u * ZR_THREADS;
         if (t < R::BLK_ITEMS) {
           int j, i;
           black_site(t, k - 1, j, i);
@@ -687,6 +755,7 @@ struct ek_ctx::MG {
   std::vector<int> sweep_tx, sweep_ty, sweep_nch;
   double* tmp0 = nullptr;
   double* tmp1 = nullptr;
+  double* tmp2 = nullptr;   // the finest level's third iterate buffer
   // the finest level's pre-smoothing sweep also restricts, and a tested
   // cycle's last sweep also takes the residual norms (k_sweep_zr: a 64 x 8
   // tile, zr_chunks chunks of an even number of planes)
@@ -741,17 +810,17 @@ size_t ek::mg_workspace_bytes(int nx, int ny, int nz) {
 // next (every coarser level fits in the latter).
 size_t ek::mg_sweep_bytes(int nx, int ny, int nz) {
   const size_t n0 = (size_t)nx * ny * nz;
-  return 2 * 256 + ((n0 * 8 + 255) & ~size_t(255)) + ((n0 + 7) / 8 * 8 + 255) / 256 * 256;
+  return 3 * 256 + 2 * ((n0 * 8 + 255) & ~size_t(255)) + ((n0 + 7) / 8 * 8 + 255) / 256 * 256;
 }
 
-// Workgroups of `kernel` (SWEEP_THREADS threads) that the device holds at
+// Workgroups of `kernel` (`threads` threads each) that the device holds at
 // once, or 0 when it cannot be asked.
 template <typename F>
-static long long resident_workgroups(F kernel) {
+static long long resident_workgroups(F kernel, int threads = SWEEP_THREADS) {
   int dev = 0, ncu = 0, occ = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, SWEEP_THREADS, 0) != hipSuccess)
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, 0) != hipSuccess)
     return 0;
   return (long long)std::max(ncu, 0) * std::max(occ, 0);
 }
@@ -900,8 +969,10 @@ void ek_ctx::mg_setup() {
   mg->sweep_nch.assign(nl, 0);
   if (mg_tmp) {
     char* t = mg_tmp + 256;
+    const size_t b0 = (((size_t)p.nx * p.ny * p.nz) * 8 + 255) & ~size_t(255);
     mg->tmp0 = (double*)t;
-    mg->tmp1 = (double*)(t + ((((size_t)p.nx * p.ny * p.nz) * 8 + 255) & ~size_t(255)) + 256);
+    mg->tmp2 = (double*)(t + b0 + 256);
+    mg->tmp1 = (double*)(t + 2 * b0 + 512);
     for (int l = 0; l < fc; ++l) {
       const Lvl& L = mg->levels[l];
       if (L.n <= FUSED_CORRECTION_MAX_SITES) continue;
@@ -939,8 +1010,9 @@ void ek_ctx::mg_setup() {
       // chunks of whole 2 x 2 x 2 blocks, h + 5 steps each, as many
       // workgroups at once as both variants hold
       const Lvl& L = mg->levels[0];
-      const long long slots = std::min(resident_workgroups(k_sweep_zr<64, 8, SWEEP_RESTRICT>),
-                                       resident_workgroups(k_sweep_zr<64, 8, SWEEP_NORMS>));
+      const long long slots =
+          std::min(resident_workgroups(k_sweep_zr<64, 8, SWEEP_RESTRICT>, ZR_THREADS),
+                   resident_workgroups(k_sweep_zr<64, 8, SWEEP_NORMS>, ZR_THREADS));
       mg->zr_chunks = sweep_chunks((long long)(L.nx / 64) * (L.ny / 8), L.nz, 2, 5, slots,
                                    std::max(1, mg->sweep_nch[0] / 2));
     }
@@ -1027,13 +1099,23 @@ static void launch_sweep_z(const Lvl& L, int tx, int ty, int nch, const double* 
   const dim3 grid((unsigned)((L.nx / tx) * (L.ny / ty) * nch));
   if (tx == 64 && ty == 16)
     hipLaunchKernelGGL((k_sweep_z<64, 16>), grid, dim3(SWEEP_THREADS), 0, s, L, xin, xout, nch, ps,
-                       level0, MG_OMEGA);
+                       level0, MG_OMEGA, L);
   else if (tx == 64)
     hipLaunchKernelGGL((k_sweep_z<64, 8>), grid, dim3(SWEEP_THREADS), 0, s, L, xin, xout, nch, ps,
-                       level0, MG_OMEGA);
+                       level0, MG_OMEGA, L);
   else
     hipLaunchKernelGGL((k_sweep_z<32, 8>), grid, dim3(SWEEP_THREADS), 0, s, L, xin, xout, nch, ps,
-                       level0, MG_OMEGA);
+                       level0, MG_OMEGA, L);
+}
+
+// A first post-smoothing sweep with the correction from level C on the way
+// in (64 x 8 tiles): xout = sweep(xin + P e).
+static void launch_sweep_z_corrected(const Lvl& L, const Lvl& C, int nch, const double* xin,
+                                     double* xout, const PoissonScalars* ps, int level0,
+                                     hipStream_t s) {
+  const dim3 grid((unsigned)((L.nx / 64) * (L.ny / 8) * nch));
+  hipLaunchKernelGGL((k_sweep_z<64, 8, true>), grid, dim3(SWEEP_THREADS), 0, s, L, xin, xout, nch,
+                     ps, level0, MG_OMEGA, C);
 }
 
 // The finest level's full sweep with the residual of its result (restriction
@@ -1044,10 +1126,10 @@ static int launch_sweep_zr(const Lvl& L, int nch, const double* xin, double* xou
                            double* partials, hipStream_t s) {
   const int nblocks = (L.nx / 64) * (L.ny / 8) * nch;
   if (mode == SWEEP_RESTRICT)
-    hipLaunchKernelGGL((k_sweep_zr<64, 8, SWEEP_RESTRICT>), dim3(nblocks), dim3(SWEEP_THREADS), 0,
+    hipLaunchKernelGGL((k_sweep_zr<64, 8, SWEEP_RESTRICT>), dim3(nblocks), dim3(ZR_THREADS), 0,
                        s, L, xin, xout, nch, ps, 1, MG_OMEGA, C, omega_red, partials);
   else
-    hipLaunchKernelGGL((k_sweep_zr<64, 8, SWEEP_NORMS>), dim3(nblocks), dim3(SWEEP_THREADS), 0, s,
+    hipLaunchKernelGGL((k_sweep_zr<64, 8, SWEEP_NORMS>), dim3(nblocks), dim3(ZR_THREADS), 0, s,
                        L, xin, xout, nch, ps, 1, MG_OMEGA, C, 0.0, partials);
   return nblocks;
 }
@@ -1127,17 +1209,36 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x, int* norm_blocks) {
   // coarse-grid correction: fused into the first post-smoothing sweep on
   // levels up to FUSED_CORRECTION_MAX_SITES, a pass of its own above
   for (int l = fc - 1; l >= 0; --l) {
+    if (l == 0 && mg->fused0) {
+      // the correction inside the first post-smoothing sweep, from the
+      // pre-smoothed iterate (in x or tmp0) into the other of tmp0 and tmp2,
+      // then the second sweep back into x (with the test's residual norms)
+      static_assert(NU2 == 2, "one sweep after the corrected one");
+      const double* pre = pre_in_x ? x : mg->tmp0;
+      double* mid = pre_in_x ? mg->tmp0 : mg->tmp2;
+      launch_sweep_z_corrected(L[0], L[1], mg->sweep_nch[0], pre, mid, ps, 1, stream);
+      if (norm_blocks)
+        *norm_blocks = launch_sweep_zr(L[0], mg->zr_chunks, mid, x, ps, SWEEP_NORMS, L[1], 0.0,
+                                       partials, stream);
+      else
+        launch_sweep_z(L[0], 64, 8, mg->sweep_nch[0], mid, x, ps, 1, stream);
+      continue;
+    }
     if (mg->sweep_tx[l]) {
       // correction (out of place from tmp0 on the finest level), then NU2
-      // full sweeps x -> tmp -> x
+      // full sweeps x -> tmp -> x; on 64 x 8 tiles of a coarser level the
+      // correction rides on the first of them
       double* tmp = l == 0 ? mg->tmp0 : mg->tmp1;
-      if (l == 0 && pre0 && !pre_in_x)
+      const bool corrected = l > 0 && mg->sweep_tx[l] == 64 && mg->sweep_ty[l] == 8;
+      if (corrected)
+        launch_sweep_z_corrected(L[l], L[l + 1], mg->sweep_nch[l], L[l].x, tmp, ps, 0, stream);
+      else if (l == 0 && pre0 && !pre_in_x)
         hipLaunchKernelGGL(k_prolong_to, level_launch(L[1]).grid, level_launch(L[1]).block, 0,
                            stream, L[0], L[1], mg->tmp0, x, ps);
       else
         hipLaunchKernelGGL(k_prolong, level_launch(L[l + 1]).grid, level_launch(L[l + 1]).block, 0,
                            stream, L[l], L[l + 1], ps);
-      for (int s = 0; s < NU2; ++s) {
+      for (int s = corrected ? 1 : 0; s < NU2; ++s) {
         const bool to_tmp = (s & 1) == 0;
         if (l == 0 && s == NU2 - 1 && norm_blocks && mg->fused0) {   // the test's residual too
           *norm_blocks = launch_sweep_zr(L[0], mg->zr_chunks, tmp, L[0].x, ps, SWEEP_NORMS,

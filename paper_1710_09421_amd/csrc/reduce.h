@@ -14,12 +14,15 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// A block of up to 1024 threads (a whole number of waves); four waves are
+// added pairwise, other counts in wave order.
 template <int NC>
 __device__ inline void block_partials(const double (&v)[NC], double* partials, int bid,
                                       int nblocks) {
-  __shared__ double sh[NC][4];
+  __shared__ double sh[NC][16];
   const int tid = threadIdx.x + blockDim.x * threadIdx.y;
   const int lane = tid & 63, wid = tid >> 6;
+  const int nw = int(blockDim.x * blockDim.y) >> 6;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     double s = wave_sum(v[c]);
@@ -27,7 +30,13 @@ __device__ inline void block_partials(const double (&v)[NC], double* partials, i
   }
   __syncthreads();
   if (tid < NC) {
-    double s = ((sh[tid][0] + sh[tid][1]) + (sh[tid][2] + sh[tid][3]));
+    double s;
+    if (nw == 4) {
+      s = ((sh[tid][0] + sh[tid][1]) + (sh[tid][2] + sh[tid][3]));
+    } else {
+      s = sh[tid][0];
+      for (int w = 1; w < nw; ++w) s += sh[tid][w];
+    }
     partials[(size_t)tid * nblocks + bid] = s;
   }
 }

@@ -8,8 +8,8 @@
 //   smoother   red-black Gauss-Seidel (x = (sum nb - h^2 f) / 6) over-relaxed
 //              by MG_OMEGA, nu1 = NU1 = 1 and nu2 = NU2 = 2 (NU1_FUSED
 //              on a finest level whose last pre-smoothing sweep restricts,
-//              NU2_COARSE = 1 on the levels of the one-workgroup coarse
-//              kernel)
+//              NU1_FINEST on a finest level of half sweeps, NU2_COARSE = 1
+//              on the levels of the one-workgroup coarse kernel)
 //   restriction  f_{l+1} = average of the 8 fine residuals (fused with the
 //                residual, also zeroes the coarse iterate)
 //   prolongation trilinear cell-centred interpolation (weights 3/4, 1/4 per
@@ -71,6 +71,12 @@ constexpr int NU2_COARSE = 1;
 // step, 3.16 -> 3.00 ms of Poisson; one more sweep gave 2.31 cycles and the
 // same time).
 constexpr int NU1_FUSED = 3;
+// Pre-smoothing sweeps on a finest level smoothed by half sweeps (too small
+// for the z-marching sweeps): the 64x64x128 single pore's solve from the
+// quadratic start (residual 1e-2 to 3e-2 there) took 3.71 cycles per step
+// with one, 3.02 with two (Poisson 0.38 -> 0.34 ms per step; three gave 2.80
+// cycles and the same time).
+constexpr int NU1_FINEST = 2;
 // A solve tests its residual from one cycle before the previous solve's count
 // on, unless the previous solve was this far above the tolerance one cycle
 // before its end.
@@ -1179,7 +1185,7 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x, int* norm_blocks) {
                      stream);
       F.x = mg->tmp0;
     } else {
-      for (int s = 0; s < NU1; ++s)
+      for (int s = 0; s < (l == 0 ? NU1_FINEST : NU1); ++s)
         for (int c = 0; c < 2; ++c) {
           if (l > 0 && s == 0 && c == 0) continue;
           hipLaunchKernelGGL(k_smooth, colour_launch(L[l]).grid, colour_launch(L[l]).block, 0,

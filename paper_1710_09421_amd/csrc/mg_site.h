@@ -15,7 +15,10 @@ namespace ek {
 // Pre- and post-smoothing sweeps of the launched multigrid (one launch per
 // half sweep): V(1,2) reaches the tolerance in about the same number of
 // cycles as V(2,2) on the pore systems (4.0-4.2 against 4.0 per step from the
-// previous solution) with a quarter fewer launches per cycle.
+// previous solution) with a quarter fewer launches per cycle.  The finest
+// level takes more pre-smoothing sweeps (NU1_FINEST, NU1_FUSED in
+// kernels_mg.hip): from the extrapolated starts its extra sweeps save whole
+// cycles.
 constexpr int NU1 = 1, NU2 = 2;
 // Relaxation factor of the red-black smoother on every level but the
 // coarsest: over-relaxed red-black Gauss-Seidel smooths the 7-point operator

@@ -363,7 +363,7 @@ ek_status ek_ctx::step_impl(int n_steps) {
     shift_pending = false;
     if (held > 0) psi_hist = std::min(psi_hist + 1, held + 1);
     launch_mean_shift(partials, nb, 1.0 / double(insulating() ? n_fluid : dims.n), inv_eps(), ps,
-                      stream);
+                      stream, partials + nb, partials_cap - nb);
     record(t, 1);
     if (p.warm_start == EK_WS_ZERO) launch_fill(psi, 0.0, dims.n, stream);
     int iters = 0;
@@ -403,7 +403,8 @@ ek_status ek_ctx::step_impl(int n_steps) {
       launch_lb_tail<T>((const T*)fcur(), (T*)fnext(), mask, psi, lp, bt, bead_origin(), n_beads,
                         partials, nb_bulk, nb_lb, dims, stream, npp, wvp);
     }
-    launch_sum_partials(partials, nb_lb, stats_dev, timing ? 1 : 0, stream);
+    launch_sum_partials(partials, nb_lb, stats_dev, timing ? 1 : 0, stream,
+                        partials + 7LL * nb_lb, partials_cap - 7LL * nb_lb);
     cur_is_a = !cur_is_a;
     ++step_count;
   }
@@ -516,6 +517,7 @@ ek_status ek_create(const ek_params* p, int32_t max_beads, void* dev_ws, size_t 
   c->psi = (double*)(ws + L.psi);
   c->b = (double*)(ws + L.b);
   c->partials = (double*)(ws + L.partials);
+  c->partials_cap = (long long)((L.ps - L.partials) / 8);
   c->ps = (PoissonScalars*)(ws + L.ps);
   c->stats_dev = (double*)(ws + L.stats);
   c->keys = (int*)(ws + L.keys);

@@ -39,6 +39,7 @@ struct ek_ctx {
   double* psi = nullptr;
   double* b = nullptr;
   double* partials = nullptr;
+  long long partials_cap = 0;          // doubles in the partials buffer
   ek::PoissonScalars* ps = nullptr;
   double* stats_dev = nullptr;
   int* keys = nullptr;                 // bead-touched node table

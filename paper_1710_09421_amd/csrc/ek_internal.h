@@ -174,11 +174,14 @@ void launch_moments(const T* f, const uint32_t* mask, int species, double nref, 
                     double* u_out, Dims d, hipStream_t s);
 
 // out[0..6] = the seven sums of the fused step's partials; count != 0 also
-// adds out[6] (sites updated) to the running count out[7].
+// adds out[6] (sites updated) to the running count out[7].  With `scratch`
+// (room: the doubles free there) many partials are first folded by a grid of
+// blocks (kernels_sums.hip).
 void launch_sum_partials(const double* partials, int nblocks, double* out, int count,
-                         hipStream_t s);
+                         hipStream_t s, double* scratch = nullptr, long long room = 0);
 void launch_mean_shift(const double* partials, int nblocks, double inv_n, double inv_eps,
-                       PoissonScalars* ps, hipStream_t s);
+                       PoissonScalars* ps, hipStream_t s, double* scratch = nullptr,
+                       long long room = 0);
 
 // Poisson (kernels_poisson.hip)
 void launch_sor_half(double* psi, const double* b, const PoissonScalars* ps, int colour,

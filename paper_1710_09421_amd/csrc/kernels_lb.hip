@@ -142,32 +142,6 @@ __global__ __launch_bounds__(BLOCK) void k_moments(const T* __restrict__ f,
   }
 }
 
-// out[0..6] = sums of the seven components; out[7] += out[6] when `count`
-// (sites updated by the timed launches).
-__global__ __launch_bounds__(1024) void k_sum7(const double* __restrict__ partials, int nblocks,
-                                               double* __restrict__ out, int count) {
-  double t[7];
-  block_sums_1024<7>(partials, nblocks, t);
-  if (threadIdx.x == 0) {
-    for (int c = 0; c < 7; ++c) out[c] = t[c];
-    if (count) out[7] += t[6];
-  }
-}
-
-__global__ __launch_bounds__(1024) void k_mean_shift(const double* __restrict__ partials,
-                                                     int nblocks, double inv_n, double inv_eps,
-                                                     PoissonScalars* ps) {
-  double t[1];
-  block_sums_1024<1>(partials, nblocks, t);
-  if (threadIdx.x == 0) {
-    ps->shift = t[0] * inv_n * inv_eps;
-    ps->done = 0;
-    ps->iters = 0;
-    ps->zero_rhs = 0;
-    ps->cycles = 0;
-  }
-}
-
 }  // namespace
 
 SiteGrid site_grid(int nx, int ny, int nz, int bx_pref) {
@@ -286,17 +260,6 @@ void launch_moments(const T* f, const uint32_t* mask, int species, double nref, 
   const int blocks = int((d.n + BLOCK - 1) / BLOCK);
   hipLaunchKernelGGL(k_moments<T>, dim3(blocks), dim3(BLOCK), 0, s, f, mask, species, nref,
                      n_out, u_out, d);
-}
-
-void launch_sum_partials(const double* partials, int nblocks, double* out, int count,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_sum7, dim3(1), dim3(1024), 0, s, partials, nblocks, out, count);
-}
-
-void launch_mean_shift(const double* partials, int nblocks, double inv_n, double inv_eps,
-                       PoissonScalars* ps, hipStream_t s) {
-  hipLaunchKernelGGL(k_mean_shift, dim3(1), dim3(1024), 0, s, partials, nblocks, inv_n, inv_eps,
-                     ps);
 }
 
 #define EK_INST(T)                                                                          \

@@ -398,10 +398,13 @@ ek_status ek_ctx::step_impl(int n_steps) {
                       timing ? events[6 * t + 3] : nullptr, timing ? events[6 * t + 4] : nullptr,
                       npp, wvp);
     if (overlap) {
-      EK_HIP(hipEventRecord(side_join, side_stream));
-      EK_HIP(hipStreamWaitEvent(stream, side_join, 0));
+      // the box sites after the chain, beside the rest of the lattice update
+      // (disjoint sites and partials); their flags are cleared once both end
       launch_lb_tail<T>((const T*)fcur(), (T*)fnext(), mask, psi, lp, bt, bead_origin(), n_beads,
                         partials, nb_bulk, nb_lb, dims, stream, npp, wvp);
+      EK_HIP(hipEventRecord(side_join, side_stream));
+      EK_HIP(hipStreamWaitEvent(stream, side_join, 0));
+      launch_defer_clear(mask, bead_origin(), n_beads, dims, stream);
     }
     launch_sum_partials(partials, nb_lb, stats_dev, timing ? 1 : 0, stream,
                         partials + 7LL * nb_lb, partials_cap - 7LL * nb_lb);

@@ -163,12 +163,14 @@ int launch_lb_step(const T* fsrc, T* fdst, const uint32_t* mask, const double* p
                    hipEvent_t start = nullptr, hipEvent_t stop = nullptr,
                    const NoiseParams* noise = nullptr, const WallView* walls = nullptr);
 // The sites flagged MASK_DEFER in the boxes of n_beads beads (box origins of
-// the step); partials of blocks first_block .. of the same layout.
+// the step); partials of blocks first_block .. of the same layout.  The flags
+// stay set (launch_defer_clear clears them after the fused step has ended).
 template <typename T>
-void launch_lb_tail(const T* fsrc, T* fdst, uint32_t* mask, const double* psi, const LBParams& lp,
-                    const BeadTableView& bt, const int* origin, int n_beads, double* partials,
-                    int first_block, int nblocks, Dims d, hipStream_t s,
+void launch_lb_tail(const T* fsrc, T* fdst, const uint32_t* mask, const double* psi,
+                    const LBParams& lp, const BeadTableView& bt, const int* origin, int n_beads,
+                    double* partials, int first_block, int nblocks, Dims d, hipStream_t s,
                     const NoiseParams* noise = nullptr, const WallView* walls = nullptr);
+void launch_defer_clear(uint32_t* mask, const int* origin, int n_beads, Dims d, hipStream_t s);
 template <typename T>
 void launch_moments(const T* f, const uint32_t* mask, int species, double nref, double* n_out,
                     double* u_out, Dims d, hipStream_t s);

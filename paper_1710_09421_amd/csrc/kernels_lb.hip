@@ -71,11 +71,14 @@ __global__ __launch_bounds__(BLOCK) void k_lb_step(const T* __restrict__ fsrc,
 // once the chain has spread its friction (component 6, the count of sites
 // the fused kernel updated, gets nothing from here).  Item = (bead i, box node t); a
 // node in several boxes is updated by the lowest bead whose box holds it
-// (the boxes' origins are fixed for the step), which also clears its flag.
-// Needs every side of the box >= BOX (no box overlaps itself).
+// (the boxes' origins are fixed for the step).  It leaves the flags set, so
+// that it can run beside k_lb_step (which skips the flagged sites);
+// k_defer_clear clears them once both have ended.  Needs every side of the
+// box >= BOX (no box overlaps itself).
 template <typename T, typename I, int V>
 __global__ __launch_bounds__(BLOCK) void k_lb_tail(const T* __restrict__ fsrc,
-                                                   T* __restrict__ fdst, uint32_t* mask,
+                                                   T* __restrict__ fdst,
+                                                   const uint32_t* __restrict__ mask,
                                                    const double* __restrict__ psi, LBParams lp,
                                                    BeadTableView bt,
                                                    const int* __restrict__ origin, int n_beads,
@@ -103,10 +106,21 @@ __global__ __launch_bounds__(BLOCK) void k_lb_tail(const T* __restrict__ fsrc,
       const int x = wrap(gx, d.nx), y = wrap(gy, d.ny), z = wrap(gz, d.nz);
       lb_site<T, I, 7, (V & 1) != 0, (V & 2) != 0>(fsrc, fdst, mask, psi, lp, bt, x, y, z, d,
                                                     acc, 0u, &np, &wv);   // not counted in acc[6]
-      atomicAnd(&mask[((long long)z * d.ny + y) * d.nx + x], ~MASK_DEFER);
     }
   }
   block_partials<7>(acc, partials, first_block + blockIdx.x, nblocks);
+}
+
+// Clears MASK_DEFER on every node of the n_beads boxes (item = bead, node).
+__global__ __launch_bounds__(BLOCK) void k_defer_clear(uint32_t* __restrict__ mask,
+                                                       const int* __restrict__ origin,
+                                                       int n_beads, Dims d) {
+  const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= n_beads * BOX3) return;
+  const int i = item / BOX3, t = item % BOX3;
+  const int x = wrap(origin[3 * i] + t % BOX, d.nx), y = wrap(origin[3 * i + 1] + (t / BOX) % BOX, d.ny),
+            z = wrap(origin[3 * i + 2] + t / (BOX * BOX), d.nz);
+  atomicAnd(&mask[((long long)z * d.ny + y) * d.nx + x], ~MASK_DEFER);
 }
 
 template <typename T>
@@ -228,10 +242,10 @@ int launch_lb_step(const T* fsrc, T* fdst, const uint32_t* mask, const double* p
 }
 
 template <typename T>
-void launch_lb_tail(const T* fsrc, T* fdst, uint32_t* mask, const double* psi, const LBParams& lp,
-                    const BeadTableView& bt, const int* origin, int n_beads, double* partials,
-                    int first_block, int nblocks, Dims d, hipStream_t s, const NoiseParams* noise,
-                    const WallView* walls) {
+void launch_lb_tail(const T* fsrc, T* fdst, const uint32_t* mask, const double* psi,
+                    const LBParams& lp, const BeadTableView& bt, const int* origin, int n_beads,
+                    double* partials, int first_block, int nblocks, Dims d, hipStream_t s,
+                    const NoiseParams* noise, const WallView* walls) {
   const int blocks = lb_tail_blocks(n_beads);
   const size_t lds = (size_t)3 * n_beads * sizeof(int);   // at most 12 KiB (MAX_BEADS = 1024)
   const NoiseParams np = noise ? *noise : NoiseParams{};
@@ -262,6 +276,11 @@ void launch_moments(const T* f, const uint32_t* mask, int species, double nref, 
                      n_out, u_out, d);
 }
 
+void launch_defer_clear(uint32_t* mask, const int* origin, int n_beads, Dims d, hipStream_t s) {
+  const int blocks = lb_tail_blocks(n_beads);
+  hipLaunchKernelGGL(k_defer_clear, dim3(blocks), dim3(BLOCK), 0, s, mask, origin, n_beads, d);
+}
+
 #define EK_INST(T)                                                                          \
   template void launch_init_species<T>(T*, const uint32_t*, const double*, int, double, Dims, \
                                        hipStream_t);                                         \
@@ -269,7 +288,7 @@ void launch_moments(const T* f, const uint32_t* mask, int species, double nref, 
                                  const LBParams&, const BeadTableView&, double*, int,        \
                                  uint32_t, Dims, const SiteGrid&, hipStream_t, hipEvent_t,   \
                                  hipEvent_t, const NoiseParams*, const WallView*);           \
-  template void launch_lb_tail<T>(const T*, T*, uint32_t*, const double*, const LBParams&,   \
+  template void launch_lb_tail<T>(const T*, T*, const uint32_t*, const double*, const LBParams&,\
                                   const BeadTableView&, const int*, int, double*, int, int,  \
                                   Dims, hipStream_t, const NoiseParams*, const WallView*);   \
   template void launch_moments<T>(const T*, const uint32_t*, int, double, double*, double*,  \

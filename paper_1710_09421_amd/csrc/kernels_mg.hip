@@ -413,7 +413,10 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_z(Lvl L, const double* 
 // planes (their heights differ by at most two).  nz even, 1 <= nch <= nz / 2;
 // TX, TY multiples of 4.
 enum : int { SWEEP_RESTRICT = 1, SWEEP_NORMS = 2 };
-constexpr int ZR_THREADS = 256;
+// Tile of the fused sweeps (64 x ZR_TY) and their workgroup size (a thread
+// pair per 2 x 2 block of the tile).
+constexpr int ZR_TY = 8;
+constexpr int ZR_THREADS = ZR_TY * 32;
 
 template <int TX, int TY>
 struct SweepRRegs {
@@ -1011,15 +1014,16 @@ void ek_ctx::mg_setup() {
       mg->sweep_nch[l] = sweep_chunks((long long)(L.nx / tx) * (L.ny / ty), L.nz, 1, 2, slots,
                                       mg->sweep_nch[l]);
     }
-    mg->fused0 = fc > 1 && mg->sweep_tx[0] == 64 && mg->sweep_ty[0] == 8;
+    mg->fused0 = fc > 1 && mg->sweep_tx[0] == 64 && mg->sweep_ty[0] == 8 &&
+                 mg->levels[0].ny % ZR_TY == 0;
     if (mg->fused0) {
       // chunks of whole 2 x 2 x 2 blocks, h + 5 steps each, as many
       // workgroups at once as both variants hold
       const Lvl& L = mg->levels[0];
       const long long slots =
-          std::min(resident_workgroups(k_sweep_zr<64, 8, SWEEP_RESTRICT>, ZR_THREADS),
-                   resident_workgroups(k_sweep_zr<64, 8, SWEEP_NORMS>, ZR_THREADS));
-      mg->zr_chunks = sweep_chunks((long long)(L.nx / 64) * (L.ny / 8), L.nz, 2, 5, slots,
+          std::min(resident_workgroups(k_sweep_zr<64, ZR_TY, SWEEP_RESTRICT>, ZR_THREADS),
+                   resident_workgroups(k_sweep_zr<64, ZR_TY, SWEEP_NORMS>, ZR_THREADS));
+      mg->zr_chunks = sweep_chunks((long long)(L.nx / 64) * (L.ny / ZR_TY), L.nz, 2, 5, slots,
                                    std::max(1, mg->sweep_nch[0] / 2));
     }
   }
@@ -1130,12 +1134,12 @@ static void launch_sweep_z_corrected(const Lvl& L, const Lvl& C, int nch, const 
 static int launch_sweep_zr(const Lvl& L, int nch, const double* xin, double* xout,
                            const PoissonScalars* ps, int mode, const Lvl& C, double omega_red,
                            double* partials, hipStream_t s) {
-  const int nblocks = (L.nx / 64) * (L.ny / 8) * nch;
+  const int nblocks = (L.nx / 64) * (L.ny / ZR_TY) * nch;
   if (mode == SWEEP_RESTRICT)
-    hipLaunchKernelGGL((k_sweep_zr<64, 8, SWEEP_RESTRICT>), dim3(nblocks), dim3(ZR_THREADS), 0,
+    hipLaunchKernelGGL((k_sweep_zr<64, ZR_TY, SWEEP_RESTRICT>), dim3(nblocks), dim3(ZR_THREADS), 0,
                        s, L, xin, xout, nch, ps, 1, MG_OMEGA, C, omega_red, partials);
   else
-    hipLaunchKernelGGL((k_sweep_zr<64, 8, SWEEP_NORMS>), dim3(nblocks), dim3(ZR_THREADS), 0, s,
+    hipLaunchKernelGGL((k_sweep_zr<64, ZR_TY, SWEEP_NORMS>), dim3(nblocks), dim3(ZR_THREADS), 0, s,
                        L, xin, xout, nch, ps, 1, MG_OMEGA, C, 0.0, partials);
   return nblocks;
 }

@@ -28,6 +28,8 @@ The JSON line also carries:
                 potential of every updated site); `traffic` is the HBM bytes
                 per launch from the committed counter passes at this
                 workload, or null when the kernel changed since;
+                `copy_kernel` the bandwidth a plain 2 GiB device-to-device
+                copy reaches in the same process (the practical peak);
   cpu_baseline  the float64 oracle timed on the host, one thread, on a
                 bounded sample of the same workload: a 64 x 64 x 128
                 periodic window around the pore with the chain inside it,
@@ -78,6 +80,27 @@ def measured_traffic(workload_name, precision):
                 and r.get("kernel_source_sha256") == lb_source_hash()):
             return r["hbm_bytes_per_launch"]
     return None
+
+
+def copy_bandwidth(gib=2.0, reps=5):
+    """Read + write bandwidth of a plain device-to-device copy of `gib` GiB
+    (torch copy_, far beyond the 256 MB Infinity Cache): the practical peak a
+    streaming kernel meets on this machine, reported beside the published one."""
+    import torch
+    n = int(gib * 2 ** 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / reps
+    del src, dst
+    return round(2 * 4 * n / (ms * 1e-3) / 1e9, 1)
 
 
 def build_workload(name):
@@ -377,6 +400,12 @@ def main():
     }
     if "roofline" in main_leg:
         line["roofline"] = main_leg["roofline"]
+        if wl is not None:
+            cb = copy_bandwidth()
+            line["roofline"]["copy_kernel"] = {
+                "what": "device-to-device copy of 2 GiB (torch copy_), bytes read + written",
+                "achieved": cb, "unit": "GB/s",
+                "frac_of_copy": round(line["roofline"]["achieved"] / cb, 4)}
     if args.copy_probe_gib > 0:
         import torch
         n = int(args.copy_probe_gib * 2 ** 30) // 4

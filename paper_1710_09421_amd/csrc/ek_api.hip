@@ -287,7 +287,9 @@ ek_status ek_ctx::poisson(const double* bb, double* x, bool learned, int& iters,
   if (!learned && p.poisson_method == EK_POISSON_MG) {
     // the start's residual stays on the device (the cycles test its flag and
     // skip themselves once converged); the host reads it with the first
-    // batch's result
+    // batch's result.  Where the finest level's first sweep can take it, the
+    // first cycle does (no pass of its own)
+    if (mg_start_in_cycle()) return mg_solve(bb, x, h, iters, res, res0, true);
     const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
     const int nr = launch_residual(x, bb, ps, partials, dims, g, stream);
     launch_residual_final(partials, nr, p.poisson_tol, 0, 1, ps, stream);

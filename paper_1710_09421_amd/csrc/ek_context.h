@@ -117,8 +117,11 @@ struct ek_ctx {
   // already evaluated.
   ek_status sor_solve(const double* b, double* x, ek::PoissonScalars h, int& iters, double& res,
                       double& res0);
+  // With start_norms the start's residual has not been evaluated: the first
+  // cycle does it (mg_start_in_cycle), before anything else of the cycle.
   ek_status mg_solve(const double* b, double* x, ek::PoissonScalars h, int& iters, double& res,
-                     double& res0);
+                     double& res0, bool start_norms = false);
+  bool mg_start_in_cycle() const;
   ek_status initial_residual(const double* b, const double* x, ek::PoissonScalars* h);
   // residual kernel of the context's problem (periodic or insulating walls);
   // returns the number of block partials
@@ -131,7 +134,9 @@ struct ek_ctx {
   // One V-cycle; with norm_blocks given, its last finest-level sweep also
   // leaves the residual norms' block partials where the finest level allows
   // it (*norm_blocks = their count, else 0: the caller takes the residual).
-  ek_status mg_vcycle(const double* b, double* x, int* norm_blocks = nullptr);
+  // With start (mg_start_in_cycle) its first sweep also takes the residual
+  // of its input, and the start's test follows it.
+  ek_status mg_vcycle(const double* b, double* x, int* norm_blocks = nullptr, bool start = false);
   bool mg_graphs(const double* b, double* x);
   ek_status poisson(const double* b, double* x, bool learned, int& iters, double& res,
                     double& res0);

@@ -165,10 +165,17 @@ __global__ __launch_bounds__(256) void k_prolong_to(Lvl F, Lvl C, const double* 
 // phase ahead), and each site then takes its four values of Ez along y and
 // x.  The separate prolongation pass (read xin, write xin + P e: 16 bytes
 // per site) is saved; xin stays unchanged.
+// With NIN the sweep also takes the residual norms of its input (the start of
+// a solve, in its first cycle's first sweep): at step k, plane k+1 is still
+// unswept in LDS, and each thread keeps the unswept values of its own region
+// sites of planes k and k+1 in registers (plane k is being swept in LDS), so
+// r = (f + shift) - A xin on the tile of plane k+1 needs only one more load,
+// f at those sites; block partials of r^2, (f + shift)^2 and xin as
+// k_residual's.
 constexpr int SWEEP_THREADS = 256;
 constexpr int SWEEP_SLOTS = 5;
 
-template <int TX, int TY, bool CORR = false>
+template <int TX, int TY, bool CORR = false, bool NIN = false>
 struct SweepRegs {
   static constexpr int REGION = (TX + 4) * (TY + 4);
   static constexpr int XPT = (REGION + SWEEP_THREADS - 1) / SWEEP_THREADS;
@@ -186,15 +193,18 @@ struct SweepRegs {
   double fb[BPT];   // f at this thread's colour-1 tile sites of a plane
   double c0[CPT];   // CORR: the coarse window of the plane's own coarse plane
   double c1[CPT];   //       and of the one above or below it
+  double ff[NIN ? XPT : 1];   // NIN: f at this thread's region sites of a plane
 };
 
-template <int TX, int TY, bool CORR = false>
+template <int TX, int TY, bool CORR = false, bool NIN = false>
 __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_z(Lvl L, const double* __restrict__ xin,
                                                            double* __restrict__ xout, int nch,
                                                            const PoissonScalars* ps, int level0,
-                                                           double omega, Lvl C) {
+                                                           double omega, Lvl C,
+                                                           double* __restrict__ partials) {
   static_assert(TX % 2 == 0 && TY % 2 == 0, "even tiles");
-  using R = SweepRegs<TX, TY, CORR>;
+  static_assert(!(CORR && NIN), "the input norms belong to a pre-smoothing sweep");
+  using R = SweepRegs<TX, TY, CORR, NIN>;
   constexpr int RX = TX + 4, RY = TY + 4;
   __shared__ double P[SWEEP_SLOTS][RY][RX];
   __shared__ double Ez[CORR ? R::CW : 1];
@@ -318,15 +328,32 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_z(Lvl L, const double* 
       r[u] = f[base + (long long)(y0 + jj) * nx + x0 + 2 * m + (black_first(jj, m, k) ? 0 : 1)];
     }
   };
+  // (NIN) f at this thread's region sites of plane q, and the unswept
+  // values of those sites in planes k and k+1 (xm2, xm1) at step k
+  auto gather_ff = [&](int q, R& r) {
+    if constexpr (NIN) {
+      const long long base = plane_base(q);
+#pragma unroll
+      for (int u = 0; u < R::XPT; ++u) {
+        const int t = min(tid + u * SWEEP_THREADS, R::REGION - 1);
+        const int j = t / RX, i = t - j * RX;
+        r.ff[u] = f[base + (long long)wrapi(y0 - 2 + j, ny) * nx + wrapi(x0 - 2 + i, nx)];
+      }
+    }
+  };
+  double xm1[NIN ? R::XPT : 1], xm2[NIN ? R::XPT : 1];
+  double acc[3] = {0.0, 0.0, 0.0};
   // Step k.  cur holds the iterate plane k+2 (stored at the end; with CORR its
-  // coarse window, combined into Ez in the first phase), f of the colour-0
-  // sites of plane k and of the colour-1 sites of plane k-1; nxt receives
-  // plane k+3 (and its coarse window) and f of planes k+1 (colour 0) and k
-  // (colour 1).
+  // coarse window, combined into Ez in the first phase; with NIN f of plane
+  // k+1 at the thread's region sites), f of the colour-0 sites of plane k and
+  // of the colour-1 sites of plane k-1; nxt receives plane k+3 (and its
+  // coarse window, or f of plane k+2 at the region sites) and f of planes
+  // k+1 (colour 0) and k (colour 1).
   auto step = [&](int k, R& cur, R& nxt) {
     // (near the chunk's end the planes are clamped: loaded, never used)
     gather_x(min(k + 3, z1 + 1), nxt.x);
     gather_c(min(k + 3, z1 + 1), nxt);
+    gather_ff(min(k + 2, z1), nxt);
     gather_fr(min(k + 1, z1), nxt.fr);
     gather_fb(max(min(k, z1 - 1), z0), nxt.fb);
     if (k + 2 <= z1 + 1) write_ez(cur);
@@ -369,6 +396,33 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_z(Lvl L, const double* 
         }
       }
     }
+    if constexpr (NIN) {
+      // residual of the unswept plane k+1 on the tile (its slot is not
+      // written during step k)
+      if (k + 1 >= z0 && k + 1 < z1) {
+        const int s1 = slot(k + 1);
+        const double ih2 = 1.0 / h2;
+#pragma unroll
+        for (int u = 0; u < R::XPT; ++u) {
+          const int t = tid + u * SWEEP_THREADS;
+          const int j = t / RX, i = t - j * RX;
+          if (t < R::REGION && j >= 2 && j < TY + 2 && i >= 2 && i < TX + 2) {
+            const double nb = P[s1][j][i - 1] + P[s1][j][i + 1] + P[s1][j - 1][i] +
+                              P[s1][j + 1][i] + xm2[u] + cur.x[u];
+            const double rhs = cur.ff[u] + shift;
+            const double res = rhs - (nb - 6.0 * xm1[u]) * ih2;
+            acc[0] += res * res;
+            acc[1] += rhs * rhs;
+            acc[2] += xm1[u];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < R::XPT; ++u) {
+        xm2[u] = xm1[u];
+        xm1[u] = cur.x[u];
+      }
+    }
     if (k + 2 <= z1 + 1) store_x(slot(k + 2), cur.x);
     __syncthreads();
   };
@@ -382,9 +436,17 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_z(Lvl L, const double* 
     }
     store_x(slot(q), A.x);
     if constexpr (CORR) __syncthreads();
+    if constexpr (NIN) {
+#pragma unroll
+      for (int u = 0; u < R::XPT; ++u) {
+        xm2[u] = xm1[u];
+        xm1[u] = A.x[u];
+      }
+    }
   }
   gather_x(z0 + 1, A.x);
   gather_c(z0 + 1, A);
+  gather_ff(z0, A);
   gather_fr(z0 - 1, A.fr);
   __syncthreads();
   int k = z0 - 1;
@@ -393,6 +455,7 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_sweep_z(Lvl L, const double* 
     step(k + 1, B, A);
   }
   if (k <= z1) step(k, A, B);
+  if constexpr (NIN) block_partials<3>(acc, partials, blockIdx.x, gridDim.x);
 }
 
 // --- a full sweep that also takes the residual of its result ---------------
@@ -770,6 +833,7 @@ struct ek_ctx::MG {
   // tile, zr_chunks chunks of an even number of planes)
   bool fused0 = false;
   int zr_chunks = 0;
+  int start_chunks = 0;     // chunks of the first sweep that also takes the start's residual
   // One V-cycle, and one V-cycle followed by the residual test, recorded as
   // graphs for the level-0 pair (b, x) they were recorded with: a replay
   // dispatches the cycle's ~30 dependent launches faster than the launches
@@ -778,6 +842,8 @@ struct ek_ctx::MG {
   // replayed on the context's stream.
   hipStream_t record_stream = nullptr;
   hipGraphExec_t cycle = nullptr, cycle_test = nullptr;
+  // the first cycle of a solve, which also evaluates its start (fused0 only)
+  hipGraphExec_t cycle_first = nullptr, cycle_first_test = nullptr;
   const double* graph_b = nullptr;
   double* graph_x = nullptr;
   bool graph_failed = false;   // recording is not possible: launch one by one
@@ -785,7 +851,9 @@ struct ek_ctx::MG {
   void drop_graphs() {
     if (cycle) (void)hipGraphExecDestroy(cycle);
     if (cycle_test) (void)hipGraphExecDestroy(cycle_test);
-    cycle = cycle_test = nullptr;
+    if (cycle_first) (void)hipGraphExecDestroy(cycle_first);
+    if (cycle_first_test) (void)hipGraphExecDestroy(cycle_first_test);
+    cycle = cycle_test = cycle_first = cycle_first_test = nullptr;
     graph_b = nullptr;
     graph_x = nullptr;
   }
@@ -1025,6 +1093,9 @@ void ek_ctx::mg_setup() {
                    resident_workgroups(k_sweep_zr<64, ZR_TY, SWEEP_NORMS>, ZR_THREADS));
       mg->zr_chunks = sweep_chunks((long long)(L.nx / 64) * (L.ny / ZR_TY), L.nz, 2, 5, slots,
                                    std::max(1, mg->sweep_nch[0] / 2));
+      mg->start_chunks = sweep_chunks((long long)(L.nx / 64) * (L.ny / 8), L.nz, 1, 2,
+                                      resident_workgroups(k_sweep_z<64, 8, false, true>),
+                                      mg->sweep_nch[0]);
     }
   }
   mg->omega_coarsest = omega_opt(c.nx, c.ny, c.nz);
@@ -1091,7 +1162,15 @@ bool ek_ctx::mg_graphs(const double* bb, double* x) {
         const int nr = nb ? nb : launch_residual(x, bb, ps, partials, dims, g, stream);
         // iteration -1: the test reads the cycle count the coarse kernel keeps
         launch_residual_final(partials, nr, p.poisson_tol, -1, 0, ps, stream);
-      });
+      }) &&
+      (!mg_start_in_cycle() ||
+       (record_graph(stream, &m.cycle_first, [&] { mg_vcycle(bb, x, nullptr, true); }) &&
+        record_graph(stream, &m.cycle_first_test, [&] {
+          int nb = 0;
+          mg_vcycle(bb, x, &nb, true);
+          const int nr = nb ? nb : launch_residual(x, bb, ps, partials, dims, g, stream);
+          launch_residual_final(partials, nr, p.poisson_tol, -1, 0, ps, stream);
+        })));
   stream = own;
   if (!ok) {
     m.drop_graphs();
@@ -1109,13 +1188,23 @@ static void launch_sweep_z(const Lvl& L, int tx, int ty, int nch, const double* 
   const dim3 grid((unsigned)((L.nx / tx) * (L.ny / ty) * nch));
   if (tx == 64 && ty == 16)
     hipLaunchKernelGGL((k_sweep_z<64, 16>), grid, dim3(SWEEP_THREADS), 0, s, L, xin, xout, nch, ps,
-                       level0, MG_OMEGA, L);
+                       level0, MG_OMEGA, L, nullptr);
   else if (tx == 64)
     hipLaunchKernelGGL((k_sweep_z<64, 8>), grid, dim3(SWEEP_THREADS), 0, s, L, xin, xout, nch, ps,
-                       level0, MG_OMEGA, L);
+                       level0, MG_OMEGA, L, nullptr);
   else
     hipLaunchKernelGGL((k_sweep_z<32, 8>), grid, dim3(SWEEP_THREADS), 0, s, L, xin, xout, nch, ps,
-                       level0, MG_OMEGA, L);
+                       level0, MG_OMEGA, L, nullptr);
+}
+
+// The finest level's first pre-smoothing sweep of a solve (64 x 8 tiles) with
+// the residual norms of its input in `partials`; returns the block count.
+static int launch_sweep_z_start(const Lvl& L, int nch, const double* xin, double* xout,
+                                const PoissonScalars* ps, double* partials, hipStream_t s) {
+  const int nblocks = (L.nx / 64) * (L.ny / 8) * nch;
+  hipLaunchKernelGGL((k_sweep_z<64, 8, false, true>), dim3(nblocks), dim3(SWEEP_THREADS), 0, s, L,
+                     xin, xout, nch, ps, 1, MG_OMEGA, L, partials);
+  return nblocks;
 }
 
 // A first post-smoothing sweep with the correction from level C on the way
@@ -1125,7 +1214,7 @@ static void launch_sweep_z_corrected(const Lvl& L, const Lvl& C, int nch, const 
                                      hipStream_t s) {
   const dim3 grid((unsigned)((L.nx / 64) * (L.ny / 8) * nch));
   hipLaunchKernelGGL((k_sweep_z<64, 8, true>), grid, dim3(SWEEP_THREADS), 0, s, L, xin, xout, nch,
-                     ps, level0, MG_OMEGA, C);
+                     ps, level0, MG_OMEGA, C, nullptr);
 }
 
 // The finest level's full sweep with the residual of its result (restriction
@@ -1144,7 +1233,9 @@ static int launch_sweep_zr(const Lvl& L, int nch, const double* xin, double* xou
   return nblocks;
 }
 
-ek_status ek_ctx::mg_vcycle(const double* bb, double* x, int* norm_blocks) {
+bool ek_ctx::mg_start_in_cycle() const { return mg && mg->fused0 && NU1_FUSED >= 2; }
+
+ek_status ek_ctx::mg_vcycle(const double* bb, double* x, int* norm_blocks, bool start) {
   if (norm_blocks) *norm_blocks = 0;
   std::vector<Lvl>& L = mg->levels;
   L[0].x = x;
@@ -1177,7 +1268,12 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x, int* norm_blocks) {
       double* a = x;
       double* b = mg->tmp0;
       for (int s = 0; s + 1 < NU1_FUSED; ++s) {
-        launch_sweep_z(L[0], 64, 8, mg->sweep_nch[0], a, b, ps, 1, stream);
+        if (s == 0 && start) {   // the start's residual, then its test
+          const int nb = launch_sweep_z_start(L[0], mg->start_chunks, a, b, ps, partials, stream);
+          launch_residual_final(partials, nb, p.poisson_tol, 0, 1, ps, stream);
+        } else {
+          launch_sweep_z(L[0], 64, 8, mg->sweep_nch[0], a, b, ps, 1, stream);
+        }
         std::swap(a, b);
       }
       launch_sweep_zr(L[0], mg->zr_chunks, a, b, ps, SWEEP_RESTRICT, L[1], omega_red, nullptr,
@@ -1281,7 +1377,7 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x, int* norm_blocks) {
 // cycles are enqueued ahead of the test in batches and skip themselves once
 // the device-side flag is set.
 ek_status ek_ctx::mg_solve(const double* bb, double* x, PoissonScalars h, int& iters, double& res,
-                          double& res0) {
+                          double& res0, bool start_norms) {
   const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
   ek_status st = EK_OK;
   int it = 0;
@@ -1304,13 +1400,16 @@ ek_status ek_ctx::mg_solve(const double* bb, double* x, PoissonScalars h, int& i
     for (int k = 0; k < nrun; ++k) {
       ++it;
       const bool test = k >= untested || it >= p.poisson_max_iter;
+      const bool first = start_norms && it == 1;   // the cycle also evaluates the start
       if (graphs) {
-        const hipError_t e = hipGraphLaunch(test ? mg->cycle_test : mg->cycle, stream);
+        hipGraphExec_t ge = first ? (test ? mg->cycle_first_test : mg->cycle_first)
+                                  : (test ? mg->cycle_test : mg->cycle);
+        const hipError_t e = hipGraphLaunch(ge, stream);
         if (e != hipSuccess) return fail(EK_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
         continue;
       }
       int nb = 0;
-      st = mg_vcycle(bb, x, test ? &nb : nullptr);
+      st = mg_vcycle(bb, x, test ? &nb : nullptr, first);
       if (st) return st;
       if (!test) continue;
       const int nr = nb ? nb : launch_residual(x, bb, ps, partials, dims, g, stream);

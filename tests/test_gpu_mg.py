@@ -85,6 +85,36 @@ def fft_solution(b):
     return np.real(np.fft.ifftn(bh / lam))
 
 
+def test_start_residual_taken_in_the_first_cycle(ek):
+    """A 128^3 box, whose finest level sweeps marching up z take the start's
+    residual inside the first cycle: the initial residual reported for a
+    rough start is the host's residual of that start, and a start that
+    already meets the tolerance (the exact solution plus a constant) leaves
+    the solve at zero cycles with that start, its mean removed."""
+    shape = (128, 128, 128)
+    rng = np.random.default_rng(9)
+    rho = rng.normal(size=shape) * 0.01
+    p = ek.make_params(shape, precision=ek.EK_FP64, poisson_method=ek.EK_POISSON_MG,
+                       poisson_tol=1e-8, poisson_max_iter=400)
+    ctx = ek.Context(p)
+    b = opoisson.rhs_from_charge(rho, EPS)
+    rt = torch.tensor(rho, dtype=torch.float64, device="cuda")
+    start = rng.normal(size=shape) * 0.05
+    pt = torch.tensor(start, dtype=torch.float64, device="cuda")
+    rep = ctx.poisson_solve(rt, pt, ek.EK_WS_PREV)
+    want = opoisson.relative_residual(start, b)
+    print(rep, want)
+    assert rep["initial_residual"] == pytest.approx(want, rel=1e-10)
+    assert opoisson.relative_residual(pt.cpu().numpy(), b) <= 1e-8
+    exact = fft_solution(b) + 0.25
+    pt = torch.tensor(exact, dtype=torch.float64, device="cuda")
+    rep = ctx.poisson_solve(rt, pt, ek.EK_WS_PREV)
+    print(rep)
+    assert rep["iterations"] == 0
+    assert rep["initial_residual"] <= 1e-8
+    assert np.abs(pt.cpu().numpy() - (exact - exact.mean())).max() < 1e-12
+
+
 @pytest.mark.parametrize("shape", [(36, 36, 36), (44, 44, 44)])
 def test_multigrid_with_a_large_coarsest_level(ek, shape):
     """Boxes whose sides stop halving early: the coarsest level of 36^3 is

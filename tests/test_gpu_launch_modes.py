@@ -72,6 +72,26 @@ def test_replayed_cycles_match_single_launches(ek, size):
         _same_state(g, e, nbd)
 
 
+def test_fused_finest_level_replays_match_single_launches(ek):
+    """A 128 x 128 x 256 pore, whose finest level runs the sweeps marching up
+    z on 64 x 8 tiles (32 tiles x 32 chunks) with the fused restriction,
+    correction and norms, and takes the start's residual in the first cycle:
+    the first-cycle and later-cycle graphs give the same bits, cycle counts
+    and initial residuals as the same launches one by one."""
+    wl = workloads.pore_system((256, 128, 128), 12, 8, 0.01, 0.01, -0.01, 8, 34, steps=4)
+    g, e = _pair(ek, wl)
+    for t in range(4):
+        g.step(1)
+        e.step(1)
+        sg, se = g.stats(), e.stats()
+        print(t, sg["poisson_iters"], sg["poisson_residual0"], sg["poisson_residual"])
+        assert sg["poisson_iters"] == se["poisson_iters"] >= 1
+        assert sg["poisson_residual0"] == se["poisson_residual0"]
+        assert sg["poisson_residual"] == se["poisson_residual"] <= 1e-8
+        assert np.array_equal(sg["mass"], se["mass"])
+        _same_state(g, e, 8)
+
+
 def test_replay_follows_the_psi_buffer(ek):
     """Stand-alone solves into caller buffers between steps: the graphs are
     recorded again for each buffer and the iteration counts kept on the

@@ -86,12 +86,13 @@ def fft_solution(b):
 
 
 def test_start_residual_taken_in_the_first_cycle(ek):
-    """A 128^3 box, whose finest level sweeps marching up z take the start's
-    residual inside the first cycle: the initial residual reported for a
-    rough start is the host's residual of that start, and a start that
-    already meets the tolerance (the exact solution plus a constant) leaves
-    the solve at zero cycles with that start, its mean removed."""
-    shape = (128, 128, 128)
+    """A 128 x 128 x 256 box, whose finest level sweeps marching up z on
+    64 x 8 tiles take the start's residual inside the first cycle: the
+    initial residual reported for a rough start is the host's residual of
+    that start, and a start that already meets the tolerance (the exact
+    solution plus a constant) leaves the solve at zero cycles with that
+    start, its mean removed."""
+    shape = (256, 128, 128)
     rng = np.random.default_rng(9)
     rho = rng.normal(size=shape) * 0.01
     p = ek.make_params(shape, precision=ek.EK_FP64, poisson_method=ek.EK_POISSON_MG,

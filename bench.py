@@ -184,7 +184,7 @@ def learned_comparison():
     sim = learned.simulate(params, scale, steps=100, warmup=10, log=lambda s: None)
     progress(f"learned start in the time loop: {json.dumps(sim)}")
     r = lambda x: round(x, 4)
-    out = {"tolerance": 1e-8, "finisher": "red-black multigrid (V(2,2) on the finest level)",
+    out = {"tolerance": 1e-8, "finisher": "red-black multigrid (V(4,2) on the finest level)",
            "model": f"{info['n_traj'] * info['per_traj']} pairs, {info['epochs']} epochs"}
     for k, v in summary.items():
         out[k] = {"solves": v["n"], "cycles": r(v["cycles"]), "ms": r(v["ms"]),

@@ -8,8 +8,9 @@
 //   smoother   red-black Gauss-Seidel (x = (sum nb - h^2 f) / 6) over-relaxed
 //              by MG_OMEGA, nu1 = NU1 = 1 and nu2 = NU2 = 2 (NU1_FUSED
 //              on a finest level whose last pre-smoothing sweep restricts,
-//              NU1_FINEST on a finest level of half sweeps, NU2_COARSE = 1
-//              on the levels of the one-workgroup coarse kernel)
+//              NU1_FINEST on a finest level without z-marching sweeps,
+//              NU2_COARSE = 1 on the levels of the one-workgroup coarse
+//              kernel)
 //   restriction  f_{l+1} = average of the 8 fine residuals (fused with the
 //                residual, also zeroes the coarse iterate)
 //   prolongation trilinear cell-centred interpolation (weights 3/4, 1/4 per
@@ -71,12 +72,13 @@ constexpr int NU2_COARSE = 1;
 // step, 3.16 -> 3.00 ms of Poisson; one more sweep gave 2.31 cycles and the
 // same time).
 constexpr int NU1_FUSED = 3;
-// Pre-smoothing sweeps on a finest level smoothed by half sweeps (too small
-// for the z-marching sweeps): the 64x64x128 single pore's solve from the
-// quadratic start (residual 1e-2 to 3e-2 there) took 3.71 cycles per step
-// with one, 3.02 with two (Poisson 0.38 -> 0.34 ms per step; three gave 2.80
-// cycles and the same time).
-constexpr int NU1_FINEST = 2;
+// Pre-smoothing sweeps on a finest level too small for the z-marching sweeps
+// (one launch per full sweep on BOX^3 tiles): the 64x64x128 single pore's
+// solve from the cubic start took 3.17 cycles per step with two, 2.64 with
+// four, at 0.313 and 0.307 ms of Poisson per step (with half sweeps, from
+// the quadratic start: 3.71 cycles with one, 3.02 with two, 0.38 -> 0.34 ms;
+// three gave 2.80 cycles and the same time).
+constexpr int NU1_FINEST = 4;
 // A solve tests its residual from one cycle before the previous solve's count
 // on, unless the previous solve was this far above the tolerance one cycle
 // before its end.
@@ -131,6 +133,286 @@ __global__ __launch_bounds__(256) void k_prolong_to(Lvl F, Lvl C, const double* 
   const int Y = blockIdx.y * blockDim.y + threadIdx.y;
   if (X >= C.nx || Y >= C.ny) return;
   prolong_cell(F, C, X, Y, blockIdx.z, src, dst);
+}
+
+// --- one full red-black sweep per launch on BOX^3 tiles (small levels) --------
+// xout = (colour-0 half sweep, then colour-1 half sweep)(xin), out of place,
+// for levels too small for the z-marching sweeps below, whose every launch
+// costs about the same few microseconds whatever its size: one launch per
+// sweep instead of two.  A workgroup loads its BOX^3 tile of xin with a
+// two-site ring, and the right-hand side with a one-site ring, into LDS,
+// relaxes the colour-0 sites of the tile and of a one-site ring around it
+// (the ring's sites are relaxed again by the neighbouring workgroups, from
+// the same old values in the same order), then the colour-1 sites of the
+// tile, and writes the tile.  The formula and summation order are those of
+// smooth_site.  With CORR the sweep is the first post-smoothing sweep of a
+// cycle: every loaded iterate value first gets the trilinear coarse-grid
+// correction of level C (prolong_value's weights and order, from a coarse
+// window in LDS), so the launch is a prolongation followed by the sweep.
+// With NIN it also takes the residual norms of its input (the start of a
+// solve, in the first cycle's first sweep) at the tile's sites, from the
+// windows before the sweep: block partials of r^2, (f + shift)^2 and xin as
+// k_residual's.  BOX divides nx, ny and nz.
+constexpr int BOX = 8;
+constexpr int BOX_X = BOX + 4;        // iterate window side (two-site ring)
+constexpr int BOX_F = BOX + 2;        // right-hand side window side
+constexpr int BOX_C = BOX / 2 + 4;    // coarse window side
+constexpr int BOX_THREADS = 256;
+
+__device__ inline int wrap_index(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+template <bool CORR, bool NIN = false>
+__global__ __launch_bounds__(BOX_THREADS) void k_sweep_box(Lvl L, const double* __restrict__ xin,
+                                                           double* __restrict__ xout,
+                                                           const PoissonScalars* ps, int level0,
+                                                           double omega, Lvl C,
+                                                           double* __restrict__ partials) {
+  static_assert(!(CORR && NIN), "the input norms belong to a pre-smoothing sweep");
+  __shared__ double sx[BOX_X * BOX_X * BOX_X];
+  __shared__ double sf[BOX_F * BOX_F * BOX_F];
+  __shared__ double sc[CORR ? BOX_C * BOX_C * BOX_C : 1];
+  const int tiles_x = L.nx / BOX, tiles_y = L.ny / BOX;
+  const int b = blockIdx.x;
+  const int bxy = b % (tiles_x * tiles_y);
+  const int x0 = (bxy % tiles_x) * BOX, y0 = (bxy / tiles_x) * BOX;
+  const int z0 = (b / (tiles_x * tiles_y)) * BOX;
+  // window coordinate i of a side starts at x0 - 2 (iterate), x0 - 1
+  // (right-hand side) and x0 / 2 - 2 (coarse).  Every load of the windows is
+  // issued before the first of them is stored (branch-free: a thread past a
+  // window's end reloads its last site and stores nothing), so the
+  // workgroup waits for memory once; the test of a finished solve is taken
+  // after the loads are on their way.
+  constexpr int NX = BOX_X * BOX_X * BOX_X, NF = BOX_F * BOX_F * BOX_F;
+  constexpr int NC = CORR ? BOX_C * BOX_C * BOX_C : 1;
+  constexpr int PX = (NX + BOX_THREADS - 1) / BOX_THREADS, PF = (NF + BOX_THREADS - 1) / BOX_THREADS;
+  constexpr int PC = (NC + BOX_THREADS - 1) / BOX_THREADS;
+  double vx[PX], vf[PF], vc[PC];
+#pragma unroll
+  for (int q = 0; q < PX; ++q) {
+    const int t = min((int)threadIdx.x + q * BOX_THREADS, NX - 1);
+    const int i = t % BOX_X, j = (t / BOX_X) % BOX_X, k = t / (BOX_X * BOX_X);
+    vx[q] = xin[idx3(wrap_index(x0 - 2 + i, L.nx), wrap_index(y0 - 2 + j, L.ny),
+                     wrap_index(z0 - 2 + k, L.nz), L)];
+  }
+#pragma unroll
+  for (int q = 0; q < PF; ++q) {
+    const int t = min((int)threadIdx.x + q * BOX_THREADS, NF - 1);
+    const int i = t % BOX_F, j = (t / BOX_F) % BOX_F, k = t / (BOX_F * BOX_F);
+    vf[q] = L.f[idx3(wrap_index(x0 - 1 + i, L.nx), wrap_index(y0 - 1 + j, L.ny),
+                     wrap_index(z0 - 1 + k, L.nz), L)];
+  }
+  if (CORR) {
+    const int X0 = x0 / 2 - 2, Y0 = y0 / 2 - 2, Z0 = z0 / 2 - 2;
+#pragma unroll
+    for (int q = 0; q < PC; ++q) {
+      const int t = min((int)threadIdx.x + q * BOX_THREADS, NC - 1);
+      const int i = t % BOX_C, j = (t / BOX_C) % BOX_C, k = t / (BOX_C * BOX_C);
+      vc[q] = C.x[idx3(wrap_index(X0 + i, C.nx), wrap_index(Y0 + j, C.ny),
+                       wrap_index(Z0 + k, C.nz), C)];
+    }
+  }
+  if (ps->done) return;
+  const double shift = level0 ? ps->shift : 0.0;
+#pragma unroll
+  for (int q = 0; q < PX; ++q) {
+    const int t = (int)threadIdx.x + q * BOX_THREADS;
+    if (t < NX) sx[t] = vx[q];
+  }
+#pragma unroll
+  for (int q = 0; q < PF; ++q) {
+    const int t = (int)threadIdx.x + q * BOX_THREADS;
+    if (t < NF) sf[t] = vf[q] + shift;
+  }
+  if (CORR) {
+#pragma unroll
+    for (int q = 0; q < PC; ++q) {
+      const int t = (int)threadIdx.x + q * BOX_THREADS;
+      if (t < NC) sc[t] = vc[q];
+    }
+  }
+  __syncthreads();
+  if (CORR) {
+    // fine window site i lies at x0 - 2 + i (an even x0: the parity of i),
+    // in coarse cell x0 / 2 - 1 + (i >> 1), window column 1 + (i >> 1); its
+    // second cell is the next one for an odd site, the previous for an even
+    constexpr int CS = BOX_C, CS2 = BOX_C * BOX_C;
+    const double a = 0.75, bb = 0.25;
+    for (int t = threadIdx.x; t < BOX_X * BOX_X * BOX_X; t += BOX_THREADS) {
+      const int i = t % BOX_X, j = (t / BOX_X) % BOX_X, k = t / (BOX_X * BOX_X);
+      const int X = 1 + (i >> 1), Y = 1 + (j >> 1), Z = 1 + (k >> 1);
+      const int Xn = (i & 1) ? X + 1 : X - 1, Yn = (j & 1) ? Y + 1 : Y - 1;
+      const int Zn = (k & 1) ? Z + 1 : Z - 1;
+      const double e = a * a * a * sc[Z * CS2 + Y * CS + X] + bb * a * a * sc[Z * CS2 + Y * CS + Xn] +
+                       a * bb * a * sc[Z * CS2 + Yn * CS + X] + a * a * bb * sc[Zn * CS2 + Y * CS + X] +
+                       bb * bb * a * sc[Z * CS2 + Yn * CS + Xn] +
+                       bb * a * bb * sc[Zn * CS2 + Y * CS + Xn] +
+                       a * bb * bb * sc[Zn * CS2 + Yn * CS + X] +
+                       bb * bb * bb * sc[Zn * CS2 + Yn * CS + Xn];
+      sx[t] = sx[t] + e;
+    }
+    __syncthreads();
+  }
+  constexpr int SX = BOX_X, SX2 = BOX_X * BOX_X;
+  const double h2 = L.h2;
+  if constexpr (NIN) {
+    const double ih2 = 1.0 / h2;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int t = threadIdx.x; t < BOX * BOX * BOX; t += BOX_THREADS) {
+      const int i = 2 + t % BOX, j = 2 + (t / BOX) % BOX, k = 2 + t / (BOX * BOX);
+      const int w = (k * SX + j) * SX + i;
+      const double c = sx[w];
+      const double nb = sx[w - 1] + sx[w + 1] + sx[w - SX] + sx[w + SX] + sx[w - SX2] + sx[w + SX2];
+      const double rhs = sf[((k - 1) * BOX_F + (j - 1)) * BOX_F + (i - 1)];
+      const double res = rhs - (nb - 6.0 * c) * ih2;
+      acc[0] += res * res;
+      acc[1] += rhs * rhs;
+      acc[2] += c;
+    }
+    block_partials<3>(acc, partials, blockIdx.x, gridDim.x);   // its barrier orders the reads
+  }
+  // colour 0 ((x + y + z) even; x0, y0, z0 are even, so i + j + k even) on
+  // the window's sites 1 .. BOX + 2 of every side: BOX / 2 + 1 per row
+  constexpr int RROW = BOX / 2 + 1, RSIDE = BOX + 2;
+  for (int t = threadIdx.x; t < RROW * RSIDE * RSIDE; t += BOX_THREADS) {
+    const int r = t / RROW;
+    const int j = 1 + r % RSIDE, k = 1 + r / RSIDE;
+    const int i = 1 + 2 * (t % RROW) + ((1 + j + k) & 1);
+    const int w = (k * SX + j) * SX + i;
+    const double xo = sx[w];
+    const double nb = sx[w - 1] + sx[w + 1] + sx[w - SX] + sx[w + SX] + sx[w - SX2] + sx[w + SX2];
+    const double gs = (nb - h2 * sf[((k - 1) * BOX_F + (j - 1)) * BOX_F + (i - 1)]) * (1.0 / 6.0);
+    sx[w] = omega == 1.0 ? gs : xo + omega * (gs - xo);
+  }
+  __syncthreads();
+  // colour 1 on the tile (window sites 2 .. BOX + 1): BOX / 2 per row
+  constexpr int BROW = BOX / 2;
+  for (int t = threadIdx.x; t < BROW * BOX * BOX; t += BOX_THREADS) {
+    const int r = t / BROW;
+    const int j = 2 + r % BOX, k = 2 + r / BOX;
+    const int i = 2 + 2 * (t % BROW) + ((j + k + 1) & 1);
+    const int w = (k * SX + j) * SX + i;
+    const double xo = sx[w];
+    const double nb = sx[w - 1] + sx[w + 1] + sx[w - SX] + sx[w + SX] + sx[w - SX2] + sx[w + SX2];
+    const double gs = (nb - h2 * sf[((k - 1) * BOX_F + (j - 1)) * BOX_F + (i - 1)]) * (1.0 / 6.0);
+    sx[w] = omega == 1.0 ? gs : xo + omega * (gs - xo);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < BOX * BOX * BOX; t += BOX_THREADS) {
+    const int i = t % BOX, j = (t / BOX) % BOX, k = t / (BOX * BOX);
+    xout[idx3(x0 + i, y0 + j, z0 + k, L)] = sx[((k + 2) * SX + (j + 2)) * SX + (i + 2)];
+  }
+}
+
+// The pre-smoothing of a coarser level with the restriction to the next in
+// one launch: the level F arrives from the restriction with its colour-0 half
+// sweep done and its colour-1 sites at zero, so its single pre-smoothing
+// sweep is the colour-1 half sweep from that zero start (omega (gs - 0)).  A
+// workgroup loads the colour-0 sites of its BOX^3 tile of F with a two-site
+// ring, and f with a one-site ring, into LDS, relaxes the colour-1 sites of
+// the tile and of a one-site ring around it (the ring again by the
+// neighbouring workgroups alike), takes the residual at the tile's sites
+// and restricts it into the (BOX/2)^3 cells of level C below the tile, as
+// restrict_site (with the first colour-0 half sweep of C when omega_red is
+// not zero), and writes the tile's colour-1 sites in place: it reads only
+// colour-0 sites of F, which no workgroup writes.
+__global__ __launch_bounds__(BOX_THREADS) void k_restrict_box(Lvl F, Lvl C,
+                                                              const PoissonScalars* ps,
+                                                              double omega, double omega_red) {
+  __shared__ double sx[BOX_X * BOX_X * BOX_X];
+  __shared__ double sf[BOX_F * BOX_F * BOX_F];
+  __shared__ double sr[BOX * BOX * BOX];
+  const int tiles_x = F.nx / BOX, tiles_y = F.ny / BOX;
+  const int b = blockIdx.x;
+  const int bxy = b % (tiles_x * tiles_y);
+  const int x0 = (bxy % tiles_x) * BOX, y0 = (bxy / tiles_x) * BOX;
+  const int z0 = (b / (tiles_x * tiles_y)) * BOX;
+  // the colour-0 sites of the iterate window ((i + j + k) even, as x0, y0,
+  // z0 are even): BOX_X / 2 per row; all loads issued before the first store
+  constexpr int NR = BOX_X / 2 * BOX_X * BOX_X, NF = BOX_F * BOX_F * BOX_F;
+  constexpr int PR = (NR + BOX_THREADS - 1) / BOX_THREADS, PF = (NF + BOX_THREADS - 1) / BOX_THREADS;
+  double vx[PR], vf[PF];
+#pragma unroll
+  for (int q = 0; q < PR; ++q) {
+    const int t = min((int)threadIdx.x + q * BOX_THREADS, NR - 1);
+    const int r = t / (BOX_X / 2);
+    const int j = r % BOX_X, k = r / BOX_X;
+    const int i = 2 * (t % (BOX_X / 2)) + ((j + k) & 1);
+    vx[q] = F.x[idx3(wrap_index(x0 - 2 + i, F.nx), wrap_index(y0 - 2 + j, F.ny),
+                     wrap_index(z0 - 2 + k, F.nz), F)];
+  }
+#pragma unroll
+  for (int q = 0; q < PF; ++q) {
+    const int t = min((int)threadIdx.x + q * BOX_THREADS, NF - 1);
+    const int i = t % BOX_F, j = (t / BOX_F) % BOX_F, k = t / (BOX_F * BOX_F);
+    vf[q] = F.f[idx3(wrap_index(x0 - 1 + i, F.nx), wrap_index(y0 - 1 + j, F.ny),
+                     wrap_index(z0 - 1 + k, F.nz), F)];
+  }
+  if (ps->done) return;
+  constexpr int SX = BOX_X, SX2 = BOX_X * BOX_X;
+#pragma unroll
+  for (int q = 0; q < PR; ++q) {
+    const int t = (int)threadIdx.x + q * BOX_THREADS;
+    if (t < NR) {
+      const int r = t / (BOX_X / 2);
+      const int j = r % BOX_X, k = r / BOX_X;
+      sx[(k * SX + j) * SX + 2 * (t % (BOX_X / 2)) + ((j + k) & 1)] = vx[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < PF; ++q) {
+    const int t = (int)threadIdx.x + q * BOX_THREADS;
+    if (t < NF) sf[t] = vf[q];   // a coarser level: no shift
+  }
+  __syncthreads();
+  const double h2 = F.h2;
+  // colour 1 on the window's sites 1 .. BOX + 2 of every side, from zero
+  constexpr int RROW = BOX / 2 + 1, RSIDE = BOX + 2;
+  for (int t = threadIdx.x; t < RROW * RSIDE * RSIDE; t += BOX_THREADS) {
+    const int r = t / RROW;
+    const int j = 1 + r % RSIDE, k = 1 + r / RSIDE;
+    const int i = 1 + 2 * (t % RROW) + ((j + k) & 1);
+    const int w = (k * SX + j) * SX + i;
+    const double xo = 0.0;
+    const double nb = sx[w - 1] + sx[w + 1] + sx[w - SX] + sx[w + SX] + sx[w - SX2] + sx[w + SX2];
+    const double gs = (nb - h2 * sf[((k - 1) * BOX_F + (j - 1)) * BOX_F + (i - 1)]) * (1.0 / 6.0);
+    sx[w] = omega == 1.0 ? gs : xo + omega * (gs - xo);
+  }
+  __syncthreads();
+  // the residual at the tile's sites (restrict_site's expression)
+  const double ih2 = 1.0 / h2;
+  for (int t = threadIdx.x; t < BOX * BOX * BOX; t += BOX_THREADS) {
+    const int i = 2 + t % BOX, j = 2 + (t / BOX) % BOX, k = 2 + t / (BOX * BOX);
+    const int w = (k * SX + j) * SX + i;
+    const double nb = sx[w - 1] + sx[w + 1] + sx[w - SX] + sx[w + SX] + sx[w - SX2] + sx[w + SX2];
+    sr[t] = sf[((k - 1) * BOX_F + (j - 1)) * BOX_F + (i - 1)] - (nb - 6.0 * sx[w]) * ih2;
+  }
+  __syncthreads();
+  // the tile's colour-1 sites back to F.x, and the coarse cells
+  constexpr int BROW = BOX / 2;
+  for (int t = threadIdx.x; t < BROW * BOX * BOX; t += BOX_THREADS) {
+    const int r = t / BROW;
+    const int j = r % BOX, k = r / BOX;
+    const int i = 2 * (t % BROW) + ((j + k + 1) & 1);
+    F.x[idx3(x0 + i, y0 + j, z0 + k, F)] = sx[((k + 2) * SX + (j + 2)) * SX + (i + 2)];
+  }
+  constexpr int H = BOX / 2;
+  for (int t = threadIdx.x; t < H * H * H; t += BOX_THREADS) {
+    const int X = t % H, Y = (t / H) % H, Z = t / (H * H);
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      s += sr[((2 * Z + ((c >> 2) & 1)) * BOX + 2 * Y + ((c >> 1) & 1)) * BOX + 2 * X + (c & 1)];
+    const int X0 = x0 / 2 + X, Y0 = y0 / 2 + Y, Z0 = z0 / 2 + Z;
+    const int u = idx3(X0, Y0, Z0, C);
+    const double fc = 0.125 * s;
+    C.f[u] = fc;
+    double xc = 0.0;
+    if (omega_red != 0.0 && ((X0 + Y0 + Z0) & 1) == 0) {
+      const double gs = (0.0 - C.h2 * (fc + 0.0)) * (1.0 / 6.0);
+      xc = omega_red == 1.0 ? gs : 0.0 + omega_red * (gs - 0.0);
+    }
+    C.x[u] = xc;
+  }
 }
 
 // --- one full red-black sweep per launch, marching up z -----------------------
@@ -825,6 +1107,9 @@ struct ek_ctx::MG {
   // fit: tile (sweep_tx, sweep_ty), sweep_nch chunks along z; 0 = half
   // sweeps.  The finest level sweeps into tmp0 and back, the others into tmp1.
   std::vector<int> sweep_tx, sweep_ty, sweep_nch;
+  // Levels without such a plan whose sides BOX divides take one launch per
+  // full sweep instead (k_sweep_box, out of place through the same buffers).
+  std::vector<char> box;
   double* tmp0 = nullptr;
   double* tmp1 = nullptr;
   double* tmp2 = nullptr;   // the finest level's third iterate buffer
@@ -1098,6 +1383,11 @@ void ek_ctx::mg_setup() {
                                       mg->sweep_nch[0]);
     }
   }
+  mg->box.assign(nl, 0);
+  for (int l = 0; mg->tmp0 && l < fc; ++l) {
+    const Lvl& L = mg->levels[l];
+    mg->box[l] = !mg->sweep_tx[l] && L.nx % BOX == 0 && L.ny % BOX == 0 && L.nz % BOX == 0;
+  }
   mg->omega_coarsest = omega_opt(c.nx, c.ny, c.nz);
   const double rate = std::max(mg->omega_coarsest - 1.0, 1e-3);
   const double reduction = nl > 1 ? COARSEST_REDUCTION : 1e-10;
@@ -1197,6 +1487,29 @@ static void launch_sweep_z(const Lvl& L, int tx, int ty, int nch, const double* 
                        level0, MG_OMEGA, L, nullptr);
 }
 
+// One full sweep of level L from xin into xout on BOX^3 tiles; with C the
+// coarse-grid correction from level C is added on the way in.
+static void launch_sweep_box(const Lvl& L, const double* xin, double* xout,
+                             const PoissonScalars* ps, int level0, const Lvl* C, hipStream_t s) {
+  const dim3 grid((unsigned)((L.nx / BOX) * (L.ny / BOX) * (L.nz / BOX)));
+  if (C)
+    hipLaunchKernelGGL((k_sweep_box<true>), grid, dim3(BOX_THREADS), 0, s, L, xin, xout, ps, level0,
+                       MG_OMEGA, *C, nullptr);
+  else
+    hipLaunchKernelGGL((k_sweep_box<false>), grid, dim3(BOX_THREADS), 0, s, L, xin, xout, ps,
+                       level0, MG_OMEGA, L, nullptr);
+}
+
+// The finest level's first pre-smoothing sweep of a solve on BOX^3 tiles with
+// the residual norms of its input in `partials`; returns the block count.
+static int launch_sweep_box_start(const Lvl& L, const double* xin, double* xout,
+                                  const PoissonScalars* ps, double* partials, hipStream_t s) {
+  const int nblocks = (L.nx / BOX) * (L.ny / BOX) * (L.nz / BOX);
+  hipLaunchKernelGGL((k_sweep_box<false, true>), dim3(nblocks), dim3(BOX_THREADS), 0, s, L, xin,
+                     xout, ps, 1, MG_OMEGA, L, partials);
+  return nblocks;
+}
+
 // The finest level's first pre-smoothing sweep of a solve (64 x 8 tiles) with
 // the residual norms of its input in `partials`; returns the block count.
 static int launch_sweep_z_start(const Lvl& L, int nch, const double* xin, double* xout,
@@ -1233,7 +1546,9 @@ static int launch_sweep_zr(const Lvl& L, int nch, const double* xin, double* xou
   return nblocks;
 }
 
-bool ek_ctx::mg_start_in_cycle() const { return mg && mg->fused0 && NU1_FUSED >= 2; }
+bool ek_ctx::mg_start_in_cycle() const {
+  return mg && ((mg->fused0 && NU1_FUSED >= 2) || (!mg->box.empty() && mg->box[0]));
+}
 
 ek_status ek_ctx::mg_vcycle(const double* bb, double* x, int* norm_blocks, bool start) {
   if (norm_blocks) *norm_blocks = 0;
@@ -1262,6 +1577,11 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x, int* norm_blocks, bool 
   for (int l = 0; l < fc; ++l) {
     Lvl F = L[l];
     const double omega_red = (l + 1 < fc && NU1 > 0) ? MG_OMEGA : 0.0;
+    if (l > 0 && mg->box[l] && NU1 == 1) {   // its colour-1 half sweep and the restriction
+      hipLaunchKernelGGL(k_restrict_box, dim3((unsigned)((F.nx / BOX) * (F.ny / BOX) * (F.nz / BOX))),
+                         dim3(BOX_THREADS), 0, stream, F, L[l + 1], ps, MG_OMEGA, omega_red);
+      continue;
+    }
     if (l == 0 && mg->fused0) {
       // NU1_FUSED sweeps back and forth between x and tmp0, the last one
       // with the restriction in the same pass
@@ -1284,6 +1604,19 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x, int* norm_blocks, bool 
       launch_sweep_z(L[0], mg->sweep_tx[0], mg->sweep_ty[0], mg->sweep_nch[0], x, mg->tmp0, ps, 1,
                      stream);
       F.x = mg->tmp0;
+    } else if (l == 0 && mg->box[0]) {
+      // NU1_FINEST full sweeps x -> tmp0 -> x
+      static_assert(NU1_FINEST % 2 == 0, "the box sweeps end in x");
+      for (int s = 0; s < NU1_FINEST; ++s) {
+        const double* in = s % 2 ? mg->tmp0 : x;
+        double* out = s % 2 ? x : mg->tmp0;
+        if (s == 0 && start) {   // the start's residual, then its test
+          const int nb = launch_sweep_box_start(L[0], in, out, ps, partials, stream);
+          launch_residual_final(partials, nb, p.poisson_tol, 0, 1, ps, stream);
+        } else {
+          launch_sweep_box(L[0], in, out, ps, 1, nullptr, stream);
+        }
+      }
     } else {
       for (int s = 0; s < (l == 0 ? NU1_FINEST : NU1); ++s)
         for (int c = 0; c < 2; ++c) {
@@ -1328,6 +1661,14 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x, int* norm_blocks, bool 
                                        partials, stream);
       else
         launch_sweep_z(L[0], 64, 8, mg->sweep_nch[0], mid, x, ps, 1, stream);
+      continue;
+    }
+    if (mg->box[l]) {
+      // the correction inside the first of the NU2 full sweeps, x -> tmp -> x
+      static_assert(NU2 == 2, "the box sweeps end in x");
+      double* tmp = l == 0 ? mg->tmp0 : mg->tmp1;
+      launch_sweep_box(L[l], L[l].x, tmp, ps, l == 0 ? 1 : 0, &L[l + 1], stream);
+      launch_sweep_box(L[l], tmp, L[l].x, ps, l == 0 ? 1 : 0, nullptr, stream);
       continue;
     }
     if (mg->sweep_tx[l]) {

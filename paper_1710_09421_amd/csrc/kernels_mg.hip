@@ -161,6 +161,12 @@ constexpr int BOX_THREADS = 256;
 
 __device__ inline int wrap_index(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// Tile of workgroup b among n: workgroups are dispatched to the eight XCDs in
+// turn, so with n a multiple of 8 XCD k takes the k-th eighth of the tiles
+// (numbered x fastest, then y, then z: whole z-slabs), whose windows overlap
+// in its own L2.
+__device__ inline int box_tile(int b, int n) { return (n & 7) ? b : (b & 7) * (n >> 3) + (b >> 3); }
+
 template <bool CORR, bool NIN = false>
 __global__ __launch_bounds__(BOX_THREADS) void k_sweep_box(Lvl L, const double* __restrict__ xin,
                                                            double* __restrict__ xout,
@@ -172,7 +178,7 @@ __global__ __launch_bounds__(BOX_THREADS) void k_sweep_box(Lvl L, const double* 
   __shared__ double sf[BOX_F * BOX_F * BOX_F];
   __shared__ double sc[CORR ? BOX_C * BOX_C * BOX_C : 1];
   const int tiles_x = L.nx / BOX, tiles_y = L.ny / BOX;
-  const int b = blockIdx.x;
+  const int b = box_tile(blockIdx.x, gridDim.x);
   const int bxy = b % (tiles_x * tiles_y);
   const int x0 = (bxy % tiles_x) * BOX, y0 = (bxy / tiles_x) * BOX;
   const int z0 = (b / (tiles_x * tiles_y)) * BOX;
@@ -322,7 +328,7 @@ __global__ __launch_bounds__(BOX_THREADS) void k_restrict_box(Lvl F, Lvl C,
   __shared__ double sf[BOX_F * BOX_F * BOX_F];
   __shared__ double sr[BOX * BOX * BOX];
   const int tiles_x = F.nx / BOX, tiles_y = F.ny / BOX;
-  const int b = blockIdx.x;
+  const int b = box_tile(blockIdx.x, gridDim.x);
   const int bxy = b % (tiles_x * tiles_y);
   const int x0 = (bxy % tiles_x) * BOX, y0 = (bxy / tiles_x) * BOX;
   const int z0 = (b / (tiles_x * tiles_y)) * BOX;

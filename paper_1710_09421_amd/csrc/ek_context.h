@@ -134,9 +134,12 @@ struct ek_ctx {
   // One V-cycle; with norm_blocks given, its last finest-level sweep also
   // leaves the residual norms' block partials where the finest level allows
   // it (*norm_blocks = their count, else 0: the caller takes the residual).
-  // With start (mg_start_in_cycle) its first sweep also takes the residual
-  // of its input, and the start's test follows it.
-  ek_status mg_vcycle(const double* b, double* x, int* norm_blocks = nullptr, bool start = false);
+  // With first (the first cycle of a solve) the finest level takes more
+  // pre-smoothing sweeps; with start (mg_start_in_cycle, implies first) its
+  // first sweep also takes the residual of its input, and the start's test
+  // follows it.
+  ek_status mg_vcycle(const double* b, double* x, int* norm_blocks = nullptr, bool start = false,
+                      bool first = false);
   bool mg_graphs(const double* b, double* x);
   ek_status poisson(const double* b, double* x, bool learned, int& iters, double& res,
                     double& res0);

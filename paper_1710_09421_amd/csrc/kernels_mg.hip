@@ -65,20 +65,28 @@ constexpr long long FUSED_CORRECTION_MAX_SITES = 1ll << 18;
 // more cycles, which cancels the gain.
 constexpr int NU2_COARSE = 1;
 // Pre-smoothing sweeps on a finest level whose last pre-smoothing sweep also
-// restricts (k_sweep_zr): with the over-relaxed sweeps a V(1,2) cycle there
-// reduces the residual about 45-fold, so the 1e-8 of the pore systems from
-// the quadratic start (1e-5 to 1e-4) takes three cycles; two more
-// pre-smoothing sweeps make it two (256x256x512: 2.94 -> 2.00 cycles per
-// step, 3.16 -> 3.00 ms of Poisson; one more sweep gave 2.31 cycles and the
-// same time).
+// restricts (k_sweep_zr), in the first cycle of a solve and in the later
+// ones: with the over-relaxed sweeps a V(1,2) cycle there reduces the
+// residual about 45-fold, so the 1e-8 of the pore systems from the quadratic
+// start (1e-5 to 1e-4) takes three such cycles; three pre-smoothing sweeps
+// in every cycle made it two (256x256x512: 2.94 -> 2.00 cycles per step,
+// 3.16 -> 3.00 ms of Poisson; two gave 2.31 cycles and the same time), and
+// the later cycles, which start far closer, need only the one (2.18 cycles,
+// 2.57 -> 2.37 ms; two there: 2.02 cycles, 2.41 ms; four or five in the
+// first cycle: 2.47 / 2.64 ms).
 constexpr int NU1_FUSED = 3;
+constexpr int NU1_FUSED_NEXT = 1;
 // Pre-smoothing sweeps on a finest level too small for the z-marching sweeps
-// (one launch per full sweep on BOX^3 tiles): the 64x64x128 single pore's
-// solve from the cubic start took 3.17 cycles per step with two, 2.64 with
-// four, at 0.313 and 0.307 ms of Poisson per step (with half sweeps, from
-// the quadratic start: 3.71 cycles with one, 3.02 with two, 0.38 -> 0.34 ms;
-// three gave 2.80 cycles and the same time).
+// (one launch per full sweep on BOX^3 tiles), in the first cycle of a solve
+// and in the later ones: the 64x64x128 single pore's solve from the cubic
+// start took 3.17 cycles per step with two in every cycle, 2.64 with four,
+// at 0.313 and 0.307 ms of Poisson per step; from the quadratic start four
+// in the first cycle and two in the later ones took 2.66 cycles and 0.278
+// against 0.290 ms (six and two: 0.276 ms; none in the later ones: 0.313)
+// (with half sweeps, from the quadratic start: 3.71 cycles with one, 3.02
+// with two, 0.38 -> 0.34 ms).
 constexpr int NU1_FINEST = 4;
+constexpr int NU1_FINEST_NEXT = 2;
 // A solve tests its residual from one cycle before the previous solve's count
 // on, unless the previous solve was this far above the tolerance one cycle
 // before its end.
@@ -1133,7 +1141,9 @@ struct ek_ctx::MG {
   // replayed on the context's stream.
   hipStream_t record_stream = nullptr;
   hipGraphExec_t cycle = nullptr, cycle_test = nullptr;
-  // the first cycle of a solve, which also evaluates its start (fused0 only)
+  // the first cycle of a solve (more pre-smoothing on the finest level),
+  // with the start's residual (cycle_start*: mg_start_in_cycle) or without
+  hipGraphExec_t cycle_start = nullptr, cycle_start_test = nullptr;
   hipGraphExec_t cycle_first = nullptr, cycle_first_test = nullptr;
   const double* graph_b = nullptr;
   double* graph_x = nullptr;
@@ -1142,9 +1152,11 @@ struct ek_ctx::MG {
   void drop_graphs() {
     if (cycle) (void)hipGraphExecDestroy(cycle);
     if (cycle_test) (void)hipGraphExecDestroy(cycle_test);
+    if (cycle_start) (void)hipGraphExecDestroy(cycle_start);
+    if (cycle_start_test) (void)hipGraphExecDestroy(cycle_start_test);
     if (cycle_first) (void)hipGraphExecDestroy(cycle_first);
     if (cycle_first_test) (void)hipGraphExecDestroy(cycle_first_test);
-    cycle = cycle_test = cycle_first = cycle_first_test = nullptr;
+    cycle = cycle_test = cycle_start = cycle_start_test = cycle_first = cycle_first_test = nullptr;
     graph_b = nullptr;
     graph_x = nullptr;
   }
@@ -1459,11 +1471,18 @@ bool ek_ctx::mg_graphs(const double* bb, double* x) {
         // iteration -1: the test reads the cycle count the coarse kernel keeps
         launch_residual_final(partials, nr, p.poisson_tol, -1, 0, ps, stream);
       }) &&
+      record_graph(stream, &m.cycle_first, [&] { mg_vcycle(bb, x, nullptr, false, true); }) &&
+      record_graph(stream, &m.cycle_first_test, [&] {
+        int nb = 0;
+        mg_vcycle(bb, x, &nb, false, true);
+        const int nr = nb ? nb : launch_residual(x, bb, ps, partials, dims, g, stream);
+        launch_residual_final(partials, nr, p.poisson_tol, -1, 0, ps, stream);
+      }) &&
       (!mg_start_in_cycle() ||
-       (record_graph(stream, &m.cycle_first, [&] { mg_vcycle(bb, x, nullptr, true); }) &&
-        record_graph(stream, &m.cycle_first_test, [&] {
+       (record_graph(stream, &m.cycle_start, [&] { mg_vcycle(bb, x, nullptr, true, true); }) &&
+        record_graph(stream, &m.cycle_start_test, [&] {
           int nb = 0;
-          mg_vcycle(bb, x, &nb, true);
+          mg_vcycle(bb, x, &nb, true, true);
           const int nr = nb ? nb : launch_residual(x, bb, ps, partials, dims, g, stream);
           launch_residual_final(partials, nr, p.poisson_tol, -1, 0, ps, stream);
         })));
@@ -1556,7 +1575,7 @@ bool ek_ctx::mg_start_in_cycle() const {
   return mg && ((mg->fused0 && NU1_FUSED >= 2) || (!mg->box.empty() && mg->box[0]));
 }
 
-ek_status ek_ctx::mg_vcycle(const double* bb, double* x, int* norm_blocks, bool start) {
+ek_status ek_ctx::mg_vcycle(const double* bb, double* x, int* norm_blocks, bool start, bool first) {
   if (norm_blocks) *norm_blocks = 0;
   std::vector<Lvl>& L = mg->levels;
   L[0].x = x;
@@ -1577,8 +1596,12 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x, int* norm_blocks, bool 
   // into x by the prolongation; with the fused restriction by NU1_FUSED
   // sweeps, which end in tmp0 (corrected into x as before) or in x
   // (corrected in place).
-  static_assert(NU1 == 1 && NU2 % 2 == 0 && NU1_FUSED >= 1, "the out-of-place sweeps end in x");
-  const bool pre_in_x = mg->fused0 && NU1_FUSED % 2 == 0;
+  static_assert(NU1 == 1 && NU2 % 2 == 0 && NU1_FUSED >= 2 && NU1_FUSED_NEXT >= 1,
+                "the out-of-place sweeps end in x");
+  first = first || start;
+  const int nu1_fused = first ? NU1_FUSED : NU1_FUSED_NEXT;
+  const int nu1_finest = first ? NU1_FINEST : NU1_FINEST_NEXT;
+  const bool pre_in_x = mg->fused0 && nu1_fused % 2 == 0;
   const bool pre0 = mg->sweep_tx[0] != 0;
   for (int l = 0; l < fc; ++l) {
     Lvl F = L[l];
@@ -1589,11 +1612,11 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x, int* norm_blocks, bool 
       continue;
     }
     if (l == 0 && mg->fused0) {
-      // NU1_FUSED sweeps back and forth between x and tmp0, the last one
+      // nu1_fused sweeps back and forth between x and tmp0, the last one
       // with the restriction in the same pass
       double* a = x;
       double* b = mg->tmp0;
-      for (int s = 0; s + 1 < NU1_FUSED; ++s) {
+      for (int s = 0; s + 1 < nu1_fused; ++s) {
         if (s == 0 && start) {   // the start's residual, then its test
           const int nb = launch_sweep_z_start(L[0], mg->start_chunks, a, b, ps, partials, stream);
           launch_residual_final(partials, nb, p.poisson_tol, 0, 1, ps, stream);
@@ -1611,9 +1634,9 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x, int* norm_blocks, bool 
                      stream);
       F.x = mg->tmp0;
     } else if (l == 0 && mg->box[0]) {
-      // NU1_FINEST full sweeps x -> tmp0 -> x
-      static_assert(NU1_FINEST % 2 == 0, "the box sweeps end in x");
-      for (int s = 0; s < NU1_FINEST; ++s) {
+      // nu1_finest full sweeps x -> tmp0 -> x
+      static_assert(NU1_FINEST % 2 == 0 && NU1_FINEST_NEXT % 2 == 0, "the box sweeps end in x");
+      for (int s = 0; s < nu1_finest; ++s) {
         const double* in = s % 2 ? mg->tmp0 : x;
         double* out = s % 2 ? x : mg->tmp0;
         if (s == 0 && start) {   // the start's residual, then its test
@@ -1624,7 +1647,7 @@ ek_status ek_ctx::mg_vcycle(const double* bb, double* x, int* norm_blocks, bool 
         }
       }
     } else {
-      for (int s = 0; s < (l == 0 ? NU1_FINEST : NU1); ++s)
+      for (int s = 0; s < (l == 0 ? nu1_finest : NU1); ++s)
         for (int c = 0; c < 2; ++c) {
           if (l > 0 && s == 0 && c == 0) continue;
           hipLaunchKernelGGL(k_smooth, colour_launch(L[l]).grid, colour_launch(L[l]).block, 0,
@@ -1747,16 +1770,18 @@ ek_status ek_ctx::mg_solve(const double* bb, double* x, PoissonScalars h, int& i
     for (int k = 0; k < nrun; ++k) {
       ++it;
       const bool test = k >= untested || it >= p.poisson_max_iter;
-      const bool first = start_norms && it == 1;   // the cycle also evaluates the start
+      const bool first = it == 1;
+      const bool start = start_norms && first;   // the cycle also evaluates the start
       if (graphs) {
-        hipGraphExec_t ge = first ? (test ? mg->cycle_first_test : mg->cycle_first)
-                                  : (test ? mg->cycle_test : mg->cycle);
+        hipGraphExec_t ge = start   ? (test ? mg->cycle_start_test : mg->cycle_start)
+                            : first ? (test ? mg->cycle_first_test : mg->cycle_first)
+                                    : (test ? mg->cycle_test : mg->cycle);
         const hipError_t e = hipGraphLaunch(ge, stream);
         if (e != hipSuccess) return fail(EK_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
         continue;
       }
       int nb = 0;
-      st = mg_vcycle(bb, x, test ? &nb : nullptr, first);
+      st = mg_vcycle(bb, x, test ? &nb : nullptr, start, first);
       if (st) return st;
       if (!test) continue;
       const int nr = nb ? nb : launch_residual(x, bb, ps, partials, dims, g, stream);

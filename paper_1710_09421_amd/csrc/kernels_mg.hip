@@ -6,9 +6,11 @@
 // the previous in every direction while all sides stay even:
 //   level l, spacing h = 2^l:  (sum of 6 neighbours - 6 x) / h^2 = f_l
 //   smoother   red-black Gauss-Seidel (x = (sum nb - h^2 f) / 6) over-relaxed
-//              by MG_OMEGA, nu1 = NU1 = 1 and nu2 = NU2 = 2 (NU1_FUSED
-//              on a finest level whose last pre-smoothing sweep restricts,
-//              NU1_FINEST on a finest level without z-marching sweeps,
+//              by MG_OMEGA, nu1 = NU1 = 1 and nu2 = NU2 = 2 (on the finest
+//              level NU1_FUSED in the first cycle of a solve and
+//              NU1_FUSED_NEXT in the later ones where its last
+//              pre-smoothing sweep restricts, NU1_FINEST and
+//              NU1_FINEST_NEXT where it has no z-marching sweeps;
 //              NU2_COARSE = 1 on the levels of the one-workgroup coarse
 //              kernel)
 //   restriction  f_{l+1} = average of the 8 fine residuals (fused with the

@@ -141,6 +141,7 @@ struct ek_ctx {
   ek_status mg_vcycle(const double* b, double* x, int* norm_blocks = nullptr, bool start = false,
                       bool first = false);
   bool mg_graphs(const double* b, double* x);
+  hipGraphExec_t mg_batch_graph(const double* b, double* x, int n, int untested, int opens);
   ek_status poisson(const double* b, double* x, bool learned, int& iters, double& res,
                     double& res0);
 

@@ -120,6 +120,29 @@ def test_start_residual_taken_in_the_first_cycle(ek, shape):
     assert np.abs(pt.cpu().numpy() - (exact - exact.mean())).max() < 1e-12
 
 
+@pytest.mark.parametrize("shape", [(128, 64, 64), (256, 128, 128)])
+def test_multigrid_stops_at_the_cycle_limit(ek, shape):
+    """A tolerance no cycle count reaches: the solve runs exactly
+    poisson_max_iter cycles (the batches before the limit replayed as
+    recorded graphs, the last one launched cycle by cycle with its test) and
+    reports EK_ENOCONV with that count; psi holds the iterate it reached,
+    whose residual the oracle confirms is far below the start's."""
+    rng = np.random.default_rng(sum(shape) + 7)
+    rho = rng.normal(size=shape) * 0.01
+    p = ek.make_params(shape, precision=ek.EK_FP64, poisson_method=ek.EK_POISSON_MG,
+                       poisson_tol=1e-30, poisson_max_iter=3)
+    ctx = ek.Context(p)
+    rt = torch.tensor(rho, dtype=torch.float64, device="cuda")
+    pt = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(ek.EKError) as e:
+        ctx.poisson_solve(rt, pt, ek.EK_WS_ZERO)
+    print(e.value)
+    assert e.value.status == ek.EK_ENOCONV
+    assert "in 3 cycles" in str(e.value)
+    b = opoisson.rhs_from_charge(rho, EPS)
+    assert opoisson.relative_residual(pt.cpu().numpy(), b) < 1e-3
+
+
 @pytest.mark.parametrize("shape", [(36, 36, 36), (44, 44, 44)])
 def test_multigrid_with_a_large_coarsest_level(ek, shape):
     """Boxes whose sides stop halving early: the coarsest level of 36^3 is

@@ -1164,6 +1164,7 @@ struct ek_ctx::MG {
   };
   static constexpr int MAX_BATCH_GRAPHS = 8;
   std::vector<Batch> batches;
+  bool batch_failed = false;   // a batch could not be recorded: per-cycle graphs
 
   void drop_graphs() {
     for (const Batch& bg : batches) (void)hipGraphExecDestroy(bg.exec);
@@ -1522,7 +1523,7 @@ hipGraphExec_t ek_ctx::mg_batch_graph(const double* bb, double* x, int n, int un
   if (!m.cycle || m.graph_b != bb || m.graph_x != x) return nullptr;
   for (const MG::Batch& bg : m.batches)
     if (bg.n == n && bg.untested == untested && bg.opens == opens) return bg.exec;
-  if ((int)m.batches.size() >= MG::MAX_BATCH_GRAPHS) return nullptr;
+  if (m.batch_failed || (int)m.batches.size() >= MG::MAX_BATCH_GRAPHS) return nullptr;
   const SiteGrid g = site_grid(p.nx, p.ny, p.nz, bx_sites);
   const hipStream_t own = stream;
   stream = m.record_stream;
@@ -1539,7 +1540,10 @@ hipGraphExec_t ek_ctx::mg_batch_graph(const double* bb, double* x, int n, int un
     (void)hipMemcpyAsync(pinned, ps, sizeof(PoissonScalars), hipMemcpyDeviceToHost, stream);
   });
   stream = own;
-  if (!ok) return nullptr;
+  if (!ok) {
+    m.batch_failed = true;
+    return nullptr;
+  }
   m.batches.push_back({n, untested, opens, exec});
   return exec;
 }

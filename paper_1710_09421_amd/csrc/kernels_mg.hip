@@ -92,7 +92,8 @@ constexpr int NU1_FINEST = 4;
 constexpr int NU1_FINEST_NEXT = 2;
 // A solve tests its residual from one cycle before the previous solve's count
 // on, unless the previous solve was this far above the tolerance one cycle
-// before its end.
+// before its end (256x256x512 pore: 2.37 ms of Poisson per step at 4 and at
+// 8, 2.41 at 2).
 constexpr double EARLY_MARGIN = 4.0;
 
 // --- grid-wide kernels for the fine levels (3-D launch: x, y from the block,

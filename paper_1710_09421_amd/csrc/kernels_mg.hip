@@ -85,7 +85,9 @@ constexpr int NU1_FUSED_NEXT = 1;
 // start took 3.17 cycles per step with two in every cycle, 2.64 with four,
 // at 0.313 and 0.307 ms of Poisson per step; from the quadratic start four
 // in the first cycle and two in the later ones took 2.66 cycles and 0.278
-// against 0.290 ms (six and two: 0.276 ms; none in the later ones: 0.313)
+// against 0.290 ms (six and two: 0.276 ms; none in the later ones: 0.313;
+// with the 512-thread box sweeps four, six and eight in the first cycle all
+// take 0.260 ms at 2.66 / 2.47 / 2.31 cycles)
 // (with half sweeps, from the quadratic start: 3.71 cycles with one, 3.02
 // with two, 0.38 -> 0.34 ms).
 constexpr int NU1_FINEST = 4;

@@ -75,8 +75,9 @@ constexpr int NU2_COARSE = 1;
 // in every cycle made it two (256x256x512: 2.94 -> 2.00 cycles per step,
 // 3.16 -> 3.00 ms of Poisson; two gave 2.31 cycles and the same time), and
 // the later cycles, which start far closer, need only the one (2.18 cycles,
-// 2.57 -> 2.37 ms; two there: 2.02 cycles, 2.41 ms; four or five in the
-// first cycle: 2.47 / 2.64 ms).
+// 2.57 -> 2.37 ms; two there: 2.02 cycles, 2.41 ms; none, a plain
+// restriction: 2.89 cycles, 2.72 ms; four or five in the first cycle:
+// 2.47 / 2.64 ms).
 constexpr int NU1_FUSED = 3;
 constexpr int NU1_FUSED_NEXT = 1;
 // Pre-smoothing sweeps on a finest level too small for the z-marching sweeps

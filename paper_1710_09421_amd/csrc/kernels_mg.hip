@@ -6,7 +6,8 @@
 // the previous in every direction while all sides stay even:
 //   level l, spacing h = 2^l:  (sum of 6 neighbours - 6 x) / h^2 = f_l
 //   smoother   red-black Gauss-Seidel (x = (sum nb - h^2 f) / 6) over-relaxed
-//              by MG_OMEGA, nu1 = NU1 = 1 and nu2 = NU2 = 2 (on the finest
+//              by MG_OMEGA (MG_OMEGA_FINEST in the z-marching sweeps of the
+//              finest level), nu1 = NU1 = 1 and nu2 = NU2 = 2 (on the finest
 //              level NU1_FUSED in the first cycle of a solve and
 //              NU1_FUSED_NEXT in the later ones where its last
 //              pre-smoothing sweep restricts, NU1_FINEST and
@@ -80,6 +81,11 @@ constexpr int NU2_COARSE = 1;
 // 2.47 / 2.64 ms).
 constexpr int NU1_FUSED = 3;
 constexpr int NU1_FUSED_NEXT = 1;
+// Relaxation factor of the z-marching sweeps on the finest level (the other
+// levels keep MG_OMEGA): with the cycle counts above the 256x256x512 pore
+// takes 2.02 cycles and 2.22 ms of Poisson per step at 1.2, against 2.18
+// cycles and 2.36 ms at 1.25, 2.23 ms at 1.15 and 2.66 ms at 1.1 (400 steps).
+constexpr double MG_OMEGA_FINEST = 1.2;
 // Pre-smoothing sweeps on a finest level too small for the z-marching sweeps
 // (one launch per full sweep on BOX^3 tiles), in the first cycle of a solve
 // and in the later ones: the 64x64x128 single pore's solve from the cubic
@@ -1561,13 +1567,13 @@ static void launch_sweep_z(const Lvl& L, int tx, int ty, int nch, const double* 
   const dim3 grid((unsigned)((L.nx / tx) * (L.ny / ty) * nch));
   if (tx == 64 && ty == 16)
     hipLaunchKernelGGL((k_sweep_z<64, 16>), grid, dim3(SWEEP_THREADS), 0, s, L, xin, xout, nch, ps,
-                       level0, MG_OMEGA, L, nullptr);
+                       level0, level0 ? MG_OMEGA_FINEST : MG_OMEGA, L, nullptr);
   else if (tx == 64)
     hipLaunchKernelGGL((k_sweep_z<64, 8>), grid, dim3(SWEEP_THREADS), 0, s, L, xin, xout, nch, ps,
-                       level0, MG_OMEGA, L, nullptr);
+                       level0, level0 ? MG_OMEGA_FINEST : MG_OMEGA, L, nullptr);
   else
     hipLaunchKernelGGL((k_sweep_z<32, 8>), grid, dim3(SWEEP_THREADS), 0, s, L, xin, xout, nch, ps,
-                       level0, MG_OMEGA, L, nullptr);
+                       level0, level0 ? MG_OMEGA_FINEST : MG_OMEGA, L, nullptr);
 }
 
 // One full sweep of level L from xin into xout on BOX^3 tiles; with C the
@@ -1589,7 +1595,7 @@ static int launch_sweep_box_start(const Lvl& L, const double* xin, double* xout,
                                   const PoissonScalars* ps, double* partials, hipStream_t s) {
   const int nblocks = (L.nx / BOX) * (L.ny / BOX) * (L.nz / BOX);
   hipLaunchKernelGGL((k_sweep_box<false, true>), dim3(nblocks), dim3(BOX_THREADS), 0, s, L, xin,
-                     xout, ps, 1, MG_OMEGA, L, partials);
+                     xout, ps, 1, MG_OMEGA_FINEST, L, partials);
   return nblocks;
 }
 
@@ -1599,7 +1605,7 @@ static int launch_sweep_z_start(const Lvl& L, int nch, const double* xin, double
                                 const PoissonScalars* ps, double* partials, hipStream_t s) {
   const int nblocks = (L.nx / 64) * (L.ny / 8) * nch;
   hipLaunchKernelGGL((k_sweep_z<64, 8, false, true>), dim3(nblocks), dim3(SWEEP_THREADS), 0, s, L,
-                     xin, xout, nch, ps, 1, MG_OMEGA, L, partials);
+                     xin, xout, nch, ps, 1, MG_OMEGA_FINEST, L, partials);
   return nblocks;
 }
 
@@ -1610,7 +1616,7 @@ static void launch_sweep_z_corrected(const Lvl& L, const Lvl& C, int nch, const 
                                      hipStream_t s) {
   const dim3 grid((unsigned)((L.nx / 64) * (L.ny / 8) * nch));
   hipLaunchKernelGGL((k_sweep_z<64, 8, true>), grid, dim3(SWEEP_THREADS), 0, s, L, xin, xout, nch,
-                     ps, level0, MG_OMEGA, C, nullptr);
+                     ps, level0, level0 ? MG_OMEGA_FINEST : MG_OMEGA, C, nullptr);
 }
 
 // The finest level's full sweep with the residual of its result (restriction
@@ -1622,10 +1628,10 @@ static int launch_sweep_zr(const Lvl& L, int nch, const double* xin, double* xou
   const int nblocks = (L.nx / 64) * (L.ny / ZR_TY) * nch;
   if (mode == SWEEP_RESTRICT)
     hipLaunchKernelGGL((k_sweep_zr<64, ZR_TY, SWEEP_RESTRICT>), dim3(nblocks), dim3(ZR_THREADS), 0,
-                       s, L, xin, xout, nch, ps, 1, MG_OMEGA, C, omega_red, partials);
+                       s, L, xin, xout, nch, ps, 1, MG_OMEGA_FINEST, C, omega_red, partials);
   else
     hipLaunchKernelGGL((k_sweep_zr<64, ZR_TY, SWEEP_NORMS>), dim3(nblocks), dim3(ZR_THREADS), 0, s,
-                       L, xin, xout, nch, ps, 1, MG_OMEGA, C, 0.0, partials);
+                       L, xin, xout, nch, ps, 1, MG_OMEGA_FINEST, C, 0.0, partials);
   return nblocks;
 }
 

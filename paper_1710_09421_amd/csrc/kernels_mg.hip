@@ -84,7 +84,10 @@ constexpr int NU1_FUSED_NEXT = 1;
 // Relaxation factor of the z-marching sweeps on the finest level (the other
 // levels keep MG_OMEGA): with the cycle counts above the 256x256x512 pore
 // takes 2.02 cycles and 2.22 ms of Poisson per step at 1.2, against 2.18
-// cycles and 2.36 ms at 1.25, 2.23 ms at 1.15 and 2.66 ms at 1.1 (400 steps).
+// cycles and 2.36 ms at 1.25, 2.21 / 2.25 ms at 1.18 / 1.22, 2.23 ms at 1.15
+// and 2.66 ms at 1.1, 2.23 ms with level 1's z-marching sweeps at 1.2 too
+// (400 steps).  The box sweeps of a smaller finest level keep MG_OMEGA (the
+// 64x64x128 pore: 0.264 against 0.261 ms at 1.2).
 constexpr double MG_OMEGA_FINEST = 1.2;
 // Pre-smoothing sweeps on a finest level too small for the z-marching sweeps
 // (one launch per full sweep on BOX^3 tiles), in the first cycle of a solve
@@ -1595,7 +1598,7 @@ static int launch_sweep_box_start(const Lvl& L, const double* xin, double* xout,
                                   const PoissonScalars* ps, double* partials, hipStream_t s) {
   const int nblocks = (L.nx / BOX) * (L.ny / BOX) * (L.nz / BOX);
   hipLaunchKernelGGL((k_sweep_box<false, true>), dim3(nblocks), dim3(BOX_THREADS), 0, s, L, xin,
-                     xout, ps, 1, MG_OMEGA_FINEST, L, partials);
+                     xout, ps, 1, MG_OMEGA, L, partials);
   return nblocks;
 }
 

@@ -65,7 +65,7 @@ constexpr long long FUSED_CORRECTION_MAX_SITES = 1ll << 18;
 // whose barrier phases on a 1k-site level are bound by LDS bandwidth: one
 // sweep there left the cycle counts of the pore systems from the
 // extrapolated start unchanged (64x64x128 and 256x256x512) and took 2 % off
-// the single pore's step; from the previous solution it needed about 3 %
+// the 64x64x128 pore's step; from the previous solution it needed about 3 %
 // more cycles, which cancels the gain.
 constexpr int NU2_COARSE = 1;
 // Pre-smoothing sweeps on a finest level whose last pre-smoothing sweep also
@@ -91,7 +91,7 @@ constexpr int NU1_FUSED_NEXT = 1;
 constexpr double MG_OMEGA_FINEST = 1.2;
 // Pre-smoothing sweeps on a finest level too small for the z-marching sweeps
 // (one launch per full sweep on BOX^3 tiles), in the first cycle of a solve
-// and in the later ones: the 64x64x128 single pore's solve from the cubic
+// and in the later ones: the 64x64x128 pore's solve from the cubic
 // start took 3.17 cycles per step with two in every cycle, 2.64 with four,
 // at 0.313 and 0.307 ms of Poisson per step; from the quadratic start four
 // in the first cycle and two in the later ones took 2.66 cycles and 0.278
@@ -181,9 +181,9 @@ constexpr int BOX = 8;
 constexpr int BOX_X = BOX + 4;        // iterate window side (two-site ring)
 constexpr int BOX_F = BOX + 2;        // right-hand side window side
 constexpr int BOX_C = BOX / 2 + 4;    // coarse window side
-// 512 threads per workgroup (one or two sites per thread and phase): single
-// pore 0.259 ms of Poisson per step against 0.268 with 256, 0.272 with 1024
-// and 0.309 with 128
+// 512 threads per workgroup (at most one or two sites per thread and
+// phase): the 64x64x128 pore's solve takes 0.259 ms per step against 0.268
+// with 256, 0.272 with 1024 and 0.309 with 128
 constexpr int BOX_THREADS = 512;
 
 __device__ inline int wrap_index(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }

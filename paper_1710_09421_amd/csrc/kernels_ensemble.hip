@@ -35,6 +35,10 @@ constexpr int ENS_COARSEST_CAP = 200;
 // (with the extrapolated start 6.3 against 6.6 ms per step of 64 replicas for
 // V(2,2); from the previous solution V(2,2) had been the faster)
 constexpr int ENS_NU1 = 1, ENS_NU2 = 2;
+// Relaxation factor of the finest level's half sweeps (the coarser levels
+// keep MG_OMEGA): 6.62 ms per step of 64 replicas against 6.78 at 1.25, 6.76
+// at 1.15 and 7.21 at 1.3 (the first 23 steps from the extrapolated start).
+constexpr double ENS_OMEGA_FINEST = 1.2;
 
 enum : int { ST_OK = 0, ST_NOCONV = 1, ST_UNSTABLE = 2, ST_TIMEOUT = 3 };
 
@@ -338,7 +342,7 @@ __global__ __launch_bounds__(MAXT) void k_ensemble(RepDev* reps, EnsConst ec) {
           for (int c = 0; ok && c < 2; ++c) ok = fine_half(c, ec.omega_coarsest);
       } else {
         for (int sw = 0; ok && sw < ENS_NU1; ++sw)
-          for (int c = 0; ok && c < 2; ++c) ok = fine_half(c, MG_OMEGA);
+          for (int c = 0; ok && c < 2; ++c) ok = fine_half(c, ENS_OMEGA_FINEST);
         if (!ok) break;
         team_restrict(L[0], L[1], shift, first, stride);
         if (!(ok = team_sync(ts, G, gen, &s_ok))) break;
@@ -357,7 +361,7 @@ __global__ __launch_bounds__(MAXT) void k_ensemble(RepDev* reps, EnsConst ec) {
         team_prolong(L[0], L[1], first, stride);
         if (!(ok = team_sync(ts, G, gen, &s_ok))) break;
         for (int sw = 0; ok && sw < ENS_NU2; ++sw)
-          for (int c = 0; ok && c < 2; ++c) ok = fine_half(c, MG_OMEGA);
+          for (int c = 0; ok && c < 2; ++c) ok = fine_half(c, ENS_OMEGA_FINEST);
         if (!ok) break;
       }
       ++cycles;

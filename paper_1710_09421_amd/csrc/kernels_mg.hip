@@ -86,8 +86,9 @@ constexpr int NU1_FUSED_NEXT = 1;
 // takes 2.02 cycles and 2.22 ms of Poisson per step at 1.2, against 2.18
 // cycles and 2.36 ms at 1.25, 2.21 / 2.25 ms at 1.18 / 1.22, 2.23 ms at 1.15
 // and 2.66 ms at 1.1, 2.23 ms with level 1's z-marching sweeps at 1.2 too
-// (400 steps).  The box sweeps of a smaller finest level keep MG_OMEGA (the
-// 64x64x128 pore: 0.264 against 0.261 ms at 1.2).
+// (400 steps; 1.25 in the first cycle and 1.2 in the later ones: 2.28 ms,
+// the reverse splits 2.21 ms).  The box sweeps of a smaller finest level keep
+// MG_OMEGA (the 64x64x128 pore: 0.264 against 0.261 ms at 1.2).
 constexpr double MG_OMEGA_FINEST = 1.2;
 // Pre-smoothing sweeps on a finest level too small for the z-marching sweeps
 // (one launch per full sweep on BOX^3 tiles), in the first cycle of a solve
